@@ -1,0 +1,211 @@
+/*
+ * librmtr: matrix-free evaluation of the pressure-induced phase-field
+ * fracture energy on uniform Q1 grids, the operators of the recursive
+ * multilevel trust-region method (RMTR) around it, and the RMTR load step,
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * Reference: P. Zulian et al., "Large scale simulation of pressure induced
+ * phase-field fracture propagation using Utopia", arXiv 2007.12908.
+ *
+ * Problem (Sec. 2, eq. (min_problem_pf)): find (u, c) in V_u^t x V_c
+ * minimising E(u, c, p) of eq. (pressurized) on the unit square / cube with
+ *   W = g(c) psi+(eps) + psi-(eps) + Gc/2 (c^2/l + l |grad c|^2) + gp(c) div(p u),
+ *   g(c) = (1-k)(1-c)^2 + k,  gp(c) = (1-c)^2,  AT2 crack density (Sec. 2.1),
+ *   psi+ = K/2 <tr eps>+^2 + mu dev(eps):dev(eps),  psi- = K/2 <tr eps>-^2
+ *   (volumetric-deviatoric split; 2D is plane strain), or the unsplit
+ *   psi+ = lambda/2 (tr eps)^2 + mu eps:eps, psi- = 0 (Sec. 2, first paragraph).
+ * Discretisation: first-order Lagrange (Q1) elements (Sec. 2.2), N^d cells,
+ * 2^d Gauss points per cell.  Feasible set V_c: c_lower <= c <= 1
+ * (eq. (space_pf)); displacements fixed on the Dirichlet set (V_u^t).
+ *
+ * Conventions shared by every entry point
+ *   - Levels are numbered as in Sec. 3: 1 = coarsest ... L = finest.  Level l
+ *     has N_l = N_L / 2^(L-l) cells per side and (N_l + 1)^d nodes.
+ *   - Node n = i + (N+1) (j + (N+1) k); vectors are node-major interleaved:
+ *     v[(d+1) n + comp], comp = (u_x, u_y[, u_z], c).  Scalar nodal fields
+ *     (pressure p, c_lower) hold one value per node.
+ *   - Every array argument is a DEVICE pointer owned by the caller unless the
+ *     comment says "host".  Arrays must not alias unless stated.
+ *   - precision: RMTR_FP64 -> the void* arrays are double; RMTR_FP32 -> float
+ *     (the mixed-precision form's Hessian and smoother arithmetic).
+ *   - dirichlet: per-node uint8 bit mask (bit comp set = that component is
+ *     fixed), device pointer, or NULL for the default set: every displacement
+ *     component on the boundary.  Gradients have zero rows and Hessians zero
+ *     rows and columns at fixed dofs.
+ *   - stream: a hipStream_t (passed as void*); work is enqueued on it.  Calls
+ *     that return host values synchronise that stream.
+ *   - Errors: no exception crosses this interface.  A negative status means
+ *     the outputs are undefined; rmtr_last_error() describes the failure.
+ *   - The library allocates its own device workspace (on first use of an
+ *     operation on a level) and frees it in rmtr_destroy().  A context is not
+ *     thread safe.
+ */
+#ifndef RMTR_H
+#define RMTR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rmtr_ctx rmtr_ctx;
+typedef int32_t rmtr_status;
+
+#define RMTR_OK 0
+#define RMTR_NOT_CONVERGED 1 /* warning: outputs valid, tolerance not met */
+#define RMTR_E_ARG (-1)
+#define RMTR_E_HIP (-2)
+#define RMTR_E_NONFINITE (-4)
+
+#define RMTR_FP64 0
+#define RMTR_FP32 1
+
+/* Restriction modes for rmtr_restrict (Sec. 3: R = I^T, projection P). */
+#define RMTR_R_DUAL 0   /* R = I^T, for gradients (dual quantities)        */
+#define RMTR_R_INJECT 1 /* P: fine node (2i,2j,2k) -> coarse node (i,j,k)  */
+#define RMTR_R_BOX_LO 2 /* max over the support of each coarse basis fn    */
+#define RMTR_R_BOX_HI 3 /* min over the support of each coarse basis fn    */
+
+/* Model (Sec. 2): material and grid.  ls = l_s (the paper uses 2h, Sec. 5). */
+typedef struct {
+  int32_t dim;      /* 2 or 3 */
+  int32_t n_cells;  /* N_L, cells per side on the finest level */
+  int32_t n_levels; /* L >= 1; N_L must be divisible by 2^(L-1) */
+  int32_t split;    /* 1: volumetric-deviatoric split, 0: unsplit density */
+  double lambda, mu, Gc, ls, k;
+} rmtr_model;
+
+/* Solver constants (Alg. 1-3, Sec. 3.2.1, Sec. 4.2.1). */
+typedef struct {
+  double eta1, eta2;       /* 0 < eta1 <= eta2 <= 1 (Alg. 3)            */
+  double gamma1, gamma2;   /* 0 < gamma1 <= 1 <= gamma2 (Alg. 3)        */
+  double delta0, delta_max; /* initial and largest TR radius             */
+  double rtol;             /* stop when chi <= rtol chi(x_initial)      */
+  double coarse_qp_rtol;   /* MPRGP relative tolerance                  */
+  double guard;            /* round-off guard of the TR ratio           */
+  int32_t mu1, mu2;        /* pre-/post-smoothing TR steps (Alg. 1)     */
+  int32_t pgs_sweeps;      /* symmetric PGS sweeps per TR subproblem    */
+  int32_t coarse_tr_its;   /* TR steps on the coarsest level (mu^1)     */
+  int32_t coarse_qp_its;   /* MPRGP iteration cap                       */
+  int32_t fallback_sweeps; /* PGS sweeps after MPRGP meets p^T A p <= 0 */
+  int32_t max_vcycles;
+  int32_t precision;       /* RMTR_FP64 or RMTR_FP32 (fine Hv + PGS)    */
+  int32_t coarse_model;    /* 0: f~ = f on the coarse grid, 1: f~ = 0   */
+} rmtr_params;
+
+typedef struct {
+  int32_t vcycles, tr_accepted, tr_rejected, status;
+  double chi0, chi, energy, seconds;
+} rmtr_stats;
+
+/* Fills p with the defaults used throughout: eta = (0.1, 0.75),
+   gamma = (0.5, 2), delta0 = 1, delta_max = 10, rtol = 1e-8, mu1 = mu2 = 1,
+   3 PGS sweeps, 5 coarse TR steps, MPRGP 500 its / 1e-10, 50 fallback sweeps,
+   200 V-cycles, FP64, f~ = f. */
+void rmtr_default_params(rmtr_params* p);
+
+/* Create a context for the hierarchy of `model`.  Returns RMTR_E_ARG on an
+   invalid model (dim, N not divisible by 2^(L-1), non-positive material). */
+rmtr_status rmtr_create(const rmtr_model* model, rmtr_ctx** out);
+void rmtr_destroy(rmtr_ctx* ctx);
+const char* rmtr_last_error(const rmtr_ctx* ctx);
+/* Nodes of level `level` ((N_l+1)^d), or -1 for an invalid level. */
+int64_t rmtr_level_nodes(const rmtr_ctx* ctx, int32_t level);
+
+/* Nodal inclusion initialisation (Sec. 5, first paragraph; Sec. 5.2):
+   c0[n] = 1 if node n lies inside a fracture's volumetric description
+   (3D: within distance `band` of a disc; 2D: inside a rectangle), else 0.
+   table (host, row-major): 3D rows (cx cy cz nx ny nz radius pressure),
+   2D rows (cx cy tx ty half_length half_width pressure).
+   p_mode 0: p[n] = p_value everywhere; 1 (3D): p[n] = max pressure of the
+   discs within distance p_band of the node, else 0.  p may be NULL. */
+rmtr_status rmtr_init_fields(rmtr_ctx* ctx, int32_t level, const double* table, int32_t n_frac, double band,
+                             int32_t p_mode, double p_value, double p_band, double* c0, double* p, void* stream);
+
+/* Energy f(x) = sum_e sum_q w_q W (eq. (pressurized), discretised), FP64.
+   x: (d+1) per node; p: nodal pressure; out: ONE double in device memory. */
+rmtr_status rmtr_energy(rmtr_ctx* ctx, int32_t level, const double* x, const double* p, double* out,
+                        void* stream);
+
+/* f(x + s) - f(x), accumulated element by element (numerator of eq. (rho_tr)
+   and (rho_ml)); s is double (s_precision RMTR_FP64) or float (RMTR_FP32). */
+rmtr_status rmtr_energy_diff(rmtr_ctx* ctx, int32_t level, const double* x, const void* s, int32_t s_precision,
+                             const double* p, double* out, void* stream);
+
+/* Gradient of f at x (first variation of W), Dirichlet rows zero. */
+rmtr_status rmtr_gradient(rmtr_ctx* ctx, int32_t level, const double* x, const double* p,
+                          const uint8_t* dirichlet, double* g, void* stream);
+
+/* Hv = grad^2 f(x_lin) v on the free dofs (second variation of W; Sec. 4.2.1:
+   the Hessian is taken at a lagged linearisation point).  FP32: x_lin, p,
+   v and Hv are float. */
+rmtr_status rmtr_hessvec(rmtr_ctx* ctx, int32_t level, const void* x_lin, const void* p,
+                         const uint8_t* dirichlet, const void* v, void* Hv, int32_t precision, void* stream);
+
+/* Node diagonal blocks of grad^2 f(x_lin): (d+1)^2 values per node,
+   row-major, Dirichlet rows and columns zero (Sec. 4.2.2, the diagonal-block
+   copy used by the Gauss-Seidel smoother). */
+rmtr_status rmtr_diag_blocks(rmtr_ctx* ctx, int32_t level, const void* x_lin, const void* p,
+                             const uint8_t* dirichlet, void* D, int32_t precision, void* stream);
+
+/* Symmetric projected Gauss-Seidel (Sec. 3.2.1) on the TR subproblem
+   eq. (model_qp) with the Hessian at x_lin:
+     min g^T s + 1/2 s^T H s,  lo <= s <= hi;
+   n_sweeps sweeps (forward then backward over the 2^d node colours), starting
+   from s_inout.  D: node diagonal blocks from rmtr_diag_blocks (or NULL: the
+   library computes them).  Arrays in `precision`. */
+rmtr_status rmtr_smooth(rmtr_ctx* ctx, int32_t level, const void* x_lin, const void* p,
+                        const uint8_t* dirichlet, const void* D, const void* g, const void* lo, const void* hi,
+                        void* s_inout, int32_t n_sweeps, int32_t precision, void* stream);
+
+/* Level transfers (Sec. 3): fine (level fine_level) -> coarse (fine_level-1). */
+rmtr_status rmtr_restrict(rmtr_ctx* ctx, int32_t fine_level, int32_t mode, const void* fine, void* coarse,
+                          int32_t precision, void* stream);
+/* Prolongation I: coarse (coarse_level) -> fine (coarse_level + 1). */
+rmtr_status rmtr_prolong(rmtr_ctx* ctx, int32_t coarse_level, const void* coarse, void* fine, int32_t precision,
+                         void* stream);
+
+/* Galerkin coarse Hessian (eq. (delta_terms): R grad^2 h I) as one dense
+   ((d+1) 2^d)^2 row-major FP64 matrix per element of level coarse_level,
+   Dirichlet rows/columns zero.  If coarse_level == L-1 it is built from the
+   matrix-free Hessian at x_lin (fine p, fine Dirichlet mask); otherwise from
+   the element matrices K_fine of level coarse_level+1 (x_lin, p, dirichlet
+   ignored). */
+rmtr_status rmtr_galerkin(rmtr_ctx* ctx, int32_t coarse_level, const double* x_lin, const double* p,
+                          const uint8_t* dirichlet, const double* K_fine, double* K_coarse, void* stream);
+/* Hv and symmetric PGS with element matrices K of `level` (FP64). */
+rmtr_status rmtr_em_hessvec(rmtr_ctx* ctx, int32_t level, const double* K, const double* v, double* Hv,
+                            void* stream);
+rmtr_status rmtr_em_smooth(rmtr_ctx* ctx, int32_t level, const double* K, const double* g, const double* lo,
+                           const double* hi, double* s_inout, int32_t n_sweeps, void* stream);
+
+/* MPRGP (Sec. 3.2.1, coarsest level) for min g^T s + 1/2 s^T K s,
+   lo <= s <= hi, from s = 0.  iterations/status (host, may be NULL):
+   status 0 converged, 1 iteration cap, 2 non-positive curvature (then
+   fallback_sweeps PGS sweeps were applied).  Synchronises the stream. */
+rmtr_status rmtr_mprgp(rmtr_ctx* ctx, int32_t level, const double* K, const double* g, const double* lo,
+                       const double* hi, double* s, int32_t max_it, double rtol, int32_t fallback_sweeps,
+                       int32_t* iterations, int32_t* status, void* stream);
+
+/* Reductions on FP64 vectors (device scalar result). */
+rmtr_status rmtr_dot(rmtr_ctx* ctx, int64_t n, const double* a, const double* b, double* out, void* stream);
+/* chi = || P_F(x - g) - x ||_2 over the free dofs, F: c_lower <= c <= 1. */
+rmtr_status rmtr_chi(rmtr_ctx* ctx, int32_t level, const double* x, const double* g, const double* c_lower,
+                     const uint8_t* dirichlet, double* out, void* stream);
+
+/* One load step (Sec. 4.1 workflow step 7b): RMTR V-cycles (Alg. 1-3 with
+   Hessian lagging, Sec. 4.2.1) from x_inout until chi <= rtol chi(x_in) or
+   max_vcycles.  p: fine nodal pressure; c_lower: c^{t-1} per fine node;
+   x_inout must be feasible.  chi_history (host, may be NULL) receives chi
+   after each V-cycle (max_vcycles entries).  Returns RMTR_OK,
+   RMTR_NOT_CONVERGED (x still feasible) or an error.  Synchronises. */
+rmtr_status rmtr_solve_loadstep(rmtr_ctx* ctx, const double* p, const double* c_lower, const uint8_t* dirichlet,
+                                const rmtr_params* params, double* x_inout, rmtr_stats* stats,
+                                double* chi_history, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RMTR_H */

@@ -208,7 +208,11 @@ class RMTR:
         c.Lb = c.x0 + loH
         c.Ub = c.x0 + hiH
         g = self.h_grad(lev, x)
-        c.Hmod = (R @ lev.Hmod @ I).tocsr()
+        # Galerkin product restricted to the coarse free dofs (the coarse
+        # problem, like the fine one, has no displacement dofs on the boundary)
+        Dc = sp.diags(c.free.astype(np.float64))
+        c.Hmod = (Dc @ (R @ lev.Hmod @ I) @ Dc).tocsr()
+        c.Hmod.sort_indices()
         if self.prm.coarse_model == "energy":
             c.Hf0 = fem.hessian(c.grid, c.x0, c.p, c.mat, c.dirichlet)
             c.dg = R @ g - fem.gradient(c.grid, c.x0, c.p, c.mat, c.dirichlet)

@@ -1,0 +1,746 @@
+// Matrix-free element kernels on the Q1 grid: energy, energy difference,
+// gradient, Hessian-vector product, node diagonal blocks and the projected
+// Gauss-Seidel colour pass.  FP64 throughout, with FP32 variants of the
+// Hessian-based operators for the mixed-precision form.
+#include "rmtr_kernels.h"
+
+namespace rmtr {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+template <int DIM>
+__device__ inline void node_ijk(int64_t n, int64_t nside, int (&ijk)[DIM]) {
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    ijk[i] = int(n % nside);
+    n /= nside;
+  }
+}
+
+template <int DIM>
+__device__ inline int64_t node_id(const int (&ijk)[DIM], int64_t nside) {
+  int64_t n = 0, s = 1;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    n += int64_t(ijk[i]) * s;
+    s *= nside;
+  }
+  return n;
+}
+
+template <int DIM>
+__device__ inline uint8_t node_mask(const uint8_t* dir, int64_t n, const int (&ijk)[DIM], int N) {
+  return dir ? dir[n] : default_mask<DIM>(ijk, N);
+}
+
+template <typename T>
+__device__ inline MatP<T> cast_mat(const MatP<double>& m) {
+  MatP<T> r;
+  r.lam = T(m.lam);
+  r.mu = T(m.mu);
+  r.K = T(m.K);
+  r.Gc = T(m.Gc);
+  r.ls = T(m.ls);
+  r.k = T(m.k);
+  r.split = m.split;
+  return r;
+}
+
+// Block sum of one double per thread; thread 0 gets the result.
+__device__ inline double block_sum(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// Load the 2^DIM nodes of element with lower corner e (node-major layout).
+template <int DIM, typename TS, typename T>
+__device__ inline void load_elem(const TS* x, const int (&e)[DIM], int64_t nside, T (&X)[1 << DIM][DIM + 1]) {
+#pragma unroll
+  for (int a = 0; a < (1 << DIM); ++a) {
+    int c[DIM];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) c[i] = e[i] + ((a >> i) & 1);
+    const int64_t n = node_id<DIM>(c, nside);
+#pragma unroll
+    for (int k = 0; k <= DIM; ++k) X[a][k] = T(x[(DIM + 1) * n + k]);
+  }
+}
+
+template <int DIM, typename TS, typename T>
+__device__ inline void load_elem_scalar(const TS* p, const int (&e)[DIM], int64_t nside, T (&P)[1 << DIM]) {
+#pragma unroll
+  for (int a = 0; a < (1 << DIM); ++a) {
+    int c[DIM];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) c[i] = e[i] + ((a >> i) & 1);
+    P[a] = T(p[node_id<DIM>(c, nside)]);
+  }
+}
+
+// Zero the Dirichlet components of an element's nodal values.
+template <int DIM, typename T>
+__device__ inline void mask_elem(const uint8_t* dir, const int (&e)[DIM], int N, T (&X)[1 << DIM][DIM + 1]) {
+  const int64_t nside = N + 1;
+#pragma unroll
+  for (int a = 0; a < (1 << DIM); ++a) {
+    int c[DIM];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) c[i] = e[i] + ((a >> i) & 1);
+    const uint8_t mk = node_mask<DIM>(dir, node_id<DIM>(c, nside), c, N);
+#pragma unroll
+    for (int k = 0; k <= DIM; ++k)
+      if (mk & (1u << k)) X[a][k] = T(0);
+  }
+}
+
+// z-vectors at all 2^DIM points (3D: sum-factorised; 2D: plain).
+template <int DIM, typename T>
+__device__ inline void elem_z(const T (&X)[1 << DIM][DIM + 1], T invh, Zq<DIM, T> (&z)[1 << DIM]) {
+  if constexpr (DIM == 3) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      T f[8], val[8], dx[8], dy[8], dz[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) f[a] = X[a][k];
+      sf_forward3<T>(f, val, dx, dy, dz);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (k < 3) {
+          z[q].u[k] = val[q];
+          z[q].G[k][0] = dx[q] * invh;
+          z[q].G[k][1] = dy[q] * invh;
+          z[q].G[k][2] = dz[q] * invh;
+        } else {
+          z[q].c = val[q];
+          z[q].dc[0] = dx[q] * invh;
+          z[q].dc[1] = dy[q] * invh;
+          z[q].dc[2] = dz[q] * invh;
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < (1 << DIM); ++q) interp_q<DIM, T>(q, X, invh, z[q]);
+  }
+}
+
+template <int DIM, typename T>
+__device__ inline void elem_pq(const T (&P)[1 << DIM], T invh, T (&pq)[1 << DIM], T (&dpq)[1 << DIM][DIM]) {
+  if constexpr (DIM == 3) {
+    T dx[8], dy[8], dz[8];
+    sf_forward3<T>(P, pq, dx, dy, dz);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      dpq[q][0] = dx[q] * invh;
+      dpq[q][1] = dy[q] * invh;
+      dpq[q][2] = dz[q] * invh;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < (1 << DIM); ++q) interp_scalar_q<DIM, T>(q, P, invh, pq[q], dpq[q]);
+  }
+}
+
+// r[a][k] = sum_q w B_{q,a}^T o_q for all nodes of the element.
+template <int DIM, typename T>
+__device__ inline void elem_project(const Zq<DIM, T> (&o)[1 << DIM], T invh, T w, T (&r)[1 << DIM][DIM + 1]) {
+  if constexpr (DIM == 3) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      T cv[8], cx[8], cy[8], cz[8], rr[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (k < 3) {
+          cv[q] = w * o[q].u[k];
+          cx[q] = w * invh * o[q].G[k][0];
+          cy[q] = w * invh * o[q].G[k][1];
+          cz[q] = w * invh * o[q].G[k][2];
+        } else {
+          cv[q] = w * o[q].c;
+          cx[q] = w * invh * o[q].dc[0];
+          cy[q] = w * invh * o[q].dc[1];
+          cz[q] = w * invh * o[q].dc[2];
+        }
+        rr[q] = T(0);
+      }
+      sf_backward3<T>(cv, cx, cy, cz, rr);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) r[a][k] = rr[a];
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < (1 << DIM); ++a)
+#pragma unroll
+      for (int k = 0; k <= DIM; ++k) r[a][k] = T(0);
+#pragma unroll
+    for (int q = 0; q < (1 << DIM); ++q)
+#pragma unroll
+      for (int a = 0; a < (1 << DIM); ++a) project_q_node<DIM, T>(q, a, invh, w, o[q], r[a]);
+  }
+}
+
+// ------------------------------------------------------------------ energy
+// One thread per element; per-block partial sums in a fixed order.
+template <int DIM, typename TS>
+__global__ __launch_bounds__(kBlock) void k_energy(int N, double h, MatP<double> m, const double* __restrict__ x,
+                                                   const TS* __restrict__ s, const double* __restrict__ p,
+                                                   double* __restrict__ partials) {
+  __shared__ double sh[kBlock];
+  const int64_t ne = int64_t(N) * N * (DIM == 3 ? N : 1);
+  const int64_t nside = N + 1;
+  const double invh = 1.0 / h;
+  double w = 1.0;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) w *= 0.5 * h;
+  double acc = 0.0;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < ne; e += int64_t(gridDim.x) * blockDim.x) {
+    int ec[DIM];
+    int64_t r = e;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+      ec[i] = int(r % N);
+      r /= N;
+    }
+    double X[1 << DIM][DIM + 1], P[1 << DIM];
+    load_elem<DIM, double, double>(x, ec, nside, X);
+    load_elem_scalar<DIM, double, double>(p, ec, nside, P);
+    double pq[1 << DIM], dpq[1 << DIM][DIM];
+    elem_pq<DIM, double>(P, invh, pq, dpq);
+    Zq<DIM, double> z[1 << DIM];
+    elem_z<DIM, double>(X, invh, z);
+    double we = 0.0;
+    if (s == nullptr) {
+#pragma unroll
+      for (int q = 0; q < (1 << DIM); ++q) we += density<DIM, double>(m, z[q], pq[q], dpq[q]);
+    } else {
+      double W0 = 0.0;
+#pragma unroll
+      for (int q = 0; q < (1 << DIM); ++q) W0 += density<DIM, double>(m, z[q], pq[q], dpq[q]);
+      double S[1 << DIM][DIM + 1];
+      load_elem<DIM, TS, double>(s, ec, nside, S);
+#pragma unroll
+      for (int a = 0; a < (1 << DIM); ++a)
+#pragma unroll
+        for (int k = 0; k <= DIM; ++k) X[a][k] += S[a][k];
+      elem_z<DIM, double>(X, invh, z);
+      double W1 = 0.0;
+#pragma unroll
+      for (int q = 0; q < (1 << DIM); ++q) W1 += density<DIM, double>(m, z[q], pq[q], dpq[q]);
+      we = W1 - W0;
+    }
+    acc += w * we;
+  }
+  double tot = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_partials(const double* __restrict__ partials, int n,
+                                                            double* __restrict__ out) {
+  __shared__ double sh[kBlock];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += partials[i];
+  double tot = block_sum(acc, sh);
+  if (threadIdx.x == 0) *out = tot;
+}
+
+// ------------------------------------------------ per-element operators
+// MODE 0: gradient of f at x.  MODE 1: Hessian at xl applied to v.
+template <int MODE, typename T>
+struct ElemOp3 {
+  // computes r[8][4] for one element
+  __device__ static inline void eval(const MatP<T>& m, T invh, T w, const T (&X)[8][4], const T (&V)[8][4],
+                                     const T (&P)[8], T (&r)[8][4]) {
+    T pq[8], dpq[8][3];
+    elem_pq<3, T>(P, invh, pq, dpq);
+    Zq<3, T> o[8];
+    {
+      Zq<3, T> z[8];
+      elem_z<3, T>(X, invh, z);
+      if (MODE == 0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) density_grad<3, T>(m, z[q], pq[q], dpq[q], o[q]);
+      } else {
+        HessCoef<3, T> hc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) hess_coef<3, T>(m, z[q], pq[q], dpq[q], hc[q]);
+        elem_z<3, T>(V, invh, z);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) hess_apply<3, T>(m, hc[q], z[q], o[q]);
+      }
+    }
+    elem_project<3, T>(o, invh, w, r);
+  }
+};
+
+// 3D element-centric kernel: a 16 x 16 tile of element columns marches up
+// in z; each element's 8 nodal contributions are exchanged through LDS and
+// summed by the thread that owns the node, so no atomics are needed and the
+// sum order is fixed.  Tiles overlap by one element column so that each
+// tile owns the 15 x 15 nodes whose four in-plane elements it computes.
+constexpr int kTile = 16;
+constexpr int kOwn = kTile - 1;
+
+template <int MODE, typename T>
+__global__ __launch_bounds__(256) void k_elem_scatter3(int N, T h, MatP<double> md, int zchunk,
+                                                       const uint8_t* __restrict__ dir,
+                                                       const T* __restrict__ x, const T* __restrict__ p,
+                                                       const T* __restrict__ v, T* __restrict__ out) {
+  __shared__ T lo_sh[256][4][4];
+  __shared__ T hi_sh[256][4][4];
+  const MatP<T> m = cast_mat<T>(md);
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int ex = int(blockIdx.x) * kOwn - 1 + tx;
+  const int ey = int(blockIdx.y) * kOwn - 1 + ty;
+  const int ox = ex + 1, oy = ey + 1;
+  const bool ecol = ex >= 0 && ex < N && ey >= 0 && ey < N;
+  const bool owner = tx < kOwn && ty < kOwn && ox <= N && oy <= N;
+  const int64_t nside = N + 1;
+  const T invh = T(1) / h;
+  const T w = h * h * h / T(8);
+  const int z0 = int(blockIdx.z) * zchunk;
+  const int z1 = min(z0 + zchunk, N + 1);
+  if (z0 >= z1) return;
+  const int zs = max(z0 - 1, 0), ze = min(z1 - 1, N - 1);
+  T acc[4] = {T(0), T(0), T(0), T(0)};
+  for (int ez = zs; ez <= ze; ++ez) {
+    T r[8][4];
+    if (ecol) {
+      const int ec[3] = {ex, ey, ez};
+      T X[8][4], V[8][4], P[8];
+      load_elem<3, T, T>(x, ec, nside, X);
+      load_elem_scalar<3, T, T>(p, ec, nside, P);
+      if (MODE == 1) {
+        load_elem<3, T, T>(v, ec, nside, V);
+        mask_elem<3, T>(dir, ec, N, V);
+      }
+      ElemOp3<MODE, T>::eval(m, invh, w, X, V, P, r);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r[a][k] = T(0);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        lo_sh[tid][a][k] = r[a][k];
+        hi_sh[tid][a][k] = r[a + 4][k];
+      }
+    __syncthreads();
+    if (owner) {
+      // node (ox, oy) is corner 3 of element (tx, ty), 2 of (tx+1, ty),
+      // 1 of (tx, ty+1) and 0 of (tx+1, ty+1)
+      if (ez >= z0) {
+        const int nz = ez;
+        const int64_t n = int64_t(ox) + nside * (int64_t(oy) + nside * nz);
+        const int c[3] = {ox, oy, nz};
+        const uint8_t mk = node_mask<3>(dir, n, c, N);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          T s = acc[k] + lo_sh[tid][3][k] + lo_sh[tid + 1][2][k] + lo_sh[tid + 16][1][k] + lo_sh[tid + 17][0][k];
+          out[4 * n + k] = (mk & (1u << k)) ? T(0) : s;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        acc[k] = hi_sh[tid][3][k] + hi_sh[tid + 1][2][k] + hi_sh[tid + 16][1][k] + hi_sh[tid + 17][0][k];
+    }
+    __syncthreads();
+  }
+  if (owner && ze + 1 < z1) {
+    const int nz = ze + 1;
+    const int64_t n = int64_t(ox) + nside * (int64_t(oy) + nside * nz);
+    const int c[3] = {ox, oy, nz};
+    const uint8_t mk = node_mask<3>(dir, n, c, N);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[4 * n + k] = (mk & (1u << k)) ? T(0) : acc[k];
+  }
+}
+
+// Node-centric kernels (any DIM): a thread per node sums the contributions
+// of the 2^DIM elements around it.  Used in 2D and for per-node quantities.
+template <int DIM, typename T>
+__device__ inline void node_contrib(int MODE, const MatP<T>& m, T invh, T w, const T (&X)[1 << DIM][DIM + 1],
+                                    const T (&V)[1 << DIM][DIM + 1], const T (&P)[1 << DIM], int aloc,
+                                    T (&r)[DIM + 1]) {
+#pragma unroll
+  for (int q = 0; q < (1 << DIM); ++q) {
+    Zq<DIM, T> z, o;
+    T pq, dpq[DIM];
+    interp_scalar_q<DIM, T>(q, P, invh, pq, dpq);
+    interp_q<DIM, T>(q, X, invh, z);
+    if (MODE == 0) {
+      density_grad<DIM, T>(m, z, pq, dpq, o);
+    } else {
+      HessCoef<DIM, T> hc;
+      hess_coef<DIM, T>(m, z, pq, dpq, hc);
+      interp_q<DIM, T>(q, V, invh, z);
+      hess_apply<DIM, T>(m, hc, z, o);
+    }
+    project_q_node<DIM, T>(q, aloc, invh, w, o, r);
+  }
+}
+
+template <int DIM, int MODE, typename T>
+__global__ __launch_bounds__(kBlock) void k_node_gather(int N, T h, MatP<double> md, const uint8_t* __restrict__ dir,
+                                                        const T* __restrict__ x, const T* __restrict__ p,
+                                                        const T* __restrict__ v, T* __restrict__ out) {
+  const MatP<T> m = cast_mat<T>(md);
+  const int64_t nside = N + 1;
+  int64_t nn = 1;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) nn *= nside;
+  const T invh = T(1) / h;
+  T w = T(1);
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) w *= T(0.5) * h;
+  for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < nn; n += int64_t(gridDim.x) * blockDim.x) {
+    int c[DIM];
+    node_ijk<DIM>(n, nside, c);
+    T r[DIM + 1];
+#pragma unroll
+    for (int k = 0; k <= DIM; ++k) r[k] = T(0);
+#pragma unroll
+    for (int a = 0; a < (1 << DIM); ++a) {
+      // element whose local node a is this node
+      int e[DIM];
+      bool ok = true;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) {
+        e[i] = c[i] - ((a >> i) & 1);
+        ok &= (e[i] >= 0) & (e[i] < N);
+      }
+      if (!ok) continue;
+      T X[1 << DIM][DIM + 1], V[1 << DIM][DIM + 1], P[1 << DIM];
+      load_elem<DIM, T, T>(x, e, nside, X);
+      load_elem_scalar<DIM, T, T>(p, e, nside, P);
+      if (MODE == 1) {
+        load_elem<DIM, T, T>(v, e, nside, V);
+        mask_elem<DIM, T>(dir, e, N, V);
+      }
+      node_contrib<DIM, T>(MODE, m, invh, w, X, V, P, a, r);
+    }
+    const uint8_t mk = node_mask<DIM>(dir, n, c, N);
+#pragma unroll
+    for (int k = 0; k <= DIM; ++k) out[(DIM + 1) * n + k] = (mk & (1u << k)) ? T(0) : r[k];
+  }
+}
+
+// Node diagonal blocks D[n][k][l] (full (DIM+1)^2 block, Dirichlet rows and
+// columns zero).
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_diag_blocks(int N, T h, MatP<double> md, const uint8_t* __restrict__ dir,
+                                                        const T* __restrict__ x, const T* __restrict__ p,
+                                                        T* __restrict__ D) {
+  constexpr int NC = DIM + 1;
+  const MatP<T> m = cast_mat<T>(md);
+  const int64_t nside = N + 1;
+  int64_t nn = 1;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) nn *= nside;
+  const T invh = T(1) / h;
+  T w = T(1);
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) w *= T(0.5) * h;
+  for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < nn; n += int64_t(gridDim.x) * blockDim.x) {
+    int c[DIM];
+    node_ijk<DIM>(n, nside, c);
+    T blk[NC][NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+      for (int l = 0; l < NC; ++l) blk[k][l] = T(0);
+    for (int a = 0; a < (1 << DIM); ++a) {
+      int e[DIM];
+      bool ok = true;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) {
+        e[i] = c[i] - ((a >> i) & 1);
+        ok &= (e[i] >= 0) & (e[i] < N);
+      }
+      if (!ok) continue;
+      T X[1 << DIM][DIM + 1], P[1 << DIM];
+      load_elem<DIM, T, T>(x, e, nside, X);
+      load_elem_scalar<DIM, T, T>(p, e, nside, P);
+#pragma unroll
+      for (int q = 0; q < (1 << DIM); ++q) {
+        Zq<DIM, T> z;
+        T pq, dpq[DIM];
+        interp_scalar_q<DIM, T>(q, P, invh, pq, dpq);
+        interp_q<DIM, T>(q, X, invh, z);
+        HessCoef<DIM, T> hc;
+        hess_coef<DIM, T>(m, z, pq, dpq, hc);
+        const T nq = T(refN<DIM>(q, a));
+        T dn[DIM];
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) dn[j] = T(refdN<DIM>(q, a, j)) * invh;
+#pragma unroll
+        for (int l = 0; l < NC; ++l) {
+          // z-vector of the unit dof (a, l)
+          Zq<DIM, T> u, o;
+          zero<DIM, T>(u);
+          if (l < DIM) {
+            u.u[l] = nq;
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) u.G[l][j] = dn[j];
+          } else {
+            u.c = nq;
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) u.dc[j] = dn[j];
+          }
+          hess_apply<DIM, T>(m, hc, u, o);
+          T col[NC];
+#pragma unroll
+          for (int k = 0; k < NC; ++k) col[k] = T(0);
+          project_q_node<DIM, T>(q, a, invh, w, o, col);
+#pragma unroll
+          for (int k = 0; k < NC; ++k) blk[k][l] += col[k];
+        }
+      }
+    }
+    const uint8_t mk = node_mask<DIM>(dir, n, c, N);
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+      for (int l = 0; l < NC; ++l)
+        D[(int64_t(NC) * NC) * n + NC * k + l] = ((mk >> k) & 1u) || ((mk >> l) & 1u) ? T(0) : blk[k][l];
+  }
+}
+
+// One colour pass of projected Gauss-Seidel.  A thread per node of colour
+// `col` computes the rows r = g + H s of its dofs from its 2^DIM elements,
+// then updates the components in order (forward) or reverse order
+// (backward) with the node's diagonal block:
+//   s_k <- clamp(s_k - (r_k + sum_{l updated} D_kl ds_l) / D_kk, lo_k, hi_k).
+// Nodes of one colour share no element, so the pass equals a sequential
+// sweep over them.
+template <typename T>
+__device__ inline T pgs_update(T s, T r, T d, T lo, T hi) {
+  if (d > T(1e-300)) {
+    T t = s - r / d;
+    t = t < lo ? lo : t;
+    t = t > hi ? hi : t;
+    return t;
+  }
+  const T tl = lo - s, th = hi - s;
+  const T ml = r * tl + T(0.5) * d * tl * tl;
+  const T mh = r * th + T(0.5) * d * th * th;
+  return mh < ml ? hi : lo;
+}
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_pgs_colour(int N, T h, MatP<double> md, int col, int backward,
+                                                       const uint8_t* __restrict__ dir, const T* __restrict__ x,
+                                                       const T* __restrict__ p, const T* __restrict__ D,
+                                                       const T* __restrict__ g, const T* __restrict__ lo,
+                                                       const T* __restrict__ hi, T* __restrict__ s) {
+  constexpr int NC = DIM + 1;
+  const MatP<T> m = cast_mat<T>(md);
+  const int64_t nside = N + 1;
+  // nodes of this colour: ijk[i] = 2 t_i + bit_i(col)
+  int cnt[DIM];
+  int64_t total = 1;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    const int b = (col >> i) & 1;
+    cnt[i] = (N - b) / 2 + 1;
+    total *= cnt[i];
+  }
+  const T invh = T(1) / h;
+  T w = T(1);
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) w *= T(0.5) * h;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
+    int c[DIM];
+    int64_t r_ = t;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+      c[i] = 2 * int(r_ % cnt[i]) + ((col >> i) & 1);
+      r_ /= cnt[i];
+    }
+    const int64_t n = node_id<DIM>(c, nside);
+    const uint8_t mk = node_mask<DIM>(dir, n, c, N);
+    if (mk == uint8_t((1u << NC) - 1u)) continue;
+    T r[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) r[k] = T(0);
+#pragma unroll
+    for (int a = 0; a < (1 << DIM); ++a) {
+      int e[DIM];
+      bool ok = true;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) {
+        e[i] = c[i] - ((a >> i) & 1);
+        ok &= (e[i] >= 0) & (e[i] < N);
+      }
+      if (!ok) continue;
+      T X[1 << DIM][DIM + 1], V[1 << DIM][DIM + 1], P[1 << DIM];
+      load_elem<DIM, T, T>(x, e, nside, X);
+      load_elem_scalar<DIM, T, T>(p, e, nside, P);
+      load_elem<DIM, T, T>(s, e, nside, V);
+      mask_elem<DIM, T>(dir, e, N, V);
+      node_contrib<DIM, T>(1, m, invh, w, X, V, P, a, r);
+    }
+    T sn[NC], s0[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      s0[k] = s[NC * n + k];
+      sn[k] = s0[k];
+      r[k] += g[NC * n + k];
+    }
+    const T* Dn = D + int64_t(NC) * NC * n;
+#pragma unroll
+    for (int kk = 0; kk < NC; ++kk) {
+      const int k = backward ? NC - 1 - kk : kk;
+      if (mk & (1u << k)) continue;
+      T rk = r[k];
+#pragma unroll
+      for (int l = 0; l < NC; ++l) rk += Dn[NC * k + l] * (sn[l] - s0[l]);
+      sn[k] = pgs_update<T>(sn[k], rk, Dn[NC * k + k], lo[NC * n + k], hi[NC * n + k]);
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) s[NC * n + k] = sn[k];
+  }
+}
+
+int grid_for(int64_t work) {
+  int64_t b = (work + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  if (b > 65535 * 4) b = 65535 * 4;
+  return int(b);
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- launch
+hipError_t launch_reduce_partials(const double* partials, int n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, partials, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy(const ElemArgs& a, const double* x, const void* s, int s_fp32, const double* p,
+                         double* partials, double* out, hipStream_t st) {
+  int64_t ne = int64_t(a.N) * a.N * (a.dim == 3 ? a.N : 1);
+  int nb = int((ne + kBlock - 1) / kBlock);
+  if (nb > kMaxPartials) nb = kMaxPartials;
+  if (nb < 1) nb = 1;
+  if (a.dim == 3) {
+    if (s_fp32)
+      hipLaunchKernelGGL((k_energy<3, float>), dim3(nb), dim3(kBlock), 0, st, a.N, a.h, a.m, x, (const float*)s, p,
+                         partials);
+    else
+      hipLaunchKernelGGL((k_energy<3, double>), dim3(nb), dim3(kBlock), 0, st, a.N, a.h, a.m, x, (const double*)s,
+                         p, partials);
+  } else {
+    if (s_fp32)
+      hipLaunchKernelGGL((k_energy<2, float>), dim3(nb), dim3(kBlock), 0, st, a.N, a.h, a.m, x, (const float*)s, p,
+                         partials);
+    else
+      hipLaunchKernelGGL((k_energy<2, double>), dim3(nb), dim3(kBlock), 0, st, a.N, a.h, a.m, x, (const double*)s,
+                         p, partials);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce_partials(partials, nb, out, st);
+}
+
+template <int MODE, typename T>
+static hipError_t launch_scatter(const ElemArgs& a, const T* x, const T* p, const T* v, T* out, hipStream_t st) {
+  if (a.dim == 3) {
+    const int tiles = (a.N + 1 + kOwn - 1) / kOwn;
+    // enough z chunks for ~4 workgroups per compute unit
+    int chunks = (1024 + tiles * tiles - 1) / (tiles * tiles);
+    if (chunks < 1) chunks = 1;
+    int zchunk = (a.N + 1 + chunks - 1) / chunks;
+    if (zchunk < 4) zchunk = 4;
+    chunks = (a.N + 1 + zchunk - 1) / zchunk;
+    hipLaunchKernelGGL((k_elem_scatter3<MODE, T>), dim3(tiles, tiles, chunks), dim3(256), 0, st, a.N, T(a.h), a.m,
+                       zchunk, a.dir, x, p, v, out);
+  } else {
+    int64_t nn = int64_t(a.N + 1) * (a.N + 1);
+    hipLaunchKernelGGL((k_node_gather<2, MODE, T>), dim3(grid_for(nn)), dim3(kBlock), 0, st, a.N, T(a.h), a.m, a.dir,
+                       x, p, v, out);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gradient(const ElemArgs& a, const double* x, const double* p, double* g, hipStream_t st) {
+  return launch_scatter<0, double>(a, x, p, nullptr, g, st);
+}
+
+hipError_t launch_hessvec(const ElemArgs& a, const void* xl, const void* p, const void* v, void* hv, int fp32,
+                          hipStream_t st) {
+  if (fp32)
+    return launch_scatter<1, float>(a, (const float*)xl, (const float*)p, (const float*)v, (float*)hv, st);
+  return launch_scatter<1, double>(a, (const double*)xl, (const double*)p, (const double*)v, (double*)hv, st);
+}
+
+hipError_t launch_diag_blocks(const ElemArgs& a, const void* xl, const void* p, void* D, int fp32, hipStream_t st) {
+  int64_t nn = 1;
+  for (int i = 0; i < a.dim; ++i) nn *= (a.N + 1);
+  dim3 grid(grid_for(nn));
+  if (a.dim == 3) {
+    if (fp32)
+      hipLaunchKernelGGL((k_diag_blocks<3, float>), grid, dim3(kBlock), 0, st, a.N, float(a.h), a.m, a.dir,
+                         (const float*)xl, (const float*)p, (float*)D);
+    else
+      hipLaunchKernelGGL((k_diag_blocks<3, double>), grid, dim3(kBlock), 0, st, a.N, a.h, a.m, a.dir,
+                         (const double*)xl, (const double*)p, (double*)D);
+  } else {
+    if (fp32)
+      hipLaunchKernelGGL((k_diag_blocks<2, float>), grid, dim3(kBlock), 0, st, a.N, float(a.h), a.m, a.dir,
+                         (const float*)xl, (const float*)p, (float*)D);
+    else
+      hipLaunchKernelGGL((k_diag_blocks<2, double>), grid, dim3(kBlock), 0, st, a.N, a.h, a.m, a.dir,
+                         (const double*)xl, (const double*)p, (double*)D);
+  }
+  return hipGetLastError();
+}
+
+template <int DIM, typename T>
+static hipError_t pgs_sweeps(const ElemArgs& a, const T* xl, const T* p, const T* D, const T* g, const T* lo,
+                             const T* hi, T* s, int n_sweeps, hipStream_t st) {
+  constexpr int NCOL = 1 << DIM;
+  for (int it = 0; it < n_sweeps; ++it) {
+    for (int dir = 0; dir < 2; ++dir) {
+      for (int cc = 0; cc < NCOL; ++cc) {
+        const int col = dir ? NCOL - 1 - cc : cc;
+        int64_t cnt = 1;
+        for (int i = 0; i < DIM; ++i) cnt *= (a.N - ((col >> i) & 1)) / 2 + 1;
+        hipLaunchKernelGGL((k_pgs_colour<DIM, T>), dim3(grid_for(cnt)), dim3(kBlock), 0, st, a.N, T(a.h), a.m, col,
+                           dir, a.dir, xl, p, D, g, lo, hi, s);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
+    }
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_pgs_matfree(const ElemArgs& a, const void* xl, const void* p, const void* D, const void* g,
+                              const void* lo, const void* hi, void* s, int n_sweeps, int fp32, hipStream_t st) {
+  if (a.dim == 3) {
+    if (fp32)
+      return pgs_sweeps<3, float>(a, (const float*)xl, (const float*)p, (const float*)D, (const float*)g,
+                                  (const float*)lo, (const float*)hi, (float*)s, n_sweeps, st);
+    return pgs_sweeps<3, double>(a, (const double*)xl, (const double*)p, (const double*)D, (const double*)g,
+                                 (const double*)lo, (const double*)hi, (double*)s, n_sweeps, st);
+  }
+  if (fp32)
+    return pgs_sweeps<2, float>(a, (const float*)xl, (const float*)p, (const float*)D, (const float*)g,
+                                (const float*)lo, (const float*)hi, (float*)s, n_sweeps, st);
+  return pgs_sweeps<2, double>(a, (const double*)xl, (const double*)p, (const double*)D, (const double*)g,
+                               (const double*)lo, (const double*)hi, (double*)s, n_sweeps, st);
+}
+
+}  // namespace rmtr

@@ -1,0 +1,676 @@
+// C-ABI of librmtr and the host-side RMTR driver.
+//
+// The driver follows the paper's Algorithms 1-3 (V-cycle, Nonlinear_solve,
+// Convergence_control) with the Hessian lagging of Sec. 4.2.1: one Hessian
+// per level and V-cycle, taken at the level's initial iterate (matrix-free on
+// the finest level, Galerkin element matrices below), reused for the
+// pre-smoothing, the coarse Galerkin product and the post-smoothing.  Every
+// vector operation runs in the HIP kernels; the host only makes the scalar
+// trust-region decisions, reading the few device scalars each needs.
+#include <math.h>
+#include <string.h>
+
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "../../include/rmtr.h"
+#include "rmtr_kernels.h"
+
+using namespace rmtr;
+
+namespace {
+
+struct Level {
+  int N = 0;
+  int64_t nodes = 0, n = 0, nelem = 0;
+  double h = 0;
+  // device buffers, allocated on first use
+  double *x0 = nullptr, *xs = nullptr, *Lb = nullptr, *Ub = nullptr, *dg = nullptr, *g = nullptr;
+  double *lo = nullptr, *hi = nullptr, *s = nullptr, *sc = nullptr, *hs = nullptr;
+  double *t1 = nullptr, *t2 = nullptr, *t3 = nullptr, *t4 = nullptr;
+  double *p = nullptr, *K = nullptr, *D = nullptr;
+  float *xlf = nullptr, *pf = nullptr, *Df = nullptr, *gf = nullptr, *lof = nullptr, *hif = nullptr, *sf = nullptr;
+  double* Dsmooth = nullptr;  // diagonal blocks for rmtr_smooth / rmtr_em_smooth calls without D
+  float* Dsmoothf = nullptr;
+  bool solver_ready = false;
+};
+
+}  // namespace
+
+struct rmtr_ctx {
+  rmtr_model model{};
+  MatP<double> mat{};
+  int L = 0;
+  std::vector<Level> lv;  // index 1..L
+  double* partials = nullptr;
+  double* scal = nullptr;  // device scalars
+  int* flag = nullptr;     // device int flag
+  double* hs = nullptr;    // pinned host scalars
+  int* hflag = nullptr;    // pinned host flag
+  double* table = nullptr;
+  size_t table_cap = 0;
+  double* mprgp_work = nullptr;
+  std::vector<void*> allocs;
+  std::string err;
+};
+
+namespace {
+
+constexpr int kScal = 64;
+
+rmtr_status fail(rmtr_ctx* c, rmtr_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                        \
+  do {                                                                                           \
+    hipError_t e__ = (expr);                                                                     \
+    if (e__ != hipSuccess)                                                                       \
+      return fail(ctx, RMTR_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e__));         \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(rmtr_ctx* c, T** p, size_t count) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T) + 256);
+  if (e != hipSuccess) return e;
+  c->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return hipSuccess;
+}
+
+bool valid_level(const rmtr_ctx* c, int l) { return c && l >= 1 && l <= c->L; }
+
+ElemArgs eargs(const rmtr_ctx* c, int l, const uint8_t* dir) {
+  ElemArgs a;
+  a.dim = c->model.dim;
+  a.N = c->lv[l].N;
+  a.h = c->lv[l].h;
+  a.m = c->mat;
+  a.dir = dir;
+  return a;
+}
+
+hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+rmtr_status ensure_common(rmtr_ctx* c) {
+  if (c->partials) return RMTR_OK;
+  HIPCHK(c, dalloc(c, &c->partials, kMaxPartials));
+  HIPCHK(c, dalloc(c, &c->scal, kScal));
+  HIPCHK(c, dalloc(c, &c->flag, 4));
+  void* h = nullptr;
+  HIPCHK(c, hipHostMalloc(&h, kScal * sizeof(double) + 64, hipHostMallocDefault));
+  c->hs = static_cast<double*>(h);
+  c->hflag = reinterpret_cast<int*>(c->hs + kScal);
+  return RMTR_OK;
+}
+
+int ndof_elem(int dim) { return (1 << dim) * (dim + 1); }
+
+rmtr_status ensure_solver_level(rmtr_ctx* c, int l, bool mixed) {
+  Level& v = c->lv[l];
+  if (!v.solver_ready) {
+    const size_t n = size_t(v.n);
+    double** vecs[] = {&v.x0, &v.xs, &v.Lb, &v.Ub, &v.dg, &v.g, &v.lo, &v.hi, &v.s, &v.sc, &v.hs,
+                       &v.t1, &v.t2, &v.t3, &v.t4};
+    for (double** b : vecs) HIPCHK(c, dalloc(c, b, n));
+    HIPCHK(c, dalloc(c, &v.p, size_t(v.nodes)));
+    const int nc = c->model.dim + 1;
+    HIPCHK(c, dalloc(c, &v.D, size_t(v.nodes) * nc * nc));
+    if (l < c->L || c->L == 1) {
+      const size_t nd = size_t(ndof_elem(c->model.dim));
+      HIPCHK(c, dalloc(c, &v.K, size_t(v.nelem) * nd * nd));
+    }
+    v.solver_ready = true;
+  }
+  if (mixed && l == c->L && !v.xlf) {
+    const size_t n = size_t(v.n);
+    const int nc = c->model.dim + 1;
+    float** fv[] = {&v.xlf, &v.gf, &v.lof, &v.hif, &v.sf};
+    for (float** b : fv) HIPCHK(c, dalloc(c, b, n));
+    HIPCHK(c, dalloc(c, &v.pf, size_t(v.nodes)));
+    HIPCHK(c, dalloc(c, &v.Df, size_t(v.nodes) * nc * nc));
+  }
+  return RMTR_OK;
+}
+
+// ------------------------------------------------------------ the solver
+struct Run {
+  rmtr_ctx* c;
+  rmtr_params prm;
+  hipStream_t st;
+  const uint8_t* fdir;
+  bool mixed;
+  bool energy_model;
+  double f_ref = 1.0;
+  int accepted = 0, rejected = 0;
+  rmtr_status status = RMTR_OK;
+
+  const uint8_t* dir(int l) const { return l == c->L ? fdir : nullptr; }
+  int dim() const { return c->model.dim; }
+
+  rmtr_status fetch(int k, bool with_flag) {
+    HIPCHK(c, hipMemcpyAsync(c->hs, c->scal, k * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (with_flag) HIPCHK(c, hipMemcpyAsync(c->hflag, c->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    return RMTR_OK;
+  }
+
+  bool ftilde(int l) const { return l == c->L || energy_model; }
+
+  // out = grad h^l(x)
+  rmtr_status h_grad(int l, const double* x, double* out) {
+    Level& v = c->lv[l];
+    if (l == c->L) {
+      HIPCHK(c, launch_gradient(eargs(c, l, fdir), x, v.p, out, st));
+      return RMTR_OK;
+    }
+    HIPCHK(c, launch_add_scaled(v.n, x, 1.0, v.x0, -1.0, nullptr, v.t1, st));
+    HIPCHK(c, launch_em_hessvec(dim(), v.N, v.K, v.t1, v.t2, nullptr, 0, st));
+    HIPCHK(c, launch_add_scaled(v.n, v.dg, 1.0, v.t2, 1.0, nullptr, out, st));
+    if (energy_model) {
+      HIPCHK(c, launch_gradient(eargs(c, l, nullptr), x, v.p, v.t3, st));
+      HIPCHK(c, launch_hessvec(eargs(c, l, nullptr), v.x0, v.p, v.t1, v.t4, 0, st));
+      HIPCHK(c, launch_add_scaled(v.n, v.t3, 1.0, v.t4, -1.0, out, out, st));
+    }
+    HIPCHK(c, launch_zero_masked(dim(), v.N, out, nullptr, st));
+    return RMTR_OK;
+  }
+
+  // enqueue the pieces of h^l(x + s) - h^l(x) into scal[base .. base+3];
+  // returns via combine_diff after a fetch
+  rmtr_status h_diff_enqueue(int l, const double* x, const double* s, int base) {
+    Level& v = c->lv[l];
+    double* sc = c->scal + base;
+    if (ftilde(l)) {
+      HIPCHK(c, launch_energy(eargs(c, l, dir(l)), x, s, 0, v.p, c->partials, sc, st));
+    } else {
+      HIPCHK(c, launch_fill(1, 0.0, sc, st));
+    }
+    if (l == c->L) return RMTR_OK;
+    HIPCHK(c, launch_dot(v.n, v.dg, s, c->partials, sc + 1, st));
+    HIPCHK(c, launch_add_scaled(v.n, x, 1.0, v.x0, -1.0, nullptr, v.t1, st));
+    HIPCHK(c, launch_em_hessvec(dim(), v.N, v.K, v.t1, v.t2, nullptr, 0, st));
+    HIPCHK(c, launch_em_hessvec(dim(), v.N, v.K, s, v.t3, nullptr, 0, st));
+    if (energy_model) {
+      HIPCHK(c, launch_hessvec(eargs(c, l, nullptr), v.x0, v.p, v.t1, v.t4, 0, st));
+      HIPCHK(c, launch_add_scaled(v.n, v.t4, -1.0, nullptr, 0.0, v.t2, v.t2, st));
+      HIPCHK(c, launch_hessvec(eargs(c, l, nullptr), v.x0, v.p, s, v.t4, 0, st));
+      HIPCHK(c, launch_add_scaled(v.n, v.t4, -1.0, nullptr, 0.0, v.t3, v.t3, st));
+    }
+    HIPCHK(c, launch_dot(v.n, s, v.t2, c->partials, sc + 2, st));
+    HIPCHK(c, launch_dot(v.n, s, v.t3, c->partials, sc + 3, st));
+    return RMTR_OK;
+  }
+
+  double h_diff_combine(int l, int base) const {
+    const double* h = c->hs + base;
+    if (l == c->L) return h[0];
+    return h[0] + ((h[1] + h[2]) + 0.5 * h[3]);
+  }
+
+  double ratio(double ared, double pred) const {
+    const double tol = prm.guard * fmax(1.0, fabs(f_ref));
+    if (!isfinite(ared) || !isfinite(pred)) return -INFINITY;
+    if (fabs(pred) <= tol) return ared >= -tol ? 1.0 : -INFINITY;
+    if (pred <= 0.0) return -INFINITY;
+    return ared / pred;
+  }
+
+  bool control(double rho, double& delta) const {
+    const bool accept = rho > prm.eta1;
+    if (rho < prm.eta1)
+      delta = prm.gamma1 * delta;
+    else if (rho > prm.eta2)
+      delta = fmin(prm.gamma2 * delta, prm.delta_max);
+    return accept;
+  }
+
+  // QP of one TR step on level l into v.s
+  rmtr_status solve_qp(int l, bool coarsest) {
+    Level& v = c->lv[l];
+    const int nc = dim() + 1;
+    if (coarsest) {
+      MprgpResult res;
+      HIPCHK(c, run_mprgp(dim(), v.N, v.K, dir(l), v.g, v.lo, v.hi, v.s, prm.coarse_qp_its, prm.coarse_qp_rtol,
+                          prm.fallback_sweeps, c->mprgp_work, c->hs + 48, &res, st));
+      return RMTR_OK;
+    }
+    if (l == c->L) {
+      if (mixed) {
+        HIPCHK(c, launch_convert(v.n, v.g, 0, v.gf, 1, st));
+        HIPCHK(c, launch_convert(v.n, v.lo, 0, v.lof, 1, st));
+        HIPCHK(c, launch_convert(v.n, v.hi, 0, v.hif, 1, st));
+        HIPCHK(c, hipMemsetAsync(v.sf, 0, size_t(v.n) * sizeof(float), st));
+        HIPCHK(c, launch_pgs_matfree(eargs(c, l, fdir), v.xlf, v.pf, v.Df, v.gf, v.lof, v.hif, v.sf, prm.pgs_sweeps,
+                                     1, st));
+        HIPCHK(c, launch_convert(v.n, v.sf, 1, v.s, 0, st));
+        HIPCHK(c, launch_clamp(v.n, v.lo, v.hi, v.s, st));
+      } else {
+        HIPCHK(c, launch_fill(v.n, 0.0, v.s, st));
+        HIPCHK(c, launch_pgs_matfree(eargs(c, l, fdir), v.x0, v.p, v.D, v.g, v.lo, v.hi, v.s, prm.pgs_sweeps, 0,
+                                     st));
+      }
+      return RMTR_OK;
+    }
+    (void)nc;
+    HIPCHK(c, launch_fill(v.n, 0.0, v.s, st));
+    HIPCHK(c, launch_em_pgs(dim(), v.N, v.K, v.D, nullptr, v.g, v.lo, v.hi, v.s, prm.pgs_sweeps, 0, st));
+    return RMTR_OK;
+  }
+
+  // Algorithm 2 body: one TR iteration on level l
+  rmtr_status tr_step(int l, double* x, double& delta, bool coarsest) {
+    Level& v = c->lv[l];
+    rmtr_status r;
+    if ((r = h_grad(l, x, v.g)) != RMTR_OK) return r;
+    HIPCHK(c, launch_step_box(dim(), v.N, x, v.Lb, v.Ub, delta, dir(l), v.lo, v.hi, st));
+    if ((r = solve_qp(l, coarsest)) != RMTR_OK) return r;
+    HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), st));
+    HIPCHK(c, launch_any_nonzero(v.n, v.s, c->flag, st));
+    // model Hessian times s: lagged matrix-free on the finest level (FP64)
+    if (l == c->L && !(c->L == 1)) {
+      HIPCHK(c, launch_hessvec(eargs(c, l, fdir), v.x0, v.p, v.s, v.hs, 0, st));
+    } else {
+      HIPCHK(c, launch_em_hessvec(dim(), v.N, v.K, v.s, v.hs, nullptr, 0, st));
+    }
+    HIPCHK(c, launch_dot(v.n, v.g, v.s, c->partials, c->scal + 4, st));
+    HIPCHK(c, launch_dot(v.n, v.s, v.hs, c->partials, c->scal + 5, st));
+    if ((r = h_diff_enqueue(l, x, v.s, 0)) != RMTR_OK) return r;
+    if ((r = fetch(6, true)) != RMTR_OK) return r;
+    if (*c->hflag == 0) return RMTR_OK;
+    const double pred = -(c->hs[4] + 0.5 * c->hs[5]);
+    const double ared = -h_diff_combine(l, 0);
+    const double rho = ratio(ared, pred);
+    if (control(rho, delta)) {
+      ++accepted;
+      HIPCHK(c, launch_axpy(v.n, 1.0, v.s, x, st));
+    } else {
+      ++rejected;
+    }
+    return RMTR_OK;
+  }
+
+  rmtr_status nonlinear_solve(int l, double* x, double& delta, int its, bool coarsest) {
+    for (int i = 0; i < its; ++i) {
+      rmtr_status r = tr_step(l, x, delta, coarsest);
+      if (r != RMTR_OK) return r;
+    }
+    return RMTR_OK;
+  }
+
+  rmtr_status setup_coarse(int l, const double* x, double delta) {
+    Level& f = c->lv[l];
+    Level& cc = c->lv[l - 1];
+    const int d = dim();
+    HIPCHK(c, launch_restrict(d, cc.N, RMTR_R_INJECT, x, cc.x0, 0, st));
+    HIPCHK(c, launch_step_box(d, f.N, x, f.Lb, f.Ub, delta, dir(l), f.lo, f.hi, st));
+    HIPCHK(c, launch_restrict(d, cc.N, RMTR_R_BOX_LO, f.lo, cc.lo, 0, st));
+    HIPCHK(c, launch_restrict(d, cc.N, RMTR_R_BOX_HI, f.hi, cc.hi, 0, st));
+    HIPCHK(c, launch_add_scaled(cc.n, cc.x0, 1.0, cc.lo, 1.0, nullptr, cc.Lb, st));
+    HIPCHK(c, launch_add_scaled(cc.n, cc.x0, 1.0, cc.hi, 1.0, nullptr, cc.Ub, st));
+    rmtr_status r = h_grad(l, x, f.g);
+    if (r != RMTR_OK) return r;
+    if (l == c->L) {
+      HIPCHK(c, launch_galerkin_from_matfree(eargs(c, l, fdir), f.x0, f.p, cc.K, 0, nullptr, st));
+    } else {
+      HIPCHK(c, launch_galerkin_from_em(d, cc.N, f.K, cc.K, nullptr, st));
+    }
+    HIPCHK(c, launch_restrict(d, cc.N, RMTR_R_DUAL, f.g, cc.dg, 0, st));
+    if (energy_model) {
+      HIPCHK(c, launch_gradient(eargs(c, l - 1, nullptr), cc.x0, cc.p, cc.t3, st));
+      HIPCHK(c, launch_add_scaled(cc.n, cc.t3, -1.0, nullptr, 0.0, cc.dg, cc.dg, st));
+    }
+    HIPCHK(c, launch_zero_masked(d, cc.N, cc.dg, nullptr, st));
+    if (l - 1 > 1) HIPCHK(c, launch_em_diag(d, cc.N, cc.K, cc.D, 0, st));
+    return RMTR_OK;
+  }
+
+  rmtr_status vcycle(int l, double* x, double& delta) {
+    rmtr_status r;
+    if (l == 1) return nonlinear_solve(1, x, delta, prm.coarse_tr_its, true);
+    if ((r = nonlinear_solve(l, x, delta, prm.mu1, false)) != RMTR_OK) return r;
+    if ((r = setup_coarse(l, x, delta)) != RMTR_OK) return r;
+    Level& f = c->lv[l];
+    Level& cc = c->lv[l - 1];
+    HIPCHK(c, hipMemcpyAsync(cc.xs, cc.x0, cc.n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    double dc = delta;
+    if ((r = vcycle(l - 1, cc.xs, dc)) != RMTR_OK) return r;
+    HIPCHK(c, launch_add_scaled(cc.n, cc.xs, 1.0, cc.x0, -1.0, nullptr, cc.sc, st));
+    HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), st));
+    HIPCHK(c, launch_any_nonzero(cc.n, cc.sc, c->flag, st));
+    HIPCHK(c, launch_prolong(dim(), cc.N, cc.sc, f.s, 0, st));
+    if ((r = h_diff_enqueue(l, x, f.s, 0)) != RMTR_OK) return r;
+    if ((r = h_diff_enqueue(l - 1, cc.x0, cc.sc, 8)) != RMTR_OK) return r;
+    if ((r = fetch(12, true)) != RMTR_OK) return r;
+    if (*c->hflag) {
+      const double ared = -h_diff_combine(l, 0);
+      const double pred = -h_diff_combine(l - 1, 8);
+      const double rho = ratio(ared, pred);
+      if (control(rho, delta)) HIPCHK(c, launch_axpy(f.n, 1.0, f.s, x, st));
+    }
+    return nonlinear_solve(l, x, delta, prm.mu2, false);
+  }
+};
+
+}  // namespace
+
+// ================================================================== C-ABI
+extern "C" {
+
+void rmtr_default_params(rmtr_params* p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->eta1 = 0.1;
+  p->eta2 = 0.75;
+  p->gamma1 = 0.5;
+  p->gamma2 = 2.0;
+  p->delta0 = 1.0;
+  p->delta_max = 10.0;
+  p->rtol = 1e-8;
+  p->coarse_qp_rtol = 1e-10;
+  p->guard = 1e-14;
+  p->mu1 = 1;
+  p->mu2 = 1;
+  p->pgs_sweeps = 3;
+  p->coarse_tr_its = 5;
+  p->coarse_qp_its = 500;
+  p->fallback_sweeps = 50;
+  p->max_vcycles = 200;
+  p->precision = RMTR_FP64;
+  p->coarse_model = 0;
+}
+
+rmtr_status rmtr_create(const rmtr_model* m, rmtr_ctx** out) {
+  if (!m || !out) return RMTR_E_ARG;
+  *out = nullptr;
+  if (m->dim != 2 && m->dim != 3) return RMTR_E_ARG;
+  if (m->n_levels < 1 || m->n_levels > 12 || m->n_cells < 1) return RMTR_E_ARG;
+  if (m->n_cells % (1 << (m->n_levels - 1)) != 0) return RMTR_E_ARG;
+  if (!(m->mu > 0.0) || !(m->lambda + 2.0 * m->mu / 3.0 > 0.0) || !(m->Gc > 0.0) || !(m->ls > 0.0) ||
+      !(m->k >= 0.0 && m->k < 1.0))
+    return RMTR_E_ARG;
+  rmtr_ctx* c = new rmtr_ctx();
+  c->model = *m;
+  c->mat.lam = m->lambda;
+  c->mat.mu = m->mu;
+  c->mat.K = m->lambda + 2.0 * m->mu / 3.0;
+  c->mat.Gc = m->Gc;
+  c->mat.ls = m->ls;
+  c->mat.k = m->k;
+  c->mat.split = m->split ? 1 : 0;
+  c->L = m->n_levels;
+  c->lv.resize(c->L + 1);
+  for (int l = 1; l <= c->L; ++l) {
+    Level& v = c->lv[l];
+    v.N = m->n_cells >> (c->L - l);
+    v.h = 1.0 / double(v.N);
+    v.nodes = 1;
+    v.nelem = 1;
+    for (int i = 0; i < m->dim; ++i) {
+      v.nodes *= (v.N + 1);
+      v.nelem *= v.N;
+    }
+    v.n = v.nodes * (m->dim + 1);
+  }
+  *out = c;
+  return RMTR_OK;
+}
+
+void rmtr_destroy(rmtr_ctx* c) {
+  if (!c) return;
+  for (void* p : c->allocs) (void)hipFree(p);
+  if (c->hs) (void)hipHostFree(c->hs);
+  delete c;
+}
+
+const char* rmtr_last_error(const rmtr_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int64_t rmtr_level_nodes(const rmtr_ctx* c, int32_t level) {
+  if (!valid_level(c, level)) return -1;
+  return c->lv[level].nodes;
+}
+
+rmtr_status rmtr_init_fields(rmtr_ctx* c, int32_t level, const double* table, int32_t n_frac, double band,
+                             int32_t p_mode, double p_value, double p_band, double* c0, double* p, void* stream) {
+  if (!valid_level(c, level) || !c0 || n_frac < 0 || (n_frac > 0 && !table))
+    return fail(c, RMTR_E_ARG, "rmtr_init_fields: bad arguments");
+  if (p_mode == 1 && c->model.dim != 3) return fail(c, RMTR_E_ARG, "rmtr_init_fields: per-fracture p needs 3D");
+  const int cols = c->model.dim == 3 ? 8 : 7;
+  const size_t need = size_t(n_frac) * cols + 1;
+  if (need > c->table_cap) {
+    HIPCHK(c, dalloc(c, &c->table, need));
+    c->table_cap = need;
+  }
+  if (n_frac > 0)
+    HIPCHK(c, hipMemcpyAsync(c->table, table, size_t(n_frac) * cols * sizeof(double), hipMemcpyHostToDevice, S(stream)));
+  HIPCHK(c, launch_init_fields(c->model.dim, c->lv[level].N, c->table, n_frac, band, p_mode, p_value, p_band, c0, p,
+                               S(stream)));
+  // the host table must stay readable until the copy is done
+  HIPCHK(c, hipStreamSynchronize(S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_energy(rmtr_ctx* c, int32_t level, const double* x, const double* p, double* out, void* stream) {
+  if (!valid_level(c, level) || !x || !p || !out) return fail(c, RMTR_E_ARG, "rmtr_energy: bad arguments");
+  rmtr_status r = ensure_common(c);
+  if (r != RMTR_OK) return r;
+  HIPCHK(c, launch_energy(eargs(c, level, nullptr), x, nullptr, 0, p, c->partials, out, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_energy_diff(rmtr_ctx* c, int32_t level, const double* x, const void* s, int32_t s_precision,
+                             const double* p, double* out, void* stream) {
+  if (!valid_level(c, level) || !x || !s || !p || !out) return fail(c, RMTR_E_ARG, "rmtr_energy_diff: bad arguments");
+  rmtr_status r = ensure_common(c);
+  if (r != RMTR_OK) return r;
+  HIPCHK(c, launch_energy(eargs(c, level, nullptr), x, s, s_precision == RMTR_FP32, p, c->partials, out, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_gradient(rmtr_ctx* c, int32_t level, const double* x, const double* p, const uint8_t* dir,
+                          double* g, void* stream) {
+  if (!valid_level(c, level) || !x || !p || !g) return fail(c, RMTR_E_ARG, "rmtr_gradient: bad arguments");
+  HIPCHK(c, launch_gradient(eargs(c, level, dir), x, p, g, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_hessvec(rmtr_ctx* c, int32_t level, const void* xl, const void* p, const uint8_t* dir,
+                         const void* v, void* hv, int32_t precision, void* stream) {
+  if (!valid_level(c, level) || !xl || !p || !v || !hv) return fail(c, RMTR_E_ARG, "rmtr_hessvec: bad arguments");
+  if (v == hv) return fail(c, RMTR_E_ARG, "rmtr_hessvec: v and Hv must not alias");
+  HIPCHK(c, launch_hessvec(eargs(c, level, dir), xl, p, v, hv, precision == RMTR_FP32, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_diag_blocks(rmtr_ctx* c, int32_t level, const void* xl, const void* p, const uint8_t* dir, void* D,
+                             int32_t precision, void* stream) {
+  if (!valid_level(c, level) || !xl || !p || !D) return fail(c, RMTR_E_ARG, "rmtr_diag_blocks: bad arguments");
+  HIPCHK(c, launch_diag_blocks(eargs(c, level, dir), xl, p, D, precision == RMTR_FP32, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_smooth(rmtr_ctx* c, int32_t level, const void* xl, const void* p, const uint8_t* dir, const void* D,
+                        const void* g, const void* lo, const void* hi, void* s, int32_t n_sweeps, int32_t precision,
+                        void* stream) {
+  if (!valid_level(c, level) || !xl || !p || !g || !lo || !hi || !s || n_sweeps < 0)
+    return fail(c, RMTR_E_ARG, "rmtr_smooth: bad arguments");
+  const bool f32 = precision == RMTR_FP32;
+  Level& v = c->lv[level];
+  const int nc = c->model.dim + 1;
+  if (!D) {
+    if (f32) {
+      if (!v.Dsmoothf) HIPCHK(c, dalloc(c, &v.Dsmoothf, size_t(v.nodes) * nc * nc));
+      D = v.Dsmoothf;
+    } else {
+      if (!v.Dsmooth) HIPCHK(c, dalloc(c, &v.Dsmooth, size_t(v.nodes) * nc * nc));
+      D = v.Dsmooth;
+    }
+    HIPCHK(c, launch_diag_blocks(eargs(c, level, dir), xl, p, const_cast<void*>(D), f32, S(stream)));
+  }
+  HIPCHK(c, launch_pgs_matfree(eargs(c, level, dir), xl, p, D, g, lo, hi, s, n_sweeps, f32, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_restrict(rmtr_ctx* c, int32_t fine_level, int32_t mode, const void* fine, void* coarse,
+                          int32_t precision, void* stream) {
+  if (!valid_level(c, fine_level) || fine_level < 2 || mode < 0 || mode > 3 || !fine || !coarse)
+    return fail(c, RMTR_E_ARG, "rmtr_restrict: bad arguments");
+  HIPCHK(c, launch_restrict(c->model.dim, c->lv[fine_level - 1].N, mode, fine, coarse, precision == RMTR_FP32,
+                            S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_prolong(rmtr_ctx* c, int32_t coarse_level, const void* coarse, void* fine, int32_t precision,
+                         void* stream) {
+  if (!valid_level(c, coarse_level) || coarse_level >= c->L || !coarse || !fine)
+    return fail(c, RMTR_E_ARG, "rmtr_prolong: bad arguments");
+  HIPCHK(c, launch_prolong(c->model.dim, c->lv[coarse_level].N, coarse, fine, precision == RMTR_FP32, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_galerkin(rmtr_ctx* c, int32_t coarse_level, const double* xl, const double* p, const uint8_t* dir,
+                          const double* Kf, double* Kc, void* stream) {
+  if (!valid_level(c, coarse_level) || coarse_level >= c->L || !Kc)
+    return fail(c, RMTR_E_ARG, "rmtr_galerkin: bad arguments");
+  if (coarse_level == c->L - 1) {
+    if (!xl || !p) return fail(c, RMTR_E_ARG, "rmtr_galerkin: x_lin and p needed below the finest level");
+    HIPCHK(c, launch_galerkin_from_matfree(eargs(c, c->L, dir), xl, p, Kc, 0, nullptr, S(stream)));
+  } else {
+    if (!Kf) return fail(c, RMTR_E_ARG, "rmtr_galerkin: K_fine needed");
+    HIPCHK(c, launch_galerkin_from_em(c->model.dim, c->lv[coarse_level].N, Kf, Kc, nullptr, S(stream)));
+  }
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_em_hessvec(rmtr_ctx* c, int32_t level, const double* K, const double* v, double* hv, void* stream) {
+  if (!valid_level(c, level) || !K || !v || !hv || v == hv) return fail(c, RMTR_E_ARG, "rmtr_em_hessvec: bad arguments");
+  HIPCHK(c, launch_em_hessvec(c->model.dim, c->lv[level].N, K, v, hv, nullptr, 0, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_em_smooth(rmtr_ctx* c, int32_t level, const double* K, const double* g, const double* lo,
+                           const double* hi, double* s, int32_t n_sweeps, void* stream) {
+  if (!valid_level(c, level) || !K || !g || !lo || !hi || !s || n_sweeps < 0)
+    return fail(c, RMTR_E_ARG, "rmtr_em_smooth: bad arguments");
+  Level& v = c->lv[level];
+  const int nc = c->model.dim + 1;
+  if (!v.Dsmooth) HIPCHK(c, dalloc(c, &v.Dsmooth, size_t(v.nodes) * nc * nc));
+  HIPCHK(c, launch_em_diag(c->model.dim, v.N, K, v.Dsmooth, 0, S(stream)));
+  HIPCHK(c, launch_em_pgs(c->model.dim, v.N, K, v.Dsmooth, nullptr, g, lo, hi, s, n_sweeps, 0, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_mprgp(rmtr_ctx* c, int32_t level, const double* K, const double* g, const double* lo, const double* hi,
+                       double* s, int32_t max_it, double rtol, int32_t fallback_sweeps, int32_t* iterations,
+                       int32_t* status, void* stream) {
+  if (!valid_level(c, level) || !K || !g || !lo || !hi || !s || max_it < 0)
+    return fail(c, RMTR_E_ARG, "rmtr_mprgp: bad arguments");
+  rmtr_status r = ensure_common(c);
+  if (r != RMTR_OK) return r;
+  double* work = nullptr;
+  HIPCHK(c, dalloc(c, &work, mprgp_work_doubles(c->model.dim, c->lv[level].N)));
+  MprgpResult res;
+  HIPCHK(c, run_mprgp(c->model.dim, c->lv[level].N, K, nullptr, g, lo, hi, s, max_it, rtol, fallback_sweeps, work,
+                      c->hs + 48, &res, S(stream)));
+  HIPCHK(c, hipStreamSynchronize(S(stream)));
+  if (iterations) *iterations = res.iterations;
+  if (status) *status = res.status;
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_dot(rmtr_ctx* c, int64_t n, const double* a, const double* b, double* out, void* stream) {
+  if (!c || n < 0 || !a || !b || !out) return fail(c, RMTR_E_ARG, "rmtr_dot: bad arguments");
+  rmtr_status r = ensure_common(c);
+  if (r != RMTR_OK) return r;
+  HIPCHK(c, launch_dot(n, a, b, c->partials, out, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_chi(rmtr_ctx* c, int32_t level, const double* x, const double* g, const double* cl,
+                     const uint8_t* dir, double* out, void* stream) {
+  if (!valid_level(c, level) || !x || !g || !cl || !out) return fail(c, RMTR_E_ARG, "rmtr_chi: bad arguments");
+  rmtr_status r = ensure_common(c);
+  if (r != RMTR_OK) return r;
+  HIPCHK(c, launch_chi(c->model.dim, c->lv[level].N, x, g, cl, dir, c->partials, c->scal + 60, S(stream)));
+  // chi = sqrt(sum of squares), on the device
+  HIPCHK(c, hipMemcpyAsync(c->hs + 60, c->scal + 60, sizeof(double), hipMemcpyDeviceToHost, S(stream)));
+  HIPCHK(c, hipStreamSynchronize(S(stream)));
+  const double v = sqrt(c->hs[60]);
+  HIPCHK(c, hipMemcpyAsync(out, &v, sizeof(double), hipMemcpyHostToDevice, S(stream)));
+  HIPCHK(c, hipStreamSynchronize(S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lower, const uint8_t* dir,
+                                const rmtr_params* prm, double* x, rmtr_stats* stats, double* chi_history,
+                                void* stream) {
+  if (!c || !p || !c_lower || !prm || !x) return fail(c, RMTR_E_ARG, "rmtr_solve_loadstep: bad arguments");
+  if (prm->mu1 < 0 || prm->mu2 < 0 || prm->pgs_sweeps < 0 || prm->max_vcycles < 0 || !(prm->eta1 > 0.0) ||
+      prm->eta1 > prm->eta2 || !(prm->gamma1 > 0.0) || prm->gamma1 > 1.0 || prm->gamma2 < 1.0 ||
+      !(prm->delta0 > 0.0))
+    return fail(c, RMTR_E_ARG, "rmtr_solve_loadstep: invalid parameters");
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = S(stream);
+  rmtr_status r = ensure_common(c);
+  if (r != RMTR_OK) return r;
+  const bool mixed = prm->precision == RMTR_FP32;
+  for (int l = 1; l <= c->L; ++l)
+    if ((r = ensure_solver_level(c, l, mixed)) != RMTR_OK) return r;
+  if (!c->mprgp_work) HIPCHK(c, dalloc(c, &c->mprgp_work, mprgp_work_doubles(c->model.dim, c->lv[1].N)));
+  Run run{c, *prm, st, dir, mixed, prm->coarse_model == 0};
+  const int L = c->L, d = c->model.dim;
+  Level& f = c->lv[L];
+  // pressure on every level: fine copy, then injection
+  HIPCHK(c, hipMemcpyAsync(f.p, p, f.nodes * sizeof(double), hipMemcpyDeviceToDevice, st));
+  for (int l = L - 1; l >= 1; --l) HIPCHK(c, launch_inject_scalar(d, c->lv[l].N, c->lv[l + 1].p, c->lv[l].p, st));
+  if (mixed) HIPCHK(c, launch_convert(f.nodes, f.p, 0, f.pf, 1, st));
+  HIPCHK(c, launch_fine_bounds(d, f.N, c_lower, f.Lb, f.Ub, st));
+  double delta = prm->delta0;
+  HIPCHK(c, launch_gradient(eargs(c, L, dir), x, f.p, f.g, st));
+  HIPCHK(c, launch_chi(d, f.N, x, f.g, c_lower, dir, c->partials, c->scal, st));
+  HIPCHK(c, launch_energy(eargs(c, L, dir), x, nullptr, 0, f.p, c->partials, c->scal + 1, st));
+  if ((r = run.fetch(2, false)) != RMTR_OK) return r;
+  const double chi0 = sqrt(c->hs[0]);
+  run.f_ref = c->hs[1];
+  rmtr_stats out{};
+  out.chi0 = out.chi = chi0;
+  int vc = 0;
+  if (chi0 > 0.0 && isfinite(chi0)) {
+    for (vc = 0; vc < prm->max_vcycles;) {
+      // lagged Hessian of this V-cycle: linearisation point x0 = x
+      HIPCHK(c, hipMemcpyAsync(f.x0, x, f.n * sizeof(double), hipMemcpyDeviceToDevice, st));
+      if (L == 1) {
+        HIPCHK(c, launch_galerkin_from_matfree(eargs(c, 1, dir), f.x0, f.p, f.K, 1, dir, st));
+      } else if (mixed) {
+        HIPCHK(c, launch_convert(f.n, f.x0, 0, f.xlf, 1, st));
+        HIPCHK(c, launch_diag_blocks(eargs(c, L, dir), f.xlf, f.pf, f.Df, 1, st));
+      } else {
+        HIPCHK(c, launch_diag_blocks(eargs(c, L, dir), f.x0, f.p, f.D, 0, st));
+      }
+      if ((r = run.vcycle(L, x, delta)) != RMTR_OK) return r;
+      ++vc;
+      HIPCHK(c, launch_gradient(eargs(c, L, dir), x, f.p, f.g, st));
+      HIPCHK(c, launch_chi(d, f.N, x, f.g, c_lower, dir, c->partials, c->scal, st));
+      if ((r = run.fetch(1, false)) != RMTR_OK) return r;
+      out.chi = sqrt(c->hs[0]);
+      if (chi_history) chi_history[vc - 1] = out.chi;
+      if (!isfinite(out.chi)) return fail(c, RMTR_E_NONFINITE, "rmtr_solve_loadstep: non-finite iterate");
+      if (out.chi <= prm->rtol * chi0) break;
+    }
+  }
+  HIPCHK(c, launch_energy(eargs(c, L, dir), x, nullptr, 0, f.p, c->partials, c->scal, st));
+  if ((r = run.fetch(1, false)) != RMTR_OK) return r;
+  out.energy = c->hs[0];
+  out.vcycles = vc;
+  out.tr_accepted = run.accepted;
+  out.tr_rejected = run.rejected;
+  out.status = (chi0 == 0.0 || out.chi <= prm->rtol * chi0) ? RMTR_OK : RMTR_NOT_CONVERGED;
+  out.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) *stats = out;
+  return out.status;
+}
+
+}  // extern "C"

@@ -1,0 +1,396 @@
+// Device-side building blocks of the phase-field fracture functional on a
+// uniform Q1 grid: reference-element data, the pointwise density and its first
+// and second variations, and sum-factorised interpolation for hexahedra.
+//
+// The discrete functional is the one of the paper's Sec. 2, eq. (pressurized)
+// with the AT2 choice w(c) = c^2, c_w = 2, integrated with 2^d Gauss points:
+//   W = g(c) psi+ + psi- + Gc/2 (c^2/l + l |grad c|^2) + gp(c) div(p u)
+//   g = (1-k)(1-c)^2 + k,  gp = (1-c)^2,  div(p u) = p tr(eps) + grad p . u
+//   psi+ = K/2 <t>+^2 + mu e:e,  psi- = K/2 <t>-^2  (t = tr eps, e its deviator
+//   in 3D, K = lambda + 2 mu / 3; 2D is plane strain), or the unsplit
+//   psi+ = lambda/2 t^2 + mu eps:eps, psi- = 0.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rmtr {
+
+// Two-point Gauss rule on [0, 1]: xi = (1 -+ 1/sqrt(3)) / 2.
+#define RMTR_GA 0.78867513459481288225457439025098  // 1 - xi_0 = xi_1
+#define RMTR_GB 0.21132486540518711774542560974902  // xi_0 = 1 - xi_1
+
+template <typename T>
+struct MatP {
+  T lam, mu, K, Gc, ls, k;
+  int split;
+};
+
+// One level of the hierarchy: N cells per side, (N+1)^DIM nodes.
+template <typename T>
+struct LevelP {
+  int N;
+  int64_t nside;   // N + 1
+  T h, invh, w;    // w = h^DIM / 2^DIM (quadrature weight)
+};
+
+// phi_b at Gauss point q along one direction: phi_0 = 1 - xi, phi_1 = xi.
+__host__ __device__ constexpr double shape1(int b, int q) {
+  return b ? (q ? RMTR_GA : RMTR_GB) : (q ? RMTR_GB : RMTR_GA);
+}
+
+template <int DIM>
+__host__ __device__ constexpr double refN(int q, int a) {
+  double v = 1.0;
+  for (int i = 0; i < DIM; ++i) v *= shape1((a >> i) & 1, (q >> i) & 1);
+  return v;
+}
+
+// derivative along j on the unit cell (multiply by 1/h)
+template <int DIM>
+__host__ __device__ constexpr double refdN(int q, int a, int j) {
+  double v = ((a >> j) & 1) ? 1.0 : -1.0;
+  for (int i = 0; i < DIM; ++i)
+    if (i != j) v *= shape1((a >> i) & 1, (q >> i) & 1);
+  return v;
+}
+
+// ------------------------------------------------------------------------
+// Quantities at one quadrature point: u, G = grad u (G[i][j] = du_i/dx_j),
+// c, grad c.
+template <int DIM, typename T>
+struct Zq {
+  T u[DIM];
+  T G[DIM][DIM];
+  T c;
+  T dc[DIM];
+};
+
+template <int DIM, typename T>
+__device__ inline void zero(Zq<DIM, T>& z) {
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    z.u[i] = T(0);
+    z.dc[i] = T(0);
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) z.G[i][j] = T(0);
+  }
+  z.c = T(0);
+}
+
+// Strain energy split: psi+, sigma+ (symmetric, DIM x DIM), sigma- (scalar
+// multiple of the identity), t = tr eps.
+template <int DIM, typename T>
+struct Split {
+  T t, psip, psim, sigp[DIM][DIM], sigm;
+};
+
+template <int DIM, typename T>
+__device__ inline void split_parts(const MatP<T>& m, const T (&G)[DIM][DIM], Split<DIM, T>& s) {
+  T t = T(0), epsq = T(0);
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) t += G[i][i];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      T e = T(0.5) * (G[i][j] + G[j][i]);
+      epsq += e * e;
+    }
+  s.t = t;
+  if (m.split) {
+    T tp = t > T(0) ? t : T(0);
+    T tm = t > T(0) ? T(0) : t;
+    s.psip = T(0.5) * m.K * tp * tp + m.mu * (epsq - t * t / T(3));
+    s.psim = T(0.5) * m.K * tm * tm;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) {
+        T e = T(0.5) * (G[i][j] + G[j][i]);
+        s.sigp[i][j] = T(2) * m.mu * e + (i == j ? (m.K * tp - T(2) * m.mu * t / T(3)) : T(0));
+      }
+    s.sigm = m.K * tm;
+  } else {
+    s.psip = T(0.5) * m.lam * t * t + m.mu * epsq;
+    s.psim = T(0);
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) {
+        T e = T(0.5) * (G[i][j] + G[j][i]);
+        s.sigp[i][j] = T(2) * m.mu * e + (i == j ? m.lam * t : T(0));
+      }
+    s.sigm = T(0);
+  }
+}
+
+// W at a quadrature point.
+template <int DIM, typename T>
+__device__ inline T density(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T (&dp)[DIM]) {
+  Split<DIM, T> s;
+  split_parts<DIM, T>(m, z.G, s);
+  T omc = T(1) - z.c;
+  T g = (T(1) - m.k) * omc * omc + m.k;
+  T gp = omc * omc;
+  T pi = p * s.t;
+  T dcq = T(0);
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    pi += dp[i] * z.u[i];
+    dcq += z.dc[i] * z.dc[i];
+  }
+  T crack = T(0.5) * m.Gc * (z.c * z.c / m.ls + m.ls * dcq);
+  return g * s.psip + s.psim + crack + gp * pi;
+}
+
+// dW/dz (first variation), written into out.
+template <int DIM, typename T>
+__device__ inline void density_grad(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T (&dp)[DIM],
+                                    Zq<DIM, T>& out) {
+  Split<DIM, T> s;
+  split_parts<DIM, T>(m, z.G, s);
+  T omc = T(1) - z.c;
+  T g = (T(1) - m.k) * omc * omc + m.k;
+  T dg = T(-2) * (T(1) - m.k) * omc;
+  T gp = omc * omc;
+  T dgp = T(-2) * omc;
+  T pi = p * s.t;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) pi += dp[i] * z.u[i];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    out.u[i] = gp * dp[i];
+    out.dc[i] = m.Gc * m.ls * z.dc[i];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j)
+      out.G[i][j] = g * s.sigp[i][j] + (i == j ? (s.sigm + gp * p) : T(0));
+  }
+  out.c = dg * s.psip + m.Gc * z.c / m.ls + dgp * pi;
+}
+
+// Coefficients of the second variation at a linearisation point.
+//   uu: vol tr(dG) tr(DG) + shear (dG:DG + dG:DG^T)
+//   uc: S : dG Dc + Pc . du Dc (and symmetric)
+//   cc: Ccc dc Dc + Gc l grad dc . grad Dc
+template <int DIM, typename T>
+struct HessCoef {
+  T vol, shear, Ccc;
+  T S[DIM][DIM];
+  T Pc[DIM];
+};
+
+template <int DIM, typename T>
+__device__ inline void hess_coef(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T (&dp)[DIM],
+                                 HessCoef<DIM, T>& hc) {
+  Split<DIM, T> s;
+  split_parts<DIM, T>(m, z.G, s);
+  T omc = T(1) - z.c;
+  T g = (T(1) - m.k) * omc * omc + m.k;
+  T dg = T(-2) * (T(1) - m.k) * omc;
+  T d2g = T(2) * (T(1) - m.k);
+  T dgp = T(-2) * omc;
+  T pi = p * s.t;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) pi += dp[i] * z.u[i];
+  if (m.split) {
+    T Hp = s.t > T(0) ? T(1) : T(0);
+    hc.vol = g * m.K * Hp + m.K * (T(1) - Hp) - g * T(2) * m.mu / T(3);
+  } else {
+    hc.vol = g * m.lam;
+  }
+  hc.shear = g * m.mu;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    hc.Pc[i] = dgp * dp[i];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) hc.S[i][j] = dg * s.sigp[i][j] + (i == j ? dgp * p : T(0));
+  }
+  hc.Ccc = d2g * s.psip + m.Gc / m.ls + T(2) * pi;
+}
+
+// Second variation applied to a direction v (z-vector of v at the point).
+template <int DIM, typename T>
+__device__ inline void hess_apply(const MatP<T>& m, const HessCoef<DIM, T>& hc, const Zq<DIM, T>& v,
+                                  Zq<DIM, T>& out) {
+  T tv = T(0);
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) tv += v.G[i][i];
+  T oc = hc.Ccc * v.c;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    out.u[i] = hc.Pc[i] * v.c;
+    out.dc[i] = m.Gc * m.ls * v.dc[i];
+    oc += hc.Pc[i] * v.u[i];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      out.G[i][j] = hc.shear * (v.G[i][j] + v.G[j][i]) + hc.S[i][j] * v.c + (i == j ? hc.vol * tv : T(0));
+      oc += hc.S[i][j] * v.G[i][j];
+    }
+  }
+  out.c = oc;
+}
+
+// ------------------------------------------------------------------------
+// Plain (not factorised) interpolation for any DIM: z_q = B_q x_e.
+template <int DIM, typename T>
+__device__ inline void interp_q(int q, const T (&X)[1 << DIM][DIM + 1], T invh, Zq<DIM, T>& z) {
+  zero<DIM, T>(z);
+#pragma unroll
+  for (int a = 0; a < (1 << DIM); ++a) {
+    const T n = T(refN<DIM>(q, a));
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) z.u[i] += n * X[a][i];
+    z.c += n * X[a][DIM];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      const T dn = T(refdN<DIM>(q, a, j)) * invh;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) z.G[i][j] += dn * X[a][i];
+      z.dc[j] += dn * X[a][DIM];
+    }
+  }
+}
+
+template <int DIM, typename T>
+__device__ inline void interp_scalar_q(int q, const T (&P)[1 << DIM], T invh, T& p, T (&dp)[DIM]) {
+  p = T(0);
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) dp[j] = T(0);
+#pragma unroll
+  for (int a = 0; a < (1 << DIM); ++a) {
+    p += T(refN<DIM>(q, a)) * P[a];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) dp[j] += T(refdN<DIM>(q, a, j)) * invh * P[a];
+  }
+}
+
+// r_a += w B_{q,a}^T out  for one local node a (all components).
+template <int DIM, typename T>
+__device__ inline void project_q_node(int q, int a, T invh, T w, const Zq<DIM, T>& o, T (&r)[DIM + 1]) {
+  const T n = T(refN<DIM>(q, a));
+  T dn[DIM];
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) dn[j] = T(refdN<DIM>(q, a, j)) * invh;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    T acc = n * o.u[i];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) acc += dn[j] * o.G[i][j];
+    r[i] += w * acc;
+  }
+  T acc = n * o.c;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) acc += dn[j] * o.dc[j];
+  r[DIM] += w * acc;
+}
+
+// ------------------------------------------------------------------------
+// Sum-factorised Q1 interpolation on a hexahedron with the 2-point rule.
+// f[a], a = ax + 2 ay + 4 az  ->  value and gradient (unit cell) at the 8
+// points q = qx + 2 qy + 4 qz.
+template <typename T>
+__device__ inline void sf_forward3(const T (&f)[8], T (&val)[8], T (&dx)[8], T (&dy)[8], T (&dz)[8]) {
+  const T A0 = T(RMTR_GA), B0 = T(RMTR_GB);  // phi_0(q0), phi_1(q0)
+  // stage x: fx[qx][ay][az], gx[ay][az]
+  T fx[2][2][2], gx[2][2];
+#pragma unroll
+  for (int ay = 0; ay < 2; ++ay)
+#pragma unroll
+    for (int az = 0; az < 2; ++az) {
+      T f0 = f[0 + 2 * ay + 4 * az], f1 = f[1 + 2 * ay + 4 * az];
+      fx[0][ay][az] = A0 * f0 + B0 * f1;
+      fx[1][ay][az] = B0 * f0 + A0 * f1;
+      gx[ay][az] = f1 - f0;
+    }
+  // stage y
+  T fxy[2][2][2], gxy[2][2], gyx[2][2];
+#pragma unroll
+  for (int az = 0; az < 2; ++az) {
+#pragma unroll
+    for (int qx = 0; qx < 2; ++qx) {
+      fxy[qx][0][az] = A0 * fx[qx][0][az] + B0 * fx[qx][1][az];
+      fxy[qx][1][az] = B0 * fx[qx][0][az] + A0 * fx[qx][1][az];
+      gyx[qx][az] = fx[qx][1][az] - fx[qx][0][az];
+    }
+    gxy[0][az] = A0 * gx[0][az] + B0 * gx[1][az];
+    gxy[1][az] = B0 * gx[0][az] + A0 * gx[1][az];
+  }
+  // stage z
+#pragma unroll
+  for (int qy = 0; qy < 2; ++qy)
+#pragma unroll
+    for (int qx = 0; qx < 2; ++qx) {
+      const int q0 = qx + 2 * qy, q1 = q0 + 4;
+      val[q0] = A0 * fxy[qx][qy][0] + B0 * fxy[qx][qy][1];
+      val[q1] = B0 * fxy[qx][qy][0] + A0 * fxy[qx][qy][1];
+      T d = fxy[qx][qy][1] - fxy[qx][qy][0];
+      dz[q0] = d;
+      dz[q1] = d;
+      T gx0 = A0 * gxy[qy][0] + B0 * gxy[qy][1];
+      T gx1 = B0 * gxy[qy][0] + A0 * gxy[qy][1];
+      dx[q0] = gx0;
+      dx[q1] = gx1;
+      T gy0 = A0 * gyx[qx][0] + B0 * gyx[qx][1];
+      T gy1 = B0 * gyx[qx][0] + A0 * gyx[qx][1];
+      dy[q0] = gy0;
+      dy[q1] = gy1;
+    }
+}
+
+// Transpose of sf_forward3: r[a] += sum_q N_qa cv[q] + dN_qa . (cx, cy, cz)[q]
+// (unit-cell derivatives; scale cx..cz by 1/h beforehand).
+template <typename T>
+__device__ inline void sf_backward3(const T (&cv)[8], const T (&cx)[8], const T (&cy)[8], const T (&cz)[8],
+                                    T (&r)[8]) {
+  const T A0 = T(RMTR_GA), B0 = T(RMTR_GB);
+  T Fxy[2][2][2], Gxy[2][2], Gyx[2][2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int az = 0; az < 2; ++az) {
+      Gxy[q][az] = T(0);
+      Gyx[q][az] = T(0);
+    }
+#pragma unroll
+  for (int qy = 0; qy < 2; ++qy)
+#pragma unroll
+    for (int qx = 0; qx < 2; ++qx) {
+      const int q0 = qx + 2 * qy, q1 = q0 + 4;
+      T zz = cz[q0] + cz[q1];
+      Fxy[qx][qy][0] = A0 * cv[q0] + B0 * cv[q1] - zz;
+      Fxy[qx][qy][1] = B0 * cv[q0] + A0 * cv[q1] + zz;
+      Gxy[qy][0] += A0 * cx[q0] + B0 * cx[q1];
+      Gxy[qy][1] += B0 * cx[q0] + A0 * cx[q1];
+      Gyx[qx][0] += A0 * cy[q0] + B0 * cy[q1];
+      Gyx[qx][1] += B0 * cy[q0] + A0 * cy[q1];
+    }
+  T Fx[2][2][2], Gx[2][2];
+#pragma unroll
+  for (int az = 0; az < 2; ++az) {
+#pragma unroll
+    for (int qx = 0; qx < 2; ++qx) {
+      Fx[qx][0][az] = A0 * Fxy[qx][0][az] + B0 * Fxy[qx][1][az] - Gyx[qx][az];
+      Fx[qx][1][az] = B0 * Fxy[qx][0][az] + A0 * Fxy[qx][1][az] + Gyx[qx][az];
+    }
+    Gx[0][az] = A0 * Gxy[0][az] + B0 * Gxy[1][az];
+    Gx[1][az] = B0 * Gxy[0][az] + A0 * Gxy[1][az];
+  }
+#pragma unroll
+  for (int ay = 0; ay < 2; ++ay)
+#pragma unroll
+    for (int az = 0; az < 2; ++az) {
+      r[0 + 2 * ay + 4 * az] += A0 * Fx[0][ay][az] + B0 * Fx[1][ay][az] - Gx[ay][az];
+      r[1 + 2 * ay + 4 * az] += B0 * Fx[0][ay][az] + A0 * Fx[1][ay][az] + Gx[ay][az];
+    }
+}
+
+// Default Dirichlet set: every displacement component on the boundary.
+template <int DIM>
+__device__ inline uint8_t default_mask(const int (&ijk)[DIM], int N) {
+  bool b = false;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) b |= (ijk[i] == 0) | (ijk[i] == N);
+  return b ? uint8_t((1u << DIM) - 1u) : uint8_t(0);
+}
+
+}  // namespace rmtr

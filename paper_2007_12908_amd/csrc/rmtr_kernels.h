@@ -1,0 +1,86 @@
+// Host-side launch interface of the HIP kernels (internal to librmtr).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rmtr_device.h"
+
+namespace rmtr {
+
+// Scratch for deterministic two-stage reductions: partial sums of at most
+// kMaxPartials blocks, then one block sums them in a fixed order.
+constexpr int kMaxPartials = 4096;
+
+struct ElemArgs {
+  int dim;
+  int N;           // cells per side on this level
+  double h;
+  MatP<double> m;
+  const uint8_t* dir;  // per-node Dirichlet bits, or null (default set)
+};
+
+// ---- element kernels (elem_kernels.hip)
+hipError_t launch_energy(const ElemArgs& a, const double* x, const void* s, int s_fp32, const double* p,
+                         double* partials, double* out, hipStream_t st);
+hipError_t launch_gradient(const ElemArgs& a, const double* x, const double* p, double* g, hipStream_t st);
+hipError_t launch_hessvec(const ElemArgs& a, const void* xl, const void* p, const void* v, void* hv,
+                          int fp32, hipStream_t st);
+hipError_t launch_diag_blocks(const ElemArgs& a, const void* xl, const void* p, void* D, int fp32,
+                              hipStream_t st);
+hipError_t launch_pgs_matfree(const ElemArgs& a, const void* xl, const void* p, const void* D, const void* g,
+                              const void* lo, const void* hi, void* s, int n_sweeps, int fp32,
+                              hipStream_t st);
+hipError_t launch_reduce_partials(const double* partials, int n, double* out, hipStream_t st);
+
+// ---- element-matrix (Galerkin) operators (galerkin_kernels.hip)
+// same_level: element matrices of the level's own Hessian (no coarsening);
+// dirc: Dirichlet mask of the output level (null: default set).
+hipError_t launch_galerkin_from_matfree(const ElemArgs& fine, const double* xl, const double* p,
+                                        double* Kc, int same_level, const uint8_t* dirc, hipStream_t st);
+hipError_t launch_galerkin_from_em(int dim, int Nc, const double* Kf, double* Kc, const uint8_t* dirc,
+                                   hipStream_t st);
+hipError_t launch_em_hessvec(int dim, int N, const void* K, const void* v, void* hv, const uint8_t* dir,
+                             int fp32, hipStream_t st);
+hipError_t launch_em_diag(int dim, int N, const void* K, void* D, int fp32, hipStream_t st);
+hipError_t launch_em_pgs(int dim, int N, const void* K, const void* D, const uint8_t* dir, const void* g,
+                         const void* lo, const void* hi, void* s, int n_sweeps, int fp32, hipStream_t st);
+hipError_t launch_em_to_fp32(int64_t n, const double* src, float* dst, hipStream_t st);
+
+// ---- transfers (transfer_kernels.hip)
+hipError_t launch_prolong(int dim, int Nc, const void* xc, void* xf, int fp32, hipStream_t st);
+hipError_t launch_restrict(int dim, int Nc, int mode, const void* xf, void* xc, int fp32, hipStream_t st);
+
+// ---- fields (fields_kernels.hip)
+hipError_t launch_init_fields(int dim, int N, const double* table, int n_frac, double band, int p_mode,
+                              double p_value, double p_band, double* c0, double* p, hipStream_t st);
+
+// ---- vector kernels (linalg_kernels.hip)
+hipError_t launch_dot(int64_t n, const double* a, const double* b, double* partials, double* out,
+                      hipStream_t st);
+hipError_t launch_chi(int dim, int N, const double* x, const double* g, const double* c_lower,
+                      const uint8_t* dir, double* partials, double* out, hipStream_t st);
+hipError_t launch_axpy(int64_t n, double alpha, const double* x, double* y, hipStream_t st);
+hipError_t launch_step_box(int dim, int N, const double* x, const double* Lb, const double* Ub, double delta,
+                           const uint8_t* dir, double* lo, double* hi, hipStream_t st);
+hipError_t launch_fine_bounds(int dim, int N, const double* c_lower, double* Lb, double* Ub,
+                              hipStream_t st);
+hipError_t launch_convert(int64_t n, const void* src, int src_fp32, void* dst, int dst_fp32, hipStream_t st);
+hipError_t launch_add_scaled(int64_t n, const double* a, double alpha, const double* b, double beta,
+                             const double* c, double* out, hipStream_t st);
+hipError_t launch_zero_masked(int dim, int N, double* v, const uint8_t* dir, hipStream_t st);
+hipError_t launch_fill(int64_t n, double v, double* out, hipStream_t st);
+hipError_t launch_clamp(int64_t n, const double* lo, const double* hi, double* s, hipStream_t st);
+hipError_t launch_inject_scalar(int dim, int Nc, const double* fine, double* coarse, hipStream_t st);
+hipError_t launch_any_nonzero(int64_t n, const double* v, int* flag, hipStream_t st);
+
+// ---- MPRGP (mprgp_kernels.hip)
+struct MprgpResult {
+  int iterations;
+  int status;  // 0 converged, 1 max iterations, 2 negative curvature (fallback applied)
+};
+hipError_t run_mprgp(int dim, int N, const double* K, const uint8_t* dir, const double* g, const double* lo,
+                     const double* hi, double* s, int max_it, double rtol, int fallback_sweeps, double* work,
+                     double* host_scalars, MprgpResult* res, hipStream_t st);
+size_t mprgp_work_doubles(int dim, int N);
+
+}  // namespace rmtr

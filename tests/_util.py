@@ -1,0 +1,50 @@
+"""Shared helpers for the tests (seeded inputs and error measures only)."""
+import numpy as np
+
+from oracle import fem
+
+
+def material(N, split=True, E=1.0, nu=0.3, Gc=1e-3, k=1e-6):
+    return fem.material_from_E_nu(E, nu, Gc, 2.0 / N, k, split)
+
+
+def rand_state(d, N, seed, u_scale=1e-2, p_scale=1e-3, c_max=1.0):
+    """Random displacement, c in [0, c_max], positive nodal p; Dirichlet
+    displacement values zero."""
+    rng = np.random.default_rng(seed)
+    g = fem.Grid(d, N)
+    x = rng.standard_normal(g.n_dofs) * u_scale
+    x.reshape(-1, d + 1)[:, d] = rng.uniform(0.0, c_max, g.n_nodes)
+    x[g.default_dirichlet()] = 0.0
+    p = rng.uniform(0.5, 1.5, g.n_nodes) * p_scale
+    return g, x, p
+
+
+def field_rel_err(a, b, d):
+    """max over the displacement block and the phase-field block of
+    ||a - b|| / ||b||."""
+    nc = d + 1
+    a = np.asarray(a).reshape(-1, nc)
+    b = np.asarray(b).reshape(-1, nc)
+    out = 0.0
+    for sl in (slice(0, d), slice(d, nc)):
+        nb = np.linalg.norm(b[:, sl])
+        out = max(out, np.linalg.norm(a[:, sl] - b[:, sl]) / max(nb, 1e-300))
+    return out
+
+
+def ctx_for(d, N, L, mat):
+    import paper_2007_12908_amd as P
+    return P.Context(d, N, L, mat.lam, mat.mu, mat.Gc, mat.ls, mat.k, mat.split)
+
+
+def dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()

@@ -1,0 +1,52 @@
+"""The C-ABI library loads on any host and exports every entry point that
+include/rmtr.h declares (no GPU call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rmtr.h")
+LIB = os.path.join(ROOT, "paper_2007_12908_amd", "librmtr.so")
+
+
+def declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(rmtr_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary_calls():
+    names = declared()
+    for n in ["rmtr_energy", "rmtr_gradient", "rmtr_hessvec", "rmtr_smooth", "rmtr_restrict",
+              "rmtr_prolong", "rmtr_solve_loadstep"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        pytest.fail("librmtr.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_lists_every_export():
+    from paper_2007_12908_amd import binding
+    assert sorted(binding.EXPORTS) == declared()
+
+
+def test_create_validates_model_without_gpu():
+    from paper_2007_12908_amd import binding
+    lib = binding.load()
+    h = ctypes.c_void_p()
+    bad = binding.Model(3, 10, 3, 1, 1.0, 1.0, 1e-3, 0.1, 1e-6)     # 10 % 4 != 0
+    assert lib.rmtr_create(ctypes.byref(bad), ctypes.byref(h)) == -1
+    good = binding.Model(3, 16, 3, 1, 1.0, 1.0, 1e-3, 0.1, 1e-6)
+    assert lib.rmtr_create(ctypes.byref(good), ctypes.byref(h)) == 0
+    assert lib.rmtr_level_nodes(h, 1) == 5 ** 3 and lib.rmtr_level_nodes(h, 3) == 17 ** 3
+    assert lib.rmtr_level_nodes(h, 4) == -1
+    lib.rmtr_destroy(h)
+    p = binding.default_params()
+    assert (p.eta1, p.eta2, p.gamma1, p.gamma2, p.pgs_sweeps, p.mu1, p.mu2) == (0.1, 0.75, 0.5, 2.0, 3, 1, 1)

@@ -1,0 +1,122 @@
+"""GPU vs oracle: initial fields, energy, energy difference, gradient, Hv,
+diagonal blocks (FP64 and the FP32 mixed-precision form).
+
+Tolerances: FP64 results within 1e-12 relative, normwise per field (the
+displacement block and the phase-field block separately); the FP32 Hv within
+2e-5 relative (single-precision arithmetic over sums of ~10^2 terms whose
+magnitudes differ by up to the stiffness contrast g(c) ~ 1e-6 .. 1)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fem, fields
+from _util import material, rand_state, field_rel_err, ctx_for, dev, host
+
+pytestmark = pytest.mark.gpu
+
+# sizes: tiny, odd (ragged tiles), and several 15-node tiles with a ragged tail
+CASES = [(2, 6), (2, 13), (3, 3), (3, 5), (3, 20), (3, 33)]
+
+
+@pytest.mark.parametrize("d,N", CASES)
+@pytest.mark.parametrize("split", [True, False])
+def test_energy_gradient_hessvec_fp64(d, N, split):
+    print(f"case d={d} N={N} split={split}", flush=True)
+    g, x, p = rand_state(d, N, seed=100 * d + N)
+    mat = material(N, split)
+    ctx = ctx_for(d, N, 1, mat)
+    xd, pd = dev(x), dev(p)
+    E = float(host(ctx.energy(1, xd, pd))[0])
+    Eo = fem.energy(g, x, p, mat)
+    assert E == pytest.approx(Eo, rel=1e-12)
+    G = host(ctx.gradient(1, xd, pd))
+    Go = fem.gradient(g, x, p, mat)
+    assert field_rel_err(G, Go, d) <= 1e-12
+    rng = np.random.default_rng(N)
+    v = rng.standard_normal(g.n_dofs)
+    HV = host(ctx.hessvec(1, xd, pd, dev(v)))
+    H = fem.hessian(g, x, p, mat)
+    HVo = H @ np.where(g.default_dirichlet(), 0.0, v)
+    assert field_rel_err(HV, HVo, d) <= 1e-12
+    s = rng.standard_normal(g.n_dofs) * 1e-3
+    dE = float(host(ctx.energy_diff(1, xd, dev(s), pd))[0])
+    dEo = fem.energy_diff(g, x, s, p, mat)
+    assert dE == pytest.approx(dEo, rel=1e-11, abs=1e-15 * abs(Eo))
+    D = host(ctx.diag_blocks(1, xd, pd)).reshape(-1, d + 1, d + 1)
+    Do = fem.diag_blocks(H, g)
+    assert np.abs(D - Do).max() <= 1e-12 * np.abs(Do).max()
+
+
+@pytest.mark.parametrize("d,N", [(2, 13), (3, 5), (3, 33)])
+def test_custom_dirichlet_mask(d, N):
+    g, x, p = rand_state(d, N, seed=7 + N)
+    mat = material(N)
+    rng = np.random.default_rng(3)
+    mask_nodes = rng.integers(0, 1 << (d + 1), g.n_nodes).astype(np.uint8)
+    dirm = np.zeros((g.n_nodes, d + 1), bool)
+    for k in range(d + 1):
+        dirm[:, k] = (mask_nodes >> k) & 1
+    dirm = dirm.reshape(-1)
+    ctx = ctx_for(d, N, 1, mat)
+    import torch
+    md = torch.from_numpy(mask_nodes).cuda()
+    G = host(ctx.gradient(1, dev(x), dev(p), md))
+    Go = fem.gradient(g, x, p, mat, dirm)
+    assert field_rel_err(G, Go, d) <= 1e-12
+    v = rng.standard_normal(g.n_dofs)
+    HV = host(ctx.hessvec(1, dev(x), dev(p), dev(v), md))
+    HVo = fem.hessian(g, x, p, mat, dirm) @ np.where(dirm, 0.0, v)
+    assert field_rel_err(HV, HVo, d) <= 1e-12
+
+
+@pytest.mark.parametrize("d,N", [(2, 13), (3, 5), (3, 33)])
+def test_hessvec_fp32_mixed(d, N):
+    import torch
+    g, x, p = rand_state(d, N, seed=11 * N)
+    mat = material(N)
+    ctx = ctx_for(d, N, 1, mat)
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(g.n_dofs)
+    HV = host(ctx.hessvec(1, dev(x, torch.float32), dev(p, torch.float32), dev(v, torch.float32)))
+    # oracle on the FP32-rounded inputs, in FP64
+    x32 = x.astype(np.float32).astype(np.float64)
+    p32 = p.astype(np.float32).astype(np.float64)
+    v32 = v.astype(np.float32).astype(np.float64)
+    HVo = fem.hessian(g, x32, p32, mat) @ np.where(g.default_dirichlet(), 0.0, v32)
+    assert field_rel_err(HV, HVo, d) <= 2e-5
+
+
+def test_init_fields_bitwise_2d():
+    wl = W.WORKLOADS["c1_2d_64"]
+    g = fem.Grid(2, 64)
+    c0o, po = fields.initial_fields(g, wl.fractures(), p_uniform=wl.p)
+    ctx = ctx_for(2, 64, 3, material(64))
+    c0, p = ctx.init_fields(3, wl.fractures(), band=g.h, p_mode=0, p_value=wl.p)
+    assert np.array_equal(host(c0), c0o) and np.array_equal(host(p), po)
+    assert host(c0).sum() == 39
+
+
+@pytest.mark.parametrize("name,N", [("c2_3d_128", 128), ("c3_3d_256", 64)])
+def test_init_fields_bitwise_3d(name, N):
+    wl = W.WORKLOADS[name]
+    g = fem.Grid(3, N)
+    tab = wl.fractures()
+    c0o, _ = fields.initial_fields(g, tab, p_uniform=wl.p)
+    ctx = ctx_for(3, N, 1, material(N))
+    c0, p = ctx.init_fields(1, tab, band=g.h, p_mode=0, p_value=wl.p)
+    assert np.array_equal(host(c0), c0o)
+    assert c0o.sum() > 0
+
+
+def test_init_fields_per_fracture_pressure_bitwise():
+    """C4-style pressure: max p_f of the discs within 4 l_s (= 8 h) of a node."""
+    wl = W.WORKLOADS["c4_3d_384"]
+    N = 48
+    g = fem.Grid(3, N)
+    tab = wl.fractures()[:200]
+    band = 8.0 * g.h
+    c0o, po = fields.initial_fields(g, tab, p_uniform=None, p_band=band)
+    ctx = ctx_for(3, N, 1, material(N))
+    c0, p = ctx.init_fields(1, tab, band=g.h, p_mode=1, p_band=band)
+    assert np.array_equal(host(c0), c0o) and np.array_equal(host(p), po)
+    assert (po > 0).sum() > 0

@@ -1,0 +1,135 @@
+"""GPU vs oracle: projected Gauss-Seidel, transfers (bitwise), Galerkin
+coarse operators, MPRGP, reductions."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import fem, qp, transfer
+from _util import material, rand_state, field_rel_err, ctx_for, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _box(g, x, delta, rng):
+    d = g.d
+    lo = np.full(g.n_dofs, -delta)
+    hi = np.full(g.n_dofs, delta)
+    ci = np.arange(g.n_nodes) * (d + 1) + d
+    lo[ci] = np.maximum(-x[ci] * rng.uniform(0, 1, g.n_nodes), -delta)
+    hi[ci] = np.minimum(1.0 - x[ci], delta)
+    dirm = g.default_dirichlet()
+    lo[dirm] = hi[dirm] = 0.0
+    return lo, hi
+
+
+@pytest.mark.parametrize("d,N", [(2, 7), (2, 16), (3, 4), (3, 17)])
+@pytest.mark.parametrize("sweeps", [1, 3])
+def test_pgs_matches_oracle(d, N, sweeps):
+    print(f"case d={d} N={N} sweeps={sweeps}", flush=True)
+    g, x, p = rand_state(d, N, seed=N + sweeps, u_scale=1e-4, c_max=0.6)
+    mat = material(N)
+    rng = np.random.default_rng(N)
+    gv = rng.standard_normal(g.n_dofs) * 1e-4
+    gv[g.default_dirichlet()] = 0.0
+    lo, hi = _box(g, x, 2e-3, rng)
+    H = fem.hessian(g, x, p, mat)
+    blocks = qp.colour_blocks(g.node_colour(), g.nc, 2 ** d)
+    so = qp.pgs(H, gv, lo, hi, np.zeros(g.n_dofs), blocks, sweeps, ~g.default_dirichlet())
+    ctx = ctx_for(d, N, 1, mat)
+    s = dev(np.zeros(g.n_dofs))
+    ctx.smooth(1, dev(x), dev(p), dev(gv), dev(lo), dev(hi), s, sweeps)
+    sh = host(s)
+    assert np.all(sh >= lo) and np.all(sh <= hi)
+    assert field_rel_err(sh, so, d) <= 1e-11
+
+
+@pytest.mark.parametrize("d,Nc", [(2, 4), (2, 9), (3, 2), (3, 5)])
+def test_transfers_bitwise(d, Nc):
+    nc = d + 1
+    rng = np.random.default_rng(Nc)
+    I = transfer.prolongation(d, Nc, nc)
+    R = transfer.restriction(d, Nc, nc)
+    P = transfer.injection(d, Nc, nc)
+    xc = rng.standard_normal(I.shape[1])
+    xf = rng.standard_normal(I.shape[0])
+    mat = material(2 * Nc)
+    ctx = ctx_for(d, 2 * Nc, 2, mat)
+    assert np.array_equal(host(ctx.prolong(1, dev(xc))), I @ xc)
+    assert np.array_equal(host(ctx.restrict(2, dev(xf), 0)), R @ xf)
+    assert np.array_equal(host(ctx.restrict(2, dev(xf), 1)), P @ xf)
+    lo, hi = -np.abs(xf), np.abs(rng.standard_normal(xf.shape))
+    loH, hiH = transfer.box_restrict(I, lo, hi)
+    assert np.array_equal(host(ctx.restrict(2, dev(lo), 2)), loH)
+    assert np.array_equal(host(ctx.restrict(2, dev(hi), 3)), hiH)
+
+
+def _masked_galerkin(d, Nc, Hf):
+    I = transfer.prolongation(d, Nc, d + 1)
+    R = transfer.restriction(d, Nc, d + 1)
+    gc = fem.Grid(d, Nc)
+    Dc = sp.diags((~gc.default_dirichlet()).astype(float))
+    return (Dc @ (R @ Hf @ I) @ Dc).tocsr(), gc
+
+
+@pytest.mark.parametrize("d,N,L", [(2, 8, 3), (2, 16, 2), (3, 4, 2), (3, 16, 3)])
+def test_galerkin_element_matrices(d, N, L):
+    print(f"case d={d} N={N} L={L}", flush=True)
+    g, x, p = rand_state(d, N, seed=N + L)
+    mat = material(N)
+    ctx = ctx_for(d, N, L, mat)
+    H = fem.hessian(g, x, p, mat)
+    K = ctx.galerkin(L - 1, dev(x), dev(p))
+    Hc, gc = _masked_galerkin(d, N // 2, H)
+    rng = np.random.default_rng(1)
+    v = rng.standard_normal(gc.n_dofs)
+    assert field_rel_err(host(ctx.em_hessvec(L - 1, K, dev(v))), Hc @ v, d) <= 1e-12
+    if L >= 3:
+        K2 = ctx.galerkin(L - 2, K_fine=K)
+        Hcc, gcc = _masked_galerkin(d, N // 4, Hc)
+        w = rng.standard_normal(gcc.n_dofs)
+        assert field_rel_err(host(ctx.em_hessvec(L - 2, K2, dev(w))), Hcc @ w, d) <= 1e-12
+    # element-matrix PGS on the coarse level
+    gv = rng.standard_normal(gc.n_dofs) * 1e-4
+    gv[gc.default_dirichlet()] = 0.0
+    xc = transfer.injection(d, N // 2, d + 1) @ x
+    lo, hi = _box(gc, xc, 2e-3, rng)
+    blocks = qp.colour_blocks(gc.node_colour(), gc.nc, 2 ** d)
+    so = qp.pgs(Hc, gv, lo, hi, np.zeros(gc.n_dofs), blocks, 2, ~gc.default_dirichlet())
+    s = dev(np.zeros(gc.n_dofs))
+    ctx.em_smooth(L - 1, K, dev(gv), dev(lo), dev(hi), s, 2)
+    assert field_rel_err(host(s), so, d) <= 1e-11
+
+
+@pytest.mark.parametrize("d,N", [(2, 8), (3, 4), (3, 8)])
+def test_mprgp_matches_oracle_on_convex_qp(d, N):
+    g, x, p = rand_state(d, N, seed=3 * N, u_scale=1e-5, p_scale=1e-6, c_max=0.3)
+    mat = material(N)
+    ctx = ctx_for(d, N, 2, mat)
+    H = fem.hessian(g, x, p, mat)
+    K = ctx.galerkin(1, dev(x), dev(p))
+    Hc, gc = _masked_galerkin(d, N // 2, H)
+    rng = np.random.default_rng(2)
+    gv = rng.standard_normal(gc.n_dofs) * 1e-4
+    gv[gc.default_dirichlet()] = 0.0
+    xc = transfer.injection(d, N // 2, d + 1) @ x
+    lo, hi = _box(gc, xc, 1e-3, rng)
+    so, its_o, st_o = qp.mprgp(Hc, gv, lo, hi, rtol=1e-12, max_it=3000)
+    s, its, st = ctx.mprgp(1, K, dev(gv), dev(lo), dev(hi), max_it=3000, rtol=1e-12)
+    assert st_o == "converged" and st == 0
+    sh = host(s)
+    assert np.all(sh >= lo) and np.all(sh <= hi)
+    assert np.abs(sh - so).max() <= 1e-8 * np.abs(so).max()
+
+
+def test_dot_and_chi():
+    d, N = 3, 9
+    g, x, p = rand_state(d, N, seed=1)
+    mat = material(N)
+    ctx = ctx_for(d, N, 1, mat)
+    rng = np.random.default_rng(0)
+    a, b = rng.standard_normal(g.n_dofs), rng.standard_normal(g.n_dofs)
+    assert float(host(ctx.dot(dev(a), dev(b)))[0]) == pytest.approx(float(a @ b), rel=1e-13)
+    gr = fem.gradient(g, x, p, mat)
+    cl = x[d::d + 1] * rng.uniform(0, 1, g.n_nodes)
+    chi = float(host(ctx.chi(1, dev(x), dev(gr), dev(cl)))[0])
+    assert chi == pytest.approx(fem.chi(g, x, gr, cl), rel=1e-13)
