@@ -1,0 +1,233 @@
+#!/usr/bin/env python
+"""Benchmark of the RMTR hot path on one MI355X.
+
+One step = energy, gradient and Hessian-vector product (FP64, matrix-free)
+over the fine level of the workload, inputs resident in HBM.  `value` is the
+fine-level dofs passed through that triple per second (GDoF/s).  The same run
+reports each kernel's own rate, the mixed-precision (FP32) Hv, the roofline
+of the dominant kernel (HIP events on the launch stream), the RMTR load step
+(plain FP64 and mixed) to 1e-8, and the CPU oracle on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GDoF/s energy/grad/Hv; RMTR s/load-step plain vs mixed+learned at 1e-8"
+PEAK_FP64 = 78.6      # TFLOP/s, MI355X FP64 vector (= FP64 matrix)
+PEAK_HBM = 8000.0     # GB/s
+KERNEL_SOURCES = ["paper_2007_12908_amd/csrc/elem_kernels.hip", "paper_2007_12908_amd/csrc/rmtr_device.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hessvec_c2_3d_128.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """Per-launch HBM bytes of the Hv kernel from committed PMC counters, or
+    None when the kernel sources changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def time_calls(fn, n, torch):
+    """Average duration of fn() over n calls, with HIP events on torch's
+    current stream (the stream librmtr launches on)."""
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(n):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / n
+
+
+def cpu_baseline(wl, x_np, p_np, v_np, budget_s=20.0):
+    """The oracle, as it is, on the first z-layers of the workload grid."""
+    import numpy as np
+    from oracle import fem
+    g = fem.Grid(3, wl.n_cells)
+    mat = fem.material_from_E_nu(wl.E, wl.nu, wl.Gc, wl.ls, wl.k)
+    ne = 256
+    while True:
+        elems = np.arange(ne)
+        t0 = time.perf_counter()
+        fem.energy(g, x_np, p_np, mat, elems)
+        fem.gradient(g, x_np, p_np, mat, None, elems)
+        H = fem.hessian(g, x_np, p_np, mat, None, elems)
+        _ = H @ v_np
+        dt = time.perf_counter() - t0
+        if dt * 4 > budget_s or ne >= wl.n_cells ** 3:
+            break
+        ne *= 2
+    # one element per node in the large-grid limit: 4 dofs per element
+    return {"value": 4 * ne / dt / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
+            "sample": f"energy+gradient+Hv over the first {ne} elements of the {wl.n_cells}^3 grid "
+                      f"(4 dofs per element), numpy/scipy FP64 single thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2_3d_128")
+    ap.add_argument("--no-loadstep", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="time only the kernel triple (for profiler runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain device copy of known size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "decomposition is not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2007_12908_amd as P
+    from paper_2007_12908_amd import binding
+
+    wl = W.WORKLOADS[args.workload]
+    assert wl.dim == 3
+    N, L = wl.n_cells, wl.n_levels
+    ctx = P.Context(3, N, L, wl.lam, wl.mu, wl.Gc, wl.ls, wl.k)
+    c0, p = ctx.init_fields(L, wl.fractures(), band=wl.h, p_mode=0, p_value=wl.p)
+    n_nodes = (N + 1) ** 3
+    n_dofs = 4 * n_nodes
+    rng = np.random.default_rng(1234)
+    x_np = np.zeros(n_dofs)
+    x_np.reshape(-1, 4)[:, :3] = rng.standard_normal((n_nodes, 3)) * 1e-4
+    c0_np = c0.cpu().numpy()
+    x_np.reshape(-1, 4)[:, 3] = c0_np
+    ijk = np.stack(np.unravel_index(np.arange(n_nodes), (N + 1,) * 3, order="F"), axis=1)
+    bnd = np.any((ijk == 0) | (ijk == N), axis=1)
+    x_np.reshape(-1, 4)[bnd, :3] = 0.0
+    v_np = rng.standard_normal(n_dofs)
+    x = torch.from_numpy(x_np).cuda()
+    v = torch.from_numpy(v_np).cuda()
+    x32, p32, v32 = x.float(), p.float(), v.float()
+    E = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = torch.empty_like(x)
+    hv = torch.empty_like(x)
+    hv32 = torch.empty_like(x32)
+
+    def step():
+        ctx.energy(L, x, p, out=E)
+        ctx.gradient(L, x, p, out=g)
+        ctx.hessvec(L, x, p, v, out=hv)
+
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float64, device="cuda")   # 2 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) / args.steps * 1e3
+
+    reps = max(args.steps, 5)
+    t_e = time_calls(lambda: ctx.energy(L, x, p, out=E), reps, torch)
+    t_g = time_calls(lambda: ctx.gradient(L, x, p, out=g), reps, torch)
+    t_h = time_calls(lambda: ctx.hessvec(L, x, p, v, out=hv), reps, torch)
+    t_h32 = time_calls(lambda: ctx.hessvec(L, x32, p32, v32, out=hv32), reps, torch)
+    if args.kernels_only:
+        log(json.dumps({"ms": {"energy": t_e, "gradient": t_g, "hessvec": t_h, "hessvec_fp32": t_h32}}))
+        return
+
+    ne = N ** 3
+    fl = {k: binding.element_flops(3, kk) for k, kk in (("energy", 0), ("gradient", 2), ("hessvec", 3))}
+    per = {
+        "energy": {"ms": t_e, "GDoF/s": n_dofs / t_e / 1e6, "TFLOP/s": fl["energy"] * ne / t_e / 1e9},
+        "gradient": {"ms": t_g, "GDoF/s": n_dofs / t_g / 1e6, "TFLOP/s": fl["gradient"] * ne / t_g / 1e9},
+        "hessvec": {"ms": t_h, "GDoF/s": n_dofs / t_h / 1e6, "TFLOP/s": fl["hessvec"] * ne / t_h / 1e9},
+        "hessvec_fp32": {"ms": t_h32, "GDoF/s": n_dofs / t_h32 / 1e6,
+                         "TFLOP/s": fl["hessvec"] * ne / t_h32 / 1e9},
+    }
+    # dominant kernel of the step: the slowest of the three FP64 kernels
+    dom = max(("energy", "gradient", "hessvec"), key=lambda k: per[k]["ms"])
+    achieved = per[dom]["TFLOP/s"]
+    traffic = measured_traffic() if dom == "hessvec" else None
+    roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_FP64, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64, "traffic": traffic,
+            "flops_per_element": fl[dom], "elements": ne,
+            "hbm_GB/s_algorithmic": {"energy": 40 * n_nodes / t_e / 1e6, "gradient": 72 * n_nodes / t_g / 1e6,
+                                     "hessvec": 104 * n_nodes / t_h / 1e6,
+                                     "hessvec_fp32": 52 * n_nodes / t_h32 / 1e6}}
+
+    rmtr = None
+    if not args.no_loadstep:
+        rmtr = {}
+        for name, prec in (("plain_fp64", 0), ("mixed_fp32", 1)):
+            xs = torch.zeros_like(x)
+            xs.view(-1, 4)[:, 3] = c0
+            prm = P.default_params(precision=prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = ctx.solve_loadstep(xs, p, c0, prm)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rmtr[name] = {"s_per_loadstep": dt, "vcycles": st["vcycles"], "chi_rel": st["chi"] / st["chi0"],
+                          "tr_accepted": st["tr_accepted"], "tr_rejected": st["tr_rejected"],
+                          "energy": st["energy"], "converged": st["code"] == 0}
+            log(name, rmtr[name])
+
+    cpu = None if args.no_cpu else cpu_baseline(wl, x_np, p.cpu().numpy(), v_np)
+
+    out = {
+        "metric": METRIC,
+        "value": n_dofs / (ms_step / 1e3) / 1e9,
+        "unit": "GDoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: 3D Q1 {N}^3 cells, {wl.n_frac} penny fractures, "
+                               f"{L} levels, p={wl.p} uniform", "n_cells": N, "n_dofs": n_dofs,
+                   "step": "energy + gradient + Hv (FP64) on the finest level"},
+        "kernels": per,
+        "roofline": roof,
+        "rmtr": rmtr,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

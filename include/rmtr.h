@@ -84,7 +84,9 @@ typedef struct {
   double delta0, delta_max; /* initial and largest TR radius             */
   double rtol;             /* stop when chi <= rtol chi(x_initial)      */
   double coarse_qp_rtol;   /* MPRGP relative tolerance                  */
-  double guard;            /* round-off guard of the TR ratio           */
+  double guard;            /* TR ratio round-off level: |pred| <= tol = guard |f(x_in)| /
+                              sqrt(elements of the level) counts as rho = 1 unless
+                              ared < -tol (eq. (rho_tr), (rho_ml) in finite precision) */
   int32_t mu1, mu2;        /* pre-/post-smoothing TR steps (Alg. 1)     */
   int32_t pgs_sweeps;      /* symmetric PGS sweeps per TR subproblem    */
   int32_t coarse_tr_its;   /* TR steps on the coarsest level (mu^1)     */
@@ -204,6 +206,16 @@ rmtr_status rmtr_chi(rmtr_ctx* ctx, int32_t level, const double* x, const double
 rmtr_status rmtr_solve_loadstep(rmtr_ctx* ctx, const double* p, const double* c_lower, const uint8_t* dirichlet,
                                 const rmtr_params* params, double* x_inout, rmtr_stats* stats,
                                 double* chi_history, void* stream);
+
+/* Floating-point additions, subtractions, multiplications and divisions that
+   the library's element operators perform on data for ONE element (the
+   figure used for arithmetic rooflines; host-only, no GPU call).  kind:
+   0 energy, 1 energy difference, 2 gradient, 3 Hessian-vector product (3D:
+   sum-factorised element-centric kernels), 4 one element's contribution to
+   one node's rows in a Gauss-Seidel colour pass.  In 2D, kinds 2 and 3 are
+   per element and node (node-centric kernels).  Returns -1 for a bad
+   argument. */
+int64_t rmtr_element_flops(int32_t dim, int32_t kind);
 
 #ifdef __cplusplus
 }

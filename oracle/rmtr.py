@@ -16,8 +16,9 @@ Readings where the paper is silent (listed in the design notes):
     or f~^l = 0 ("zero" coarse model);
   * coarse feasible set: x0 + box_restrict(fine correction box);
   * ratio guards: pred <= 0 with s != 0 -> rho = -inf; s = 0 -> skip;
-    |pred| <= 1e-14 max(1, |f_ref|) -> rho = 1 if ared >= -1e-14 max(1, |f_ref|)
-    else -inf; non-finite -> -inf;
+    |pred| <= tol -> rho = 1 if ared >= -tol else -inf, with the round-off
+    level tol = 1e-14 |f_ref| / sqrt(n_elements of the level), f_ref the
+    energy at the start of the load step; non-finite -> -inf;
   * Alg. 3 literally: accept iff rho > eta1; radius gamma1 D if rho < eta1,
     unchanged on [eta1, eta2], min(gamma2 D, D_max) if rho > eta2;
   * Alg. 2 runs exactly i_max iterations.
@@ -143,8 +144,10 @@ class RMTR:
         return lo, hi
 
     # ------------------------------------------------------------ ratio
-    def ratio(self, ared, pred, s_nonzero):
-        tol = self.prm.guard * max(1.0, abs(self.f_ref))
+    def ratio(self, ared, pred, lev):
+        # round-off level of a sum of per-element energy differences: about
+        # eps |f| / sqrt(number of elements) (independent element errors)
+        tol = self.prm.guard * abs(self.f_ref) / np.sqrt(lev.grid.n_elems)
         if not np.isfinite(ared) or not np.isfinite(pred):
             return -np.inf
         if abs(pred) <= tol:
@@ -183,7 +186,7 @@ class RMTR:
             return x, delta
         pred = -(float(g @ s) + 0.5 * float(s @ (lev.Hmod @ s)))
         ared = -self.h_diff(lev, x, s)
-        rho = self.ratio(ared, pred, True)
+        rho = self.ratio(ared, pred, lev)
         accept, delta = self.control(rho, delta)
         if accept:
             self.stats.tr_accepted += 1
@@ -234,7 +237,7 @@ class RMTR:
             s = self.I[l - 1] @ sc
             ared = -self.h_diff(lev, x, s)
             pred = -self.h_diff(c, c.x0, sc)
-            rho = self.ratio(ared, pred, True)
+            rho = self.ratio(ared, pred, lev)
             accept, delta = self.control(rho, delta)
             if accept:
                 x = x + s

@@ -24,6 +24,7 @@ EXPORTS = [
     "rmtr_init_fields", "rmtr_energy", "rmtr_energy_diff", "rmtr_gradient", "rmtr_hessvec",
     "rmtr_diag_blocks", "rmtr_smooth", "rmtr_restrict", "rmtr_prolong", "rmtr_galerkin",
     "rmtr_em_hessvec", "rmtr_em_smooth", "rmtr_mprgp", "rmtr_dot", "rmtr_chi", "rmtr_solve_loadstep",
+    "rmtr_element_flops",
 ]
 
 
@@ -85,6 +86,7 @@ def load():
             "rmtr_chi": (I32, [P, I32, P, P, P, P, P, P]),
             "rmtr_solve_loadstep": (I32, [P, P, P, P, ctypes.POINTER(Params), P, ctypes.POINTER(Stats),
                                           P, P]),
+            "rmtr_element_flops": (I64, [I32, I32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -100,6 +102,11 @@ def default_params(**over):
     for k, v in over.items():
         setattr(p, k, v)
     return p
+
+
+def element_flops(dim, kind):
+    """Algorithmic flops of one element for an operator kind (see rmtr.h)."""
+    return int(load().rmtr_element_flops(dim, kind))
 
 
 def _ptr(t):

@@ -101,92 +101,6 @@ __device__ inline void mask_elem(const uint8_t* dir, const int (&e)[DIM], int N,
   }
 }
 
-// z-vectors at all 2^DIM points (3D: sum-factorised; 2D: plain).
-template <int DIM, typename T>
-__device__ inline void elem_z(const T (&X)[1 << DIM][DIM + 1], T invh, Zq<DIM, T> (&z)[1 << DIM]) {
-  if constexpr (DIM == 3) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      T f[8], val[8], dx[8], dy[8], dz[8];
-#pragma unroll
-      for (int a = 0; a < 8; ++a) f[a] = X[a][k];
-      sf_forward3<T>(f, val, dx, dy, dz);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        if (k < 3) {
-          z[q].u[k] = val[q];
-          z[q].G[k][0] = dx[q] * invh;
-          z[q].G[k][1] = dy[q] * invh;
-          z[q].G[k][2] = dz[q] * invh;
-        } else {
-          z[q].c = val[q];
-          z[q].dc[0] = dx[q] * invh;
-          z[q].dc[1] = dy[q] * invh;
-          z[q].dc[2] = dz[q] * invh;
-        }
-      }
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < (1 << DIM); ++q) interp_q<DIM, T>(q, X, invh, z[q]);
-  }
-}
-
-template <int DIM, typename T>
-__device__ inline void elem_pq(const T (&P)[1 << DIM], T invh, T (&pq)[1 << DIM], T (&dpq)[1 << DIM][DIM]) {
-  if constexpr (DIM == 3) {
-    T dx[8], dy[8], dz[8];
-    sf_forward3<T>(P, pq, dx, dy, dz);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      dpq[q][0] = dx[q] * invh;
-      dpq[q][1] = dy[q] * invh;
-      dpq[q][2] = dz[q] * invh;
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < (1 << DIM); ++q) interp_scalar_q<DIM, T>(q, P, invh, pq[q], dpq[q]);
-  }
-}
-
-// r[a][k] = sum_q w B_{q,a}^T o_q for all nodes of the element.
-template <int DIM, typename T>
-__device__ inline void elem_project(const Zq<DIM, T> (&o)[1 << DIM], T invh, T w, T (&r)[1 << DIM][DIM + 1]) {
-  if constexpr (DIM == 3) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      T cv[8], cx[8], cy[8], cz[8], rr[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        if (k < 3) {
-          cv[q] = w * o[q].u[k];
-          cx[q] = w * invh * o[q].G[k][0];
-          cy[q] = w * invh * o[q].G[k][1];
-          cz[q] = w * invh * o[q].G[k][2];
-        } else {
-          cv[q] = w * o[q].c;
-          cx[q] = w * invh * o[q].dc[0];
-          cy[q] = w * invh * o[q].dc[1];
-          cz[q] = w * invh * o[q].dc[2];
-        }
-        rr[q] = T(0);
-      }
-      sf_backward3<T>(cv, cx, cy, cz, rr);
-#pragma unroll
-      for (int a = 0; a < 8; ++a) r[a][k] = rr[a];
-    }
-  } else {
-#pragma unroll
-    for (int a = 0; a < (1 << DIM); ++a)
-#pragma unroll
-      for (int k = 0; k <= DIM; ++k) r[a][k] = T(0);
-#pragma unroll
-    for (int q = 0; q < (1 << DIM); ++q)
-#pragma unroll
-      for (int a = 0; a < (1 << DIM); ++a) project_q_node<DIM, T>(q, a, invh, w, o[q], r[a]);
-  }
-}
-
 // ------------------------------------------------------------------ energy
 // One thread per element; per-block partial sums in a fixed order.
 template <int DIM, typename TS>
@@ -250,35 +164,6 @@ __global__ __launch_bounds__(kBlock) void k_reduce_partials(const double* __rest
   double tot = block_sum(acc, sh);
   if (threadIdx.x == 0) *out = tot;
 }
-
-// ------------------------------------------------ per-element operators
-// MODE 0: gradient of f at x.  MODE 1: Hessian at xl applied to v.
-template <int MODE, typename T>
-struct ElemOp3 {
-  // computes r[8][4] for one element
-  __device__ static inline void eval(const MatP<T>& m, T invh, T w, const T (&X)[8][4], const T (&V)[8][4],
-                                     const T (&P)[8], T (&r)[8][4]) {
-    T pq[8], dpq[8][3];
-    elem_pq<3, T>(P, invh, pq, dpq);
-    Zq<3, T> o[8];
-    {
-      Zq<3, T> z[8];
-      elem_z<3, T>(X, invh, z);
-      if (MODE == 0) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) density_grad<3, T>(m, z[q], pq[q], dpq[q], o[q]);
-      } else {
-        HessCoef<3, T> hc[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) hess_coef<3, T>(m, z[q], pq[q], dpq[q], hc[q]);
-        elem_z<3, T>(V, invh, z);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) hess_apply<3, T>(m, hc[q], z[q], o[q]);
-      }
-    }
-    elem_project<3, T>(o, invh, w, r);
-  }
-};
 
 // 3D element-centric kernel: a 16 x 16 tile of element columns marches up
 // in z; each element's 8 nodal contributions are exchanged through LDS and
@@ -369,28 +254,6 @@ __global__ __launch_bounds__(256) void k_elem_scatter3(int N, T h, MatP<double> 
 
 // Node-centric kernels (any DIM): a thread per node sums the contributions
 // of the 2^DIM elements around it.  Used in 2D and for per-node quantities.
-template <int DIM, typename T>
-__device__ inline void node_contrib(int MODE, const MatP<T>& m, T invh, T w, const T (&X)[1 << DIM][DIM + 1],
-                                    const T (&V)[1 << DIM][DIM + 1], const T (&P)[1 << DIM], int aloc,
-                                    T (&r)[DIM + 1]) {
-#pragma unroll
-  for (int q = 0; q < (1 << DIM); ++q) {
-    Zq<DIM, T> z, o;
-    T pq, dpq[DIM];
-    interp_scalar_q<DIM, T>(q, P, invh, pq, dpq);
-    interp_q<DIM, T>(q, X, invh, z);
-    if (MODE == 0) {
-      density_grad<DIM, T>(m, z, pq, dpq, o);
-    } else {
-      HessCoef<DIM, T> hc;
-      hess_coef<DIM, T>(m, z, pq, dpq, hc);
-      interp_q<DIM, T>(q, V, invh, z);
-      hess_apply<DIM, T>(m, hc, z, o);
-    }
-    project_q_node<DIM, T>(q, aloc, invh, w, o, r);
-  }
-}
-
 template <int DIM, int MODE, typename T>
 __global__ __launch_bounds__(kBlock) void k_node_gather(int N, T h, MatP<double> md, const uint8_t* __restrict__ dir,
                                                         const T* __restrict__ x, const T* __restrict__ p,

@@ -8,6 +8,8 @@
 // vector operation runs in the HIP kernels; the host only makes the scalar
 // trust-region decisions, reading the few device scalars each needs.
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <chrono>
@@ -147,6 +149,7 @@ struct Run {
   double f_ref = 1.0;
   int accepted = 0, rejected = 0;
   rmtr_status status = RMTR_OK;
+  bool trace = false;  // per-step log on stderr (RMTR_VERBOSE=2)
 
   const uint8_t* dir(int l) const { return l == c->L ? fdir : nullptr; }
   int dim() const { return c->model.dim; }
@@ -211,8 +214,12 @@ struct Run {
     return h[0] + ((h[1] + h[2]) + 0.5 * h[3]);
   }
 
-  double ratio(double ared, double pred) const {
-    const double tol = prm.guard * fmax(1.0, fabs(f_ref));
+  // TR ratio with a round-off guard: below the resolution of a sum of
+  // per-element energy differences, about eps |f| / sqrt(n_elements), a
+  // step the model predicts to be a decrease is accepted unless it is
+  // measurably uphill.
+  double ratio(double ared, double pred, int l) const {
+    const double tol = prm.guard * fabs(f_ref) / sqrt(double(c->lv[l].nelem));
     if (!isfinite(ared) || !isfinite(pred)) return -INFINITY;
     if (fabs(pred) <= tol) return ared >= -tol ? 1.0 : -INFINITY;
     if (pred <= 0.0) return -INFINITY;
@@ -280,11 +287,19 @@ struct Run {
     HIPCHK(c, launch_dot(v.n, v.s, v.hs, c->partials, c->scal + 5, st));
     if ((r = h_diff_enqueue(l, x, v.s, 0)) != RMTR_OK) return r;
     if ((r = fetch(6, true)) != RMTR_OK) return r;
-    if (*c->hflag == 0) return RMTR_OK;
+    if (*c->hflag == 0) {
+      if (trace) fprintf(stderr, "rmtr:   tr l=%d s=0\n", l);
+      return RMTR_OK;
+    }
     const double pred = -(c->hs[4] + 0.5 * c->hs[5]);
     const double ared = -h_diff_combine(l, 0);
-    const double rho = ratio(ared, pred);
-    if (control(rho, delta)) {
+    const double rho = ratio(ared, pred, l);
+    const double d0 = delta;
+    const bool acc = control(rho, delta);
+    if (trace)
+      fprintf(stderr, "rmtr:   tr l=%d pred %.3e ared %.3e rho %.3e delta %.2e %s\n", l, pred, ared, rho, d0,
+              acc ? "acc" : "rej");
+    if (acc) {
       ++accepted;
       HIPCHK(c, launch_axpy(v.n, 1.0, v.s, x, st));
     } else {
@@ -348,17 +363,133 @@ struct Run {
     if (*c->hflag) {
       const double ared = -h_diff_combine(l, 0);
       const double pred = -h_diff_combine(l - 1, 8);
-      const double rho = ratio(ared, pred);
-      if (control(rho, delta)) HIPCHK(c, launch_axpy(f.n, 1.0, f.s, x, st));
+      const double rho = ratio(ared, pred, l);
+      const double d0 = delta;
+      const bool acc = control(rho, delta);
+      if (trace)
+        fprintf(stderr, "rmtr:   cc l=%d pred %.3e ared %.3e rho %.3e delta %.2e %s\n", l, pred, ared, rho, d0,
+                acc ? "acc" : "rej");
+      if (acc) HIPCHK(c, launch_axpy(f.n, 1.0, f.s, x, st));
+    } else if (trace) {
+      fprintf(stderr, "rmtr:   cc l=%d s=0\n", l);
     }
     return nonlinear_solve(l, x, delta, prm.mu2, false);
   }
 };
 
+// ------------------------------------------------ arithmetic of one element
+// A scalar that counts the floating-point additions, subtractions,
+// multiplications and divisions done on data; operations among constants
+// (material parameters, h, literals) are folded by the compiler and are not
+// counted.  Instantiating the element operators with it gives their exact
+// algorithmic flop count per element.
+struct Cnt {
+  double v = 0.0;
+  bool k = true;  // constant
+  static int64_t ops;
+  Cnt() = default;
+  Cnt(double x) : v(x), k(true) {}
+  static Cnt var(double x) {
+    Cnt c(x);
+    c.k = false;
+    return c;
+  }
+  static Cnt bin(const Cnt& a, const Cnt& b, double r) {
+    Cnt c(r);
+    c.k = a.k && b.k;
+    if (!c.k) ++ops;
+    return c;
+  }
+  friend Cnt operator+(const Cnt& a, const Cnt& b) { return bin(a, b, a.v + b.v); }
+  friend Cnt operator-(const Cnt& a, const Cnt& b) { return bin(a, b, a.v - b.v); }
+  friend Cnt operator*(const Cnt& a, const Cnt& b) { return bin(a, b, a.v * b.v); }
+  friend Cnt operator/(const Cnt& a, const Cnt& b) { return bin(a, b, a.v / b.v); }
+  Cnt operator-() const {
+    Cnt c = *this;
+    c.v = -v;
+    return c;
+  }
+  Cnt& operator+=(const Cnt& b) { return *this = *this + b; }
+  Cnt& operator-=(const Cnt& b) { return *this = *this - b; }
+  Cnt& operator*=(const Cnt& b) { return *this = *this * b; }
+  friend bool operator>(const Cnt& a, const Cnt& b) { return a.v > b.v; }
+  friend bool operator<(const Cnt& a, const Cnt& b) { return a.v < b.v; }
+};
+int64_t Cnt::ops = 0;
+
+template <int DIM>
+MatP<Cnt> cnt_mat() {
+  MatP<Cnt> m;
+  m.lam = 0.57;
+  m.mu = 0.38;
+  m.K = m.lam.v + 2.0 * m.mu.v / 3.0;
+  m.Gc = 1e-3;
+  m.ls = 0.1;
+  m.k = 1e-6;
+  m.split = 1;
+  return m;
+}
+
+template <int DIM>
+int64_t count_kind(int kind) {
+  constexpr int NL = 1 << DIM, NC = DIM + 1;
+  const MatP<Cnt> m = cnt_mat<DIM>();
+  const Cnt invh(20.0), w(1e-4);
+  Cnt X[NL][NC], V[NL][NC], P[NL];
+  for (int a = 0; a < NL; ++a) {
+    P[a] = Cnt::var(1e-3 * (1 + a));
+    for (int k = 0; k < NC; ++k) {
+      X[a][k] = Cnt::var(k == DIM ? 0.1 * a : 1e-3 * (a + k));
+      V[a][k] = Cnt::var(0.3 * (a - k));
+    }
+  }
+  Cnt::ops = 0;
+  if (kind == 4 || (DIM == 2 && (kind == 2 || kind == 3))) {
+    // node-centric visit of one element for one node (PGS pass, 2D kernels)
+    Cnt r[NC];
+    node_contrib<DIM, Cnt>(kind == 2 ? 0 : 1, m, invh, w, X, V, P, 0, r);
+    return Cnt::ops;
+  }
+  Cnt pq[NL], dpq[NL][DIM];
+  elem_pq<DIM, Cnt>(P, invh, pq, dpq);
+  Zq<DIM, Cnt> z[NL];
+  if (kind == 0 || kind == 1) {
+    elem_z<DIM, Cnt>(X, invh, z);
+    Cnt e = 0.0;
+    e.k = false;
+    for (int q = 0; q < NL; ++q) e += density<DIM, Cnt>(m, z[q], pq[q], dpq[q]);
+    if (kind == 1) {
+      for (int a = 0; a < NL; ++a)
+        for (int k = 0; k < NC; ++k) X[a][k] += V[a][k];
+      elem_z<DIM, Cnt>(X, invh, z);
+      Cnt e1 = 0.0;
+      e1.k = false;
+      for (int q = 0; q < NL; ++q) e1 += density<DIM, Cnt>(m, z[q], pq[q], dpq[q]);
+      e = e1 - e;
+    }
+    e = w * e;
+    return Cnt::ops;
+  }
+  if constexpr (DIM == 3) {
+    Cnt r[8][4];
+    if (kind == 2) ElemOp3<0, Cnt>::eval(m, invh, w, X, V, P, r);
+    if (kind == 3) ElemOp3<1, Cnt>::eval(m, invh, w, X, V, P, r);
+    return Cnt::ops;
+  }
+  return -1;
+}
+
 }  // namespace
 
 // ================================================================== C-ABI
 extern "C" {
+
+int64_t rmtr_element_flops(int32_t dim, int32_t kind) {
+  if (kind < 0 || kind > 4) return -1;
+  if (dim == 3) return count_kind<3>(kind);
+  if (dim == 2) return count_kind<2>(kind);
+  return -1;
+}
 
 void rmtr_default_params(rmtr_params* p) {
   if (!p) return;
@@ -638,6 +769,10 @@ rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lo
   rmtr_stats out{};
   out.chi0 = out.chi = chi0;
   int vc = 0;
+  const char* vb = getenv("RMTR_VERBOSE");
+  const bool verbose = vb && vb[0] && vb[0] != '0';
+  run.trace = vb && vb[0] == '2';
+  if (verbose) fprintf(stderr, "rmtr: chi0 %.6e f %.6e\n", chi0, run.f_ref);
   if (chi0 > 0.0 && isfinite(chi0)) {
     for (vc = 0; vc < prm->max_vcycles;) {
       // lagged Hessian of this V-cycle: linearisation point x0 = x
@@ -657,6 +792,11 @@ rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lo
       if ((r = run.fetch(1, false)) != RMTR_OK) return r;
       out.chi = sqrt(c->hs[0]);
       if (chi_history) chi_history[vc - 1] = out.chi;
+      if (verbose) {
+        fprintf(stderr, "rmtr: vcycle %d chi/chi0 %.3e delta %.3e accepted %d rejected %d\n", vc, out.chi / chi0,
+                delta, run.accepted, run.rejected);
+        fflush(stderr);
+      }
       if (!isfinite(out.chi)) return fail(c, RMTR_E_NONFINITE, "rmtr_solve_loadstep: non-finite iterate");
       if (out.chi <= prm->rtol * chi0) break;
     }

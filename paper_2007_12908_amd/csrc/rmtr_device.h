@@ -13,6 +13,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Element-level building blocks are callable from host code as well, so the
+// library can count their arithmetic by instantiating them with a counting
+// scalar type (rmtr_element_flops).
+#define RMTR_FN __host__ __device__ inline
+
 namespace rmtr {
 
 // Two-point Gauss rule on [0, 1]: xi = (1 -+ 1/sqrt(3)) / 2.
@@ -66,7 +71,7 @@ struct Zq {
 };
 
 template <int DIM, typename T>
-__device__ inline void zero(Zq<DIM, T>& z) {
+RMTR_FN void zero(Zq<DIM, T>& z) {
 #pragma unroll
   for (int i = 0; i < DIM; ++i) {
     z.u[i] = T(0);
@@ -85,7 +90,7 @@ struct Split {
 };
 
 template <int DIM, typename T>
-__device__ inline void split_parts(const MatP<T>& m, const T (&G)[DIM][DIM], Split<DIM, T>& s) {
+RMTR_FN void split_parts(const MatP<T>& m, const T (&G)[DIM][DIM], Split<DIM, T>& s) {
   T t = T(0), epsq = T(0);
 #pragma unroll
   for (int i = 0; i < DIM; ++i) t += G[i][i];
@@ -126,7 +131,7 @@ __device__ inline void split_parts(const MatP<T>& m, const T (&G)[DIM][DIM], Spl
 
 // W at a quadrature point.
 template <int DIM, typename T>
-__device__ inline T density(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T (&dp)[DIM]) {
+RMTR_FN T density(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T (&dp)[DIM]) {
   Split<DIM, T> s;
   split_parts<DIM, T>(m, z.G, s);
   T omc = T(1) - z.c;
@@ -145,7 +150,7 @@ __device__ inline T density(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T 
 
 // dW/dz (first variation), written into out.
 template <int DIM, typename T>
-__device__ inline void density_grad(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T (&dp)[DIM],
+RMTR_FN void density_grad(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T (&dp)[DIM],
                                     Zq<DIM, T>& out) {
   Split<DIM, T> s;
   split_parts<DIM, T>(m, z.G, s);
@@ -180,7 +185,7 @@ struct HessCoef {
 };
 
 template <int DIM, typename T>
-__device__ inline void hess_coef(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T (&dp)[DIM],
+RMTR_FN void hess_coef(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T (&dp)[DIM],
                                  HessCoef<DIM, T>& hc) {
   Split<DIM, T> s;
   split_parts<DIM, T>(m, z.G, s);
@@ -210,7 +215,7 @@ __device__ inline void hess_coef(const MatP<T>& m, const Zq<DIM, T>& z, T p, con
 
 // Second variation applied to a direction v (z-vector of v at the point).
 template <int DIM, typename T>
-__device__ inline void hess_apply(const MatP<T>& m, const HessCoef<DIM, T>& hc, const Zq<DIM, T>& v,
+RMTR_FN void hess_apply(const MatP<T>& m, const HessCoef<DIM, T>& hc, const Zq<DIM, T>& v,
                                   Zq<DIM, T>& out) {
   T tv = T(0);
 #pragma unroll
@@ -233,7 +238,7 @@ __device__ inline void hess_apply(const MatP<T>& m, const HessCoef<DIM, T>& hc, 
 // ------------------------------------------------------------------------
 // Plain (not factorised) interpolation for any DIM: z_q = B_q x_e.
 template <int DIM, typename T>
-__device__ inline void interp_q(int q, const T (&X)[1 << DIM][DIM + 1], T invh, Zq<DIM, T>& z) {
+RMTR_FN void interp_q(int q, const T (&X)[1 << DIM][DIM + 1], T invh, Zq<DIM, T>& z) {
   zero<DIM, T>(z);
 #pragma unroll
   for (int a = 0; a < (1 << DIM); ++a) {
@@ -252,7 +257,7 @@ __device__ inline void interp_q(int q, const T (&X)[1 << DIM][DIM + 1], T invh, 
 }
 
 template <int DIM, typename T>
-__device__ inline void interp_scalar_q(int q, const T (&P)[1 << DIM], T invh, T& p, T (&dp)[DIM]) {
+RMTR_FN void interp_scalar_q(int q, const T (&P)[1 << DIM], T invh, T& p, T (&dp)[DIM]) {
   p = T(0);
 #pragma unroll
   for (int j = 0; j < DIM; ++j) dp[j] = T(0);
@@ -266,7 +271,7 @@ __device__ inline void interp_scalar_q(int q, const T (&P)[1 << DIM], T invh, T&
 
 // r_a += w B_{q,a}^T out  for one local node a (all components).
 template <int DIM, typename T>
-__device__ inline void project_q_node(int q, int a, T invh, T w, const Zq<DIM, T>& o, T (&r)[DIM + 1]) {
+RMTR_FN void project_q_node(int q, int a, T invh, T w, const Zq<DIM, T>& o, T (&r)[DIM + 1]) {
   const T n = T(refN<DIM>(q, a));
   T dn[DIM];
 #pragma unroll
@@ -289,7 +294,7 @@ __device__ inline void project_q_node(int q, int a, T invh, T w, const Zq<DIM, T
 // f[a], a = ax + 2 ay + 4 az  ->  value and gradient (unit cell) at the 8
 // points q = qx + 2 qy + 4 qz.
 template <typename T>
-__device__ inline void sf_forward3(const T (&f)[8], T (&val)[8], T (&dx)[8], T (&dy)[8], T (&dz)[8]) {
+RMTR_FN void sf_forward3(const T (&f)[8], T (&val)[8], T (&dx)[8], T (&dy)[8], T (&dz)[8]) {
   const T A0 = T(RMTR_GA), B0 = T(RMTR_GB);  // phi_0(q0), phi_1(q0)
   // stage x: fx[qx][ay][az], gx[ay][az]
   T fx[2][2][2], gx[2][2];
@@ -340,7 +345,7 @@ __device__ inline void sf_forward3(const T (&f)[8], T (&val)[8], T (&dx)[8], T (
 // Transpose of sf_forward3: r[a] += sum_q N_qa cv[q] + dN_qa . (cx, cy, cz)[q]
 // (unit-cell derivatives; scale cx..cz by 1/h beforehand).
 template <typename T>
-__device__ inline void sf_backward3(const T (&cv)[8], const T (&cx)[8], const T (&cy)[8], const T (&cz)[8],
+RMTR_FN void sf_backward3(const T (&cv)[8], const T (&cx)[8], const T (&cy)[8], const T (&cz)[8],
                                     T (&r)[8]) {
   const T A0 = T(RMTR_GA), B0 = T(RMTR_GB);
   T Fxy[2][2][2], Gxy[2][2], Gyx[2][2];
@@ -384,9 +389,149 @@ __device__ inline void sf_backward3(const T (&cv)[8], const T (&cx)[8], const T 
     }
 }
 
+// z-vectors at all 2^DIM points (3D: sum-factorised; 2D: plain).
+template <int DIM, typename T>
+RMTR_FN void elem_z(const T (&X)[1 << DIM][DIM + 1], T invh, Zq<DIM, T> (&z)[1 << DIM]) {
+  if constexpr (DIM == 3) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      T f[8], val[8], dx[8], dy[8], dz[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) f[a] = X[a][k];
+      sf_forward3<T>(f, val, dx, dy, dz);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (k < 3) {
+          z[q].u[k] = val[q];
+          z[q].G[k][0] = dx[q] * invh;
+          z[q].G[k][1] = dy[q] * invh;
+          z[q].G[k][2] = dz[q] * invh;
+        } else {
+          z[q].c = val[q];
+          z[q].dc[0] = dx[q] * invh;
+          z[q].dc[1] = dy[q] * invh;
+          z[q].dc[2] = dz[q] * invh;
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < (1 << DIM); ++q) interp_q<DIM, T>(q, X, invh, z[q]);
+  }
+}
+
+template <int DIM, typename T>
+RMTR_FN void elem_pq(const T (&P)[1 << DIM], T invh, T (&pq)[1 << DIM], T (&dpq)[1 << DIM][DIM]) {
+  if constexpr (DIM == 3) {
+    T dx[8], dy[8], dz[8];
+    sf_forward3<T>(P, pq, dx, dy, dz);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      dpq[q][0] = dx[q] * invh;
+      dpq[q][1] = dy[q] * invh;
+      dpq[q][2] = dz[q] * invh;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < (1 << DIM); ++q) interp_scalar_q<DIM, T>(q, P, invh, pq[q], dpq[q]);
+  }
+}
+
+// r[a][k] = sum_q w B_{q,a}^T o_q for all nodes of the element.
+template <int DIM, typename T>
+RMTR_FN void elem_project(const Zq<DIM, T> (&o)[1 << DIM], T invh, T w, T (&r)[1 << DIM][DIM + 1]) {
+  if constexpr (DIM == 3) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      T cv[8], cx[8], cy[8], cz[8], rr[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (k < 3) {
+          cv[q] = w * o[q].u[k];
+          cx[q] = w * invh * o[q].G[k][0];
+          cy[q] = w * invh * o[q].G[k][1];
+          cz[q] = w * invh * o[q].G[k][2];
+        } else {
+          cv[q] = w * o[q].c;
+          cx[q] = w * invh * o[q].dc[0];
+          cy[q] = w * invh * o[q].dc[1];
+          cz[q] = w * invh * o[q].dc[2];
+        }
+        rr[q] = T(0);
+      }
+      sf_backward3<T>(cv, cx, cy, cz, rr);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) r[a][k] = rr[a];
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < (1 << DIM); ++a)
+#pragma unroll
+      for (int k = 0; k <= DIM; ++k) r[a][k] = T(0);
+#pragma unroll
+    for (int q = 0; q < (1 << DIM); ++q)
+#pragma unroll
+      for (int a = 0; a < (1 << DIM); ++a) project_q_node<DIM, T>(q, a, invh, w, o[q], r[a]);
+  }
+}
+
+// ------------------------------------------------ per-element operators
+// MODE 0: gradient of f at x.  MODE 1: Hessian at xl applied to v.
+template <int MODE, typename T>
+struct ElemOp3 {
+  // computes r[8][4] for one element
+  __host__ __device__ static inline void eval(const MatP<T>& m, T invh, T w, const T (&X)[8][4], const T (&V)[8][4],
+                                     const T (&P)[8], T (&r)[8][4]) {
+    T pq[8], dpq[8][3];
+    elem_pq<3, T>(P, invh, pq, dpq);
+    Zq<3, T> o[8];
+    {
+      Zq<3, T> z[8];
+      elem_z<3, T>(X, invh, z);
+      if (MODE == 0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) density_grad<3, T>(m, z[q], pq[q], dpq[q], o[q]);
+      } else {
+        HessCoef<3, T> hc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) hess_coef<3, T>(m, z[q], pq[q], dpq[q], hc[q]);
+        elem_z<3, T>(V, invh, z);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) hess_apply<3, T>(m, hc[q], z[q], o[q]);
+      }
+    }
+    elem_project<3, T>(o, invh, w, r);
+  }
+};
+
+// Contribution of one element to the rows of its local node aloc:
+// MODE 0 gradient of f at X, MODE 1 Hessian at X applied to V.
+template <int DIM, typename T>
+RMTR_FN void node_contrib(int MODE, const MatP<T>& m, T invh, T w, const T (&X)[1 << DIM][DIM + 1],
+                                    const T (&V)[1 << DIM][DIM + 1], const T (&P)[1 << DIM], int aloc,
+                                    T (&r)[DIM + 1]) {
+#pragma unroll
+  for (int q = 0; q < (1 << DIM); ++q) {
+    Zq<DIM, T> z, o;
+    T pq, dpq[DIM];
+    interp_scalar_q<DIM, T>(q, P, invh, pq, dpq);
+    interp_q<DIM, T>(q, X, invh, z);
+    if (MODE == 0) {
+      density_grad<DIM, T>(m, z, pq, dpq, o);
+    } else {
+      HessCoef<DIM, T> hc;
+      hess_coef<DIM, T>(m, z, pq, dpq, hc);
+      interp_q<DIM, T>(q, V, invh, z);
+      hess_apply<DIM, T>(m, hc, z, o);
+    }
+    project_q_node<DIM, T>(q, aloc, invh, w, o, r);
+  }
+}
+
+
 // Default Dirichlet set: every displacement component on the boundary.
 template <int DIM>
-__device__ inline uint8_t default_mask(const int (&ijk)[DIM], int N) {
+RMTR_FN uint8_t default_mask(const int (&ijk)[DIM], int N) {
   bool b = false;
 #pragma unroll
   for (int i = 0; i < DIM; ++i) b |= (ijk[i] == 0) | (ijk[i] == N);

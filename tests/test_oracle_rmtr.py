@@ -102,7 +102,7 @@ def test_one_level_is_plain_trust_region():
     Lb[d::d + 1] = c0; Ub[d::d + 1] = 1.0
     y = x.copy()
     delta = prm.delta0
-    fref = max(1.0, abs(fem.energy(g, y, p, mat)))
+    fref = abs(fem.energy(g, y, p, mat)) / np.sqrt(g.n_elems)
     for cyc in range(4):
         H = fem.hessian(g, y, p, mat)
         for it in range(prm.coarse_tr_its):
