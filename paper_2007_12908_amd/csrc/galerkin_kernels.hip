@@ -188,6 +188,150 @@ __global__ __launch_bounds__(64) void k_galerkin_matfree(int Nf, double h, MatP<
   }
 }
 
+// ------------------------------- from matrix-free H, fine-quadrature form
+// Because the coarse Q1 space is nested in the fine one, R H I restricted to
+// a coarse element E is E's element matrix integrated with the 2^d x 2^d
+// fine quadrature points of its children, using the second-variation
+// coefficients of the fine level at those points:
+//   K_E[(b,al),(b',be)] = sum_k w_f z_k(b,al)^T d2W_k z_k(b',be),
+// where z_k(b, al) is coarse basis function b in component al evaluated
+// (value and gradient) at fine point k.  Those values are constants
+// (pn[k][b], pd[k][b][j], unit fine cell) passed in `tab`.  Valid when no
+// fine Dirichlet dof feeds a free coarse dof, which holds for the default
+// Dirichlet set (a fine boundary node interpolates only from coarse
+// boundary nodes).
+template <int DIM, int NE>
+__global__ __launch_bounds__(256) void k_galerkin_fineq(int Nf, double h, MatP<double> m,
+                                                        const double* __restrict__ tab,
+                                                        const double* __restrict__ x,
+                                                        const double* __restrict__ p, double* __restrict__ Kc) {
+  constexpr int NL = 1 << DIM, NC = DIM + 1, ND = NL * NC, NK = NL * NL;
+  constexpr int NCOEF = 3 + DIM * DIM + DIM;  // vol, shear, Ccc, S, Pc
+  __shared__ double sT[NK][NL][DIM + 1];      // pd[k][b][0..DIM-1], pn[k][b]
+  __shared__ double sC[NE][NK][NCOEF];
+  const int Nc = Nf / 2;
+  int64_t nce = 1;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) nce *= Nc;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < NK * NL * (DIM + 1); i += 256) (&sT[0][0][0])[i] = tab[i];
+  const double invh = 1.0 / h;
+  // phase 1: coefficients at every fine point of NE coarse elements
+  for (int t = tid; t < NE * NK; t += 256) {
+    const int el = t / NK, k = t % NK, c = k / NL, q = k % NL;
+    const int64_t E = int64_t(blockIdx.x) * NE + el;
+    if (E >= nce) continue;
+    int e[DIM];
+    int64_t r = E;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+      e[i] = 2 * int(r % Nc) + ((c >> i) & 1);
+      r /= Nc;
+    }
+    double X[NL][NC], P[NL];
+#pragma unroll
+    for (int a = 0; a < NL; ++a) {
+      int64_t n = 0, s = 1;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) {
+        n += int64_t(e[i] + ((a >> i) & 1)) * s;
+        s *= (Nf + 1);
+      }
+#pragma unroll
+      for (int kk = 0; kk < NC; ++kk) X[a][kk] = x[NC * n + kk];
+      P[a] = p[n];
+    }
+    Zq<DIM, double> z;
+    double pq, dpq[DIM];
+    interp_scalar_q<DIM, double>(q, P, invh, pq, dpq);
+    interp_q<DIM, double>(q, X, invh, z);
+    HessCoef<DIM, double> hc;
+    hess_coef<DIM, double>(m, z, pq, dpq, hc);
+    double* o = sC[el][k];
+    o[0] = hc.vol;
+    o[1] = hc.shear;
+    o[2] = hc.Ccc;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+      o[3 + DIM * DIM + i] = hc.Pc[i];
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) o[3 + DIM * i + j] = hc.S[i][j];
+    }
+  }
+  __syncthreads();
+  // phase 2: every entry of the NE coarse element matrices
+  double w = 1.0;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) w *= 0.5 * h;
+  const double s2 = w * invh * invh, s1 = w * invh, s0 = w;
+  const double gcl = m.Gc * m.ls;
+  for (int ent = tid; ent < ND * ND; ent += 256) {
+    const int row = ent / ND, col = ent % ND;
+    const int b = row / NC, al = row % NC, bp = col / NC, be = col % NC;
+    double acc[NE];
+#pragma unroll
+    for (int el = 0; el < NE; ++el) acc[el] = 0.0;
+    for (int k = 0; k < NK; ++k) {
+      const double* tb = sT[k][b];
+      const double* tp = sT[k][bp];
+      if (al < DIM && be < DIM) {
+        double dd = 0.0;
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) dd += tb[j] * tp[j];
+        const double tv = s2 * tb[al] * tp[be];
+        const double ts = s2 * ((al == be ? dd : 0.0) + tb[be] * tp[al]);
+#pragma unroll
+        for (int el = 0; el < NE; ++el) acc[el] += sC[el][k][0] * tv + sC[el][k][1] * ts;
+      } else if (al < DIM) {
+        const double nn = s0 * tb[DIM] * tp[DIM];
+#pragma unroll
+        for (int el = 0; el < NE; ++el) {
+          double v = sC[el][k][3 + DIM * DIM + al] * nn;
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) v += sC[el][k][3 + DIM * al + j] * s1 * tb[j] * tp[DIM];
+          acc[el] += v;
+        }
+      } else if (be < DIM) {
+        const double nn = s0 * tb[DIM] * tp[DIM];
+#pragma unroll
+        for (int el = 0; el < NE; ++el) {
+          double v = sC[el][k][3 + DIM * DIM + be] * nn;
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) v += sC[el][k][3 + DIM * be + j] * s1 * tp[j] * tb[DIM];
+          acc[el] += v;
+        }
+      } else {
+        double dd = 0.0;
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) dd += tb[j] * tp[j];
+        const double nn = s0 * tb[DIM] * tp[DIM];
+#pragma unroll
+        for (int el = 0; el < NE; ++el) acc[el] += sC[el][k][2] * nn + gcl * s2 * dd;
+      }
+    }
+#pragma unroll
+    for (int el = 0; el < NE; ++el) {
+      const int64_t E = int64_t(blockIdx.x) * NE + el;
+      if (E >= nce) continue;
+      int Ec[DIM];
+      int64_t r = E;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) {
+        Ec[i] = int(r % Nc);
+        r /= Nc;
+      }
+      int nb[DIM], nbp[DIM];
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) {
+        nb[i] = Ec[i] + ((b >> i) & 1);
+        nbp[i] = Ec[i] + ((bp >> i) & 1);
+      }
+      const bool mk = ((default_mask<DIM>(nb, Nc) >> al) & 1u) || ((default_mask<DIM>(nbp, Nc) >> be) & 1u);
+      Kc[E * (ND * ND) + ent] = mk ? 0.0 : acc[el];
+    }
+  }
+}
+
 // ------------------------------------------------- from element matrices
 template <int DIM>
 __global__ __launch_bounds__(64) void k_galerkin_em(int Nc, const double* __restrict__ Kf,
@@ -456,11 +600,45 @@ int gridn(int64_t work, int block) {
 
 }  // namespace
 
+void galerkin_fineq_table(int dim, std::vector<double>& out) {
+  const int NL = 1 << dim;
+  out.assign(size_t(NL) * NL * NL * (dim + 1), 0.0);
+  for (int c = 0; c < NL; ++c)
+    for (int q = 0; q < NL; ++q)
+      for (int b = 0; b < NL; ++b) {
+        double* o = &out[((size_t(c) * NL + q) * NL + b) * (dim + 1)];
+        for (int a = 0; a < NL; ++a) {
+          double wgt = 1.0;
+          for (int i = 0; i < dim; ++i) {
+            const double t = 0.5 * double(((c >> i) & 1) + ((a >> i) & 1));
+            wgt *= ((b >> i) & 1) ? t : 1.0 - t;
+          }
+          if (wgt == 0.0) continue;
+          for (int j = 0; j < dim; ++j)
+            o[j] += wgt * (dim == 3 ? refdN<3>(q, a, j) : refdN<2>(q, a, j));
+          o[dim] += wgt * (dim == 3 ? refN<3>(q, a) : refN<2>(q, a));
+        }
+      }
+}
+
 hipError_t launch_galerkin_from_matfree(const ElemArgs& fine, const double* xl, const double* p, double* Kc,
-                                        int same_level, const uint8_t* dirc, hipStream_t st) {
+                                        int same_level, const uint8_t* dirc, const double* fineq_tab,
+                                        hipStream_t st) {
   const int Nc = same_level ? fine.N : fine.N / 2;
   int64_t nce = 1;
   for (int i = 0; i < fine.dim; ++i) nce *= Nc;
+  if (!same_level && fine.dir == nullptr && dirc == nullptr && fineq_tab != nullptr) {
+    if (fine.dim == 3) {
+      constexpr int NE = 4;
+      hipLaunchKernelGGL((k_galerkin_fineq<3, NE>), dim3(int((nce + NE - 1) / NE)), dim3(256), 0, st, fine.N,
+                         fine.h, fine.m, fineq_tab, xl, p, Kc);
+    } else {
+      constexpr int NE = 16;
+      hipLaunchKernelGGL((k_galerkin_fineq<2, NE>), dim3(int((nce + NE - 1) / NE)), dim3(256), 0, st, fine.N,
+                         fine.h, fine.m, fineq_tab, xl, p, Kc);
+    }
+    return hipGetLastError();
+  }
   if (fine.dim == 3) {
     const int epb = 64 / 32;
     hipLaunchKernelGGL(k_galerkin_matfree<3>, dim3(int((nce + epb - 1) / epb)), dim3(64), 0, st, fine.N, fine.h,

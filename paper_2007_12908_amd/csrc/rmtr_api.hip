@@ -53,6 +53,7 @@ struct rmtr_ctx {
   double* table = nullptr;
   size_t table_cap = 0;
   double* mprgp_work = nullptr;
+  double* fineq_tab = nullptr;  // coarse basis at fine quadrature points
   std::vector<void*> allocs;
   std::string err;
 };
@@ -106,6 +107,10 @@ rmtr_status ensure_common(rmtr_ctx* c) {
   HIPCHK(c, hipHostMalloc(&h, kScal * sizeof(double) + 64, hipHostMallocDefault));
   c->hs = static_cast<double*>(h);
   c->hflag = reinterpret_cast<int*>(c->hs + kScal);
+  std::vector<double> tab;
+  galerkin_fineq_table(c->model.dim, tab);
+  HIPCHK(c, dalloc(c, &c->fineq_tab, tab.size()));
+  HIPCHK(c, hipMemcpy(c->fineq_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
   return RMTR_OK;
 }
 
@@ -329,7 +334,7 @@ struct Run {
     rmtr_status r = h_grad(l, x, f.g);
     if (r != RMTR_OK) return r;
     if (l == c->L) {
-      HIPCHK(c, launch_galerkin_from_matfree(eargs(c, l, fdir), f.x0, f.p, cc.K, 0, nullptr, st));
+      HIPCHK(c, launch_galerkin_from_matfree(eargs(c, l, fdir), f.x0, f.p, cc.K, 0, nullptr, c->fineq_tab, st));
     } else {
       HIPCHK(c, launch_galerkin_from_em(d, cc.N, f.K, cc.K, nullptr, st));
     }
@@ -668,7 +673,9 @@ rmtr_status rmtr_galerkin(rmtr_ctx* c, int32_t coarse_level, const double* xl, c
     return fail(c, RMTR_E_ARG, "rmtr_galerkin: bad arguments");
   if (coarse_level == c->L - 1) {
     if (!xl || !p) return fail(c, RMTR_E_ARG, "rmtr_galerkin: x_lin and p needed below the finest level");
-    HIPCHK(c, launch_galerkin_from_matfree(eargs(c, c->L, dir), xl, p, Kc, 0, nullptr, S(stream)));
+    rmtr_status r = ensure_common(c);
+    if (r != RMTR_OK) return r;
+    HIPCHK(c, launch_galerkin_from_matfree(eargs(c, c->L, dir), xl, p, Kc, 0, nullptr, c->fineq_tab, S(stream)));
   } else {
     if (!Kf) return fail(c, RMTR_E_ARG, "rmtr_galerkin: K_fine needed");
     HIPCHK(c, launch_galerkin_from_em(c->model.dim, c->lv[coarse_level].N, Kf, Kc, nullptr, S(stream)));
@@ -778,7 +785,7 @@ rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lo
       // lagged Hessian of this V-cycle: linearisation point x0 = x
       HIPCHK(c, hipMemcpyAsync(f.x0, x, f.n * sizeof(double), hipMemcpyDeviceToDevice, st));
       if (L == 1) {
-        HIPCHK(c, launch_galerkin_from_matfree(eargs(c, 1, dir), f.x0, f.p, f.K, 1, dir, st));
+        HIPCHK(c, launch_galerkin_from_matfree(eargs(c, 1, dir), f.x0, f.p, f.K, 1, dir, nullptr, st));
       } else if (mixed) {
         HIPCHK(c, launch_convert(f.n, f.x0, 0, f.xlf, 1, st));
         HIPCHK(c, launch_diag_blocks(eargs(c, L, dir), f.xlf, f.pf, f.Df, 1, st));

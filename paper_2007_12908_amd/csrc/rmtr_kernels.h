@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "rmtr_device.h"
 
 namespace rmtr {
@@ -35,8 +37,12 @@ hipError_t launch_reduce_partials(const double* partials, int n, double* out, hi
 // ---- element-matrix (Galerkin) operators (galerkin_kernels.hip)
 // same_level: element matrices of the level's own Hessian (no coarsening);
 // dirc: Dirichlet mask of the output level (null: default set).
+// fineq_tab: coarse basis values/gradients at the fine quadrature points
+// (galerkin_fineq_table), used on the fast path (default Dirichlet sets).
 hipError_t launch_galerkin_from_matfree(const ElemArgs& fine, const double* xl, const double* p,
-                                        double* Kc, int same_level, const uint8_t* dirc, hipStream_t st);
+                                        double* Kc, int same_level, const uint8_t* dirc,
+                                        const double* fineq_tab, hipStream_t st);
+void galerkin_fineq_table(int dim, std::vector<double>& out);
 hipError_t launch_galerkin_from_em(int dim, int Nc, const double* Kf, double* Kc, const uint8_t* dirc,
                                    hipStream_t st);
 hipError_t launch_em_hessvec(int dim, int N, const void* K, const void* v, void* hv, const uint8_t* dir,
