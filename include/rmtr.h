@@ -155,11 +155,14 @@ rmtr_status rmtr_diag_blocks(rmtr_ctx* ctx, int32_t level, const void* x_lin, co
 /* Symmetric projected Gauss-Seidel (Sec. 3.2.1) on the TR subproblem
    eq. (model_qp) with the Hessian at x_lin:
      min g^T s + 1/2 s^T H s,  lo <= s <= hi;
-   n_sweeps sweeps (forward then backward over the 2^d node colours), starting
-   from s_inout.  D: node diagonal blocks from rmtr_diag_blocks (or NULL: the
-   library computes them).  Arrays in `precision`. */
-rmtr_status rmtr_smooth(rmtr_ctx* ctx, int32_t level, const void* x_lin, const void* p,
-                        const uint8_t* dirichlet, const void* D, const void* g, const void* lo, const void* hi,
+   n_sweeps sweeps (forward then backward over the 2^d node colours; the
+   components of a node in order, then reversed), starting from s_inout.
+   The Hessian at x_lin (FP64 x_lin and p) is first assembled into a block
+   stencil held by the library (Sec. 4.2.2: the diagonal blocks are kept
+   apart); g, lo, hi and s_inout, the stencil and the sweeps are in
+   `precision`. */
+rmtr_status rmtr_smooth(rmtr_ctx* ctx, int32_t level, const double* x_lin, const double* p,
+                        const uint8_t* dirichlet, const void* g, const void* lo, const void* hi,
                         void* s_inout, int32_t n_sweeps, int32_t precision, void* stream);
 
 /* Level transfers (Sec. 3): fine (level fine_level) -> coarse (fine_level-1). */

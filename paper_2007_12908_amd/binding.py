@@ -74,7 +74,7 @@ def load():
             "rmtr_gradient": (I32, [P, I32, P, P, P, P, P]),
             "rmtr_hessvec": (I32, [P, I32, P, P, P, P, P, I32, P]),
             "rmtr_diag_blocks": (I32, [P, I32, P, P, P, P, I32, P]),
-            "rmtr_smooth": (I32, [P, I32, P, P, P, P, P, P, P, P, I32, I32, P]),
+            "rmtr_smooth": (I32, [P, I32, P, P, P, P, P, P, P, I32, I32, P]),
             "rmtr_restrict": (I32, [P, I32, I32, P, P, I32, P]),
             "rmtr_prolong": (I32, [P, I32, P, P, I32, P]),
             "rmtr_galerkin": (I32, [P, I32, P, P, P, P, P, P]),
@@ -206,8 +206,9 @@ class Context:
                                               _prec(x_lin), _stream()), "rmtr_diag_blocks")
         return D
 
-    def smooth(self, level, x_lin, p, g, lo, hi, s, n_sweeps, dirichlet=None, D=None):
-        self._check(self.lib.rmtr_smooth(self.h, level, _ptr(x_lin), _ptr(p), _ptr(dirichlet), _ptr(D), _ptr(g),
+    def smooth(self, level, x_lin, p, g, lo, hi, s, n_sweeps, dirichlet=None):
+        """Symmetric PGS; x_lin and p are FP64, g/lo/hi/s FP64 or FP32."""
+        self._check(self.lib.rmtr_smooth(self.h, level, _ptr(x_lin), _ptr(p), _ptr(dirichlet), _ptr(g),
                                          _ptr(lo), _ptr(hi), _ptr(s), n_sweeps, _prec(s), _stream()),
                     "rmtr_smooth")
         return s

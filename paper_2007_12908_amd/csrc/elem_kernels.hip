@@ -1,6 +1,5 @@
 // Matrix-free element kernels on the Q1 grid: energy, energy difference,
-// gradient, Hessian-vector product, node diagonal blocks and the projected
-// Gauss-Seidel colour pass.  FP64 throughout, with FP32 variants of the
+// gradient, Hessian-vector product and node diagonal blocks.  FP64 throughout, with FP32 variants of the
 // Hessian-based operators for the mixed-precision form.
 #include "rmtr_kernels.h"
 
@@ -380,102 +379,6 @@ __global__ __launch_bounds__(kBlock) void k_diag_blocks(int N, T h, MatP<double>
   }
 }
 
-// One colour pass of projected Gauss-Seidel.  A thread per node of colour
-// `col` computes the rows r = g + H s of its dofs from its 2^DIM elements,
-// then updates the components in order (forward) or reverse order
-// (backward) with the node's diagonal block:
-//   s_k <- clamp(s_k - (r_k + sum_{l updated} D_kl ds_l) / D_kk, lo_k, hi_k).
-// Nodes of one colour share no element, so the pass equals a sequential
-// sweep over them.
-template <typename T>
-__device__ inline T pgs_update(T s, T r, T d, T lo, T hi) {
-  if (d > T(1e-300)) {
-    T t = s - r / d;
-    t = t < lo ? lo : t;
-    t = t > hi ? hi : t;
-    return t;
-  }
-  const T tl = lo - s, th = hi - s;
-  const T ml = r * tl + T(0.5) * d * tl * tl;
-  const T mh = r * th + T(0.5) * d * th * th;
-  return mh < ml ? hi : lo;
-}
-
-template <int DIM, typename T>
-__global__ __launch_bounds__(kBlock) void k_pgs_colour(int N, T h, MatP<double> md, int col, int backward,
-                                                       const uint8_t* __restrict__ dir, const T* __restrict__ x,
-                                                       const T* __restrict__ p, const T* __restrict__ D,
-                                                       const T* __restrict__ g, const T* __restrict__ lo,
-                                                       const T* __restrict__ hi, T* __restrict__ s) {
-  constexpr int NC = DIM + 1;
-  const MatP<T> m = cast_mat<T>(md);
-  const int64_t nside = N + 1;
-  // nodes of this colour: ijk[i] = 2 t_i + bit_i(col)
-  int cnt[DIM];
-  int64_t total = 1;
-#pragma unroll
-  for (int i = 0; i < DIM; ++i) {
-    const int b = (col >> i) & 1;
-    cnt[i] = (N - b) / 2 + 1;
-    total *= cnt[i];
-  }
-  const T invh = T(1) / h;
-  T w = T(1);
-#pragma unroll
-  for (int i = 0; i < DIM; ++i) w *= T(0.5) * h;
-  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
-    int c[DIM];
-    int64_t r_ = t;
-#pragma unroll
-    for (int i = 0; i < DIM; ++i) {
-      c[i] = 2 * int(r_ % cnt[i]) + ((col >> i) & 1);
-      r_ /= cnt[i];
-    }
-    const int64_t n = node_id<DIM>(c, nside);
-    const uint8_t mk = node_mask<DIM>(dir, n, c, N);
-    if (mk == uint8_t((1u << NC) - 1u)) continue;
-    T r[NC];
-#pragma unroll
-    for (int k = 0; k < NC; ++k) r[k] = T(0);
-#pragma unroll
-    for (int a = 0; a < (1 << DIM); ++a) {
-      int e[DIM];
-      bool ok = true;
-#pragma unroll
-      for (int i = 0; i < DIM; ++i) {
-        e[i] = c[i] - ((a >> i) & 1);
-        ok &= (e[i] >= 0) & (e[i] < N);
-      }
-      if (!ok) continue;
-      T X[1 << DIM][DIM + 1], V[1 << DIM][DIM + 1], P[1 << DIM];
-      load_elem<DIM, T, T>(x, e, nside, X);
-      load_elem_scalar<DIM, T, T>(p, e, nside, P);
-      load_elem<DIM, T, T>(s, e, nside, V);
-      mask_elem<DIM, T>(dir, e, N, V);
-      node_contrib<DIM, T>(1, m, invh, w, X, V, P, a, r);
-    }
-    T sn[NC], s0[NC];
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      s0[k] = s[NC * n + k];
-      sn[k] = s0[k];
-      r[k] += g[NC * n + k];
-    }
-    const T* Dn = D + int64_t(NC) * NC * n;
-#pragma unroll
-    for (int kk = 0; kk < NC; ++kk) {
-      const int k = backward ? NC - 1 - kk : kk;
-      if (mk & (1u << k)) continue;
-      T rk = r[k];
-#pragma unroll
-      for (int l = 0; l < NC; ++l) rk += Dn[NC * k + l] * (sn[l] - s0[l]);
-      sn[k] = pgs_update<T>(sn[k], rk, Dn[NC * k + k], lo[NC * n + k], hi[NC * n + k]);
-    }
-#pragma unroll
-    for (int k = 0; k < NC; ++k) s[NC * n + k] = sn[k];
-  }
-}
-
 int grid_for(int64_t work) {
   int64_t b = (work + kBlock - 1) / kBlock;
   if (b < 1) b = 1;
@@ -568,42 +471,6 @@ hipError_t launch_diag_blocks(const ElemArgs& a, const void* xl, const void* p, 
                          (const double*)xl, (const double*)p, (double*)D);
   }
   return hipGetLastError();
-}
-
-template <int DIM, typename T>
-static hipError_t pgs_sweeps(const ElemArgs& a, const T* xl, const T* p, const T* D, const T* g, const T* lo,
-                             const T* hi, T* s, int n_sweeps, hipStream_t st) {
-  constexpr int NCOL = 1 << DIM;
-  for (int it = 0; it < n_sweeps; ++it) {
-    for (int dir = 0; dir < 2; ++dir) {
-      for (int cc = 0; cc < NCOL; ++cc) {
-        const int col = dir ? NCOL - 1 - cc : cc;
-        int64_t cnt = 1;
-        for (int i = 0; i < DIM; ++i) cnt *= (a.N - ((col >> i) & 1)) / 2 + 1;
-        hipLaunchKernelGGL((k_pgs_colour<DIM, T>), dim3(grid_for(cnt)), dim3(kBlock), 0, st, a.N, T(a.h), a.m, col,
-                           dir, a.dir, xl, p, D, g, lo, hi, s);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-      }
-    }
-  }
-  return hipSuccess;
-}
-
-hipError_t launch_pgs_matfree(const ElemArgs& a, const void* xl, const void* p, const void* D, const void* g,
-                              const void* lo, const void* hi, void* s, int n_sweeps, int fp32, hipStream_t st) {
-  if (a.dim == 3) {
-    if (fp32)
-      return pgs_sweeps<3, float>(a, (const float*)xl, (const float*)p, (const float*)D, (const float*)g,
-                                  (const float*)lo, (const float*)hi, (float*)s, n_sweeps, st);
-    return pgs_sweeps<3, double>(a, (const double*)xl, (const double*)p, (const double*)D, (const double*)g,
-                                 (const double*)lo, (const double*)hi, (double*)s, n_sweeps, st);
-  }
-  if (fp32)
-    return pgs_sweeps<2, float>(a, (const float*)xl, (const float*)p, (const float*)D, (const float*)g,
-                                (const float*)lo, (const float*)hi, (float*)s, n_sweeps, st);
-  return pgs_sweeps<2, double>(a, (const double*)xl, (const double*)p, (const double*)D, (const double*)g,
-                               (const double*)lo, (const double*)hi, (double*)s, n_sweeps, st);
 }
 
 }  // namespace rmtr

@@ -474,123 +474,6 @@ __global__ __launch_bounds__(256) void k_em_hessvec(int N, const T* __restrict__
   }
 }
 
-template <int DIM, typename T>
-__global__ __launch_bounds__(256) void k_em_diag(int N, const T* __restrict__ K, T* __restrict__ D) {
-  constexpr int NL = 1 << DIM, NC = DIM + 1, ND = NL * NC;
-  const int64_t nside = N + 1;
-  int64_t nn = 1;
-#pragma unroll
-  for (int i = 0; i < DIM; ++i) nn *= nside;
-  for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < nn; n += int64_t(gridDim.x) * blockDim.x) {
-    int c[DIM];
-    int64_t r_ = n;
-#pragma unroll
-    for (int i = 0; i < DIM; ++i) {
-      c[i] = int(r_ % nside);
-      r_ /= nside;
-    }
-    T blk[NC * NC];
-#pragma unroll
-    for (int i = 0; i < NC * NC; ++i) blk[i] = T(0);
-    for (int a = 0; a < NL; ++a) {
-      int e[DIM];
-      bool ok = true;
-#pragma unroll
-      for (int i = 0; i < DIM; ++i) {
-        e[i] = c[i] - ((a >> i) & 1);
-        ok &= (e[i] >= 0) & (e[i] < N);
-      }
-      if (!ok) continue;
-      int64_t eid = 0, s = 1;
-#pragma unroll
-      for (int i = 0; i < DIM; ++i) {
-        eid += int64_t(e[i]) * s;
-        s *= N;
-      }
-      const T* Ke = K + eid * (ND * ND);
-#pragma unroll
-      for (int k = 0; k < NC; ++k)
-#pragma unroll
-        for (int l = 0; l < NC; ++l) blk[NC * k + l] += Ke[(NC * a + k) * ND + NC * a + l];
-    }
-#pragma unroll
-    for (int i = 0; i < NC * NC; ++i) D[int64_t(NC * NC) * n + i] = blk[i];
-  }
-}
-
-template <typename T>
-__device__ inline T pgs_update_em(T s, T r, T d, T lo, T hi) {
-  if (d > T(1e-300)) {
-    T t = s - r / d;
-    t = t < lo ? lo : t;
-    t = t > hi ? hi : t;
-    return t;
-  }
-  const T tl = lo - s, th = hi - s;
-  const T ml = r * tl + T(0.5) * d * tl * tl;
-  const T mh = r * th + T(0.5) * d * th * th;
-  return mh < ml ? hi : lo;
-}
-
-template <int DIM, typename T>
-__global__ __launch_bounds__(256) void k_em_pgs_colour(int N, int col, int backward, const T* __restrict__ K,
-                                                       const T* __restrict__ D, const uint8_t* __restrict__ dir,
-                                                       const T* __restrict__ g, const T* __restrict__ lo,
-                                                       const T* __restrict__ hi, T* __restrict__ s) {
-  constexpr int NC = DIM + 1;
-  const int64_t nside = N + 1;
-  int cnt[DIM];
-  int64_t total = 1;
-#pragma unroll
-  for (int i = 0; i < DIM; ++i) {
-    cnt[i] = (N - ((col >> i) & 1)) / 2 + 1;
-    total *= cnt[i];
-  }
-  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
-    int c[DIM];
-    int64_t r_ = t;
-#pragma unroll
-    for (int i = 0; i < DIM; ++i) {
-      c[i] = 2 * int(r_ % cnt[i]) + ((col >> i) & 1);
-      r_ /= cnt[i];
-    }
-    int64_t n = 0, st = 1;
-#pragma unroll
-    for (int i = 0; i < DIM; ++i) {
-      n += int64_t(c[i]) * st;
-      st *= nside;
-    }
-    const uint8_t mk = dir ? dir[n] : default_mask<DIM>(c, N);
-    if (mk == uint8_t((1u << NC) - 1u)) continue;
-    T r[NC];
-    em_rows<DIM, T>(N, K, s, c, r);
-    T sn[NC], s0[NC];
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      s0[k] = s[NC * n + k];
-      sn[k] = s0[k];
-      r[k] += g[NC * n + k];
-    }
-    const T* Dn = D + int64_t(NC) * NC * n;
-#pragma unroll
-    for (int kk = 0; kk < NC; ++kk) {
-      const int k = backward ? NC - 1 - kk : kk;
-      if (mk & (1u << k)) continue;
-      T rk = r[k];
-#pragma unroll
-      for (int l = 0; l < NC; ++l) rk += Dn[NC * k + l] * (sn[l] - s0[l]);
-      sn[k] = pgs_update_em<T>(sn[k], rk, Dn[NC * k + k], lo[NC * n + k], hi[NC * n + k]);
-    }
-#pragma unroll
-    for (int k = 0; k < NC; ++k) s[NC * n + k] = sn[k];
-  }
-}
-
-__global__ void k_to_fp32(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-    b[i] = float(a[i]);
-}
-
 int gridn(int64_t work, int block) {
   int64_t b = (work + block - 1) / block;
   if (b < 1) b = 1;
@@ -683,63 +566,6 @@ hipError_t launch_em_hessvec(int dim, int N, const void* K, const void* v, void*
       hipLaunchKernelGGL((k_em_hessvec<2, double>), g, dim3(256), 0, st, N, (const double*)K, (const double*)v,
                          (double*)hv);
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_em_diag(int dim, int N, const void* K, void* D, int fp32, hipStream_t st) {
-  int64_t nn = 1;
-  for (int i = 0; i < dim; ++i) nn *= (N + 1);
-  dim3 g(gridn(nn, 256));
-  if (dim == 3) {
-    if (fp32)
-      hipLaunchKernelGGL((k_em_diag<3, float>), g, dim3(256), 0, st, N, (const float*)K, (float*)D);
-    else
-      hipLaunchKernelGGL((k_em_diag<3, double>), g, dim3(256), 0, st, N, (const double*)K, (double*)D);
-  } else {
-    if (fp32)
-      hipLaunchKernelGGL((k_em_diag<2, float>), g, dim3(256), 0, st, N, (const float*)K, (float*)D);
-    else
-      hipLaunchKernelGGL((k_em_diag<2, double>), g, dim3(256), 0, st, N, (const double*)K, (double*)D);
-  }
-  return hipGetLastError();
-}
-
-template <int DIM, typename T>
-static hipError_t em_pgs(int N, const T* K, const T* D, const uint8_t* dir, const T* g, const T* lo, const T* hi,
-                         T* s, int n_sweeps, hipStream_t st) {
-  constexpr int NCOL = 1 << DIM;
-  for (int it = 0; it < n_sweeps; ++it)
-    for (int bw = 0; bw < 2; ++bw)
-      for (int cc = 0; cc < NCOL; ++cc) {
-        const int col = bw ? NCOL - 1 - cc : cc;
-        int64_t cnt = 1;
-        for (int i = 0; i < DIM; ++i) cnt *= (N - ((col >> i) & 1)) / 2 + 1;
-        hipLaunchKernelGGL((k_em_pgs_colour<DIM, T>), dim3(gridn(cnt, 256)), dim3(256), 0, st, N, col, bw, K, D, dir,
-                           g, lo, hi, s);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-      }
-  return hipSuccess;
-}
-
-hipError_t launch_em_pgs(int dim, int N, const void* K, const void* D, const uint8_t* dir, const void* g,
-                         const void* lo, const void* hi, void* s, int n_sweeps, int fp32, hipStream_t st) {
-  if (dim == 3) {
-    if (fp32)
-      return em_pgs<3, float>(N, (const float*)K, (const float*)D, dir, (const float*)g, (const float*)lo,
-                              (const float*)hi, (float*)s, n_sweeps, st);
-    return em_pgs<3, double>(N, (const double*)K, (const double*)D, dir, (const double*)g, (const double*)lo,
-                             (const double*)hi, (double*)s, n_sweeps, st);
-  }
-  if (fp32)
-    return em_pgs<2, float>(N, (const float*)K, (const float*)D, dir, (const float*)g, (const float*)lo,
-                            (const float*)hi, (float*)s, n_sweeps, st);
-  return em_pgs<2, double>(N, (const double*)K, (const double*)D, dir, (const double*)g, (const double*)lo,
-                           (const double*)hi, (double*)s, n_sweeps, st);
-}
-
-hipError_t launch_em_to_fp32(int64_t n, const double* src, float* dst, hipStream_t st) {
-  hipLaunchKernelGGL(k_to_fp32, dim3(gridn(n, 256)), dim3(256), 0, st, n, src, dst);
   return hipGetLastError();
 }
 

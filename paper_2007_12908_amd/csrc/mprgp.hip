@@ -2,8 +2,8 @@
 // for the coarsest-level trust-region subproblem (Sec. 3.2.1):
 //     min 1/2 s^T A s - b^T s,  lo <= s <= hi,   A = coarse Hessian, b = -g.
 // The level's element matrices are first assembled into a 3^d-point block
-// stencil (one row of (d+1) x 3^d x (d+1) values per node row), so every
-// matrix-vector product is a row-parallel pass over contiguous rows.  The
+// stencil (stencil_kernels.hip), so every matrix-vector product is a
+// row-parallel pass over contiguous rows.  The
 // host drives the iteration; every reduction is a fixed-order two-stage tree,
 // so the scalars (and the branch taken) do not depend on scheduling.
 #include <math.h>
@@ -62,127 +62,6 @@ __global__ __launch_bounds__(kB) void k_final(const double* __restrict__ partial
     v[kNV - 1] = fmin(v[kNV - 1], partials[kNV * i + kNV - 1]);
   }
   bred(v, sh, out);
-}
-
-// ---------------------------------------------------------------- stencil
-// S[((n NC + al) NO + o) NC + be]: assembled entry between row (n, al) and
-// column (n + off(o), be); off(o) = (o%3 - 1, (o/3)%3 - 1, o/9 - 1).
-template <int DIM>
-__global__ __launch_bounds__(kB) void k_em_to_stencil(int N, const double* __restrict__ K, double* __restrict__ S) {
-  constexpr int NL = 1 << DIM, NC = DIM + 1, ND = NL * NC, NO = n_off<DIM>();
-  const int64_t ns = N + 1;
-  int64_t nn = 1;
-#pragma unroll
-  for (int i = 0; i < DIM; ++i) nn *= ns;
-  for (int64_t row = int64_t(blockIdx.x) * kB + threadIdx.x; row < nn * NC; row += int64_t(gridDim.x) * kB) {
-    const int64_t n = row / NC;
-    const int al = int(row % NC);
-    int c[DIM];
-    int64_t r = n;
-#pragma unroll
-    for (int i = 0; i < DIM; ++i) {
-      c[i] = int(r % ns);
-      r /= ns;
-    }
-    double* out = S + row * (NO * NC);
-    for (int o = 0; o < NO; ++o) {
-      int m[DIM];
-      bool ok = true;
-      int oo = o;
-#pragma unroll
-      for (int i = 0; i < DIM; ++i) {
-        m[i] = c[i] + oo % 3 - 1;
-        oo /= 3;
-        ok &= (m[i] >= 0) & (m[i] <= N);
-      }
-      for (int be = 0; be < NC; ++be) {
-        double entry = 0.0;
-        if (ok) {
-          for (int a = 0; a < NL; ++a) {
-            int e[DIM];
-            bool eok = true;
-            int b = 0;
-#pragma unroll
-            for (int i = 0; i < DIM; ++i) {
-              e[i] = c[i] - ((a >> i) & 1);
-              eok &= (e[i] >= 0) & (e[i] < N);
-              const int bi = m[i] - e[i];
-              eok &= (bi == 0) | (bi == 1);
-              b |= (bi & 1) << i;
-            }
-            if (!eok) continue;
-            int64_t eid = 0, st = 1;
-#pragma unroll
-            for (int i = 0; i < DIM; ++i) {
-              eid += int64_t(e[i]) * st;
-              st *= N;
-            }
-            entry += K[eid * ND * ND + (NC * a + al) * ND + NC * b + be];
-          }
-        }
-        out[o * NC + be] = entry;
-      }
-    }
-  }
-}
-
-template <int DIM>
-__global__ __launch_bounds__(kB) void k_st_matvec(int N, const double* __restrict__ S, const double* __restrict__ v,
-                                                  double* __restrict__ y) {
-  constexpr int NC = DIM + 1, NO = n_off<DIM>();
-  const int64_t ns = N + 1;
-  int64_t nn = 1;
-#pragma unroll
-  for (int i = 0; i < DIM; ++i) nn *= ns;
-  for (int64_t row = int64_t(blockIdx.x) * kB + threadIdx.x; row < nn * NC; row += int64_t(gridDim.x) * kB) {
-    const int64_t n = row / NC;
-    int c[DIM];
-    int64_t r = n;
-#pragma unroll
-    for (int i = 0; i < DIM; ++i) {
-      c[i] = int(r % ns);
-      r /= ns;
-    }
-    const double* srow = S + row * (NO * NC);
-    double acc = 0.0;
-#pragma unroll
-    for (int o = 0; o < NO; ++o) {
-      int64_t m = 0, st = 1;
-      bool ok = true;
-      int oo = o;
-#pragma unroll
-      for (int i = 0; i < DIM; ++i) {
-        const int mi = c[i] + oo % 3 - 1;
-        oo /= 3;
-        ok &= (mi >= 0) & (mi <= N);
-        m += int64_t(mi) * st;
-        st *= ns;
-      }
-      if (!ok) continue;
-#pragma unroll
-      for (int be = 0; be < NC; ++be) acc += srow[o * NC + be] * v[NC * m + be];
-    }
-    y[row] = acc;
-  }
-}
-
-// Gershgorin bound of ||A|| (max row sum of |A|, as -min in the last slot)
-// and g^T g in slot 0.
-template <int DIM>
-__global__ __launch_bounds__(kB) void k_rowabs(int64_t nrows, const double* __restrict__ S,
-                                               const double* __restrict__ g, double* __restrict__ partials) {
-  constexpr int NC = DIM + 1, NO = n_off<DIM>();
-  __shared__ double sh[kNV][kB];
-  double v[kNV];
-  vinit(v);
-  for (int64_t row = int64_t(blockIdx.x) * kB + threadIdx.x; row < nrows; row += int64_t(gridDim.x) * kB) {
-    const double* srow = S + row * (NO * NC);
-    double rs = 0.0;
-    for (int j = 0; j < NO * NC; ++j) rs += fabs(srow[j]);
-    v[kNV - 1] = fmin(v[kNV - 1], -rs);
-    v[0] += g[row] * g[row];
-  }
-  bred(v, sh, partials + kNV * blockIdx.x);
 }
 
 __device__ inline bool is_free(double s, double lo, double hi) { return s > lo && s < hi; }
@@ -313,7 +192,7 @@ size_t mprgp_work_doubles(int dim, int N) {
   for (int i = 0; i < dim; ++i) nn *= (N + 1);
   const int64_t n = nn * (dim + 1);
   const int64_t st = dim == 3 ? stencil_doubles<3>(N) : stencil_doubles<2>(N);
-  return size_t(5 * n + n * (dim + 1) + st + kNV * 1024 + 2 * kNV + 16);
+  return size_t(5 * n + st + kNV * 1024 + 2 * kNV + 16);
 }
 
 hipError_t run_mprgp(int dim, int N, const double* K, const uint8_t* dir, const double* g, const double* lo,
@@ -327,8 +206,7 @@ hipError_t run_mprgp(int dim, int N, const double* K, const uint8_t* dir, const 
   double* beta = phi + n;
   double* p = beta + n;
   double* Ad = p + n;
-  double* D = Ad + n;  // node diagonal blocks for the fallback sweeps: n * (dim+1) doubles
-  double* S = D + n * (dim + 1);
+  double* S = Ad + n;  // assembled stencil of K
   double* part = S + (dim == 3 ? stencil_doubles<3>(N) : stencil_doubles<2>(N));
   double* red = part + kNV * 1024;
   const int nb = nblocks(n);
@@ -346,33 +224,20 @@ hipError_t run_mprgp(int dim, int N, const double* K, const uint8_t* dir, const 
     CK(hipMemcpyAsync(hs, red, kNV * sizeof(double), hipMemcpyDeviceToHost, st));   \
     CK(hipStreamSynchronize(st));                                                   \
   } while (0)
-#define MATVEC(v, out)                                                                    \
-  do {                                                                                    \
-    if (dim == 3)                                                                         \
-      hipLaunchKernelGGL(k_st_matvec<3>, dim3(nblocks(n)), tb, 0, st, N, S, v, out);     \
-    else                                                                                  \
-      hipLaunchKernelGGL(k_st_matvec<2>, dim3(nblocks(n)), tb, 0, st, N, S, v, out);     \
-    CK(hipGetLastError());                                                                \
-  } while (0)
+#define MATVEC(v, out) CK(launch_st_matvec(dim, N, S, v, out, 0, st))
   res->iterations = 0;
   res->status = 1;
   CK(launch_fill(n, 0.0, s, st));
   // assembled stencil, ||A|| bound and ||b||
+  CK(launch_em_to_st(dim, N, K, S, 0, st));
   {
-    int64_t gbk = (n + kB - 1) / kB;
-    if (gbk > 262140) gbk = 262140;
-    if (dim == 3)
-      hipLaunchKernelGGL(k_em_to_stencil<3>, dim3(int(gbk)), tb, 0, st, N, K, S);
-    else
-      hipLaunchKernelGGL(k_em_to_stencil<2>, dim3(int(gbk)), tb, 0, st, N, K, S);
+    int nbr = 0;
+    CK(launch_st_rowabs(dim, N, S, g, part, &nbr, st));
+    hipLaunchKernelGGL(k_final, dim3(1), tb, 0, st, part, nbr, red);
     CK(hipGetLastError());
+    CK(hipMemcpyAsync(hs, red, kNV * sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
   }
-  if (dim == 3)
-    hipLaunchKernelGGL(k_rowabs<3>, gb, tb, 0, st, n, S, g, part);
-  else
-    hipLaunchKernelGGL(k_rowabs<2>, gb, tb, 0, st, n, S, g, part);
-  CK(hipGetLastError());
-  FETCH();
   const double normA = -hs[kNV - 1];
   const double bnorm = sqrt(hs[0]);
   if (!(normA > 0.0)) {
@@ -446,8 +311,7 @@ hipError_t run_mprgp(int dim, int N, const double* K, const uint8_t* dir, const 
   res->iterations = it;
   if (negcurv) {
     res->status = 2;
-    CK(launch_em_diag(dim, N, K, D, 0, st));
-    CK(launch_em_pgs(dim, N, K, D, dir, g, lo, hi, s, fallback_sweeps, 0, st));
+    CK(launch_st_pgs(dim, N, S, dir, g, lo, hi, s, fallback_sweeps, 0, st));
   } else if (it >= max_it && res->status != 0) {
     res->status = 1;
   }

@@ -33,8 +33,12 @@ struct Level {
   double *t1 = nullptr, *t2 = nullptr, *t3 = nullptr, *t4 = nullptr;
   double *p = nullptr, *K = nullptr, *D = nullptr;
   float *xlf = nullptr, *pf = nullptr, *Df = nullptr, *gf = nullptr, *lof = nullptr, *hif = nullptr, *sf = nullptr;
-  double* Dsmooth = nullptr;  // diagonal blocks for rmtr_smooth / rmtr_em_smooth calls without D
-  float* Dsmoothf = nullptr;
+  double* S = nullptr;      // lagged Hessian as a block stencil (FP64)
+  float* Sf = nullptr;      // the same in FP32 (finest level, mixed precision)
+  double* coef = nullptr;   // per-element second-variation coefficients (finest level)
+  double* Sop = nullptr;    // stencil scratch of rmtr_smooth / rmtr_em_smooth
+  float* Sopf = nullptr;
+  double* coefop = nullptr;
   bool solver_ready = false;
 };
 
@@ -124,21 +128,23 @@ rmtr_status ensure_solver_level(rmtr_ctx* c, int l, bool mixed) {
                        &v.t1, &v.t2, &v.t3, &v.t4};
     for (double** b : vecs) HIPCHK(c, dalloc(c, b, n));
     HIPCHK(c, dalloc(c, &v.p, size_t(v.nodes)));
-    const int nc = c->model.dim + 1;
-    HIPCHK(c, dalloc(c, &v.D, size_t(v.nodes) * nc * nc));
     if (l < c->L || c->L == 1) {
       const size_t nd = size_t(ndof_elem(c->model.dim));
       HIPCHK(c, dalloc(c, &v.K, size_t(v.nelem) * nd * nd));
     }
+    if (l == c->L && c->L > 1) HIPCHK(c, dalloc(c, &v.coef, coef_values(c->model.dim, v.N)));
     v.solver_ready = true;
   }
+  // stencil of the lagged Hessian: FP32 on the finest level in mixed mode
+  const bool want_f32 = mixed && l == c->L && c->L > 1;
+  if (want_f32 && !v.Sf) HIPCHK(c, dalloc(c, &v.Sf, stencil_values(c->model.dim, v.N)));
+  if (!want_f32 && !v.S && !(l == c->L && c->L == 1))
+    HIPCHK(c, dalloc(c, &v.S, stencil_values(c->model.dim, v.N)));
   if (mixed && l == c->L && !v.xlf) {
     const size_t n = size_t(v.n);
-    const int nc = c->model.dim + 1;
     float** fv[] = {&v.xlf, &v.gf, &v.lof, &v.hif, &v.sf};
     for (float** b : fv) HIPCHK(c, dalloc(c, b, n));
     HIPCHK(c, dalloc(c, &v.pf, size_t(v.nodes)));
-    HIPCHK(c, dalloc(c, &v.Df, size_t(v.nodes) * nc * nc));
   }
   return RMTR_OK;
 }
@@ -176,7 +182,7 @@ struct Run {
       return RMTR_OK;
     }
     HIPCHK(c, launch_add_scaled(v.n, x, 1.0, v.x0, -1.0, nullptr, v.t1, st));
-    HIPCHK(c, launch_em_hessvec(dim(), v.N, v.K, v.t1, v.t2, nullptr, 0, st));
+    HIPCHK(c, launch_st_matvec(dim(), v.N, v.S, v.t1, v.t2, 0, st));
     HIPCHK(c, launch_add_scaled(v.n, v.dg, 1.0, v.t2, 1.0, nullptr, out, st));
     if (energy_model) {
       HIPCHK(c, launch_gradient(eargs(c, l, nullptr), x, v.p, v.t3, st));
@@ -200,8 +206,8 @@ struct Run {
     if (l == c->L) return RMTR_OK;
     HIPCHK(c, launch_dot(v.n, v.dg, s, c->partials, sc + 1, st));
     HIPCHK(c, launch_add_scaled(v.n, x, 1.0, v.x0, -1.0, nullptr, v.t1, st));
-    HIPCHK(c, launch_em_hessvec(dim(), v.N, v.K, v.t1, v.t2, nullptr, 0, st));
-    HIPCHK(c, launch_em_hessvec(dim(), v.N, v.K, s, v.t3, nullptr, 0, st));
+    HIPCHK(c, launch_st_matvec(dim(), v.N, v.S, v.t1, v.t2, 0, st));
+    HIPCHK(c, launch_st_matvec(dim(), v.N, v.S, s, v.t3, 0, st));
     if (energy_model) {
       HIPCHK(c, launch_hessvec(eargs(c, l, nullptr), v.x0, v.p, v.t1, v.t4, 0, st));
       HIPCHK(c, launch_add_scaled(v.n, v.t4, -1.0, nullptr, 0.0, v.t2, v.t2, st));
@@ -243,33 +249,26 @@ struct Run {
   // QP of one TR step on level l into v.s
   rmtr_status solve_qp(int l, bool coarsest) {
     Level& v = c->lv[l];
-    const int nc = dim() + 1;
     if (coarsest) {
       MprgpResult res;
       HIPCHK(c, run_mprgp(dim(), v.N, v.K, dir(l), v.g, v.lo, v.hi, v.s, prm.coarse_qp_its, prm.coarse_qp_rtol,
                           prm.fallback_sweeps, c->mprgp_work, c->hs + 48, &res, st));
       return RMTR_OK;
     }
-    if (l == c->L) {
-      if (mixed) {
-        HIPCHK(c, launch_convert(v.n, v.g, 0, v.gf, 1, st));
-        HIPCHK(c, launch_convert(v.n, v.lo, 0, v.lof, 1, st));
-        HIPCHK(c, launch_convert(v.n, v.hi, 0, v.hif, 1, st));
-        HIPCHK(c, hipMemsetAsync(v.sf, 0, size_t(v.n) * sizeof(float), st));
-        HIPCHK(c, launch_pgs_matfree(eargs(c, l, fdir), v.xlf, v.pf, v.Df, v.gf, v.lof, v.hif, v.sf, prm.pgs_sweeps,
-                                     1, st));
-        HIPCHK(c, launch_convert(v.n, v.sf, 1, v.s, 0, st));
-        HIPCHK(c, launch_clamp(v.n, v.lo, v.hi, v.s, st));
-      } else {
-        HIPCHK(c, launch_fill(v.n, 0.0, v.s, st));
-        HIPCHK(c, launch_pgs_matfree(eargs(c, l, fdir), v.x0, v.p, v.D, v.g, v.lo, v.hi, v.s, prm.pgs_sweeps, 0,
-                                     st));
-      }
+    if (l == c->L && mixed) {
+      // mixed precision: FP32 sweeps on the FP32 stencil, step clamped back
+      // into the FP64 box
+      HIPCHK(c, launch_convert(v.n, v.g, 0, v.gf, 1, st));
+      HIPCHK(c, launch_convert(v.n, v.lo, 0, v.lof, 1, st));
+      HIPCHK(c, launch_convert(v.n, v.hi, 0, v.hif, 1, st));
+      HIPCHK(c, hipMemsetAsync(v.sf, 0, size_t(v.n) * sizeof(float), st));
+      HIPCHK(c, launch_st_pgs(dim(), v.N, v.Sf, fdir, v.gf, v.lof, v.hif, v.sf, prm.pgs_sweeps, 1, st));
+      HIPCHK(c, launch_convert(v.n, v.sf, 1, v.s, 0, st));
+      HIPCHK(c, launch_clamp(v.n, v.lo, v.hi, v.s, st));
       return RMTR_OK;
     }
-    (void)nc;
     HIPCHK(c, launch_fill(v.n, 0.0, v.s, st));
-    HIPCHK(c, launch_em_pgs(dim(), v.N, v.K, v.D, nullptr, v.g, v.lo, v.hi, v.s, prm.pgs_sweeps, 0, st));
+    HIPCHK(c, launch_st_pgs(dim(), v.N, v.S, dir(l), v.g, v.lo, v.hi, v.s, prm.pgs_sweeps, 0, st));
     return RMTR_OK;
   }
 
@@ -285,6 +284,8 @@ struct Run {
     // model Hessian times s: lagged matrix-free on the finest level (FP64)
     if (l == c->L && !(c->L == 1)) {
       HIPCHK(c, launch_hessvec(eargs(c, l, fdir), v.x0, v.p, v.s, v.hs, 0, st));
+    } else if (v.S) {
+      HIPCHK(c, launch_st_matvec(dim(), v.N, v.S, v.s, v.hs, 0, st));
     } else {
       HIPCHK(c, launch_em_hessvec(dim(), v.N, v.K, v.s, v.hs, nullptr, 0, st));
     }
@@ -344,7 +345,7 @@ struct Run {
       HIPCHK(c, launch_add_scaled(cc.n, cc.t3, -1.0, nullptr, 0.0, cc.dg, cc.dg, st));
     }
     HIPCHK(c, launch_zero_masked(d, cc.N, cc.dg, nullptr, st));
-    if (l - 1 > 1) HIPCHK(c, launch_em_diag(d, cc.N, cc.K, cc.D, 0, st));
+    HIPCHK(c, launch_em_to_st(d, cc.N, cc.K, cc.S, 0, st));
     return RMTR_OK;
   }
 
@@ -628,25 +629,24 @@ rmtr_status rmtr_diag_blocks(rmtr_ctx* c, int32_t level, const void* xl, const v
   return RMTR_OK;
 }
 
-rmtr_status rmtr_smooth(rmtr_ctx* c, int32_t level, const void* xl, const void* p, const uint8_t* dir, const void* D,
+rmtr_status rmtr_smooth(rmtr_ctx* c, int32_t level, const double* xl, const double* p, const uint8_t* dir,
                         const void* g, const void* lo, const void* hi, void* s, int32_t n_sweeps, int32_t precision,
                         void* stream) {
   if (!valid_level(c, level) || !xl || !p || !g || !lo || !hi || !s || n_sweeps < 0)
     return fail(c, RMTR_E_ARG, "rmtr_smooth: bad arguments");
   const bool f32 = precision == RMTR_FP32;
   Level& v = c->lv[level];
-  const int nc = c->model.dim + 1;
-  if (!D) {
-    if (f32) {
-      if (!v.Dsmoothf) HIPCHK(c, dalloc(c, &v.Dsmoothf, size_t(v.nodes) * nc * nc));
-      D = v.Dsmoothf;
-    } else {
-      if (!v.Dsmooth) HIPCHK(c, dalloc(c, &v.Dsmooth, size_t(v.nodes) * nc * nc));
-      D = v.Dsmooth;
-    }
-    HIPCHK(c, launch_diag_blocks(eargs(c, level, dir), xl, p, const_cast<void*>(D), f32, S(stream)));
+  if (!v.coefop) HIPCHK(c, dalloc(c, &v.coefop, coef_values(c->model.dim, v.N)));
+  void* Sm = nullptr;
+  if (f32) {
+    if (!v.Sopf) HIPCHK(c, dalloc(c, &v.Sopf, stencil_values(c->model.dim, v.N)));
+    Sm = v.Sopf;
+  } else {
+    if (!v.Sop) HIPCHK(c, dalloc(c, &v.Sop, stencil_values(c->model.dim, v.N)));
+    Sm = v.Sop;
   }
-  HIPCHK(c, launch_pgs_matfree(eargs(c, level, dir), xl, p, D, g, lo, hi, s, n_sweeps, f32, S(stream)));
+  HIPCHK(c, launch_st_assemble(eargs(c, level, dir), xl, p, v.coefop, Sm, f32, S(stream)));
+  HIPCHK(c, launch_st_pgs(c->model.dim, v.N, Sm, dir, g, lo, hi, s, n_sweeps, f32, S(stream)));
   return RMTR_OK;
 }
 
@@ -694,10 +694,9 @@ rmtr_status rmtr_em_smooth(rmtr_ctx* c, int32_t level, const double* K, const do
   if (!valid_level(c, level) || !K || !g || !lo || !hi || !s || n_sweeps < 0)
     return fail(c, RMTR_E_ARG, "rmtr_em_smooth: bad arguments");
   Level& v = c->lv[level];
-  const int nc = c->model.dim + 1;
-  if (!v.Dsmooth) HIPCHK(c, dalloc(c, &v.Dsmooth, size_t(v.nodes) * nc * nc));
-  HIPCHK(c, launch_em_diag(c->model.dim, v.N, K, v.Dsmooth, 0, S(stream)));
-  HIPCHK(c, launch_em_pgs(c->model.dim, v.N, K, v.Dsmooth, nullptr, g, lo, hi, s, n_sweeps, 0, S(stream)));
+  if (!v.Sop) HIPCHK(c, dalloc(c, &v.Sop, stencil_values(c->model.dim, v.N)));
+  HIPCHK(c, launch_em_to_st(c->model.dim, v.N, K, v.Sop, 0, S(stream)));
+  HIPCHK(c, launch_st_pgs(c->model.dim, v.N, v.Sop, nullptr, g, lo, hi, s, n_sweeps, 0, S(stream)));
   return RMTR_OK;
 }
 
@@ -787,10 +786,9 @@ rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lo
       if (L == 1) {
         HIPCHK(c, launch_galerkin_from_matfree(eargs(c, 1, dir), f.x0, f.p, f.K, 1, dir, nullptr, st));
       } else if (mixed) {
-        HIPCHK(c, launch_convert(f.n, f.x0, 0, f.xlf, 1, st));
-        HIPCHK(c, launch_diag_blocks(eargs(c, L, dir), f.xlf, f.pf, f.Df, 1, st));
+        HIPCHK(c, launch_st_assemble(eargs(c, L, dir), f.x0, f.p, f.coef, f.Sf, 1, st));
       } else {
-        HIPCHK(c, launch_diag_blocks(eargs(c, L, dir), f.x0, f.p, f.D, 0, st));
+        HIPCHK(c, launch_st_assemble(eargs(c, L, dir), f.x0, f.p, f.coef, f.S, 0, st));
       }
       if ((r = run.vcycle(L, x, delta)) != RMTR_OK) return r;
       ++vc;

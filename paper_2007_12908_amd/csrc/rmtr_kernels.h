@@ -29,9 +29,6 @@ hipError_t launch_hessvec(const ElemArgs& a, const void* xl, const void* p, cons
                           int fp32, hipStream_t st);
 hipError_t launch_diag_blocks(const ElemArgs& a, const void* xl, const void* p, void* D, int fp32,
                               hipStream_t st);
-hipError_t launch_pgs_matfree(const ElemArgs& a, const void* xl, const void* p, const void* D, const void* g,
-                              const void* lo, const void* hi, void* s, int n_sweeps, int fp32,
-                              hipStream_t st);
 hipError_t launch_reduce_partials(const double* partials, int n, double* out, hipStream_t st);
 
 // ---- element-matrix (Galerkin) operators (galerkin_kernels.hip)
@@ -47,10 +44,22 @@ hipError_t launch_galerkin_from_em(int dim, int Nc, const double* Kf, double* Kc
                                    hipStream_t st);
 hipError_t launch_em_hessvec(int dim, int N, const void* K, const void* v, void* hv, const uint8_t* dir,
                              int fp32, hipStream_t st);
-hipError_t launch_em_diag(int dim, int N, const void* K, void* D, int fp32, hipStream_t st);
-hipError_t launch_em_pgs(int dim, int N, const void* K, const void* D, const uint8_t* dir, const void* g,
-                         const void* lo, const void* hi, void* s, int n_sweeps, int fp32, hipStream_t st);
-hipError_t launch_em_to_fp32(int64_t n, const double* src, float* dst, hipStream_t st);
+
+// ---- assembled block stencils (stencil_kernels.hip)
+size_t stencil_values(int dim, int N);
+size_t coef_values(int dim, int N);
+// lagged Hessian at xl (FP64 arithmetic) -> stencil S (double, or float if fp32);
+// coef: scratch of coef_values doubles
+hipError_t launch_st_assemble(const ElemArgs& a, const double* xl, const double* p, double* coef, void* S,
+                              int fp32, hipStream_t st);
+hipError_t launch_em_to_st(int dim, int N, const double* K, void* S, int fp32, hipStream_t st);
+hipError_t launch_st_matvec(int dim, int N, const void* S, const void* v, void* y, int fp32, hipStream_t st);
+hipError_t launch_st_pgs(int dim, int N, const void* S, const uint8_t* dir, const void* g, const void* lo,
+                         const void* hi, void* s, int n_sweeps, int fp32, hipStream_t st);
+// Gershgorin row sums of |S| (as -min in slot 4) and g^T g (slot 0): five
+// partial values per block, block count returned in nblocks_out (<= 1024)
+hipError_t launch_st_rowabs(int dim, int N, const double* S, const double* gv, double* partials, int* nblocks_out,
+                            hipStream_t st);
 
 // ---- transfers (transfer_kernels.hip)
 hipError_t launch_prolong(int dim, int Nc, const void* xc, void* xf, int fp32, hipStream_t st);

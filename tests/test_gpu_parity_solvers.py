@@ -133,3 +133,27 @@ def test_dot_and_chi():
     cl = x[d::d + 1] * rng.uniform(0, 1, g.n_nodes)
     chi = float(host(ctx.chi(1, dev(x), dev(gr), dev(cl)))[0])
     assert chi == pytest.approx(fem.chi(g, x, gr, cl), rel=1e-13)
+
+
+@pytest.mark.parametrize("d,N", [(2, 16), (3, 17)])
+def test_pgs_fp32_mixed(d, N):
+    """FP32 stencil and sweeps (mixed form) vs the FP64 oracle: 3 sweeps of
+    single-precision Gauss-Seidel agree to 1e-4 relative; bounds exact."""
+    import torch
+    g, x, p = rand_state(d, N, seed=77 + N, u_scale=1e-4, c_max=0.6)
+    mat = material(N)
+    rng = np.random.default_rng(N + 1)
+    gv = rng.standard_normal(g.n_dofs) * 1e-4
+    gv[g.default_dirichlet()] = 0.0
+    lo, hi = _box(g, x, 2e-3, rng)
+    lo32 = lo.astype(np.float32).astype(np.float64)
+    hi32 = hi.astype(np.float32).astype(np.float64)
+    H = fem.hessian(g, x, p, mat)
+    blocks = qp.colour_blocks(g.node_colour(), g.nc, 2 ** d)
+    so = qp.pgs(H, gv, lo32, hi32, np.zeros(g.n_dofs), blocks, 3, ~g.default_dirichlet())
+    ctx = ctx_for(d, N, 1, mat)
+    s = torch.zeros(g.n_dofs, dtype=torch.float32, device="cuda")
+    ctx.smooth(1, dev(x), dev(p), dev(gv, torch.float32), dev(lo, torch.float32), dev(hi, torch.float32), s, 3)
+    sh = host(s).astype(np.float64)
+    assert np.all(sh >= lo32) and np.all(sh <= hi32)
+    assert field_rel_err(sh, so, d) <= 1e-4
