@@ -78,6 +78,14 @@ typedef struct {
 } rmtr_model;
 
 /* Solver constants (Alg. 1-3, Sec. 3.2.1, Sec. 4.2.1). */
+/* A trained proposal network (see the learned-proposal section below);
+   every pointer is device memory owned by the caller. */
+typedef struct {
+  const uint16_t* w;    /* RMTR_NN_WEIGHTS BF16 weights, layer by layer      */
+  const float* bias;    /* RMTR_NN_BIASES FP32 biases, layer by layer        */
+  const float* scales;  /* 12 FP32: input scales (x: 4, g: 4), output (4)   */
+} rmtr_nn;
+
 typedef struct {
   double eta1, eta2;       /* 0 < eta1 <= eta2 <= 1 (Alg. 3)            */
   double gamma1, gamma2;   /* 0 < gamma1 <= 1 <= gamma2 (Alg. 3)        */
@@ -95,17 +103,21 @@ typedef struct {
   int32_t max_vcycles;
   int32_t precision;       /* RMTR_FP64 or RMTR_FP32 (fine Hv + PGS)    */
   int32_t coarse_model;    /* 0: f~ = f on the coarse grid, 1: f~ = 0   */
+  int32_t use_learned;     /* 1: learned proposal before the first finest-level
+                              pre-smoothing step of each V-cycle (3D; needs nn) */
+  const rmtr_nn* nn;       /* host pointer, read during the call         */
 } rmtr_params;
 
 typedef struct {
   int32_t vcycles, tr_accepted, tr_rejected, status;
   double chi0, chi, energy, seconds;
+  int32_t nn_proposed, nn_accepted; /* learned proposals made / accepted */
 } rmtr_stats;
 
 /* Fills p with the defaults used throughout: eta = (0.1, 0.75),
    gamma = (0.5, 2), delta0 = 1, delta_max = 10, rtol = 1e-8, mu1 = mu2 = 1,
    3 PGS sweeps, 5 coarse TR steps, MPRGP 500 its / 1e-10, 50 fallback sweeps,
-   200 V-cycles, FP64, f~ = f. */
+   200 V-cycles, FP64, f~ = f, no learned proposal. */
 void rmtr_default_params(rmtr_params* p);
 
 /* Create a context for the hierarchy of `model`.  Returns RMTR_E_ARG on an
@@ -202,13 +214,88 @@ rmtr_status rmtr_chi(rmtr_ctx* ctx, int32_t level, const double* x, const double
 
 /* One load step (Sec. 4.1 workflow step 7b): RMTR V-cycles (Alg. 1-3 with
    Hessian lagging, Sec. 4.2.1) from x_inout until chi <= rtol chi(x_in) or
-   max_vcycles.  p: fine nodal pressure; c_lower: c^{t-1} per fine node;
+   max_vcycles.  With params->use_learned, each V-cycle first tries the
+   learned proposal on the finest level: it is projected onto the step box,
+   judged by the FP64 ratio of eq. (rho_tr) against the lagged model, and
+   taken in place of the first PGS pre-smoothing step if rho > eta1 and its
+   predicted decrease is at least that of the Cauchy step (the model
+   minimiser along -g, projected onto the box); otherwise the PGS step runs.  A rejected proposal leaves delta unchanged.  p: fine nodal pressure; c_lower: c^{t-1} per fine node;
    x_inout must be feasible.  chi_history (host, may be NULL) receives chi
    after each V-cycle (max_vcycles entries).  Returns RMTR_OK,
    RMTR_NOT_CONVERGED (x still feasible) or an error.  Synchronises. */
 rmtr_status rmtr_solve_loadstep(rmtr_ctx* ctx, const double* p, const double* c_lower, const uint8_t* dirichlet,
                                 const rmtr_params* params, double* x_inout, rmtr_stats* stats,
                                 double* chi_history, void* stream);
+
+/* Trust-region step box of Alg. 3 on the finest level (Sec. 3, the
+   constraints of eq. (model_qp)): lo = max(-delta, L - x), hi = min(delta,
+   U - x) with L = (-inf, c_lower) and U = (+inf, 1) per node (u, c); zero at
+   Dirichlet dofs.  level must be the finest level. */
+rmtr_status rmtr_step_box(rmtr_ctx* ctx, int32_t level, const double* x, const double* c_lower, double delta,
+                          const uint8_t* dirichlet, double* lo, double* hi, void* stream);
+
+/* ------------------------------------------------------------------------
+   Learned proposal (not part of the paper's method: a learned form of the
+   finest-level smoother, gated by the unchanged trust-region ratio test of
+   eq. (rho_tr), a Cauchy sufficient-decrease check and the bound
+   projection, with the PGS smoother of Sec. 3.2.1 as fallback).
+
+   Network: six 3x3x3 convolutions with zero padding on the node grid,
+   channels 8 -> 32 -> 32 -> 32 -> 32 -> 32 -> 4, ReLU after the first five:
+     y[v][co] = b[co] + sum_k sum_ci W[k][ci][co] x[v + off(k)][ci],
+   off(k) = (k%3 - 1, (k/3)%3 - 1, k/9 - 1) in (x, y, z).  Tensors are
+   channels-last FP32 on nx*ny*nz voxels, voxel v = i + nx (j + ny k).
+   Weights are BF16 (round-to-nearest-even of FP32 masters), [27][Cin][Cout]
+   per layer, layers concatenated; FP32 arithmetic.
+   Input channels: (u, c) of x times scales[0..3], then g times
+   scales[4..7]; output channel k times scales[8+k] is the proposed step of
+   component k (3D only). */
+#define RMTR_NN_WEIGHTS 120960
+#define RMTR_NN_BIASES 164
+
+/* Sizes in floats: what 0 = weights, 1 = biases, 2 = activation buffer of
+   rmtr_nn_forward (all 7 layer tensors: 172 floats per voxel), 3 = work
+   buffer of rmtr_nn_backward.  -1 on a bad argument. */
+int64_t rmtr_nn_size(int32_t what, int32_t nx, int32_t ny, int32_t nz);
+
+/* Forward pass.  act: rmtr_nn_size(2) floats; its first 8 nx ny nz floats
+   are the input (caller-filled); the layer outputs follow in order, the
+   4-channel result last (offset 168 nx ny nz). */
+rmtr_status rmtr_nn_forward(rmtr_ctx* ctx, const uint16_t* w, const float* bias, float* act, int32_t nx,
+                            int32_t ny, int32_t nz, void* stream);
+
+/* Backward pass of L(result) given dL/d(result) = dout (4 floats per voxel)
+   on the activations of a forward pass: grad (RMTR_NN_WEIGHTS +
+   RMTR_NN_BIASES floats) receives dL/dW then dL/db, summed over voxels in a
+   fixed order (deterministic).  work: rmtr_nn_size(3) floats. */
+rmtr_status rmtr_nn_backward(rmtr_ctx* ctx, const uint16_t* w, const float* act, const float* dout, float* grad,
+                             float* work, int32_t nx, int32_t ny, int32_t nz, void* stream);
+
+/* Mean squared error over the window [window[0], window[1]) x [window[2],
+   window[3]) x [window[4], window[5]) (host int32, voxel indices in x, y, z)
+   and the 4 channels: loss (one device double) and dout = dL/d(out). */
+rmtr_status rmtr_nn_mse(rmtr_ctx* ctx, const float* out, const float* target, const int32_t* window, float* dout,
+                        double* loss, int32_t nx, int32_t ny, int32_t nz, void* stream);
+
+/* One Adam step (Kingma and Ba, beta = (0.9, 0.999), eps = 1e-8, bias
+   correction with step number t >= 1) on n FP32 masters; the first n_bf16
+   of them are also written to w_bf16 (may be NULL). */
+rmtr_status rmtr_nn_adam_step(rmtr_ctx* ctx, int64_t n, int64_t n_bf16, float lr, int32_t t, const float* grad,
+                              float* master, float* m, float* v, uint16_t* w_bf16, void* stream);
+
+/* w_bf16[i] = round-to-nearest-even BF16 of master[i], i < n. */
+rmtr_status rmtr_nn_to_bf16(rmtr_ctx* ctx, int64_t n, const float* master, uint16_t* w_bf16, void* stream);
+
+/* Network input from a state of `level`: in8[8 n + k] = x[4 n + k] *
+   scales[k] (k < 4), g[4 n + k - 4] * scales[k] (k >= 4). */
+rmtr_status rmtr_nn_features(rmtr_ctx* ctx, int32_t level, const double* x, const double* g, const float* scales,
+                             float* in8, void* stream);
+
+/* Proposed step of `level` (3D): features of (x, g), forward pass, output
+   scaled and projected onto [lo, hi] (non-finite values become 0 before the
+   projection); s: FP64, (d+1) per node. */
+rmtr_status rmtr_nn_propose(rmtr_ctx* ctx, int32_t level, const rmtr_nn* net, const double* x, const double* g,
+                            const double* lo, const double* hi, double* s, void* stream);
 
 /* Floating-point additions, subtractions, multiplications and divisions that
    the library's element operators perform on data for ONE element (the

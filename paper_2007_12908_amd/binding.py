@@ -24,8 +24,18 @@ EXPORTS = [
     "rmtr_init_fields", "rmtr_energy", "rmtr_energy_diff", "rmtr_gradient", "rmtr_hessvec",
     "rmtr_diag_blocks", "rmtr_smooth", "rmtr_restrict", "rmtr_prolong", "rmtr_galerkin",
     "rmtr_em_hessvec", "rmtr_em_smooth", "rmtr_mprgp", "rmtr_dot", "rmtr_chi", "rmtr_solve_loadstep",
-    "rmtr_element_flops",
+    "rmtr_step_box", "rmtr_nn_size", "rmtr_nn_forward", "rmtr_nn_backward", "rmtr_nn_mse", "rmtr_nn_adam_step",
+    "rmtr_nn_to_bf16", "rmtr_nn_features", "rmtr_nn_propose", "rmtr_element_flops",
 ]
+
+NN_WEIGHTS = 120960
+NN_BIASES = 164
+NN_CHANNELS = (8, 32, 32, 32, 32, 32, 4)
+
+
+class Net(ctypes.Structure):
+    """rmtr_nn: device pointers of a trained proposal network."""
+    _fields_ = [("w", ctypes.c_void_p), ("bias", ctypes.c_void_p), ("scales", ctypes.c_void_p)]
 
 
 class Model(ctypes.Structure):
@@ -41,14 +51,16 @@ class Params(ctypes.Structure):
                 ("mu1", ctypes.c_int32), ("mu2", ctypes.c_int32), ("pgs_sweeps", ctypes.c_int32),
                 ("coarse_tr_its", ctypes.c_int32), ("coarse_qp_its", ctypes.c_int32),
                 ("fallback_sweeps", ctypes.c_int32), ("max_vcycles", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("coarse_model", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("coarse_model", ctypes.c_int32),
+                ("use_learned", ctypes.c_int32), ("nn", ctypes.POINTER(Net))]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("vcycles", ctypes.c_int32), ("tr_accepted", ctypes.c_int32),
                 ("tr_rejected", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("chi0", ctypes.c_double), ("chi", ctypes.c_double), ("energy", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("nn_proposed", ctypes.c_int32),
+                ("nn_accepted", ctypes.c_int32)]
 
 
 _lib = None
@@ -87,6 +99,15 @@ def load():
             "rmtr_solve_loadstep": (I32, [P, P, P, P, ctypes.POINTER(Params), P, ctypes.POINTER(Stats),
                                           P, P]),
             "rmtr_element_flops": (I64, [I32, I32]),
+            "rmtr_step_box": (I32, [P, I32, P, P, D, P, P, P, P]),
+            "rmtr_nn_size": (I64, [I32, I32, I32, I32]),
+            "rmtr_nn_forward": (I32, [P, P, P, P, I32, I32, I32, P]),
+            "rmtr_nn_backward": (I32, [P, P, P, P, P, P, I32, I32, I32, P]),
+            "rmtr_nn_mse": (I32, [P, P, P, P, P, P, I32, I32, I32, P]),
+            "rmtr_nn_adam_step": (I32, [P, I64, I64, ctypes.c_float, I32, P, P, P, P, P, P]),
+            "rmtr_nn_to_bf16": (I32, [P, I64, P, P, P]),
+            "rmtr_nn_features": (I32, [P, I32, P, P, P, P, P]),
+            "rmtr_nn_propose": (I32, [P, I32, ctypes.POINTER(Net), P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -266,6 +287,56 @@ class Context:
         out = torch.empty(1, dtype=torch.float64, device=x.device)
         self._check(self.lib.rmtr_chi(self.h, level, _ptr(x), _ptr(g), _ptr(c_lower), _ptr(dirichlet), _ptr(out),
                                       _stream()), "rmtr_chi")
+        return out
+
+    def step_box(self, level, x, c_lower, delta, dirichlet=None):
+        lo, hi = torch.empty_like(x), torch.empty_like(x)
+        self._check(self.lib.rmtr_step_box(self.h, level, _ptr(x), _ptr(c_lower), delta, _ptr(dirichlet), _ptr(lo),
+                                           _ptr(hi), _stream()), "rmtr_step_box")
+        return lo, hi
+
+    # -- learned proposal network
+    def nn_size(self, what, nx, ny, nz):
+        return int(self.lib.rmtr_nn_size(what, nx, ny, nz))
+
+    def nn_forward(self, w, bias, act, box):
+        nx, ny, nz = box
+        self._check(self.lib.rmtr_nn_forward(self.h, _ptr(w), _ptr(bias), _ptr(act), nx, ny, nz, _stream()),
+                    "rmtr_nn_forward")
+        return act
+
+    def nn_backward(self, w, act, dout, grad, work, box):
+        nx, ny, nz = box
+        self._check(self.lib.rmtr_nn_backward(self.h, _ptr(w), _ptr(act), _ptr(dout), _ptr(grad), _ptr(work), nx,
+                                              ny, nz, _stream()), "rmtr_nn_backward")
+        return grad
+
+    def nn_mse(self, out, target, window, dout, loss, box):
+        nx, ny, nz = box
+        win = (ctypes.c_int32 * 6)(*[int(v) for v in window])
+        self._check(self.lib.rmtr_nn_mse(self.h, _ptr(out), _ptr(target), win, _ptr(dout), _ptr(loss), nx, ny, nz,
+                                         _stream()), "rmtr_nn_mse")
+        return loss
+
+    def nn_adam_step(self, lr, t, grad, master, m, v, w_bf16=None, n_bf16=0):
+        self._check(self.lib.rmtr_nn_adam_step(self.h, master.numel(), n_bf16, lr, t, _ptr(grad), _ptr(master),
+                                               _ptr(m), _ptr(v), _ptr(w_bf16), _stream()), "rmtr_nn_adam_step")
+
+    def nn_to_bf16(self, master, w_bf16):
+        self._check(self.lib.rmtr_nn_to_bf16(self.h, w_bf16.numel(), _ptr(master), _ptr(w_bf16), _stream()),
+                    "rmtr_nn_to_bf16")
+        return w_bf16
+
+    def nn_features(self, level, x, g, scales, out=None):
+        out = torch.empty(self.level_nodes(level) * 8, dtype=torch.float32, device=x.device) if out is None else out
+        self._check(self.lib.rmtr_nn_features(self.h, level, _ptr(x), _ptr(g), _ptr(scales), _ptr(out), _stream()),
+                    "rmtr_nn_features")
+        return out
+
+    def nn_propose(self, level, net, x, g, lo, hi, out=None):
+        out = torch.empty_like(x) if out is None else out
+        self._check(self.lib.rmtr_nn_propose(self.h, level, ctypes.byref(net), _ptr(x), _ptr(g), _ptr(lo), _ptr(hi),
+                                             _ptr(out), _stream()), "rmtr_nn_propose")
         return out
 
     # -- load step

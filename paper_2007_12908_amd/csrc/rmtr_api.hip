@@ -58,6 +58,10 @@ struct rmtr_ctx {
   size_t table_cap = 0;
   double* mprgp_work = nullptr;
   double* fineq_tab = nullptr;  // coarse basis at fine quadrature points
+  double* box_tmp = nullptr;    // bounds scratch of rmtr_step_box
+  size_t box_cap = 0;
+  float* nn_buf = nullptr;      // inference tensors of the proposal network
+  size_t nn_cap = 0;
   std::vector<void*> allocs;
   std::string err;
 };
@@ -149,6 +153,41 @@ rmtr_status ensure_solver_level(rmtr_ctx* c, int l, bool mixed) {
   return RMTR_OK;
 }
 
+// grows a context-owned buffer, freeing the previous one
+template <typename T>
+hipError_t grow(rmtr_ctx* c, T** buf, size_t* cap, size_t count) {
+  if (*cap >= count) return hipSuccess;
+  if (*buf) {
+    for (auto& a : c->allocs)
+      if (a == *buf) a = nullptr;
+    hipError_t e = hipFree(*buf);
+    if (e != hipSuccess) return e;
+    *buf = nullptr;
+    *cap = 0;
+  }
+  hipError_t e = dalloc(c, buf, count);
+  if (e == hipSuccess) *cap = count;
+  return e;
+}
+
+// learned proposal on a 3D level: features, ping-pong forward pass, output
+// scaled and projected onto [lo, hi]
+rmtr_status nn_propose(rmtr_ctx* c, int l, const rmtr_nn& net, const double* x, const double* g, const double* lo,
+                       const double* hi, double* s, hipStream_t st) {
+  Level& v = c->lv[l];
+  const int64_t nvox = v.nodes;
+  HIPCHK(c, grow(c, &c->nn_buf, &c->nn_cap, size_t(nvox) * (8 + 32 + 32 + 4)));
+  float* in = c->nn_buf;
+  float* A = in + nvox * 8;
+  float* B = A + nvox * 32;
+  float* out = B + nvox * 32;
+  float* const layer[7] = {in, A, B, A, B, A, out};
+  HIPCHK(c, nn_features(nvox, x, g, net.scales, in, st));
+  HIPCHK(c, nn_forward(net.w, net.bias, layer, v.N + 1, v.N + 1, v.N + 1, st));
+  HIPCHK(c, nn_proposal(v.n, out, net.scales, lo, hi, s, st));
+  return RMTR_OK;
+}
+
 // ------------------------------------------------------------ the solver
 struct Run {
   rmtr_ctx* c;
@@ -159,6 +198,7 @@ struct Run {
   bool energy_model;
   double f_ref = 1.0;
   int accepted = 0, rejected = 0;
+  int nn_proposed = 0, nn_accepted = 0;
   rmtr_status status = RMTR_OK;
   bool trace = false;  // per-step log on stderr (RMTR_VERBOSE=2)
 
@@ -314,6 +354,56 @@ struct Run {
     return RMTR_OK;
   }
 
+  // learned proposal on the finest level, judged like a TR step on the
+  // lagged model: taken if the ratio test accepts it and its predicted
+  // decrease is at least that of the Cauchy step (the model minimiser along
+  // -g, projected onto the step box).  A rejection leaves delta unchanged.
+  rmtr_status nn_step(double* x, double delta, bool& taken) {
+    taken = false;
+    const int L = c->L;
+    Level& v = c->lv[L];
+    rmtr_status r;
+    if ((r = h_grad(L, x, v.g)) != RMTR_OK) return r;
+    HIPCHK(c, launch_step_box(dim(), v.N, x, v.Lb, v.Ub, delta, fdir, v.lo, v.hi, st));
+    // Cauchy step s_c = P(-t g), t = g^T g / g^T H g (or the box edge)
+    HIPCHK(c, launch_hessvec(eargs(c, L, fdir), v.x0, v.p, v.g, v.t1, 0, st));
+    HIPCHK(c, launch_dot(v.n, v.g, v.g, c->partials, c->scal + 6, st));
+    HIPCHK(c, launch_dot(v.n, v.g, v.t1, c->partials, c->scal + 7, st));
+    if ((r = fetch(8, false)) != RMTR_OK) return r;
+    const double gg = c->hs[6], gHg = c->hs[7];
+    if (!(gg > 0.0) || !isfinite(gg) || !isfinite(gHg)) return RMTR_OK;
+    const double t = gHg > 0.0 ? gg / gHg : 1e300;
+    HIPCHK(c, launch_add_scaled(v.n, v.g, -t, nullptr, 0.0, nullptr, v.t2, st));
+    HIPCHK(c, launch_clamp(v.n, v.lo, v.hi, v.t2, st));
+    HIPCHK(c, launch_hessvec(eargs(c, L, fdir), v.x0, v.p, v.t2, v.t3, 0, st));
+    HIPCHK(c, launch_dot(v.n, v.g, v.t2, c->partials, c->scal + 6, st));
+    HIPCHK(c, launch_dot(v.n, v.t2, v.t3, c->partials, c->scal + 7, st));
+    // the proposal
+    if ((r = nn_propose(c, L, *prm.nn, x, v.g, v.lo, v.hi, v.s, st)) != RMTR_OK) return r;
+    ++nn_proposed;
+    HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), st));
+    HIPCHK(c, launch_any_nonzero(v.n, v.s, c->flag, st));
+    HIPCHK(c, launch_hessvec(eargs(c, L, fdir), v.x0, v.p, v.s, v.hs, 0, st));
+    HIPCHK(c, launch_dot(v.n, v.g, v.s, c->partials, c->scal + 4, st));
+    HIPCHK(c, launch_dot(v.n, v.s, v.hs, c->partials, c->scal + 5, st));
+    if ((r = h_diff_enqueue(L, x, v.s, 0)) != RMTR_OK) return r;
+    if ((r = fetch(8, true)) != RMTR_OK) return r;
+    if (*c->hflag == 0) return RMTR_OK;
+    const double pred = -(c->hs[4] + 0.5 * c->hs[5]);
+    const double pred_c = -(c->hs[6] + 0.5 * c->hs[7]);
+    const double ared = -h_diff_combine(L, 0);
+    const double rho = ratio(ared, pred, L);
+    taken = rho > prm.eta1 && pred >= pred_c;
+    if (trace)
+      fprintf(stderr, "rmtr:   nn l=%d pred %.3e cauchy %.3e ared %.3e rho %.3e %s\n", L, pred, pred_c, ared, rho,
+              taken ? "acc" : "rej");
+    if (taken) {
+      ++nn_accepted;
+      HIPCHK(c, launch_axpy(v.n, 1.0, v.s, x, st));
+    }
+    return RMTR_OK;
+  }
+
   rmtr_status nonlinear_solve(int l, double* x, double& delta, int its, bool coarsest) {
     for (int i = 0; i < its; ++i) {
       rmtr_status r = tr_step(l, x, delta, coarsest);
@@ -352,7 +442,13 @@ struct Run {
   rmtr_status vcycle(int l, double* x, double& delta) {
     rmtr_status r;
     if (l == 1) return nonlinear_solve(1, x, delta, prm.coarse_tr_its, true);
-    if ((r = nonlinear_solve(l, x, delta, prm.mu1, false)) != RMTR_OK) return r;
+    int pre = prm.mu1;
+    if (l == c->L && prm.use_learned && pre > 0) {
+      bool taken = false;
+      if ((r = nn_step(x, delta, taken)) != RMTR_OK) return r;
+      if (taken) --pre;
+    }
+    if ((r = nonlinear_solve(l, x, delta, pre, false)) != RMTR_OK) return r;
     if ((r = setup_coarse(l, x, delta)) != RMTR_OK) return r;
     Level& f = c->lv[l];
     Level& cc = c->lv[l - 1];
@@ -749,6 +845,9 @@ rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lo
       prm->eta1 > prm->eta2 || !(prm->gamma1 > 0.0) || prm->gamma1 > 1.0 || prm->gamma2 < 1.0 ||
       !(prm->delta0 > 0.0))
     return fail(c, RMTR_E_ARG, "rmtr_solve_loadstep: invalid parameters");
+  if (prm->use_learned &&
+      (c->model.dim != 3 || c->L < 2 || !prm->nn || !prm->nn->w || !prm->nn->bias || !prm->nn->scales))
+    return fail(c, RMTR_E_ARG, "rmtr_solve_loadstep: the learned proposal needs 3D, L >= 2 and a network");
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t st = S(stream);
   rmtr_status r = ensure_common(c);
@@ -798,8 +897,8 @@ rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lo
       out.chi = sqrt(c->hs[0]);
       if (chi_history) chi_history[vc - 1] = out.chi;
       if (verbose) {
-        fprintf(stderr, "rmtr: vcycle %d chi/chi0 %.3e delta %.3e accepted %d rejected %d\n", vc, out.chi / chi0,
-                delta, run.accepted, run.rejected);
+        fprintf(stderr, "rmtr: vcycle %d chi/chi0 %.3e delta %.3e accepted %d rejected %d nn %d/%d\n", vc,
+                out.chi / chi0, delta, run.accepted, run.rejected, run.nn_accepted, run.nn_proposed);
         fflush(stderr);
       }
       if (!isfinite(out.chi)) return fail(c, RMTR_E_NONFINITE, "rmtr_solve_loadstep: non-finite iterate");
@@ -812,10 +911,102 @@ rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lo
   out.vcycles = vc;
   out.tr_accepted = run.accepted;
   out.tr_rejected = run.rejected;
+  out.nn_proposed = run.nn_proposed;
+  out.nn_accepted = run.nn_accepted;
   out.status = (chi0 == 0.0 || out.chi <= prm->rtol * chi0) ? RMTR_OK : RMTR_NOT_CONVERGED;
   out.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (stats) *stats = out;
   return out.status;
+}
+
+
+rmtr_status rmtr_step_box(rmtr_ctx* c, int32_t level, const double* x, const double* cl, double delta,
+                          const uint8_t* dir, double* lo, double* hi, void* stream) {
+  if (!valid_level(c, level) || level != c->L || !x || !cl || !lo || !hi || !(delta >= 0.0))
+    return fail(c, RMTR_E_ARG, "rmtr_step_box: bad arguments");
+  Level& v = c->lv[level];
+  HIPCHK(c, grow(c, &c->box_tmp, &c->box_cap, size_t(2 * v.n)));
+  double* Lb = c->box_tmp;
+  double* Ub = c->box_tmp + v.n;
+  HIPCHK(c, launch_fine_bounds(c->model.dim, v.N, cl, Lb, Ub, S(stream)));
+  HIPCHK(c, launch_step_box(c->model.dim, v.N, x, Lb, Ub, delta, dir, lo, hi, S(stream)));
+  return RMTR_OK;
+}
+
+int64_t rmtr_nn_size(int32_t what, int32_t nx, int32_t ny, int32_t nz) {
+  if (what == 0) return nn_weight_count();
+  if (what == 1) return nn_bias_count();
+  if (nx < 1 || ny < 1 || nz < 1) return -1;
+  const int64_t nvox = int64_t(nx) * ny * nz;
+  if (what == 2) return nn_act_floats(nvox);
+  if (what == 3) return int64_t(nn_backward_work_floats(nvox));
+  return -1;
+}
+
+static bool nn_box_ok(int32_t nx, int32_t ny, int32_t nz) {
+  return nx >= 1 && ny >= 1 && nz >= 1 && int64_t(nx) * ny * nz <= (int64_t(1) << 31) / 32;
+}
+
+rmtr_status rmtr_nn_forward(rmtr_ctx* c, const uint16_t* w, const float* bias, float* act, int32_t nx, int32_t ny,
+                            int32_t nz, void* stream) {
+  if (!c || !w || !bias || !act || !nn_box_ok(nx, ny, nz)) return fail(c, RMTR_E_ARG, "rmtr_nn_forward: bad arguments");
+  float* layer[7];
+  nn_layers(act, int64_t(nx) * ny * nz, layer);
+  HIPCHK(c, nn_forward(w, bias, layer, nx, ny, nz, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_nn_backward(rmtr_ctx* c, const uint16_t* w, const float* act, const float* dout, float* grad,
+                             float* work, int32_t nx, int32_t ny, int32_t nz, void* stream) {
+  if (!c || !w || !act || !dout || !grad || !work || !nn_box_ok(nx, ny, nz))
+    return fail(c, RMTR_E_ARG, "rmtr_nn_backward: bad arguments");
+  HIPCHK(c, nn_backward(w, act, dout, grad, grad + nn_weight_count(), nx, ny, nz, work, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_nn_mse(rmtr_ctx* c, const float* out, const float* target, const int32_t* win, float* dout,
+                        double* loss, int32_t nx, int32_t ny, int32_t nz, void* stream) {
+  if (!c || !out || !target || !win || !dout || !loss || !nn_box_ok(nx, ny, nz))
+    return fail(c, RMTR_E_ARG, "rmtr_nn_mse: bad arguments");
+  const int32_t n3[3] = {nx, ny, nz};
+  for (int i = 0; i < 3; ++i)
+    if (win[2 * i] < 0 || win[2 * i + 1] > n3[i] || win[2 * i] >= win[2 * i + 1])
+      return fail(c, RMTR_E_ARG, "rmtr_nn_mse: empty or out-of-range window");
+  rmtr_status r = ensure_common(c);
+  if (r != RMTR_OK) return r;
+  const int wi[6] = {win[0], win[1], win[2], win[3], win[4], win[5]};
+  HIPCHK(c, nn_mse(out, target, dout, nx, ny, nz, wi, c->partials, loss, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_nn_adam_step(rmtr_ctx* c, int64_t n, int64_t n_bf16, float lr, int32_t t, const float* grad,
+                              float* master, float* m, float* v, uint16_t* w_bf16, void* stream) {
+  if (!c || n < 0 || n_bf16 < 0 || n_bf16 > n || t < 1 || !grad || !master || !m || !v || (n_bf16 > 0 && !w_bf16))
+    return fail(c, RMTR_E_ARG, "rmtr_nn_adam_step: bad arguments");
+  HIPCHK(c, nn_adam(n, n_bf16, lr, t, grad, master, m, v, w_bf16, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_nn_to_bf16(rmtr_ctx* c, int64_t n, const float* master, uint16_t* w_bf16, void* stream) {
+  if (!c || n < 0 || (n > 0 && (!master || !w_bf16))) return fail(c, RMTR_E_ARG, "rmtr_nn_to_bf16: bad arguments");
+  HIPCHK(c, nn_to_bf16(n, master, w_bf16, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_nn_features(rmtr_ctx* c, int32_t level, const double* x, const double* g, const float* scales,
+                             float* in8, void* stream) {
+  if (!valid_level(c, level) || c->model.dim != 3 || !x || !g || !scales || !in8)
+    return fail(c, RMTR_E_ARG, "rmtr_nn_features: bad arguments (3D only)");
+  HIPCHK(c, nn_features(c->lv[level].nodes, x, g, scales, in8, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_nn_propose(rmtr_ctx* c, int32_t level, const rmtr_nn* net, const double* x, const double* g,
+                            const double* lo, const double* hi, double* s, void* stream) {
+  if (!valid_level(c, level) || c->model.dim != 3 || !net || !net->w || !net->bias || !net->scales || !x || !g ||
+      !lo || !hi || !s)
+    return fail(c, RMTR_E_ARG, "rmtr_nn_propose: bad arguments (3D only)");
+  return nn_propose(c, level, *net, x, g, lo, hi, s, S(stream));
 }
 
 }  // extern "C"

@@ -98,4 +98,26 @@ hipError_t run_mprgp(int dim, int N, const double* K, const uint8_t* dir, const 
                      double* host_scalars, MprgpResult* res, hipStream_t st);
 size_t mprgp_work_doubles(int dim, int N);
 
+// ---- learned proposal network (cnn_kernels.hip)
+// channels 8 -> 32 -> 32 -> 32 -> 32 -> 32 -> 4; weights BF16 [27][Cin][Cout]
+// per layer, concatenated; biases FP32, concatenated; tensors channels-last
+int64_t nn_weight_count();
+int64_t nn_bias_count();
+int64_t nn_act_floats(int64_t nvox);  // all seven layer tensors of one box
+void nn_layers(float* act, int64_t nvox, float* layer[7]);
+hipError_t nn_forward(const uint16_t* w, const float* bias, float* const layer[7], int nx, int ny, int nz,
+                      hipStream_t st);
+size_t nn_backward_work_floats(int64_t nvox);
+hipError_t nn_backward(const uint16_t* w, const float* act, const float* dout, float* dw, float* db, int nx, int ny,
+                       int nz, float* work, hipStream_t st);
+hipError_t nn_mse(const float* out, const float* target, float* dout, int nx, int ny, int nz, const int* window,
+                  double* partials, double* loss_dev, hipStream_t st);
+hipError_t nn_adam(int64_t n, int64_t n_bf16, float lr, int t, const float* g, float* p, float* m, float* v,
+                   uint16_t* pbf, hipStream_t st);
+hipError_t nn_to_bf16(int64_t n, const float* a, uint16_t* b, hipStream_t st);
+hipError_t nn_features(int64_t nn, const double* x, const double* g, const float* scales, float* feat,
+                       hipStream_t st);
+hipError_t nn_proposal(int64_t n, const float* out, const float* scales, const double* lo, const double* hi,
+                       double* s, hipStream_t st);
+
 }  // namespace rmtr

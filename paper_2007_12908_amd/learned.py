@@ -1,0 +1,166 @@
+"""Learned finest-level proposal: harvesting, training and deployment.
+
+The network (six 3x3x3 convolutions, 8 -> 32 x 5 -> 4 channels, see
+include/rmtr.h) maps the state (u, c) and gradient g of the finest level to
+a proposed step.  It is trained on pairs harvested from the plain method:
+for a state x at the start of a V-cycle, the target is the correction the
+projected Gauss-Seidel smoother computes for the trust-region subproblem
+eq. (model_qp) with the Hessian at x (Sec. 3.2.1), i.e. the step the first
+finest-level pre-smoothing step of Alg. 1 would take.  Training runs on the
+GPU through the library's own forward, backward, loss and Adam kernels
+(BF16 weights, FP32 masters and arithmetic).  Deployed, every proposal is
+projected onto the step box and must pass the FP64 trust-region ratio test;
+the smoother is the fallback (rmtr_solve_loadstep with use_learned).
+
+Torch is used for device memory, copies between buffers and the per-channel
+RMS normalisation constants of the harvested data.
+"""
+import ctypes
+import time
+
+import numpy as np
+import torch
+
+from . import binding
+
+NW = binding.NN_WEIGHTS
+NB = binding.NN_BIASES
+
+
+class ProposalNet:
+    """FP32 master parameters, Adam moments, BF16 weights and scales on the GPU."""
+
+    def __init__(self, ctx, seed=0):
+        self.ctx = ctx
+        rng = np.random.default_rng(seed)
+        parts = []
+        chans = binding.NN_CHANNELS
+        for cin, cout in zip(chans[:-1], chans[1:]):
+            parts.append(rng.standard_normal(27 * cin * cout) * np.sqrt(2.0 / (27 * cin)))
+        parts.append(np.zeros(NB))
+        self.master = torch.from_numpy(np.concatenate(parts).astype(np.float32)).cuda()
+        self.m = torch.zeros_like(self.master)
+        self.v = torch.zeros_like(self.master)
+        self.w = torch.zeros(NW, dtype=torch.int16, device="cuda")
+        self.scales = torch.ones(12, dtype=torch.float32, device="cuda")
+        self.t = 0
+        ctx.nn_to_bf16(self.master[:NW], self.w)
+
+    @property
+    def bias(self):
+        return self.master[NW:]
+
+    def net(self):
+        """rmtr_nn view (keep this object alive while it is used)."""
+        return binding.Net(ctypes.c_void_p(self.w.data_ptr()), ctypes.c_void_p(self.bias.data_ptr()),
+                           ctypes.c_void_p(self.scales.data_ptr()))
+
+    def state_dict(self):
+        return {"master": self.master.cpu().numpy(), "scales": self.scales.cpu().numpy()}
+
+    def load_state_dict(self, d):
+        self.master.copy_(torch.from_numpy(np.asarray(d["master"], dtype=np.float32)))
+        self.scales.copy_(torch.from_numpy(np.asarray(d["scales"], dtype=np.float32)))
+        self.ctx.nn_to_bf16(self.master[:NW], self.w)
+
+
+def harvest(ctx, x, p, c_lower, delta=1.0, sweeps=3, dirichlet=None):
+    """(g, s) at state x of the finest level: the gradient and the projected
+    Gauss-Seidel correction of the trust-region subproblem at x."""
+    L = ctx.L
+    g = ctx.gradient(L, x, p, dirichlet)
+    lo, hi = ctx.step_box(L, x, c_lower, delta, dirichlet)
+    s = torch.zeros_like(x)
+    ctx.smooth(L, x, p, g, lo, hi, s, sweeps, dirichlet)
+    return g, s
+
+
+def harvest_run(ctx, x, p, c_lower, n_states, sweeps=3, params=None, dirichlet=None):
+    """States along a plain RMTR run: harvest at x, then one V-cycle, repeated."""
+    prm = params if params is not None else binding.default_params()
+    prm.max_vcycles = 1
+    prm.use_learned = 0
+    out = []
+    for _ in range(n_states):
+        g, s = harvest(ctx, x, p, c_lower, prm.delta0, sweeps, dirichlet)
+        out.append((x.clone(), g, s))
+        st = ctx.solve_loadstep(x, p, c_lower, prm, dirichlet)
+        if st["code"] == binding.RMTR_OK:
+            break
+    return out
+
+
+def channel_rms(t):
+    v = t.view(-1, 4)
+    return v.pow(2).mean(0).sqrt()
+
+
+def fit_scales(net, samples):
+    """Per-channel RMS normalisation of inputs (x, g) and targets s."""
+    xs = torch.stack([channel_rms(x) for x, _, _ in samples]).mean(0)
+    gs = torch.stack([channel_rms(g) for _, g, _ in samples]).mean(0)
+    ss = torch.stack([channel_rms(s) for _, _, s in samples]).mean(0)
+    one = torch.ones_like(xs)
+    xs, gs, ss = (torch.where(t > 0, t, one) for t in (xs, gs, ss))
+    net.scales.copy_(torch.cat([1.0 / xs, 1.0 / gs, ss]).float())
+
+
+class Trainer:
+    """Adam on the MSE between the network output and the scaled targets,
+    one whole node grid per step (every 32^3 patch of it at once)."""
+
+    def __init__(self, net, level, lr=1e-3):
+        self.net, self.ctx, self.level, self.lr = net, net.ctx, level, lr
+        n = net.ctx.level_cells(level) + 1
+        self.box = (n, n, n)
+        self.nvox = n ** 3
+        self.act = torch.zeros(self.ctx.nn_size(2, *self.box), dtype=torch.float32, device="cuda")
+        self.work = torch.empty(self.ctx.nn_size(3, *self.box), dtype=torch.float32, device="cuda")
+        self.dout = torch.empty(self.nvox * 4, dtype=torch.float32, device="cuda")
+        self.grad = torch.empty(NW + NB, dtype=torch.float32, device="cuda")
+        self.loss = torch.empty(1, dtype=torch.float64, device="cuda")
+        self.window = (1, n - 1, 1, n - 1, 1, n - 1)
+        self.data = []
+
+    def add(self, samples):
+        """Scaled features and targets of (x, g, s) samples (after fit_scales)."""
+        inv_s = 1.0 / self.net.scales[8:].double()
+        for x, g, s in samples:
+            feat = self.ctx.nn_features(self.level, x, g, self.net.scales)
+            tgt = (s.view(-1, 4) * inv_s).float().reshape(-1).contiguous()
+            self.data.append((feat, tgt))
+
+    def forward_loss(self, i):
+        feat, tgt = self.data[i]
+        self.act[: feat.numel()].copy_(feat)
+        self.ctx.nn_forward(self.net.w, self.net.bias, self.act, self.box)
+        self.ctx.nn_mse(self.act[168 * self.nvox:], tgt, self.window, self.dout, self.loss, self.box)
+
+    def step(self, i):
+        self.forward_loss(i)
+        self.ctx.nn_backward(self.net.w, self.act, self.dout, self.grad, self.work, self.box)
+        self.net.t += 1
+        self.ctx.nn_adam_step(self.lr, self.net.t, self.grad, self.net.master, self.net.m, self.net.v, self.net.w,
+                              n_bf16=NW)
+
+    def mean_loss(self, idx=None):
+        idx = range(len(self.data)) if idx is None else idx
+        tot = 0.0
+        for i in idx:
+            self.forward_loss(i)
+            tot += float(self.loss.item())
+        return tot / max(len(idx), 1)
+
+    def train(self, steps, seed=0, time_limit=None):
+        rng = np.random.default_rng(seed)
+        t0 = time.perf_counter()
+        done = 0
+        for k in range(steps):
+            self.step(int(rng.integers(len(self.data))))
+            done = k + 1
+            if time_limit is not None and (k & 7) == 7:
+                torch.cuda.synchronize()
+                if time.perf_counter() - t0 > time_limit:
+                    break
+        torch.cuda.synchronize()
+        return done, time.perf_counter() - t0

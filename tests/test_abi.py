@@ -50,3 +50,18 @@ def test_create_validates_model_without_gpu():
     lib.rmtr_destroy(h)
     p = binding.default_params()
     assert (p.eta1, p.eta2, p.gamma1, p.gamma2, p.pgs_sweeps, p.mu1, p.mu2) == (0.1, 0.75, 0.5, 2.0, 3, 1, 1)
+    assert p.use_learned == 0 and not p.nn
+
+
+def test_nn_sizes_without_gpu():
+    """Parameter counts of the 8-32-32-32-32-32-4 network of 3x3x3 layers."""
+    from oracle import cnn
+    from paper_2007_12908_amd import binding
+    lib = binding.load()
+    nw = sum(27 * a * b for a, b in zip(cnn.CHANNELS[:-1], cnn.CHANNELS[1:]))
+    nb = sum(cnn.CHANNELS[1:])
+    assert lib.rmtr_nn_size(0, 1, 1, 1) == nw == binding.NN_WEIGHTS
+    assert lib.rmtr_nn_size(1, 1, 1, 1) == nb == binding.NN_BIASES
+    assert nw + nb == 121124
+    assert lib.rmtr_nn_size(2, 3, 4, 5) == 60 * sum(cnn.CHANNELS)
+    assert lib.rmtr_nn_size(2, 0, 4, 5) == -1 and lib.rmtr_nn_size(7, 1, 1, 1) == -1

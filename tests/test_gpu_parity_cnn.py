@@ -1,0 +1,216 @@
+"""GPU vs oracle: the proposal network's forward pass, MSE loss, backward
+pass (weight and bias gradients), Adam step, BF16 rounding and input
+features, through the C-ABI.
+
+The oracle runs in FP64 on the same BF16-rounded weights, so the only
+difference is the kernels' FP32 arithmetic (sums of up to 27 x 32 products
+per output): forward and loss agree to 1e-5 relative to the largest output,
+gradients to 1e-4 relative to the largest entry of each layer's gradient."""
+import numpy as np
+import pytest
+
+from oracle import cnn
+from _util import ctx_for, dev, host, material
+
+pytestmark = pytest.mark.gpu
+
+
+def bf16_bits(a):
+    """Round-to-nearest-even FP32 -> BF16 bit patterns (uint16)."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return r.astype(np.uint16)
+
+
+def bf16_value(bits):
+    return (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def flat_params(params):
+    w = np.concatenate([W.ravel() for W, _ in params])
+    b = np.concatenate([bb for _, bb in params])
+    return w, b
+
+
+def unflat_weights(wv, bv):
+    out, ow, ob = [], 0, 0
+    for cin, cout in zip(cnn.CHANNELS[:-1], cnn.CHANNELS[1:]):
+        n = 27 * cin * cout
+        out.append((wv[ow:ow + n].reshape(27, cin, cout), bv[ob:ob + cout]))
+        ow += n
+        ob += cout
+    return out
+
+
+def setup(box, seed):
+    import torch
+    rng = np.random.default_rng(seed)
+    params = cnn.init_params(seed)
+    params = [(W, rng.standard_normal(W.shape[2]) * 0.1) for W, _ in params]
+    w, b = flat_params(params)
+    wbits = bf16_bits(w)
+    b32 = b.astype(np.float32)
+    params_q = unflat_weights(bf16_value(wbits), b32.astype(np.float64))
+    nx, ny, nz = box
+    x = rng.standard_normal((nz, ny, nx, 8)).astype(np.float32)
+    ctx = ctx_for(3, 4, 1, material(4))
+    wd = torch.from_numpy(wbits.view(np.int16)).cuda()
+    bd = dev(b32)
+    act = torch.zeros(ctx.nn_size(2, nx, ny, nz), dtype=torch.float32, device="cuda")
+    act[: x.size] = dev(x.ravel())
+    return ctx, params_q, x.astype(np.float64), wd, bd, act
+
+
+def out_of(act, box):
+    nx, ny, nz = box
+    nvox = nx * ny * nz
+    return host(act[168 * nvox:]).reshape(nz, ny, nx, 4)
+
+
+BOXES = [(5, 4, 3), (7, 6, 5), (33, 20, 17), (40, 30, 29)]
+
+
+@pytest.mark.parametrize("box", BOXES)
+def test_forward_matches_oracle(box):
+    print(f"case forward box={box}", flush=True)
+    ctx, pq, x, wd, bd, act = setup(box, seed=sum(box))
+    ctx.nn_forward(wd, bd, act, box)
+    ref, acts = cnn.forward(pq, x)
+    got = out_of(act, box)
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() <= 1e-5 * scale
+    # hidden layers too (post-ReLU activations)
+    nx, ny, nz = box
+    nvox = nx * ny * nz
+    off = 8 * nvox
+    for l in range(1, 6):
+        h = host(act[off: off + 32 * nvox]).reshape(nz, ny, nx, 32)
+        assert np.abs(h - acts[l]).max() <= 1e-5 * max(np.abs(acts[l]).max(), 1e-30)
+        off += 32 * nvox
+
+
+@pytest.mark.parametrize("box", BOXES)
+def test_loss_and_backward_match_oracle(box):
+    import torch
+    print(f"case backward box={box}", flush=True)
+    ctx, pq, x, wd, bd, act = setup(box, seed=3 * sum(box))
+    nx, ny, nz = box
+    rng = np.random.default_rng(7)
+    target = rng.standard_normal((nz, ny, nx, 4))
+    win = (1, nx - 1, 1, ny - 1, 0, nz) if min(box) > 2 else (0, nx, 0, ny, 0, nz)
+    window = (slice(win[4], win[5]), slice(win[2], win[3]), slice(win[0], win[1]))
+    ctx.nn_forward(wd, bd, act, box)
+    dout = torch.empty(nx * ny * nz * 4, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    out_view = act[168 * nx * ny * nz:]
+    ctx.nn_mse(out_view, dev(target.astype(np.float32).ravel()), win, dout, loss, box)
+    grad = torch.empty(cnn_param_count(), dtype=torch.float32, device="cuda")
+    work = torch.empty(ctx.nn_size(3, nx, ny, nz), dtype=torch.float32, device="cuda")
+    ctx.nn_backward(wd, act, dout, grad, work, box)
+    ref_loss, ref_grads = cnn.loss_and_grads(pq, x, target.astype(np.float32).astype(np.float64), window)
+    assert abs(host(loss)[0] - ref_loss) <= 1e-5 * ref_loss
+    g = host(grad).astype(np.float64)
+    gw, gb = g[:120960], g[120960:]
+    got = unflat_weights(gw, gb)
+    for l, ((dW, db), (rW, rb)) in enumerate(zip(got, ref_grads)):
+        sw = np.abs(rW).max()
+        sb = max(np.abs(rb).max(), 1e-30)
+        assert np.abs(dW - rW).max() <= 1e-4 * sw, (l, np.abs(dW - rW).max() / sw)
+        assert np.abs(db - rb).max() <= 1e-4 * sb, (l, np.abs(db - rb).max() / sb)
+
+
+def cnn_param_count():
+    return sum(27 * a * b + b for a, b in zip(cnn.CHANNELS[:-1], cnn.CHANNELS[1:]))
+
+
+def test_backward_is_deterministic():
+    import torch
+    box = (40, 30, 29)
+    ctx, pq, x, wd, bd, act = setup(box, seed=11)
+    nx, ny, nz = box
+    ctx.nn_forward(wd, bd, act, box)
+    rng = np.random.default_rng(3)
+    dout = dev(rng.standard_normal(nx * ny * nz * 4).astype(np.float32))
+    work = torch.empty(ctx.nn_size(3, nx, ny, nz), dtype=torch.float32, device="cuda")
+    g1 = torch.empty(cnn_param_count(), dtype=torch.float32, device="cuda")
+    g2 = torch.empty_like(g1)
+    ctx.nn_backward(wd, act, dout, g1, work, box)
+    ctx.nn_backward(wd, act, dout, g2, work, box)
+    assert torch.equal(g1, g2)
+
+
+def test_adam_and_bf16_match_oracle():
+    import torch
+    n = cnn_param_count()
+    rng = np.random.default_rng(5)
+    p = rng.standard_normal(n).astype(np.float32)
+    g = (rng.standard_normal(n) * 1e-2).astype(np.float32)
+    m = (rng.standard_normal(n) * 1e-3).astype(np.float32)
+    v = (rng.uniform(0, 1e-4, n)).astype(np.float32)
+    ctx = ctx_for(3, 4, 1, material(4))
+    pd, gd, md, vd = dev(p), dev(g), dev(m), dev(v)
+    wb = torch.zeros(120960, dtype=torch.int16, device="cuda")
+    ctx.nn_adam_step(1e-3, 3, gd, pd, md, vd, wb, n_bf16=120960)
+    rp, rm, rv = cnn.adam_step(p.astype(np.float64), g.astype(np.float64), m.astype(np.float64),
+                               v.astype(np.float64), 3, 1e-3)
+    assert np.abs(host(md) - rm).max() <= 1e-6 * np.abs(rm).max()
+    assert np.abs(host(vd) - rv).max() <= 1e-6 * np.abs(rv).max()
+    assert np.abs(host(pd) - rp).max() <= 1e-6 * np.abs(rp).max()
+    # the BF16 copy is the RNE rounding of the updated FP32 master, bit for bit
+    assert np.array_equal(host(wb).view(np.uint16), bf16_bits(host(pd)[:120960]))
+    wb2 = torch.zeros_like(wb)
+    ctx.nn_to_bf16(pd, wb2)
+    assert torch.equal(wb, wb2)
+
+
+def test_features_bitwise():
+    """in8 = FP32(x) * scale and FP32(g) * scale: one rounding each."""
+    N = 6
+    ctx = ctx_for(3, N, 1, material(N))
+    n = (N + 1) ** 3
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal(4 * n)
+    g = rng.standard_normal(4 * n) * 1e-5
+    sc = rng.uniform(0.5, 2e3, 12).astype(np.float32)
+    got = host(ctx.nn_features(1, dev(x), dev(g), dev(sc))).reshape(n, 8)
+    ref = np.empty((n, 8), dtype=np.float32)
+    ref[:, :4] = x.reshape(n, 4).astype(np.float32) * sc[:4]
+    ref[:, 4:] = g.reshape(n, 4).astype(np.float32) * sc[4:8]
+    assert np.array_equal(got, ref)
+
+
+def test_propose_matches_oracle_and_stays_in_box():
+    """Features, forward pass and projection onto [lo, hi] in one call."""
+    import ctypes
+    import torch
+    from paper_2007_12908_amd import binding
+    N = 8
+    box = (N + 1,) * 3
+    ctx, pq, _, wd, bd, _ = setup(box, seed=21)
+    ctx = ctx_for(3, N, 1, material(N))
+    n = (N + 1) ** 3
+    rng = np.random.default_rng(13)
+    x = rng.standard_normal(4 * n) * 1e-3
+    g = rng.standard_normal(4 * n) * 1e-6
+    lo = -rng.uniform(0, 2e-3, 4 * n)
+    hi = rng.uniform(0, 2e-3, 4 * n)
+    lo[::7] = hi[::7] = 0.0
+    sc = np.array([1e3] * 4 + [1e6] * 4 + [1e-3] * 4, dtype=np.float32)
+    scd = dev(sc)
+    net = binding.Net(ctypes.c_void_p(wd.data_ptr()), ctypes.c_void_p(bd.data_ptr()),
+                      ctypes.c_void_p(scd.data_ptr()))
+    s = host(ctx.nn_propose(1, net, dev(x), dev(g), dev(lo), dev(hi)))
+    feat = np.empty((n, 8))
+    feat[:, :4] = (x.reshape(n, 4).astype(np.float32) * sc[:4]).astype(np.float64)
+    feat[:, 4:] = (g.reshape(n, 4).astype(np.float32) * sc[4:8]).astype(np.float64)
+    out, _ = cnn.forward(pq, feat.reshape(N + 1, N + 1, N + 1, 8))
+    raw = out.reshape(n, 4) * sc[8:].astype(np.float64)
+    ref = np.clip(raw.ravel(), lo, hi)
+    assert np.all(s >= lo) and np.all(s <= hi)
+    assert np.abs(s - ref).max() <= 1e-5 * np.abs(raw).max()
+    # non-finite network output (NaN bias) gives a zero step
+    bnan = torch.full_like(bd, float("nan"))
+    net2 = binding.Net(ctypes.c_void_p(wd.data_ptr()), ctypes.c_void_p(bnan.data_ptr()),
+                       ctypes.c_void_p(scd.data_ptr()))
+    s2 = host(ctx.nn_propose(1, net2, dev(x), dev(g), dev(lo), dev(hi)))
+    assert np.all(s2 == np.clip(0.0, lo, hi))
