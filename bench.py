@@ -6,7 +6,9 @@ over the fine level of the workload, inputs resident in HBM.  `value` is the
 fine-level dofs passed through that triple per second (GDoF/s).  The same run
 reports each kernel's own rate, the mixed-precision (FP32) Hv, the roofline
 of the dominant kernel (HIP events on the launch stream), the RMTR load step
-(plain FP64 and mixed) to 1e-8, and the CPU oracle on a bounded sample.
+to 1e-8 (plain FP64, mixed precision, and mixed precision with the learned
+proposal, whose harvesting and training are timed apart), and the CPU oracle
+on a bounded sample.
 """
 import argparse
 import hashlib
@@ -87,6 +89,38 @@ def cpu_baseline(wl, x_np, p_np, v_np, budget_s=20.0):
                       f"(4 dofs per element), numpy/scipy FP64 single thread, {dt:.1f} s"}
 
 
+def learned_leg(ctx, wl, P, W, torch, train_seconds):
+    """Harvest (state, gradient) -> PGS-correction pairs from plain runs on
+    other fracture networks of the same grid (10-50 discs, seeds 1000 + r),
+    train the proposal network on the GPU, and return it with the training
+    figures (reported apart from the load-step time)."""
+    from paper_2007_12908_amd import learned
+    N, L = wl.n_cells, wl.n_levels
+    t0 = time.perf_counter()
+    samples = []
+    for r in range(3):
+        nf = (10, 30, 50)[r]
+        tab = W.disc_table(nf, 1000 + r, 0.2, 0.8, 0.03, 0.08)
+        c0r, pr = ctx.init_fields(L, tab, band=wl.h, p_mode=0, p_value=wl.p)
+        xr = torch.zeros(4 * (N + 1) ** 3, dtype=torch.float64, device="cuda")
+        xr.view(-1, 4)[:, 3] = c0r
+        samples += learned.harvest_run(ctx, xr, pr, c0r, 6)
+    torch.cuda.synchronize()
+    t_harvest = time.perf_counter() - t0
+    net = learned.ProposalNet(ctx, seed=0)
+    learned.fit_scales(net, samples)
+    tr = learned.Trainer(net, L, lr=1e-3)
+    tr.add(samples)
+    del samples
+    loss0 = tr.mean_loss()
+    steps, t_train = tr.train(100000, seed=1, time_limit=train_seconds)
+    loss1 = tr.mean_loss()
+    info = {"samples": len(tr.data), "harvest_s": t_harvest, "train_steps": steps, "train_s": t_train,
+            "loss_initial": loss0, "loss_final": loss1}
+    tr.data = []
+    return net, info
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +128,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2_3d_128")
     ap.add_argument("--no-loadstep", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--train-seconds", type=float, default=30.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernels-only", action="store_true",
                     help="time only the kernel triple (for profiler runs)")
@@ -188,11 +224,22 @@ def main():
 
     rmtr = None
     if not args.no_loadstep:
+        import ctypes
         rmtr = {}
-        for name, prec in (("plain_fp64", 0), ("mixed_fp32", 1)):
+        legs = [("plain_fp64", 0, None), ("mixed_fp32", 1, None)]
+        net = None
+        if not args.no_learned:
+            net, rmtr["training"] = learned_leg(ctx, wl, P, W, torch, args.train_seconds)
+            log("training", rmtr["training"])
+            legs.append(("mixed_learned", 1, net))
+        for name, prec, nn in legs:
             xs = torch.zeros_like(x)
             xs.view(-1, 4)[:, 3] = c0
             prm = P.default_params(precision=prec)
+            if nn is not None:
+                nnv = nn.net()
+                prm.use_learned = 1
+                prm.nn = ctypes.pointer(nnv)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             st = ctx.solve_loadstep(xs, p, c0, prm)
@@ -200,6 +247,7 @@ def main():
             dt = time.perf_counter() - t0
             rmtr[name] = {"s_per_loadstep": dt, "vcycles": st["vcycles"], "chi_rel": st["chi"] / st["chi0"],
                           "tr_accepted": st["tr_accepted"], "tr_rejected": st["tr_rejected"],
+                          "nn_proposed": st["nn_proposed"], "nn_accepted": st["nn_accepted"],
                           "energy": st["energy"], "converged": st["code"] == 0}
             log(name, rmtr[name])
 
