@@ -192,6 +192,17 @@ rmtr_status rmtr_prolong(rmtr_ctx* ctx, int32_t coarse_level, const void* coarse
    ignored). */
 rmtr_status rmtr_galerkin(rmtr_ctx* ctx, int32_t coarse_level, const double* x_lin, const double* p,
                           const uint8_t* dirichlet, const double* K_fine, double* K_coarse, void* stream);
+/* Hv with the Galerkin coarse Hessian of `level` < L as the load step
+   builds it (eq. (delta_terms), Alg. 1, lagged at x_lin): the finest-level
+   Hessian at x_lin (FP64 x_lin and p; stored FP64, or FP32 if precision is
+   RMTR_FP32) assembled into a block stencil (finest Dirichlet mask
+   `dirichlet`) and coarsened level by level, H_l = D_l R H_{l+1} I D_l with
+   D_l the default Dirichlet set of level l, in FP64.  v, Hv: FP64 on
+   `level`. */
+rmtr_status rmtr_coarse_hessvec(rmtr_ctx* ctx, int32_t level, const double* x_lin, const double* p,
+                                const uint8_t* dirichlet, const double* v, double* Hv, int32_t precision,
+                                void* stream);
+
 /* Hv and symmetric PGS with element matrices K of `level` (FP64). */
 rmtr_status rmtr_em_hessvec(rmtr_ctx* ctx, int32_t level, const double* K, const double* v, double* Hv,
                             void* stream);

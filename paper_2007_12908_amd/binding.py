@@ -22,7 +22,7 @@ R_DUAL, R_INJECT, R_BOX_LO, R_BOX_HI = 0, 1, 2, 3
 EXPORTS = [
     "rmtr_default_params", "rmtr_create", "rmtr_destroy", "rmtr_last_error", "rmtr_level_nodes",
     "rmtr_init_fields", "rmtr_energy", "rmtr_energy_diff", "rmtr_gradient", "rmtr_hessvec",
-    "rmtr_diag_blocks", "rmtr_smooth", "rmtr_restrict", "rmtr_prolong", "rmtr_galerkin",
+    "rmtr_diag_blocks", "rmtr_smooth", "rmtr_restrict", "rmtr_prolong", "rmtr_galerkin", "rmtr_coarse_hessvec",
     "rmtr_em_hessvec", "rmtr_em_smooth", "rmtr_mprgp", "rmtr_dot", "rmtr_chi", "rmtr_solve_loadstep",
     "rmtr_step_box", "rmtr_nn_size", "rmtr_nn_forward", "rmtr_nn_backward", "rmtr_nn_mse", "rmtr_nn_adam_step",
     "rmtr_nn_to_bf16", "rmtr_nn_features", "rmtr_nn_propose", "rmtr_element_flops",
@@ -90,6 +90,7 @@ def load():
             "rmtr_restrict": (I32, [P, I32, I32, P, P, I32, P]),
             "rmtr_prolong": (I32, [P, I32, P, P, I32, P]),
             "rmtr_galerkin": (I32, [P, I32, P, P, P, P, P, P]),
+            "rmtr_coarse_hessvec": (I32, [P, I32, P, P, P, P, P, I32, P]),
             "rmtr_em_hessvec": (I32, [P, I32, P, P, P, P]),
             "rmtr_em_smooth": (I32, [P, I32, P, P, P, P, P, I32, P]),
             "rmtr_mprgp": (I32, [P, I32, P, P, P, P, P, I32, D, I32, ctypes.POINTER(I32),
@@ -257,6 +258,15 @@ class Context:
         self._check(self.lib.rmtr_galerkin(self.h, coarse_level, _ptr(x_lin), _ptr(p), _ptr(dirichlet),
                                            _ptr(K_fine), _ptr(K), _stream()), "rmtr_galerkin")
         return K
+
+    def coarse_hessvec(self, level, x_lin, p, v, dirichlet=None, fp32_stencil=False):
+        """Galerkin coarse Hessian of `level` (built from the finest stencil at
+        x_lin, FP64 or FP32 storage) applied to the FP64 vector v."""
+        out = torch.empty_like(v)
+        self._check(self.lib.rmtr_coarse_hessvec(self.h, level, _ptr(x_lin), _ptr(p), _ptr(dirichlet), _ptr(v),
+                                                 _ptr(out), RMTR_FP32 if fp32_stencil else RMTR_FP64, _stream()),
+                    "rmtr_coarse_hessvec")
+        return out
 
     def em_hessvec(self, level, K, v):
         out = torch.empty_like(v)

@@ -178,12 +178,6 @@ __global__ __launch_bounds__(kB) void k_pupd(int64_t n, double bet, const double
     p[i] = phi[i] - bet * p[i];
 }
 
-template <int DIM>
-int64_t stencil_doubles(int N) {
-  int64_t nn = 1;
-  for (int i = 0; i < DIM; ++i) nn *= (N + 1);
-  return nn * (DIM + 1) * n_off<DIM>() * (DIM + 1);
-}
 
 }  // namespace
 
@@ -191,11 +185,10 @@ size_t mprgp_work_doubles(int dim, int N) {
   int64_t nn = 1;
   for (int i = 0; i < dim; ++i) nn *= (N + 1);
   const int64_t n = nn * (dim + 1);
-  const int64_t st = dim == 3 ? stencil_doubles<3>(N) : stencil_doubles<2>(N);
-  return size_t(5 * n + st + kNV * 1024 + 2 * kNV + 16);
+  return size_t(5 * n + kNV * 1024 + 2 * kNV + 16);
 }
 
-hipError_t run_mprgp(int dim, int N, const double* K, const uint8_t* dir, const double* g, const double* lo,
+hipError_t run_mprgp(int dim, int N, const double* S, const uint8_t* dir, const double* g, const double* lo,
                      const double* hi, double* s, int max_it, double rtol, int fallback_sweeps, double* work,
                      double* hs, MprgpResult* res, hipStream_t st) {
   int64_t nn = 1;
@@ -206,8 +199,7 @@ hipError_t run_mprgp(int dim, int N, const double* K, const uint8_t* dir, const 
   double* beta = phi + n;
   double* p = beta + n;
   double* Ad = p + n;
-  double* S = Ad + n;  // assembled stencil of K
-  double* part = S + (dim == 3 ? stencil_doubles<3>(N) : stencil_doubles<2>(N));
+  double* part = Ad + n;
   double* red = part + kNV * 1024;
   const int nb = nblocks(n);
   const dim3 gb(nb), tb(kB);
@@ -228,8 +220,7 @@ hipError_t run_mprgp(int dim, int N, const double* K, const uint8_t* dir, const 
   res->iterations = 0;
   res->status = 1;
   CK(launch_fill(n, 0.0, s, st));
-  // assembled stencil, ||A|| bound and ||b||
-  CK(launch_em_to_st(dim, N, K, S, 0, st));
+  // ||A|| bound and ||b||
   {
     int nbr = 0;
     CK(launch_st_rowabs(dim, N, S, g, part, &nbr, st));

@@ -62,6 +62,10 @@ struct rmtr_ctx {
   size_t box_cap = 0;
   float* nn_buf = nullptr;      // inference tensors of the proposal network
   size_t nn_cap = 0;
+  double* rap_work = nullptr;   // intermediate stencils of the Galerkin coarsening
+  size_t rap_cap = 0;
+  double* op_st = nullptr;      // stencil scratch of rmtr_mprgp
+  size_t op_cap = 0;
   std::vector<void*> allocs;
   std::string err;
 };
@@ -132,18 +136,13 @@ rmtr_status ensure_solver_level(rmtr_ctx* c, int l, bool mixed) {
                        &v.t1, &v.t2, &v.t3, &v.t4};
     for (double** b : vecs) HIPCHK(c, dalloc(c, b, n));
     HIPCHK(c, dalloc(c, &v.p, size_t(v.nodes)));
-    if (l < c->L || c->L == 1) {
-      const size_t nd = size_t(ndof_elem(c->model.dim));
-      HIPCHK(c, dalloc(c, &v.K, size_t(v.nelem) * nd * nd));
-    }
-    if (l == c->L && c->L > 1) HIPCHK(c, dalloc(c, &v.coef, coef_values(c->model.dim, v.N)));
+    if (l == c->L) HIPCHK(c, dalloc(c, &v.coef, coef_values(c->model.dim, v.N)));
     v.solver_ready = true;
   }
   // stencil of the lagged Hessian: FP32 on the finest level in mixed mode
   const bool want_f32 = mixed && l == c->L && c->L > 1;
   if (want_f32 && !v.Sf) HIPCHK(c, dalloc(c, &v.Sf, stencil_values(c->model.dim, v.N)));
-  if (!want_f32 && !v.S && !(l == c->L && c->L == 1))
-    HIPCHK(c, dalloc(c, &v.S, stencil_values(c->model.dim, v.N)));
+  if (!want_f32 && !v.S) HIPCHK(c, dalloc(c, &v.S, stencil_values(c->model.dim, v.N)));
   if (mixed && l == c->L && !v.xlf) {
     const size_t n = size_t(v.n);
     float** fv[] = {&v.xlf, &v.gf, &v.lof, &v.hif, &v.sf};
@@ -291,7 +290,7 @@ struct Run {
     Level& v = c->lv[l];
     if (coarsest) {
       MprgpResult res;
-      HIPCHK(c, run_mprgp(dim(), v.N, v.K, dir(l), v.g, v.lo, v.hi, v.s, prm.coarse_qp_its, prm.coarse_qp_rtol,
+      HIPCHK(c, run_mprgp(dim(), v.N, v.S, dir(l), v.g, v.lo, v.hi, v.s, prm.coarse_qp_its, prm.coarse_qp_rtol,
                           prm.fallback_sweeps, c->mprgp_work, c->hs + 48, &res, st));
       return RMTR_OK;
     }
@@ -324,10 +323,8 @@ struct Run {
     // model Hessian times s: lagged matrix-free on the finest level (FP64)
     if (l == c->L && !(c->L == 1)) {
       HIPCHK(c, launch_hessvec(eargs(c, l, fdir), v.x0, v.p, v.s, v.hs, 0, st));
-    } else if (v.S) {
-      HIPCHK(c, launch_st_matvec(dim(), v.N, v.S, v.s, v.hs, 0, st));
     } else {
-      HIPCHK(c, launch_em_hessvec(dim(), v.N, v.K, v.s, v.hs, nullptr, 0, st));
+      HIPCHK(c, launch_st_matvec(dim(), v.N, v.S, v.s, v.hs, 0, st));
     }
     HIPCHK(c, launch_dot(v.n, v.g, v.s, c->partials, c->scal + 4, st));
     HIPCHK(c, launch_dot(v.n, v.s, v.hs, c->partials, c->scal + 5, st));
@@ -424,18 +421,17 @@ struct Run {
     HIPCHK(c, launch_add_scaled(cc.n, cc.x0, 1.0, cc.hi, 1.0, nullptr, cc.Ub, st));
     rmtr_status r = h_grad(l, x, f.g);
     if (r != RMTR_OK) return r;
-    if (l == c->L) {
-      HIPCHK(c, launch_galerkin_from_matfree(eargs(c, l, fdir), f.x0, f.p, cc.K, 0, nullptr, c->fineq_tab, st));
-    } else {
-      HIPCHK(c, launch_galerkin_from_em(d, cc.N, f.K, cc.K, nullptr, st));
-    }
+    // lagged coarse Hessian R H I (default coarse Dirichlet set) from the
+    // level's stencil
+    const bool f32 = l == c->L && mixed;
+    HIPCHK(c, launch_st_rap(d, f.N, f32 ? static_cast<const void*>(f.Sf) : static_cast<const void*>(f.S), f32 ? 1 : 0,
+                            cc.S, nullptr, c->rap_work, st));
     HIPCHK(c, launch_restrict(d, cc.N, RMTR_R_DUAL, f.g, cc.dg, 0, st));
     if (energy_model) {
       HIPCHK(c, launch_gradient(eargs(c, l - 1, nullptr), cc.x0, cc.p, cc.t3, st));
       HIPCHK(c, launch_add_scaled(cc.n, cc.t3, -1.0, nullptr, 0.0, cc.dg, cc.dg, st));
     }
     HIPCHK(c, launch_zero_masked(d, cc.N, cc.dg, nullptr, st));
-    HIPCHK(c, launch_em_to_st(d, cc.N, cc.K, cc.S, 0, st));
     return RMTR_OK;
   }
 
@@ -779,6 +775,37 @@ rmtr_status rmtr_galerkin(rmtr_ctx* c, int32_t coarse_level, const double* xl, c
   return RMTR_OK;
 }
 
+rmtr_status rmtr_coarse_hessvec(rmtr_ctx* c, int32_t level, const double* xl, const double* p, const uint8_t* dir,
+                                const double* v, double* hv, int32_t precision, void* stream) {
+  if (!valid_level(c, level) || level >= c->L || !xl || !p || !v || !hv || v == hv)
+    return fail(c, RMTR_E_ARG, "rmtr_coarse_hessvec: bad arguments");
+  const bool f32 = precision == RMTR_FP32;
+  const int L = c->L, d = c->model.dim;
+  Level& f = c->lv[L];
+  if (!f.coefop) HIPCHK(c, dalloc(c, &f.coefop, coef_values(d, f.N)));
+  void* Sm = nullptr;
+  if (f32) {
+    if (!f.Sopf) HIPCHK(c, dalloc(c, &f.Sopf, stencil_values(d, f.N)));
+    Sm = f.Sopf;
+  } else {
+    if (!f.Sop) HIPCHK(c, dalloc(c, &f.Sop, stencil_values(d, f.N)));
+    Sm = f.Sop;
+  }
+  HIPCHK(c, launch_st_assemble(eargs(c, L, dir), xl, p, f.coefop, Sm, f32, S(stream)));
+  HIPCHK(c, grow(c, &c->rap_work, &c->rap_cap, st_rap_work_doubles(d, f.N)));
+  const void* src = Sm;
+  int src32 = f32 ? 1 : 0;
+  for (int l = L - 1; l >= level; --l) {
+    Level& cl = c->lv[l];
+    if (!cl.Sop) HIPCHK(c, dalloc(c, &cl.Sop, stencil_values(d, cl.N)));
+    HIPCHK(c, launch_st_rap(d, c->lv[l + 1].N, src, src32, cl.Sop, nullptr, c->rap_work, S(stream)));
+    src = cl.Sop;
+    src32 = 0;
+  }
+  HIPCHK(c, launch_st_matvec(d, c->lv[level].N, c->lv[level].Sop, v, hv, 0, S(stream)));
+  return RMTR_OK;
+}
+
 rmtr_status rmtr_em_hessvec(rmtr_ctx* c, int32_t level, const double* K, const double* v, double* hv, void* stream) {
   if (!valid_level(c, level) || !K || !v || !hv || v == hv) return fail(c, RMTR_E_ARG, "rmtr_em_hessvec: bad arguments");
   HIPCHK(c, launch_em_hessvec(c->model.dim, c->lv[level].N, K, v, hv, nullptr, 0, S(stream)));
@@ -805,9 +832,11 @@ rmtr_status rmtr_mprgp(rmtr_ctx* c, int32_t level, const double* K, const double
   if (r != RMTR_OK) return r;
   double* work = nullptr;
   HIPCHK(c, dalloc(c, &work, mprgp_work_doubles(c->model.dim, c->lv[level].N)));
+  HIPCHK(c, grow(c, &c->op_st, &c->op_cap, stencil_values(c->model.dim, c->lv[level].N)));
+  HIPCHK(c, launch_em_to_st(c->model.dim, c->lv[level].N, K, c->op_st, 0, S(stream)));
   MprgpResult res;
-  HIPCHK(c, run_mprgp(c->model.dim, c->lv[level].N, K, nullptr, g, lo, hi, s, max_it, rtol, fallback_sweeps, work,
-                      c->hs + 48, &res, S(stream)));
+  HIPCHK(c, run_mprgp(c->model.dim, c->lv[level].N, c->op_st, nullptr, g, lo, hi, s, max_it, rtol, fallback_sweeps,
+                      work, c->hs + 48, &res, S(stream)));
   HIPCHK(c, hipStreamSynchronize(S(stream)));
   if (iterations) *iterations = res.iterations;
   if (status) *status = res.status;
@@ -856,6 +885,7 @@ rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lo
   for (int l = 1; l <= c->L; ++l)
     if ((r = ensure_solver_level(c, l, mixed)) != RMTR_OK) return r;
   if (!c->mprgp_work) HIPCHK(c, dalloc(c, &c->mprgp_work, mprgp_work_doubles(c->model.dim, c->lv[1].N)));
+  if (c->L > 1) HIPCHK(c, grow(c, &c->rap_work, &c->rap_cap, st_rap_work_doubles(c->model.dim, c->lv[c->L].N)));
   Run run{c, *prm, st, dir, mixed, prm->coarse_model == 0};
   const int L = c->L, d = c->model.dim;
   Level& f = c->lv[L];
@@ -883,7 +913,7 @@ rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lo
       // lagged Hessian of this V-cycle: linearisation point x0 = x
       HIPCHK(c, hipMemcpyAsync(f.x0, x, f.n * sizeof(double), hipMemcpyDeviceToDevice, st));
       if (L == 1) {
-        HIPCHK(c, launch_galerkin_from_matfree(eargs(c, 1, dir), f.x0, f.p, f.K, 1, dir, nullptr, st));
+        HIPCHK(c, launch_st_assemble(eargs(c, 1, dir), f.x0, f.p, f.coef, f.S, 0, st));
       } else if (mixed) {
         HIPCHK(c, launch_st_assemble(eargs(c, L, dir), f.x0, f.p, f.coef, f.Sf, 1, st));
       } else {

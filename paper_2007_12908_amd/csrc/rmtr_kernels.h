@@ -53,6 +53,13 @@ size_t coef_values(int dim, int N);
 hipError_t launch_st_assemble(const ElemArgs& a, const double* xl, const double* p, double* coef, void* S,
                               int fp32, hipStream_t st);
 hipError_t launch_em_to_st(int dim, int N, const double* K, void* S, int fp32, hipStream_t st);
+// Galerkin coarse stencil Sc (level with Nf/2 cells, FP64) = R Sf I of the
+// fine stencil Sf (FP64, or FP32 if fp32), rows and columns of the coarse
+// Dirichlet dofs (mask dirc, null: default set) zero; work holds
+// st_rap_work_doubles(dim, Nf) doubles
+size_t st_rap_work_doubles(int dim, int Nf);
+hipError_t launch_st_rap(int dim, int Nf, const void* Sf, int fp32, double* Sc, const uint8_t* dirc, double* work,
+                         hipStream_t st);
 hipError_t launch_st_matvec(int dim, int N, const void* S, const void* v, void* y, int fp32, hipStream_t st);
 hipError_t launch_st_pgs(int dim, int N, const void* S, const uint8_t* dir, const void* g, const void* lo,
                          const void* hi, void* s, int n_sweeps, int fp32, hipStream_t st);
@@ -93,7 +100,8 @@ struct MprgpResult {
   int iterations;
   int status;  // 0 converged, 1 max iterations, 2 negative curvature (fallback applied)
 };
-hipError_t run_mprgp(int dim, int N, const double* K, const uint8_t* dir, const double* g, const double* lo,
+// S: the level's assembled block stencil (FP64)
+hipError_t run_mprgp(int dim, int N, const double* S, const uint8_t* dir, const double* g, const double* lo,
                      const double* hi, double* s, int max_it, double rtol, int fallback_sweeps, double* work,
                      double* host_scalars, MprgpResult* res, hipStream_t st);
 size_t mprgp_work_doubles(int dim, int N);

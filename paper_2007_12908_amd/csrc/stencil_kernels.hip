@@ -88,7 +88,7 @@ __device__ inline int locate(const Colours& g, int64_t id, int64_t& t, int (&c)[
 }
 
 // Second-variation coefficients at the 2^DIM quadrature points of every
-// element, stored structure-of-arrays: C[(q n_coef + k) ne + e].
+// element, element-major: C[(e 2^DIM + q) n_coef + k].
 template <int DIM>
 __global__ __launch_bounds__(kB) void k_coef(int N, double h, MatP<double> m, const double* __restrict__ x,
                                              const double* __restrict__ p, double* __restrict__ C) {
@@ -127,183 +127,331 @@ __global__ __launch_bounds__(kB) void k_coef(int N, double h, MatP<double> m, co
     for (int q = 0; q < NL; ++q) {
       HessCoef<DIM, double> hc;
       hess_coef<DIM, double>(m, z[q], pq[q], dpq[q], hc);
-      double* o = C + int64_t(q * NK) * ne + e;
-      o[0 * ne] = hc.vol;
-      o[1 * ne] = hc.shear;
-      o[2 * ne] = hc.Ccc;
+      double* o = C + (e * NL + q) * NK;
+      o[0] = hc.vol;
+      o[1] = hc.shear;
+      o[2] = hc.Ccc;
 #pragma unroll
       for (int i = 0; i < DIM; ++i) {
-        o[int64_t(3 + DIM * DIM + i) * ne] = hc.Pc[i];
+        o[3 + DIM * DIM + i] = hc.Pc[i];
 #pragma unroll
-        for (int j = 0; j < DIM; ++j) o[int64_t(3 + DIM * i + j) * ne] = hc.S[i][j];
+        for (int j = 0; j < DIM; ++j) o[3 + DIM * i + j] = hc.S[i][j];
       }
     }
   }
 }
 
-// Element contributions of one parity class of elements (class bits =
-// e_i % 2): elements of one class share no node, so each pass adds its
-// contributions with plain read-modify-write, and the 2^d passes sum every
-// entry in the same order.  A thread owns one element and one (local node a,
-// component al) row block: the 2^d x (d+1) entries towards the element's
-// local nodes b,
-//   sum_q w B_{q,a,al}^T d2W_q B_{q,b,be}.
-// Lanes take consecutive elements of the class, whose nodes a are
-// consecutive nodes of one colour, so the stencil updates are coalesced.
-// Blocks are laid out so that the 2^d (d+1) row planes of an element chunk
-// run on the same XCD (block b: xcd = b % 8) and share its L2 for the
-// coefficients.
+// Node-centric assembly: a thread owns one row (n, al) and, in 3D, one
+// z-plane of its neighbour blocks (dz = pz - 1, 9 blocks); 2D has one plane
+// of 9 blocks.  It sums, over the elements around n and their quadrature
+// points,
+//   w B_{q,a,al}^T d2W_q B_{q,b,be}     (n = local node a, neighbour = b),
+// and writes each stencil value once (zero on Dirichlet rows and columns
+// and towards missing neighbours), so no zeroing pass or read-modify-write
+// is needed.  Work items run al fastest: the four rows of a node share the
+// element coefficients they load, and consecutive nodes of a colour give
+// coalesced stores.
 template <int DIM, typename TO>
-__global__ __launch_bounds__(kB) void k_st_elem(Colours g, double h, double gcl, int cls, int64_t ncls,
-                                                int64_t nchunks, const double* __restrict__ C,
+__global__ __launch_bounds__(kB) void k_st_node(Colours g, double h, double gcl, const double* __restrict__ C,
                                                 const uint8_t* __restrict__ dir, TO* __restrict__ S) {
   constexpr int NL = 1 << DIM, NC = DIM + 1, NK = n_coef<DIM>(), NO = n_off<DIM>(), RB = row_block<DIM>();
-  constexpr int NPL = NL * NC;  // row planes (a, al)
+  constexpr int NP = DIM == 3 ? 3 : 1, OPP = NO / NP;
   const int N = g.N;
-  int64_t ne = 1;
-#pragma unroll
-  for (int i = 0; i < DIM; ++i) ne *= N;
-  const int64_t bid = blockIdx.x;
-  const int xcd = int(bid % 8);
-  const int64_t j = bid / 8;
-  const int plane = int(j % NPL);
-  const int64_t chunk = (j / NPL) * 8 + xcd;
-  if (chunk >= nchunks) return;
-  const int64_t k = chunk * kB + threadIdx.x;  // element index within the class
-  if (k >= ncls) return;
-  const int a = plane / NC, al = plane % NC;
-  // element coordinates: e_i = 2 t_i + bit_i(cls)
-  int e[DIM];
-  {
-    int64_t r = k;
-#pragma unroll
-    for (int i = 0; i < DIM; ++i) {
-      const int bit = (cls >> i) & 1;
-      const int len = (N - bit + 1) / 2;
-      e[i] = 2 * int(r % len) + bit;
-      r /= len;
-    }
-  }
-  int64_t eid = 0, st = 1;
-#pragma unroll
-  for (int i = 0; i < DIM; ++i) {
-    eid += int64_t(e[i]) * st;
-    st *= N;
-  }
+  const int64_t nodes = g.base[1 << DIM];
+  const int64_t ns = N + 1;
   const double invh = 1.0 / h;
   double w = 1.0;
 #pragma unroll
   for (int i = 0; i < DIM; ++i) w *= 0.5 * h;
-  double acc[NL][NC];
+  const int64_t work = nodes * NC * NP;
+  for (int64_t it = int64_t(blockIdx.x) * kB + threadIdx.x; it < work; it += int64_t(gridDim.x) * kB) {
+    const int al = int(it % NC);
+    const int64_t r1 = it / NC;
+    const int64_t id = r1 % nodes;
+    const int pz = int(r1 / nodes);
+    int64_t t, n;
+    int c[DIM];
+    const int col = locate<DIM>(g, id, t, c, n);
+    const uint8_t mrow = dir ? dir[n] : default_mask<DIM>(c, N);
+    const bool row_fixed = (mrow >> al) & 1u;
+    double acc[OPP][NC];
 #pragma unroll
-  for (int b = 0; b < NL; ++b)
+    for (int o = 0; o < OPP; ++o)
 #pragma unroll
-    for (int be = 0; be < NC; ++be) acc[b][be] = 0.0;
+      for (int be = 0; be < NC; ++be) acc[o][be] = 0.0;
+    if (!row_fixed) {
 #pragma unroll
-  for (int q = 0; q < NL; ++q) {
-    const double* cf = C + int64_t(q * NK) * ne + eid;
-    const double vol = cf[0], shear = cf[ne], ccc = cf[2 * ne];
-    double Sr[DIM][DIM], Pc[DIM];
+      for (int a = 0; a < NL; ++a) {
+        // element e = c - bits(a); n is its local node a
+        const int az = DIM == 3 ? (a >> 2) & 1 : 0;
+        if (DIM == 3 && ((pz == 0 && az == 0) || (pz == 2 && az == 1))) continue;
+        int e[DIM];
+        bool ok = true;
 #pragma unroll
-    for (int i = 0; i < DIM; ++i) {
-      Pc[i] = cf[int64_t(3 + DIM * DIM + i) * ne];
-#pragma unroll
-      for (int jj = 0; jj < DIM; ++jj) Sr[i][jj] = cf[int64_t(3 + DIM * i + jj) * ne];
-    }
-    // shape data of local node a (runtime a: select from the unrolled table)
-    double Na = 0.0, dNa[DIM];
-#pragma unroll
-    for (int jj = 0; jj < DIM; ++jj) dNa[jj] = 0.0;
-#pragma unroll
-    for (int aa = 0; aa < NL; ++aa)
-      if (aa == a) {
-        Na = refN<DIM>(q, aa);
-#pragma unroll
-        for (int jj = 0; jj < DIM; ++jj) dNa[jj] = refdN<DIM>(q, aa, jj) * invh;
-      }
-    double dNal = 0.0, Sal[DIM], Pcal = 0.0;
-#pragma unroll
-    for (int jj = 0; jj < DIM; ++jj) Sal[jj] = 0.0;
-#pragma unroll
-    for (int i = 0; i < DIM; ++i)
-      if (i == al) {
-        dNal = dNa[i];
-        Pcal = Pc[i];
-#pragma unroll
-        for (int jj = 0; jj < DIM; ++jj) Sal[jj] = Sr[i][jj];
-      }
-    double SdNa = 0.0;  // sum_j S[al][j] dNa[j]
-#pragma unroll
-    for (int jj = 0; jj < DIM; ++jj) SdNa += Sal[jj] * dNa[jj];
-#pragma unroll
-    for (int b = 0; b < NL; ++b) {
-      const double Nb = refN<DIM>(q, b);
-      double dNb[DIM];
-      double dd = 0.0;
-#pragma unroll
-      for (int jj = 0; jj < DIM; ++jj) {
-        dNb[jj] = refdN<DIM>(q, b, jj) * invh;
-        dd += dNa[jj] * dNb[jj];
-      }
-      if (al < DIM) {
-        double dNbal = 0.0;
-#pragma unroll
-        for (int i = 0; i < DIM; ++i)
-          if (i == al) dNbal = dNb[i];
-#pragma unroll
-        for (int be = 0; be < DIM; ++be)
-          acc[b][be] += w * (vol * dNal * dNb[be] + shear * ((al == be ? dd : 0.0) + dNa[be] * dNbal));
-        acc[b][DIM] += w * (SdNa * Nb + Pcal * Na * Nb);
-      } else {
-#pragma unroll
-        for (int be = 0; be < DIM; ++be) {
-          double cu = Pc[be] * Na * Nb;
-#pragma unroll
-          for (int jj = 0; jj < DIM; ++jj) cu += Sr[be][jj] * dNb[jj] * Na;
-          acc[b][be] += w * cu;
+        for (int i = 0; i < DIM; ++i) {
+          e[i] = c[i] - ((a >> i) & 1);
+          ok &= (e[i] >= 0) & (e[i] < N);
         }
-        acc[b][DIM] += w * (ccc * Na * Nb + gcl * dd);
+        if (!ok) continue;
+        int64_t eid = 0, st = 1;
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) {
+          eid += int64_t(e[i]) * st;
+          st *= N;
+        }
+        const double* cfe = C + eid * (NL * NK);
+#pragma unroll 1
+        for (int q = 0; q < NL; ++q) {
+          const double* cf = cfe + q * NK;
+          const double vol = cf[0], shear = cf[1], ccc = cf[2];
+          double Sr[DIM][DIM], Pc[DIM];
+#pragma unroll
+          for (int i = 0; i < DIM; ++i) {
+            Pc[i] = cf[3 + DIM * DIM + i];
+#pragma unroll
+            for (int jj = 0; jj < DIM; ++jj) Sr[i][jj] = cf[3 + DIM * i + jj];
+          }
+          const double Na = refN<DIM>(q, a);
+          double dNa[DIM];
+#pragma unroll
+          for (int jj = 0; jj < DIM; ++jj) dNa[jj] = refdN<DIM>(q, a, jj) * invh;
+          double dNal = 0.0, Sal[DIM], Pcal = 0.0;
+#pragma unroll
+          for (int jj = 0; jj < DIM; ++jj) Sal[jj] = 0.0;
+#pragma unroll
+          for (int i = 0; i < DIM; ++i)
+            if (i == al) {
+              dNal = dNa[i];
+              Pcal = Pc[i];
+#pragma unroll
+              for (int jj = 0; jj < DIM; ++jj) Sal[jj] = Sr[i][jj];
+            }
+          double SdNa = 0.0;
+#pragma unroll
+          for (int jj = 0; jj < DIM; ++jj) SdNa += Sal[jj] * dNa[jj];
+#pragma unroll
+          for (int b = 0; b < NL; ++b) {
+            const int bz = DIM == 3 ? (b >> 2) & 1 : 0;
+            if (DIM == 3 && bz - az + 1 != pz) continue;
+            // in-plane offset of node b relative to node a
+            int o = 0, om = 1;
+#pragma unroll
+            for (int i = 0; i < (DIM == 3 ? 2 : DIM); ++i) {
+              o += (((b >> i) & 1) - ((a >> i) & 1) + 1) * om;
+              om *= 3;
+            }
+            const double Nb = refN<DIM>(q, b);
+            double dNb[DIM];
+            double dd = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < DIM; ++jj) {
+              dNb[jj] = refdN<DIM>(q, b, jj) * invh;
+              dd += dNa[jj] * dNb[jj];
+            }
+            if (al < DIM) {
+              double dNbal = 0.0;
+#pragma unroll
+              for (int i = 0; i < DIM; ++i)
+                if (i == al) dNbal = dNb[i];
+#pragma unroll
+              for (int be = 0; be < DIM; ++be)
+                acc[o][be] += w * (vol * dNal * dNb[be] + shear * ((al == be ? dd : 0.0) + dNa[be] * dNbal));
+              acc[o][DIM] += w * (SdNa * Nb + Pcal * Na * Nb);
+            } else {
+#pragma unroll
+              for (int be = 0; be < DIM; ++be) {
+                double cu = Pc[be] * Na * Nb;
+#pragma unroll
+                for (int jj = 0; jj < DIM; ++jj) cu += Sr[be][jj] * dNb[jj] * Na;
+                acc[o][be] += w * cu;
+              }
+              acc[o][DIM] += w * (ccc * Na * Nb + gcl * dd);
+            }
+          }
+        }
+      }
+    }
+    const int64_t cnt = g.cnt[col];
+    TO* out = S + g.base[col] * RB + t;
+#pragma unroll
+    for (int o = 0; o < OPP; ++o) {
+      const int of = o + OPP * pz;
+      int m[DIM];
+      bool inside = true;
+      int64_t mid = 0, s2 = 1;
+      int oo = of;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) {
+        m[i] = c[i] + oo % 3 - 1;
+        oo /= 3;
+        inside &= (m[i] >= 0) & (m[i] <= N);
+        mid += int64_t(m[i]) * s2;
+        s2 *= ns;
+      }
+      const uint8_t mcol = inside ? (dir ? dir[mid] : default_mask<DIM>(m, N)) : uint8_t(0xff);
+#pragma unroll
+      for (int be = 0; be < NC; ++be) {
+        const double v = (row_fixed || ((mcol >> be) & 1u)) ? 0.0 : acc[o][be];
+        out[int64_t((al * NO + of) * NC + be) * cnt] = TO(v);
       }
     }
   }
-  // node a of this element: colour and index within the colour
-  int c[DIM];
+}
+
+// ---------------------------------------------------------------- RAP
+// Galerkin coarsening R S I of a block stencil (eq. (delta_terms)) for the
+// nested trilinear (bilinear) prolongation, done one direction at a time:
+// I = I_x (x) I_y (x) I_z, so R S I = R_z R_y R_x S I_x I_y I_z, and each
+// factor maps a 3-point stencil direction to a 3-point one.  One pass
+// coarsens direction D: output node C takes the fine rows a_D = 2 C_D + da
+// (weight 1 for da = 0, 1/2 for da = +-1); an entry towards offset o_D in
+// {-1, 0, 1} reaches the fine node b_D = a_D + o_D, whose coarse parents are
+// J_D = C_D + e/2 (e = da + o_D even, weight 1) or C_D + (e -+ 1)/2 (odd,
+// weight 1/2 each).  Components are not mixed (the prolongation is scalar).
+// Intermediate stencils are node-major structure-of-arrays,
+// T[k nn + node] with k = (al 3^d + o)(d+1) + be; the finest input and the
+// coarse output use the colour-major layout above.  The last pass zeroes the
+// rows and columns of the coarse Dirichlet dofs.
+struct Box3 {
+  int n[3];  // nodes per direction (n[2] = 1 in 2D)
+};
+
+template <int DIM>
+__device__ inline int64_t colour_index(const Colours& g, const int (&a)[DIM], int64_t k) {
+  constexpr int RB = row_block<DIM>();
   int col = 0;
-  int64_t t = 0, n = 0, mul = 1, sn = 1;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) col |= (a[i] & 1) << i;
+  int64_t t = 0, mul = 1;
 #pragma unroll
   for (int i = 0; i < DIM; ++i) {
-    c[i] = e[i] + ((a >> i) & 1);
-    col |= (c[i] & 1) << i;
-  }
-#pragma unroll
-  for (int i = 0; i < DIM; ++i) {
-    t += int64_t(c[i] >> 1) * mul;
+    t += int64_t(a[i] >> 1) * mul;
     mul *= g.len[col][i];
-    n += int64_t(c[i]) * sn;
-    sn *= (N + 1);
   }
-  const uint8_t mrow = dir ? dir[n] : default_mask<DIM>(c, N);
-  if ((mrow >> al) & 1u) return;
-  const int64_t cnt = g.cnt[col];
-  TO* out = S + g.base[col] * RB + t;
+  return g.base[col] * RB + k * g.cnt[col] + t;
+}
+
+template <int DIM>
+__device__ inline int64_t box_index(const Box3& b, const int (&a)[DIM]) {
+  int64_t id = 0, mul = 1;
 #pragma unroll
-  for (int b = 0; b < NL; ++b) {
-    int m[DIM], o = 0, om = 1;
-    int64_t mid = 0, s2 = 1;
+  for (int i = 0; i < DIM; ++i) {
+    id += int64_t(a[i]) * mul;
+    mul *= b.n[i];
+  }
+  return id;
+}
+
+template <int DIM, int D, typename TI, int IN_COL, int OUT_COL>
+__global__ __launch_bounds__(kB) void k_st_rap1(Colours gin, Box3 bin, Colours gout, Box3 bout,
+                                                const TI* __restrict__ Sin, double* __restrict__ Sout,
+                                                const uint8_t* __restrict__ dirc) {
+  constexpr int NC = DIM + 1, NO = n_off<DIM>(), NOTH = NO / 3;
+  int64_t nin = 1, nout = 1;
 #pragma unroll
-    for (int i = 0; i < DIM; ++i) {
-      m[i] = e[i] + ((b >> i) & 1);
-      o += (((b >> i) & 1) - ((a >> i) & 1) + 1) * om;
-      om *= 3;
-      mid += int64_t(m[i]) * s2;
-      s2 *= (N + 1);
+  for (int i = 0; i < DIM; ++i) {
+    nin *= bin.n[i];
+    nout *= bout.n[i];
+  }
+  const int64_t work = nout * NC * NOTH;
+  for (int64_t it = int64_t(blockIdx.x) * kB + threadIdx.x; it < work; it += int64_t(gridDim.x) * kB) {
+    const int64_t node = it % nout;
+    const int64_t r1 = it / nout;
+    const int al = int(r1 % NC);
+    const int oth = int(r1 / NC);
+    int C[DIM];
+    {
+      int64_t r = node;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) {
+        C[i] = int(r % bout.n[i]);
+        r /= bout.n[i];
+      }
     }
-    const uint8_t mcol = dir ? dir[mid] : default_mask<DIM>(m, N);
+    // offset digits of the other directions (in order of increasing index)
+    int od[DIM];
+    {
+      int r = oth;
 #pragma unroll
-    for (int be = 0; be < NC; ++be) {
-      if ((mcol >> be) & 1u) continue;
-      TO* dst = out + int64_t((al * NO + o) * NC + be) * cnt;
-      *dst = TO(double(*dst) + acc[b][be]);
+      for (int i = 0; i < DIM; ++i) {
+        if (i == D) continue;
+        od[i] = r % 3;
+        r /= 3;
+      }
+    }
+    double acc[3][NC];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int be = 0; be < NC; ++be) acc[j][be] = 0.0;
+#pragma unroll
+    for (int da = -1; da <= 1; ++da) {
+      int a[DIM];
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) a[i] = C[i];
+      a[D] = 2 * C[D] + da;
+      if (a[D] < 0 || a[D] >= bin.n[D]) continue;
+      const double wa = da == 0 ? 1.0 : 0.5;
+#pragma unroll
+      for (int oD = 0; oD < 3; ++oD) {
+        int o = 0, om = 1;
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) {
+          o += (i == D ? oD : od[i]) * om;
+          om *= 3;
+        }
+        const int e = da + oD - 1;  // b_D - 2 C_D, in -2 .. 2
+        double v[NC];
+#pragma unroll
+        for (int be = 0; be < NC; ++be) {
+          const int64_t k = int64_t((al * NO + o) * NC + be);
+          v[be] = IN_COL ? double(Sin[colour_index<DIM>(gin, a, k)]) : double(Sin[k * nin + box_index<DIM>(bin, a)]);
+        }
+        if ((e & 1) == 0) {
+          const int J = e / 2 + 1;
+#pragma unroll
+          for (int be = 0; be < NC; ++be) acc[J][be] += wa * v[be];
+        } else {
+          const int J0 = (e - 1) / 2 + 1, J1 = (e + 1) / 2 + 1;
+#pragma unroll
+          for (int be = 0; be < NC; ++be) {
+            acc[J0][be] += 0.5 * wa * v[be];
+            acc[J1][be] += 0.5 * wa * v[be];
+          }
+        }
+      }
+    }
+    bool row_fixed = false;
+    if (OUT_COL) {
+      const uint8_t mrow = dirc ? dirc[box_index<DIM>(bout, C)] : default_mask<DIM>(C, bout.n[0] - 1);
+      row_fixed = (mrow >> al) & 1u;
+    }
+#pragma unroll
+    for (int J = 0; J < 3; ++J) {
+      int o = 0, om = 1;
+      int m[DIM];
+      bool inside = true;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) {
+        const int di = i == D ? J : od[i];
+        o += di * om;
+        om *= 3;
+        m[i] = C[i] + di - 1;
+        inside &= (m[i] >= 0) & (m[i] < bout.n[i]);
+      }
+      uint8_t mcol = 0;
+      if (OUT_COL && inside) mcol = dirc ? dirc[box_index<DIM>(bout, m)] : default_mask<DIM>(m, bout.n[0] - 1);
+#pragma unroll
+      for (int be = 0; be < NC; ++be) {
+        const int64_t k = int64_t((al * NO + o) * NC + be);
+        double val = acc[J][be];
+        if (OUT_COL) {
+          if (row_fixed || !inside || ((mcol >> be) & 1u)) val = 0.0;
+          Sout[colour_index<DIM>(gout, C, k)] = val;
+        } else {
+          Sout[k * nout + node] = val;
+        }
+      }
     }
   }
 }
@@ -559,21 +707,10 @@ static hipError_t st_assemble_t(const ElemArgs& a, const double* xl, const doubl
   for (int i = 0; i < DIM; ++i) ne *= a.N;
   const Colours g = colours(DIM, a.N);
   const double gcl = a.m.Gc * a.m.ls;
-  const int64_t nval = int64_t(stencil_values(DIM, a.N));
-  if (sizeof(TO) == 8)
-    hipLaunchKernelGGL(k_zero_d, dim3(gridn(nval)), dim3(kB), 0, st, nval, (double*)S);
-  else
-    hipLaunchKernelGGL(k_zero_f, dim3(gridn(nval)), dim3(kB), 0, st, nval, (float*)S);
   hipLaunchKernelGGL(k_coef<DIM>, dim3(gridn(ne)), dim3(kB), 0, st, a.N, a.h, a.m, xl, p, coef);
-  for (int cls = 0; cls < NL; ++cls) {
-    int64_t ncls = 1;
-    for (int i = 0; i < DIM; ++i) ncls *= (a.N - ((cls >> i) & 1) + 1) / 2;
-    if (ncls == 0) continue;
-    const int64_t nchunks = (ncls + kB - 1) / kB;
-    const int64_t nblk = ((nchunks + 7) / 8) * 8 * (NL * NC);
-    hipLaunchKernelGGL((k_st_elem<DIM, TO>), dim3(unsigned(nblk)), dim3(kB), 0, st, g, a.h, gcl, cls, ncls, nchunks,
-                       coef, a.dir, S);
-  }
+  constexpr int NP = DIM == 3 ? 3 : 1;
+  const int64_t work = g.base[NL] * NC * NP;
+  hipLaunchKernelGGL((k_st_node<DIM, TO>), dim3(gridn(work)), dim3(kB), 0, st, g, a.h, gcl, coef, a.dir, S);
   return hipGetLastError();
 }
 
@@ -666,6 +803,52 @@ hipError_t launch_st_pgs(int dim, int N, const void* S, const uint8_t* dir, cons
                                (float*)s, n_sweeps, st);
   return st_sweeps<2, double>(N, (const double*)S, dir, (const double*)g, (const double*)lo, (const double*)hi,
                               (double*)s, n_sweeps, st);
+}
+
+size_t st_rap_work_doubles(int dim, int Nf) {
+  const int Nc = Nf / 2;
+  const size_t rb = size_t(dim == 3 ? row_block<3>() : row_block<2>());
+  size_t a = 1, b = 1;
+  for (int i = 0; i < dim; ++i) {
+    a *= size_t(i == 0 ? Nc + 1 : Nf + 1);
+    b *= size_t(i <= 1 ? Nc + 1 : Nf + 1);
+  }
+  return (a + (dim == 3 ? b : 0)) * rb;
+}
+
+template <int DIM, typename TI>
+static hipError_t st_rap_t(int Nf, const TI* Sf, double* Sc, const uint8_t* dirc, double* work, hipStream_t st) {
+  const int Nc = Nf / 2;
+  const Colours gf = colours(DIM, Nf), gc = colours(DIM, Nc);
+  Box3 b0{{Nf + 1, Nf + 1, DIM == 3 ? Nf + 1 : 1}};
+  Box3 b1{{Nc + 1, Nf + 1, DIM == 3 ? Nf + 1 : 1}};
+  Box3 b2{{Nc + 1, Nc + 1, DIM == 3 ? Nf + 1 : 1}};
+  Box3 b3{{Nc + 1, Nc + 1, DIM == 3 ? Nc + 1 : 1}};
+  constexpr int NC = DIM + 1, NOTH = n_off<DIM>() / 3;
+  auto grid = [&](const Box3& b) {
+    int64_t n = int64_t(b.n[0]) * b.n[1] * b.n[2];
+    return dim3(gridn(n * NC * NOTH));
+  };
+  double* T1 = work;
+  if constexpr (DIM == 3) {
+    double* T2 = work + int64_t(b1.n[0]) * b1.n[1] * b1.n[2] * row_block<DIM>();
+    hipLaunchKernelGGL((k_st_rap1<DIM, 0, TI, 1, 0>), grid(b1), dim3(kB), 0, st, gf, b0, gc, b1, Sf, T1, dirc);
+    hipLaunchKernelGGL((k_st_rap1<DIM, 1, double, 0, 0>), grid(b2), dim3(kB), 0, st, gf, b1, gc, b2, T1, T2, dirc);
+    hipLaunchKernelGGL((k_st_rap1<DIM, 2, double, 0, 1>), grid(b3), dim3(kB), 0, st, gf, b2, gc, b3, T2, Sc, dirc);
+  } else {
+    hipLaunchKernelGGL((k_st_rap1<DIM, 0, TI, 1, 0>), grid(b1), dim3(kB), 0, st, gf, b0, gc, b1, Sf, T1, dirc);
+    hipLaunchKernelGGL((k_st_rap1<DIM, 1, double, 0, 1>), grid(b3), dim3(kB), 0, st, gf, b1, gc, b3, T1, Sc, dirc);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_st_rap(int dim, int Nf, const void* Sf, int fp32, double* Sc, const uint8_t* dirc, double* work,
+                         hipStream_t st) {
+  if (dim == 3)
+    return fp32 ? st_rap_t<3, float>(Nf, (const float*)Sf, Sc, dirc, work, st)
+                : st_rap_t<3, double>(Nf, (const double*)Sf, Sc, dirc, work, st);
+  return fp32 ? st_rap_t<2, float>(Nf, (const float*)Sf, Sc, dirc, work, st)
+              : st_rap_t<2, double>(Nf, (const double*)Sf, Sc, dirc, work, st);
 }
 
 }  // namespace rmtr

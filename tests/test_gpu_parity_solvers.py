@@ -100,6 +100,28 @@ def test_galerkin_element_matrices(d, N, L):
     assert field_rel_err(host(s), so, d) <= 1e-11
 
 
+@pytest.mark.parametrize("d,N,L", [(2, 16, 3), (2, 14, 2), (3, 8, 3), (3, 12, 2), (3, 16, 4)])
+def test_coarse_hessvec_is_dense_rap(d, N, L):
+    """The load step's coarse Hessians (finest stencil coarsened direction by
+    direction) equal D_c (I^T H I) D_c formed densely, level after level."""
+    print(f"case d={d} N={N} L={L}", flush=True)
+    g, x, p = rand_state(d, N, seed=5 * N + L)
+    mat = material(N)
+    ctx = ctx_for(d, N, L, mat)
+    H = fem.hessian(g, x, p, mat)
+    rng = np.random.default_rng(N)
+    Hl, Nl = H, N
+    for level in range(L - 1, 0, -1):
+        Hl, gl = _masked_galerkin(d, Nl // 2, Hl)
+        Nl //= 2
+        v = rng.standard_normal(gl.n_dofs)
+        ref = Hl @ v
+        got = host(ctx.coarse_hessvec(level, dev(x), dev(p), dev(v)))
+        assert field_rel_err(got, ref, d) <= 1e-12, (level, field_rel_err(got, ref, d))
+        got32 = host(ctx.coarse_hessvec(level, dev(x), dev(p), dev(v), fp32_stencil=True))
+        assert field_rel_err(got32, ref, d) <= 1e-5
+
+
 @pytest.mark.parametrize("d,N", [(2, 8), (3, 4), (3, 8)])
 def test_mprgp_matches_oracle_on_convex_qp(d, N):
     g, x, p = rand_state(d, N, seed=3 * N, u_scale=1e-5, p_scale=1e-6, c_max=0.3)
