@@ -8,12 +8,13 @@
 // 3^d x (d+1) values,
 //   row (n, al), entry (o, be) = H[(n, al), (n + off(o), be)],
 //   off(o) = (o % 3 - 1, (o / 3) % 3 - 1, o / 9 - 1),
-// with rows and columns of Dirichlet dofs zero.  Storage is colour-major so
-// that the threads of a Gauss-Seidel colour pass read consecutive addresses:
-// nodes are grouped by colour (i%2 + 2 (j%2) + 4 (k%2)); node t of colour c
-// (t = lexicographic index among the colour's nodes) keeps value k of its
-// row block (k = (al 3^d + o)(d+1) + be) at
-//   S[base[c] * RB + k * cnt[c] + t],   RB = (d+1) 3^d (d+1).
+// with rows and columns of Dirichlet dofs zero.  Storage is colour-major and
+// chunked so that a wavefront of a Gauss-Seidel colour pass streams one
+// contiguous block: nodes are grouped by colour (i%2 + 2 (j%2) + 4 (k%2)),
+// each colour padded to a multiple of 64 nodes (pbase[c] = padded start);
+// node t of colour c (t = lexicographic index among the colour's nodes)
+// keeps value k of its row block (k = (al 3^d + o)(d+1) + be) at
+//   S[(pbase[c] + 64 (t / 64)) RB + 64 k + t % 64],   RB = (d+1) 3^d (d+1).
 #include "rmtr_kernels.h"
 
 namespace rmtr {
@@ -44,17 +45,21 @@ int gridn(int64_t work) {
 }
 
 // Colour geometry of one level.
+constexpr int kChunk = 64;  // nodes per stencil chunk (one wavefront)
+
 struct Colours {
   int N;
-  int64_t cnt[8];   // nodes per colour
-  int64_t base[9];  // prefix sums of cnt
-  int len[8][3];    // nodes per direction within a colour
+  int64_t cnt[8];    // nodes per colour
+  int64_t base[9];   // prefix sums of cnt
+  int64_t pbase[9];  // prefix sums of cnt rounded up to kChunk
+  int len[8][3];     // nodes per direction within a colour
 };
 
 Colours colours(int dim, int N) {
   Colours g{};
   g.N = N;
   g.base[0] = 0;
+  g.pbase[0] = 0;
   for (int c = 0; c < (1 << dim); ++c) {
     int64_t n = 1;
     for (int i = 0; i < dim; ++i) {
@@ -63,6 +68,7 @@ Colours colours(int dim, int N) {
     }
     g.cnt[c] = n;
     g.base[c + 1] = g.base[c] + n;
+    g.pbase[c + 1] = g.pbase[c] + (n + kChunk - 1) / kChunk * kChunk;
   }
   return g;
 }
@@ -85,6 +91,12 @@ __device__ inline int locate(const Colours& g, int64_t id, int64_t& t, int (&c)[
     s *= (g.N + 1);
   }
   return col;
+}
+
+// start of the row block of node t of colour col; value k sits at + kChunk k
+template <int DIM>
+__device__ inline int64_t st_row(const Colours& g, int col, int64_t t) {
+  return (g.pbase[col] + (t & ~int64_t(kChunk - 1))) * row_block<DIM>() + (t & (kChunk - 1));
 }
 
 // Second-variation coefficients at the 2^DIM quadrature points of every
@@ -271,8 +283,7 @@ __global__ __launch_bounds__(kB) void k_st_node(Colours g, double h, double gcl,
         }
       }
     }
-    const int64_t cnt = g.cnt[col];
-    TO* out = S + g.base[col] * RB + t;
+    TO* out = S + st_row<DIM>(g, col, t);
 #pragma unroll
     for (int o = 0; o < OPP; ++o) {
       const int of = o + OPP * pz;
@@ -292,7 +303,7 @@ __global__ __launch_bounds__(kB) void k_st_node(Colours g, double h, double gcl,
 #pragma unroll
       for (int be = 0; be < NC; ++be) {
         const double v = (row_fixed || ((mcol >> be) & 1u)) ? 0.0 : acc[o][be];
-        out[int64_t((al * NO + of) * NC + be) * cnt] = TO(v);
+        out[((al * NO + of) * NC + be) * kChunk] = TO(v);
       }
     }
   }
@@ -328,7 +339,7 @@ __device__ inline int64_t colour_index(const Colours& g, const int (&a)[DIM], in
     t += int64_t(a[i] >> 1) * mul;
     mul *= g.len[col][i];
   }
-  return g.base[col] * RB + k * g.cnt[col] + t;
+  return (g.pbase[col] + (t & ~int64_t(kChunk - 1))) * RB + k * kChunk + (t & (kChunk - 1));
 }
 
 template <int DIM>
@@ -510,12 +521,11 @@ __global__ __launch_bounds__(kB) void k_em_to_st(Colours g, const double* __rest
         for (int be = 0; be < NC; ++be) acc[o][be] += Ke[NC * b + be];
       }
     }
-    const int64_t cnt = g.cnt[col];
-    TO* out = S + g.base[col] * RB + t;
+    TO* out = S + st_row<DIM>(g, col, t);
 #pragma unroll
     for (int o = 0; o < NO; ++o)
 #pragma unroll
-      for (int be = 0; be < NC; ++be) out[int64_t((al * NO + o) * NC + be) * cnt] = TO(acc[o][be]);
+      for (int be = 0; be < NC; ++be) out[((al * NO + o) * NC + be) * kChunk] = TO(acc[o][be]);
   }
 }
 
@@ -534,8 +544,7 @@ __global__ __launch_bounds__(kB) void k_st_mv(Colours g, const T* __restrict__ S
     int64_t t, n;
     int c[DIM];
     const int col = locate<DIM>(g, id, t, c, n);
-    const int64_t cnt = g.cnt[col];
-    const T* Sn = S + g.base[col] * RB + int64_t(al * NO * NC) * cnt + t;
+    const T* Sn = S + st_row<DIM>(g, col, t) + al * NO * NC * kChunk;
     T acc = T(0);
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
@@ -552,7 +561,7 @@ __global__ __launch_bounds__(kB) void k_st_mv(Colours g, const T* __restrict__ S
       }
       if (!ok) continue;
 #pragma unroll
-      for (int be = 0; be < NC; ++be) acc += Sn[int64_t(o * NC + be) * cnt] * v[NC * m + be];
+      for (int be = 0; be < NC; ++be) acc += Sn[(o * NC + be) * kChunk] * v[NC * m + be];
     }
     y[NC * n + al] = acc;
   }
@@ -570,11 +579,10 @@ __global__ __launch_bounds__(kB) void k_st_rowabs(Colours g, const double* __res
     int64_t t, n;
     int c[DIM];
     const int col = locate<DIM>(g, id, t, c, n);
-    const int64_t cnt = g.cnt[col];
-    const double* Sn = S + g.base[col] * RB + t;
+    const double* Sn = S + st_row<DIM>(g, col, t);
     for (int al = 0; al < NC; ++al) {
       double rs = 0.0;
-      for (int j = 0; j < NO * NC; ++j) rs += fabs(Sn[int64_t(al * NO * NC + j) * cnt]);
+      for (int j = 0; j < NO * NC; ++j) rs += fabs(Sn[(al * NO * NC + j) * kChunk]);
       mn = fmin(mn, -rs);
       gg += gv[NC * n + al] * gv[NC * n + al];
     }
@@ -616,8 +624,8 @@ __device__ inline T pgs_update_st(T s, T r, T d, T lo, T hi) {
 // One colour pass of projected Gauss-Seidel: a thread per node of colour
 // `col`; the components are updated in order (backward: reverse) with the
 // node's diagonal block (offset (3^d - 1) / 2).
-template <int DIM, typename T>
-__global__ __launch_bounds__(kB) void k_st_pgs(Colours g, int col, int backward, const T* __restrict__ S,
+template <int DIM, typename T, int BACKWARD>
+__global__ __launch_bounds__(kB) void k_st_pgs(Colours g, int col, const T* __restrict__ S,
                                                const uint8_t* __restrict__ dir, const T* __restrict__ gv,
                                                const T* __restrict__ lo, const T* __restrict__ hi,
                                                T* __restrict__ s) {
@@ -637,7 +645,7 @@ __global__ __launch_bounds__(kB) void k_st_pgs(Colours g, int col, int backward,
     }
     const uint8_t mk = dir ? dir[n] : default_mask<DIM>(c, N);
     if (mk == uint8_t((1u << NC) - 1u)) continue;
-    const T* Sn = S + g.base[col] * RB + t;
+    const T* Sn = S + st_row<DIM>(g, col, t);
     T r[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) r[k] = gv[NC * n + k];
@@ -661,7 +669,7 @@ __global__ __launch_bounds__(kB) void k_st_pgs(Colours g, int col, int backward,
 #pragma unroll
       for (int al = 0; al < NC; ++al)
 #pragma unroll
-        for (int be = 0; be < NC; ++be) r[al] += Sn[int64_t((al * NO + o) * NC + be) * cnt] * sv[be];
+        for (int be = 0; be < NC; ++be) r[al] += Sn[((al * NO + o) * NC + be) * kChunk] * sv[be];
     }
     T sn[NC], s0[NC], D[NC][NC];
 #pragma unroll
@@ -669,11 +677,11 @@ __global__ __launch_bounds__(kB) void k_st_pgs(Colours g, int col, int backward,
       s0[k] = s[NC * n + k];
       sn[k] = s0[k];
 #pragma unroll
-      for (int l = 0; l < NC; ++l) D[k][l] = Sn[int64_t((k * NO + CEN) * NC + l) * cnt];
+      for (int l = 0; l < NC; ++l) D[k][l] = Sn[((k * NO + CEN) * NC + l) * kChunk];
     }
 #pragma unroll
     for (int kk = 0; kk < NC; ++kk) {
-      const int k = backward ? NC - 1 - kk : kk;
+      const int k = BACKWARD ? NC - 1 - kk : kk;
       if (mk & (1u << k)) continue;
       T rk = r[k];
 #pragma unroll
@@ -688,9 +696,8 @@ __global__ __launch_bounds__(kB) void k_st_pgs(Colours g, int col, int backward,
 }  // namespace
 
 size_t stencil_values(int dim, int N) {
-  int64_t nn = 1;
-  for (int i = 0; i < dim; ++i) nn *= (N + 1);
-  return size_t(nn) * (dim + 1) * (dim == 3 ? 27 : 9) * (dim + 1);
+  const Colours g = colours(dim, N);
+  return size_t(g.pbase[1 << dim]) * (dim + 1) * (dim == 3 ? 27 : 9) * (dim + 1);
 }
 
 size_t coef_values(int dim, int N) {
@@ -781,8 +788,12 @@ static hipError_t st_sweeps(int N, const T* S, const uint8_t* dir, const T* gv, 
     for (int bw = 0; bw < 2; ++bw)
       for (int cc = 0; cc < NCOL; ++cc) {
         const int col = bw ? NCOL - 1 - cc : cc;
-        hipLaunchKernelGGL((k_st_pgs<DIM, T>), dim3(gridn(g.cnt[col])), dim3(kB), 0, st, g, col, bw, S, dir, gv, lo,
-                           hi, s);
+        if (bw)
+          hipLaunchKernelGGL((k_st_pgs<DIM, T, 1>), dim3(gridn(g.cnt[col])), dim3(kB), 0, st, g, col, S, dir, gv, lo,
+                             hi, s);
+        else
+          hipLaunchKernelGGL((k_st_pgs<DIM, T, 0>), dim3(gridn(g.cnt[col])), dim3(kB), 0, st, g, col, S, dir, gv, lo,
+                             hi, s);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
       }
