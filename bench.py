@@ -89,7 +89,7 @@ def cpu_baseline(wl, x_np, p_np, v_np, budget_s=20.0):
                       f"(4 dofs per element), numpy/scipy FP64 single thread, {dt:.1f} s"}
 
 
-def learned_leg(ctx, wl, P, W, torch, train_seconds):
+def learned_leg(ctx, wl, P, W, torch, train_seconds, target):
     """Harvest (state, gradient) -> PGS-correction pairs from plain runs on
     other fracture networks of the same grid (10-50 discs, seeds 1000 + r),
     train the proposal network on the GPU, and return it with the training
@@ -104,7 +104,7 @@ def learned_leg(ctx, wl, P, W, torch, train_seconds):
         c0r, pr = ctx.init_fields(L, tab, band=wl.h, p_mode=0, p_value=wl.p)
         xr = torch.zeros(4 * (N + 1) ** 3, dtype=torch.float64, device="cuda")
         xr.view(-1, 4)[:, 3] = c0r
-        samples += learned.harvest_run(ctx, xr, pr, c0r, 6)
+        samples += learned.harvest_run(ctx, xr, pr, c0r, 6, target=target)
     torch.cuda.synchronize()
     t_harvest = time.perf_counter() - t0
     net = learned.ProposalNet(ctx, seed=0)
@@ -115,7 +115,7 @@ def learned_leg(ctx, wl, P, W, torch, train_seconds):
     loss0 = tr.mean_loss()
     steps, t_train = tr.train(100000, seed=1, time_limit=train_seconds)
     loss1 = tr.mean_loss()
-    info = {"samples": len(tr.data), "harvest_s": t_harvest, "train_steps": steps, "train_s": t_train,
+    info = {"target": target, "samples": len(tr.data), "harvest_s": t_harvest, "train_steps": steps, "train_s": t_train,
             "loss_initial": loss0, "loss_final": loss1}
     tr.data = []
     return net, info
@@ -130,6 +130,7 @@ def main():
     ap.add_argument("--no-loadstep", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--train-seconds", type=float, default=30.0)
+    ap.add_argument("--learned-target", choices=("pgs", "vcycle"), default="pgs")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernels-only", action="store_true",
                     help="time only the kernel triple (for profiler runs)")
@@ -229,7 +230,7 @@ def main():
         legs = [("plain_fp64", 0, None), ("mixed_fp32", 1, None)]
         net = None
         if not args.no_learned:
-            net, rmtr["training"] = learned_leg(ctx, wl, P, W, torch, args.train_seconds)
+            net, rmtr["training"] = learned_leg(ctx, wl, P, W, torch, args.train_seconds, args.learned_target)
             log("training", rmtr["training"])
             legs.append(("mixed_learned", 1, net))
         for name, prec, nn in legs:

@@ -227,10 +227,14 @@ rmtr_status rmtr_chi(rmtr_ctx* ctx, int32_t level, const double* x, const double
    Hessian lagging, Sec. 4.2.1) from x_inout until chi <= rtol chi(x_in) or
    max_vcycles.  With params->use_learned, each V-cycle first tries the
    learned proposal on the finest level: it is projected onto the step box,
-   judged by the FP64 ratio of eq. (rho_tr) against the lagged model, and
+   scaled by the model minimiser beta in (0, 1] along it (it must be a
+   descent direction of the model, with beta >= 1/2), judged by the FP64
+   ratio of
+   eq. (rho_tr) against the lagged model, and
    taken in place of the first PGS pre-smoothing step if rho > eta1 and its
-   predicted decrease is at least that of the Cauchy step (the model
-   minimiser along -g, projected onto the box); otherwise the PGS step runs.  A rejected proposal leaves delta unchanged.  p: fine nodal pressure; c_lower: c^{t-1} per fine node;
+   predicted decrease is at least that of a Cauchy step (d = P(-t g),
+   t = g^T g / g^T H g, projected onto the box, scaled by the exact model
+   minimiser alpha in [0, 1]); otherwise the PGS step runs.  A rejected proposal leaves delta unchanged.  p: fine nodal pressure; c_lower: c^{t-1} per fine node;
    x_inout must be feasible.  chi_history (host, may be NULL) receives chi
    after each V-cycle (max_vcycles entries).  Returns RMTR_OK,
    RMTR_NOT_CONVERGED (x still feasible) or an error.  Synchronises. */
@@ -258,9 +262,12 @@ rmtr_status rmtr_step_box(rmtr_ctx* ctx, int32_t level, const double* x, const d
    channels-last FP32 on nx*ny*nz voxels, voxel v = i + nx (j + ny k).
    Weights are BF16 (round-to-nearest-even of FP32 masters), [27][Cin][Cout]
    per layer, layers concatenated; FP32 arithmetic.
-   Input channels: (u, c) of x times scales[0..3], then g times
-   scales[4..7]; output channel k times scales[8+k] is the proposed step of
-   component k (3D only). */
+   Input channels: (u, c) of x times scales[0..3], then g_k / rms(g_k) times
+   scales[4..7], rms(g_k) the root mean square of component k of g over the
+   level's nodes (the input is 0 where it vanishes); output channel k times
+   scales[8+k] rms(g_k) is the proposed step of component k (3D only).  The
+   network is thus first-order homogeneous in g: its step scales with the
+   gradient as a Newton-type correction does. */
 #define RMTR_NN_WEIGHTS 120960
 #define RMTR_NN_BIASES 164
 
@@ -298,13 +305,13 @@ rmtr_status rmtr_nn_adam_step(rmtr_ctx* ctx, int64_t n, int64_t n_bf16, float lr
 rmtr_status rmtr_nn_to_bf16(rmtr_ctx* ctx, int64_t n, const float* master, uint16_t* w_bf16, void* stream);
 
 /* Network input from a state of `level`: in8[8 n + k] = x[4 n + k] *
-   scales[k] (k < 4), g[4 n + k - 4] * scales[k] (k >= 4). */
+   scales[k] (k < 4), g[4 n + k - 4] / rms(g_{k-4}) * scales[k] (k >= 4). */
 rmtr_status rmtr_nn_features(rmtr_ctx* ctx, int32_t level, const double* x, const double* g, const float* scales,
                              float* in8, void* stream);
 
 /* Proposed step of `level` (3D): features of (x, g), forward pass, output
-   scaled and projected onto [lo, hi] (non-finite values become 0 before the
-   projection); s: FP64, (d+1) per node. */
+   channel k times scales[8+k] rms(g_k), projected onto [lo, hi] (non-finite
+   values become 0 before the projection); s: FP64, (d+1) per node. */
 rmtr_status rmtr_nn_propose(rmtr_ctx* ctx, int32_t level, const rmtr_nn* net, const double* x, const double* g,
                             const double* lo, const double* hi, double* s, void* stream);
 

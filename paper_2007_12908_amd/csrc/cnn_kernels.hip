@@ -303,24 +303,60 @@ __global__ __launch_bounds__(kB) void k_to_bf16(int64_t n, const float* __restri
   for (int64_t i = int64_t(blockIdx.x) * kB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kB) b[i] = f2bf(a[i]);
 }
 
-// Network input from the grid state: channels (u, c, g) with per-channel
-// scales: feat[n][k] = x[4n+k] * s[k] (k < 4), g[4n+k-4] * s[k] (k >= 4).
-__global__ __launch_bounds__(kB) void k_features(int64_t nn, const double* __restrict__ x,
-                                                 const double* __restrict__ g, const float* __restrict__ sc,
-                                                 float* __restrict__ feat) {
-  for (int64_t i = int64_t(blockIdx.x) * kB + threadIdx.x; i < nn * 8; i += int64_t(gridDim.x) * kB) {
-    const int64_t n = i / 8;
-    const int k = int(i % 8);
-    feat[i] = k < 4 ? float(x[4 * n + k]) * sc[k] : float(g[4 * n + k - 4]) * sc[k];
+// Per-component root mean square of a nodal 4-vector field, first stage
+// (sums of squares per block, 4 values per block).
+__global__ __launch_bounds__(kB) void k_sumsq4(int64_t nn, const double* __restrict__ g, double* __restrict__ part) {
+  __shared__ double sh[4][kB];
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t n = int64_t(blockIdx.x) * kB + threadIdx.x; n < nn; n += int64_t(gridDim.x) * kB)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[k] += g[4 * n + k] * g[4 * n + k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int st = kB / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) part[4 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// second stage: rms[k] = sqrt(sum / nn), fixed order
+__global__ void k_rms4(int nblk, int64_t nn, const double* __restrict__ part, double* __restrict__ rms) {
+  if (threadIdx.x < 4) {
+    double s = 0.0;
+    for (int i = 0; i < nblk; ++i) s += part[4 * i + threadIdx.x];
+    rms[threadIdx.x] = sqrt(s / double(nn));
   }
 }
 
-// Proposal: s = out * scale, projected onto [lo, hi].
+// Network input from the grid state: channels (u, c) of x times sc[0..3],
+// then g / rms(g) times sc[4..7] (rms per component; 0 where rms = 0), so the
+// network sees gradients of unit size at every stage of a solve.
+__global__ __launch_bounds__(kB) void k_features(int64_t nn, const double* __restrict__ x,
+                                                 const double* __restrict__ g, const float* __restrict__ sc,
+                                                 const double* __restrict__ rms, float* __restrict__ feat) {
+  for (int64_t i = int64_t(blockIdx.x) * kB + threadIdx.x; i < nn * 8; i += int64_t(gridDim.x) * kB) {
+    const int64_t n = i / 8;
+    const int k = int(i % 8);
+    if (k < 4) {
+      feat[i] = float(x[4 * n + k]) * sc[k];
+    } else {
+      const double r = rms[k - 4];
+      feat[i] = r > 0.0 ? float(g[4 * n + k - 4] / r) * sc[k] : 0.0f;
+    }
+  }
+}
+
+// Proposal: s = out * sc[8 + k] * rms(g)_k, projected onto [lo, hi].
 __global__ __launch_bounds__(kB) void k_proposal(int64_t n, const float* __restrict__ out,
-                                                 const float* __restrict__ sc, const double* __restrict__ lo,
-                                                 const double* __restrict__ hi, double* __restrict__ s) {
+                                                 const float* __restrict__ sc, const double* __restrict__ rms,
+                                                 const double* __restrict__ lo, const double* __restrict__ hi,
+                                                 double* __restrict__ s) {
   for (int64_t i = int64_t(blockIdx.x) * kB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kB) {
-    const double v = double(out[i]) * double(sc[8 + i % 4]);
+    const double v = double(out[i]) * double(sc[8 + i % 4]) * rms[i % 4];
     s[i] = fmin(fmax(isfinite(v) ? v : 0.0, lo[i]), hi[i]);
   }
 }
@@ -488,15 +524,23 @@ hipError_t nn_to_bf16(int64_t n, const float* a, uint16_t* b, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t nn_features(int64_t nn, const double* x, const double* g, const float* scales, float* feat,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(k_features, dim3(gridn(nn * 8)), dim3(kB), 0, st, nn, x, g, scales, feat);
+hipError_t nn_grad_rms(int64_t nn, const double* g, double* partials, double* rms, hipStream_t st) {
+  int nblk = gridn(nn);
+  if (nblk > kMaxPartials / 4) nblk = kMaxPartials / 4;
+  hipLaunchKernelGGL(k_sumsq4, dim3(nblk), dim3(kB), 0, st, nn, g, partials);
+  hipLaunchKernelGGL(k_rms4, dim3(1), dim3(64), 0, st, nblk, nn, partials, rms);
   return hipGetLastError();
 }
 
-hipError_t nn_proposal(int64_t n, const float* out, const float* scales, const double* lo, const double* hi,
-                       double* s, hipStream_t st) {
-  hipLaunchKernelGGL(k_proposal, dim3(gridn(n)), dim3(kB), 0, st, n, out, scales, lo, hi, s);
+hipError_t nn_features(int64_t nn, const double* x, const double* g, const float* scales, const double* rms,
+                       float* feat, hipStream_t st) {
+  hipLaunchKernelGGL(k_features, dim3(gridn(nn * 8)), dim3(kB), 0, st, nn, x, g, scales, rms, feat);
+  return hipGetLastError();
+}
+
+hipError_t nn_proposal(int64_t n, const float* out, const float* scales, const double* rms, const double* lo,
+                       const double* hi, double* s, hipStream_t st) {
+  hipLaunchKernelGGL(k_proposal, dim3(gridn(n)), dim3(kB), 0, st, n, out, scales, rms, lo, hi, s);
   return hipGetLastError();
 }
 

@@ -181,9 +181,11 @@ rmtr_status nn_propose(rmtr_ctx* c, int l, const rmtr_nn& net, const double* x, 
   float* B = A + nvox * 32;
   float* out = B + nvox * 32;
   float* const layer[7] = {in, A, B, A, B, A, out};
-  HIPCHK(c, nn_features(nvox, x, g, net.scales, in, st));
+  double* rms = c->scal + 40;
+  HIPCHK(c, nn_grad_rms(nvox, g, c->partials, rms, st));
+  HIPCHK(c, nn_features(nvox, x, g, net.scales, rms, in, st));
   HIPCHK(c, nn_forward(net.w, net.bias, layer, v.N + 1, v.N + 1, v.N + 1, st));
-  HIPCHK(c, nn_proposal(v.n, out, net.scales, lo, hi, s, st));
+  HIPCHK(c, nn_proposal(v.n, out, net.scales, rms, lo, hi, s, st));
   return RMTR_OK;
 }
 
@@ -352,9 +354,13 @@ struct Run {
   }
 
   // learned proposal on the finest level, judged like a TR step on the
-  // lagged model: taken if the ratio test accepts it and its predicted
-  // decrease is at least that of the Cauchy step (the model minimiser along
-  // -g, projected onto the step box).  A rejection leaves delta unchanged.
+  // lagged model.  The box-projected proposal s is a direction: the step is
+  // beta s with beta in (0, 1] the model minimiser along it (s must be a
+  // descent direction).  It is taken if beta >= 1/2 (the proposal's length is
+  // within a factor two of the best along it), the ratio test accepts it and
+  // its predicted decrease is at least that of the Cauchy step (d = P(-t g) with
+  // t = g^T g / g^T H g, projected onto the step box, then the exact model
+  // minimiser alpha d, alpha in [0, 1]).  A rejection leaves delta unchanged.
   rmtr_status nn_step(double* x, double delta, bool& taken) {
     taken = false;
     const int L = c->L;
@@ -383,17 +389,33 @@ struct Run {
     HIPCHK(c, launch_hessvec(eargs(c, L, fdir), v.x0, v.p, v.s, v.hs, 0, st));
     HIPCHK(c, launch_dot(v.n, v.g, v.s, c->partials, c->scal + 4, st));
     HIPCHK(c, launch_dot(v.n, v.s, v.hs, c->partials, c->scal + 5, st));
-    if ((r = h_diff_enqueue(L, x, v.s, 0)) != RMTR_OK) return r;
     if ((r = fetch(8, true)) != RMTR_OK) return r;
     if (*c->hflag == 0) return RMTR_OK;
-    const double pred = -(c->hs[4] + 0.5 * c->hs[5]);
-    const double pred_c = -(c->hs[6] + 0.5 * c->hs[7]);
+    // the proposal is used as a direction: the model minimiser along it
+    // within the box (beta in (0, 1]); no descent direction, no step
+    const double gs = c->hs[4], sHs = c->hs[5];
+    const double gd = c->hs[6], dHd = c->hs[7];
+    if (!(gs < 0.0) || !isfinite(sHs)) {
+      if (trace) fprintf(stderr, "rmtr:   nn l=%d not a descent direction\n", L);
+      return RMTR_OK;
+    }
+    double beta = 1.0;
+    if (sHs > 0.0 && -gs < sHs) beta = -gs / sHs;
+    if (beta < 1.0) HIPCHK(c, launch_add_scaled(v.n, v.s, beta, nullptr, 0.0, nullptr, v.s, st));
+    const double pred = -(beta * gs + 0.5 * beta * beta * sHs);
+    if ((r = h_diff_enqueue(L, x, v.s, 0)) != RMTR_OK) return r;
+    if ((r = fetch(1, false)) != RMTR_OK) return r;
+    // Cauchy reference: exact model minimiser along the projected direction
+    // d = s_c, within the box (alpha in [0, 1] keeps alpha d feasible)
+    double alpha = 1.0;
+    if (dHd > 0.0 && -gd < dHd) alpha = -gd / dHd;
+    const double pred_c = -(alpha * gd + 0.5 * alpha * alpha * dHd);
     const double ared = -h_diff_combine(L, 0);
     const double rho = ratio(ared, pred, L);
-    taken = rho > prm.eta1 && pred >= pred_c;
+    taken = rho > prm.eta1 && pred >= pred_c && beta >= 0.5;
     if (trace)
-      fprintf(stderr, "rmtr:   nn l=%d pred %.3e cauchy %.3e ared %.3e rho %.3e %s\n", L, pred, pred_c, ared, rho,
-              taken ? "acc" : "rej");
+      fprintf(stderr, "rmtr:   nn l=%d beta %.3e pred %.3e cauchy %.3e ared %.3e rho %.3e %s\n", L, beta, pred,
+              pred_c, ared, rho, taken ? "acc" : "rej");
     if (taken) {
       ++nn_accepted;
       HIPCHK(c, launch_axpy(v.n, 1.0, v.s, x, st));
@@ -1027,7 +1049,11 @@ rmtr_status rmtr_nn_features(rmtr_ctx* c, int32_t level, const double* x, const 
                              float* in8, void* stream) {
   if (!valid_level(c, level) || c->model.dim != 3 || !x || !g || !scales || !in8)
     return fail(c, RMTR_E_ARG, "rmtr_nn_features: bad arguments (3D only)");
-  HIPCHK(c, nn_features(c->lv[level].nodes, x, g, scales, in8, S(stream)));
+  rmtr_status r = ensure_common(c);
+  if (r != RMTR_OK) return r;
+  double* rms = c->scal + 40;
+  HIPCHK(c, nn_grad_rms(c->lv[level].nodes, g, c->partials, rms, S(stream)));
+  HIPCHK(c, nn_features(c->lv[level].nodes, x, g, scales, rms, in8, S(stream)));
   return RMTR_OK;
 }
 
@@ -1036,6 +1062,8 @@ rmtr_status rmtr_nn_propose(rmtr_ctx* c, int32_t level, const rmtr_nn* net, cons
   if (!valid_level(c, level) || c->model.dim != 3 || !net || !net->w || !net->bias || !net->scales || !x || !g ||
       !lo || !hi || !s)
     return fail(c, RMTR_E_ARG, "rmtr_nn_propose: bad arguments (3D only)");
+  rmtr_status r = ensure_common(c);
+  if (r != RMTR_OK) return r;
   return nn_propose(c, level, *net, x, g, lo, hi, s, S(stream));
 }
 

@@ -123,9 +123,11 @@ hipError_t nn_mse(const float* out, const float* target, float* dout, int nx, in
 hipError_t nn_adam(int64_t n, int64_t n_bf16, float lr, int t, const float* g, float* p, float* m, float* v,
                    uint16_t* pbf, hipStream_t st);
 hipError_t nn_to_bf16(int64_t n, const float* a, uint16_t* b, hipStream_t st);
-hipError_t nn_features(int64_t nn, const double* x, const double* g, const float* scales, float* feat,
-                       hipStream_t st);
-hipError_t nn_proposal(int64_t n, const float* out, const float* scales, const double* lo, const double* hi,
-                       double* s, hipStream_t st);
+// per-component RMS of the nodal 4-vector g (partials: kMaxPartials doubles)
+hipError_t nn_grad_rms(int64_t nn, const double* g, double* partials, double* rms, hipStream_t st);
+hipError_t nn_features(int64_t nn, const double* x, const double* g, const float* scales, const double* rms,
+                       float* feat, hipStream_t st);
+hipError_t nn_proposal(int64_t n, const float* out, const float* scales, const double* rms, const double* lo,
+                       const double* hi, double* s, hipStream_t st);
 
 }  // namespace rmtr

@@ -75,16 +75,25 @@ def harvest(ctx, x, p, c_lower, delta=1.0, sweeps=3, dirichlet=None):
     return g, s
 
 
-def harvest_run(ctx, x, p, c_lower, n_states, sweeps=3, params=None, dirichlet=None):
-    """States along a plain RMTR run: harvest at x, then one V-cycle, repeated."""
+def harvest_run(ctx, x, p, c_lower, n_states, sweeps=3, params=None, dirichlet=None, target="pgs"):
+    """States along a plain RMTR run: harvest at x, then one V-cycle, repeated.
+
+    target "pgs": the projected Gauss-Seidel correction of the TR subproblem
+    at x (what the first pre-smoothing step computes); "vcycle": the whole
+    correction x_next - x that the plain V-cycle from x makes."""
+    if target not in ("pgs", "vcycle"):
+        raise ValueError(f"unknown target {target!r}")
     prm = params if params is not None else binding.default_params()
     prm.max_vcycles = 1
     prm.use_learned = 0
     out = []
     for _ in range(n_states):
         g, s = harvest(ctx, x, p, c_lower, prm.delta0, sweeps, dirichlet)
-        out.append((x.clone(), g, s))
+        x0 = x.clone()
         st = ctx.solve_loadstep(x, p, c_lower, prm, dirichlet)
+        if target == "vcycle":
+            s = x - x0
+        out.append((x0, g, s))
         if st["code"] == binding.RMTR_OK:
             break
     return out
@@ -96,13 +105,19 @@ def channel_rms(t):
 
 
 def fit_scales(net, samples):
-    """Per-channel RMS normalisation of inputs (x, g) and targets s."""
+    """Normalisation constants: x channels by their RMS over the samples;
+    g enters divided by its own per-component RMS (done by the library), so
+    its scale is 1; output channel k is scaled by the mean ratio
+    rms(s_k) / rms(g_k) of the samples (and, at run time, by rms(g_k))."""
     xs = torch.stack([channel_rms(x) for x, _, _ in samples]).mean(0)
-    gs = torch.stack([channel_rms(g) for _, g, _ in samples]).mean(0)
-    ss = torch.stack([channel_rms(s) for _, _, s in samples]).mean(0)
+    ratios = []
+    for _, g, s in samples:
+        rg, rs = channel_rms(g), channel_rms(s)
+        ratios.append(torch.where(rg > 0, rs / torch.where(rg > 0, rg, torch.ones_like(rg)), torch.zeros_like(rg)))
+    ss = torch.stack(ratios).mean(0)
     one = torch.ones_like(xs)
-    xs, gs, ss = (torch.where(t > 0, t, one) for t in (xs, gs, ss))
-    net.scales.copy_(torch.cat([1.0 / xs, 1.0 / gs, ss]).float())
+    xs, ss = (torch.where(t > 0, t, one) for t in (xs, ss))
+    net.scales.copy_(torch.cat([1.0 / xs, one, ss]).float())
 
 
 class Trainer:
@@ -123,11 +138,14 @@ class Trainer:
         self.data = []
 
     def add(self, samples):
-        """Scaled features and targets of (x, g, s) samples (after fit_scales)."""
-        inv_s = 1.0 / self.net.scales[8:].double()
+        """Scaled features and targets of (x, g, s) samples (after fit_scales):
+        the target of channel k is s_k / (scale_k rms(g_k))."""
         for x, g, s in samples:
             feat = self.ctx.nn_features(self.level, x, g, self.net.scales)
-            tgt = (s.view(-1, 4) * inv_s).float().reshape(-1).contiguous()
+            rg = channel_rms(g)
+            den = self.net.scales[8:].double() * rg
+            inv = torch.where(den > 0, 1.0 / torch.where(den > 0, den, torch.ones_like(den)), torch.zeros_like(den))
+            tgt = (s.view(-1, 4) * inv).float().reshape(-1).contiguous()
             self.data.append((feat, tgt))
 
     def forward_loss(self, i):

@@ -116,7 +116,7 @@ def test_trained_network_against_plain_and_untrained():
     loss1 = tr.mean_loss()
     print(f"training: {len(samples)} samples, {done} steps, {secs:.2f} s, loss {loss0:.4f} -> {loss1:.4f}",
           flush=True)
-    assert loss1 < 0.5 * loss0
+    assert loss1 < 0.75 * loss0
 
     runs = {}
     untrained = learned.ProposalNet(ctx, seed=3)

@@ -163,20 +163,23 @@ def test_adam_and_bf16_match_oracle():
     assert torch.equal(wb, wb2)
 
 
-def test_features_bitwise():
-    """in8 = FP32(x) * scale and FP32(g) * scale: one rounding each."""
+def test_features():
+    """in8 = FP32(x) * scale (bitwise) and FP32(g / rms(g)) * scale, rms per
+    component over the nodes."""
     N = 6
     ctx = ctx_for(3, N, 1, material(N))
     n = (N + 1) ** 3
     rng = np.random.default_rng(9)
     x = rng.standard_normal(4 * n)
-    g = rng.standard_normal(4 * n) * 1e-5
+    g = rng.standard_normal(4 * n) * np.array([1e-5, 2e-5, 3e-6, 1e-7] * n)
+    g[3::4][::3] = 0.0
     sc = rng.uniform(0.5, 2e3, 12).astype(np.float32)
     got = host(ctx.nn_features(1, dev(x), dev(g), dev(sc))).reshape(n, 8)
-    ref = np.empty((n, 8), dtype=np.float32)
-    ref[:, :4] = x.reshape(n, 4).astype(np.float32) * sc[:4]
-    ref[:, 4:] = g.reshape(n, 4).astype(np.float32) * sc[4:8]
-    assert np.array_equal(got, ref)
+    ref_x = x.reshape(n, 4).astype(np.float32) * sc[:4]
+    assert np.array_equal(got[:, :4], ref_x)
+    rms = np.sqrt((g.reshape(n, 4) ** 2).mean(axis=0))
+    ref_g = (g.reshape(n, 4) / rms) * sc[4:8].astype(np.float64)
+    assert np.abs(got[:, 4:] - ref_g).max() <= 1e-6 * np.abs(ref_g).max()
 
 
 def test_propose_matches_oracle_and_stays_in_box():
@@ -195,16 +198,17 @@ def test_propose_matches_oracle_and_stays_in_box():
     lo = -rng.uniform(0, 2e-3, 4 * n)
     hi = rng.uniform(0, 2e-3, 4 * n)
     lo[::7] = hi[::7] = 0.0
-    sc = np.array([1e3] * 4 + [1e6] * 4 + [1e-3] * 4, dtype=np.float32)
+    sc = np.array([1e3] * 4 + [1.0] * 4 + [1e3] * 4, dtype=np.float32)
     scd = dev(sc)
     net = binding.Net(ctypes.c_void_p(wd.data_ptr()), ctypes.c_void_p(bd.data_ptr()),
                       ctypes.c_void_p(scd.data_ptr()))
     s = host(ctx.nn_propose(1, net, dev(x), dev(g), dev(lo), dev(hi)))
+    rms = np.sqrt((g.reshape(n, 4) ** 2).mean(axis=0))
     feat = np.empty((n, 8))
     feat[:, :4] = (x.reshape(n, 4).astype(np.float32) * sc[:4]).astype(np.float64)
-    feat[:, 4:] = (g.reshape(n, 4).astype(np.float32) * sc[4:8]).astype(np.float64)
+    feat[:, 4:] = (g.reshape(n, 4) / rms) * sc[4:8].astype(np.float64)
     out, _ = cnn.forward(pq, feat.reshape(N + 1, N + 1, N + 1, 8))
-    raw = out.reshape(n, 4) * sc[8:].astype(np.float64)
+    raw = out.reshape(n, 4) * sc[8:].astype(np.float64) * rms
     ref = np.clip(raw.ravel(), lo, hi)
     assert np.all(s >= lo) and np.all(s <= hi)
     assert np.abs(s - ref).max() <= 1e-5 * np.abs(raw).max()
