@@ -106,6 +106,8 @@ typedef struct {
   int32_t use_learned;     /* 1: learned proposal before the first finest-level
                               pre-smoothing step of each V-cycle (3D; needs nn) */
   const rmtr_nn* nn;       /* host pointer, read during the call         */
+  int32_t nn_patience;     /* stop proposing after this many consecutive
+                              rejections in a load step (0: never stop)  */
 } rmtr_params;
 
 typedef struct {
@@ -117,7 +119,7 @@ typedef struct {
 /* Fills p with the defaults used throughout: eta = (0.1, 0.75),
    gamma = (0.5, 2), delta0 = 1, delta_max = 10, rtol = 1e-8, mu1 = mu2 = 1,
    3 PGS sweeps, 5 coarse TR steps, MPRGP 500 its / 1e-10, 50 fallback sweeps,
-   200 V-cycles, FP64, f~ = f, no learned proposal. */
+   200 V-cycles, FP64, f~ = f, no learned proposal (patience 3). */
 void rmtr_default_params(rmtr_params* p);
 
 /* Create a context for the hierarchy of `model`.  Returns RMTR_E_ARG on an
@@ -228,8 +230,9 @@ rmtr_status rmtr_chi(rmtr_ctx* ctx, int32_t level, const double* x, const double
    max_vcycles.  With params->use_learned, each V-cycle first tries the
    learned proposal on the finest level: it is projected onto the step box,
    scaled by the model minimiser beta in (0, 1] along it (it must be a
-   descent direction of the model, with beta >= 1/2), judged by the FP64
-   ratio of
+   descent direction of the model, with beta >= 1/2), required to predict
+   at least the decrease of the last accepted finest-level smoother step
+   (if any), judged by the FP64 ratio of
    eq. (rho_tr) against the lagged model, and
    taken in place of the first PGS pre-smoothing step if rho > eta1 and its
    predicted decrease is at least that of a Cauchy step (d = P(-t g),

@@ -52,7 +52,8 @@ class Params(ctypes.Structure):
                 ("coarse_tr_its", ctypes.c_int32), ("coarse_qp_its", ctypes.c_int32),
                 ("fallback_sweeps", ctypes.c_int32), ("max_vcycles", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("coarse_model", ctypes.c_int32),
-                ("use_learned", ctypes.c_int32), ("nn", ctypes.POINTER(Net))]
+                ("use_learned", ctypes.c_int32), ("nn", ctypes.POINTER(Net)),
+                ("nn_patience", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -199,7 +199,8 @@ struct Run {
   bool energy_model;
   double f_ref = 1.0;
   int accepted = 0, rejected = 0;
-  int nn_proposed = 0, nn_accepted = 0;
+  int nn_proposed = 0, nn_accepted = 0, nn_misses = 0;
+  double fine_pred = -1.0;  // predicted decrease of the last accepted finest-level smoother step
   rmtr_status status = RMTR_OK;
   bool trace = false;  // per-step log on stderr (RMTR_VERBOSE=2)
 
@@ -235,8 +236,13 @@ struct Run {
   }
 
   // enqueue the pieces of h^l(x + s) - h^l(x) into scal[base .. base+3];
-  // returns via combine_diff after a fetch
-  rmtr_status h_diff_enqueue(int l, const double* x, const double* s, int base) {
+  // returns via combine_diff after a fetch.  Reuse of work already done:
+  //   kind 1 (after h_grad(l, x) on this level): t1 = x - x0, t2 = S t1 and,
+  //          with the energy model, t4 = H~ t1 are valid;
+  //   kind 2: x is the level's x0 (t1 = 0);
+  //   Ss (may be null): S s, already computed.
+  rmtr_status h_diff_enqueue(int l, const double* x, const double* s, int base, int kind = 0,
+                             const double* Ss = nullptr) {
     Level& v = c->lv[l];
     double* sc = c->scal + base;
     if (ftilde(l)) {
@@ -246,17 +252,30 @@ struct Run {
     }
     if (l == c->L) return RMTR_OK;
     HIPCHK(c, launch_dot(v.n, v.dg, s, c->partials, sc + 1, st));
-    HIPCHK(c, launch_add_scaled(v.n, x, 1.0, v.x0, -1.0, nullptr, v.t1, st));
-    HIPCHK(c, launch_st_matvec(dim(), v.N, v.S, v.t1, v.t2, 0, st));
-    HIPCHK(c, launch_st_matvec(dim(), v.N, v.S, s, v.t3, 0, st));
-    if (energy_model) {
-      HIPCHK(c, launch_hessvec(eargs(c, l, nullptr), v.x0, v.p, v.t1, v.t4, 0, st));
-      HIPCHK(c, launch_add_scaled(v.n, v.t4, -1.0, nullptr, 0.0, v.t2, v.t2, st));
-      HIPCHK(c, launch_hessvec(eargs(c, l, nullptr), v.x0, v.p, s, v.t4, 0, st));
-      HIPCHK(c, launch_add_scaled(v.n, v.t4, -1.0, nullptr, 0.0, v.t3, v.t3, st));
+    // t2 = (S - H~) (x - x0)
+    if (kind == 2) {
+      HIPCHK(c, launch_fill(1, 0.0, sc + 2, st));
+    } else {
+      if (kind == 0) {
+        HIPCHK(c, launch_add_scaled(v.n, x, 1.0, v.x0, -1.0, nullptr, v.t1, st));
+        HIPCHK(c, launch_st_matvec(dim(), v.N, v.S, v.t1, v.t2, 0, st));
+        if (energy_model) HIPCHK(c, launch_hessvec(eargs(c, l, nullptr), v.x0, v.p, v.t1, v.t4, 0, st));
+      }
+      if (energy_model) HIPCHK(c, launch_add_scaled(v.n, v.t4, -1.0, nullptr, 0.0, v.t2, v.t2, st));
+      HIPCHK(c, launch_dot(v.n, s, v.t2, c->partials, sc + 2, st));
     }
-    HIPCHK(c, launch_dot(v.n, s, v.t2, c->partials, sc + 2, st));
-    HIPCHK(c, launch_dot(v.n, s, v.t3, c->partials, sc + 3, st));
+    // t3 = (S - H~) s
+    const double* Sv = Ss;
+    if (!Sv) {
+      HIPCHK(c, launch_st_matvec(dim(), v.N, v.S, s, v.t3, 0, st));
+      Sv = v.t3;
+    }
+    if (energy_model) {
+      HIPCHK(c, launch_hessvec(eargs(c, l, nullptr), v.x0, v.p, s, v.t4, 0, st));
+      HIPCHK(c, launch_add_scaled(v.n, v.t4, -1.0, nullptr, 0.0, Sv, v.t3, st));
+      Sv = v.t3;
+    }
+    HIPCHK(c, launch_dot(v.n, s, Sv, c->partials, sc + 3, st));
     return RMTR_OK;
   }
 
@@ -330,7 +349,9 @@ struct Run {
     }
     HIPCHK(c, launch_dot(v.n, v.g, v.s, c->partials, c->scal + 4, st));
     HIPCHK(c, launch_dot(v.n, v.s, v.hs, c->partials, c->scal + 5, st));
-    if ((r = h_diff_enqueue(l, x, v.s, 0)) != RMTR_OK) return r;
+    // on levels below the finest h_grad left t1, t2 (t4) for this x and
+    // v.hs = S s
+    if ((r = h_diff_enqueue(l, x, v.s, 0, l < c->L ? 1 : 0, l < c->L ? v.hs : nullptr)) != RMTR_OK) return r;
     if ((r = fetch(6, true)) != RMTR_OK) return r;
     if (*c->hflag == 0) {
       if (trace) fprintf(stderr, "rmtr:   tr l=%d s=0\n", l);
@@ -346,6 +367,7 @@ struct Run {
               acc ? "acc" : "rej");
     if (acc) {
       ++accepted;
+      if (l == c->L) fine_pred = pred;
       HIPCHK(c, launch_axpy(v.n, 1.0, v.s, x, st));
     } else {
       ++rejected;
@@ -357,7 +379,10 @@ struct Run {
   // lagged model.  The box-projected proposal s is a direction: the step is
   // beta s with beta in (0, 1] the model minimiser along it (s must be a
   // descent direction).  It is taken if beta >= 1/2 (the proposal's length is
-  // within a factor two of the best along it), the ratio test accepts it and
+  // within a factor two of the best along it), it predicts at least the
+  // decrease of the last accepted finest-level smoother step when there is
+  // one (so it replaces the smoother only where it does as well), the ratio
+  // test accepts it and
   // its predicted decrease is at least that of the Cauchy step (d = P(-t g) with
   // t = g^T g / g^T H g, projected onto the step box, then the exact model
   // minimiser alpha d, alpha in [0, 1]).  A rejection leaves delta unchanged.
@@ -412,10 +437,10 @@ struct Run {
     const double pred_c = -(alpha * gd + 0.5 * alpha * alpha * dHd);
     const double ared = -h_diff_combine(L, 0);
     const double rho = ratio(ared, pred, L);
-    taken = rho > prm.eta1 && pred >= pred_c && beta >= 0.5;
+    taken = rho > prm.eta1 && pred >= pred_c && beta >= 0.5 && (fine_pred <= 0.0 || pred >= fine_pred);
     if (trace)
-      fprintf(stderr, "rmtr:   nn l=%d beta %.3e pred %.3e cauchy %.3e ared %.3e rho %.3e %s\n", L, beta, pred,
-              pred_c, ared, rho, taken ? "acc" : "rej");
+      fprintf(stderr, "rmtr:   nn l=%d beta %.3e pred %.3e cauchy %.3e smoother %.3e ared %.3e rho %.3e %s\n", L,
+              beta, pred, pred_c, fine_pred, ared, rho, taken ? "acc" : "rej");
     if (taken) {
       ++nn_accepted;
       HIPCHK(c, launch_axpy(v.n, 1.0, v.s, x, st));
@@ -461,9 +486,10 @@ struct Run {
     rmtr_status r;
     if (l == 1) return nonlinear_solve(1, x, delta, prm.coarse_tr_its, true);
     int pre = prm.mu1;
-    if (l == c->L && prm.use_learned && pre > 0) {
+    if (l == c->L && prm.use_learned && pre > 0 && (prm.nn_patience <= 0 || nn_misses < prm.nn_patience)) {
       bool taken = false;
       if ((r = nn_step(x, delta, taken)) != RMTR_OK) return r;
+      nn_misses = taken ? 0 : nn_misses + 1;
       if (taken) --pre;
     }
     if ((r = nonlinear_solve(l, x, delta, pre, false)) != RMTR_OK) return r;
@@ -477,8 +503,9 @@ struct Run {
     HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), st));
     HIPCHK(c, launch_any_nonzero(cc.n, cc.sc, c->flag, st));
     HIPCHK(c, launch_prolong(dim(), cc.N, cc.sc, f.s, 0, st));
-    if ((r = h_diff_enqueue(l, x, f.s, 0)) != RMTR_OK) return r;
-    if ((r = h_diff_enqueue(l - 1, cc.x0, cc.sc, 8)) != RMTR_OK) return r;
+    // setup_coarse's h_grad(l, x) left t1, t2 (t4) of level l for this x
+    if ((r = h_diff_enqueue(l, x, f.s, 0, 1)) != RMTR_OK) return r;
+    if ((r = h_diff_enqueue(l - 1, cc.x0, cc.sc, 8, 2)) != RMTR_OK) return r;
     if ((r = fetch(12, true)) != RMTR_OK) return r;
     if (*c->hflag) {
       const double ared = -h_diff_combine(l, 0);
@@ -632,6 +659,7 @@ void rmtr_default_params(rmtr_params* p) {
   p->max_vcycles = 200;
   p->precision = RMTR_FP64;
   p->coarse_model = 0;
+  p->nn_patience = 3;
 }
 
 rmtr_status rmtr_create(const rmtr_model* m, rmtr_ctx** out) {

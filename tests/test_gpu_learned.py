@@ -46,10 +46,10 @@ def _certify(mat, x, p, c0):
     return chi / chi0
 
 
-def _solve(ctx, x, p, c0, net=None, max_vcycles=200):
+def _solve(ctx, x, p, c0, net=None, max_vcycles=200, patience=0):
     import ctypes
     import paper_2007_12908_amd as P
-    prm = P.default_params(max_vcycles=max_vcycles)
+    prm = P.default_params(max_vcycles=max_vcycles, nn_patience=patience)
     if net is not None:
         prm.use_learned = 1
         prm.nn = ctypes.pointer(net)
@@ -70,6 +70,10 @@ def test_nonfinite_proposals_leave_the_run_unchanged():
     assert torch.equal(xa, xb)
     assert sb["vcycles"] == sa["vcycles"] and sb["nn_accepted"] == 0
     assert sb["nn_proposed"] == sb["vcycles"]
+    # with patience 3 the network stops proposing after three rejections
+    xc = x.clone()
+    sc = _solve(ctx, xc, p, c0, net.net(), patience=3)
+    assert torch.equal(xa, xc) and sc["nn_proposed"] == min(3, sc["vcycles"])
 
 
 def test_absurd_proposals_are_gated():
