@@ -120,3 +120,27 @@ def test_init_fields_per_fracture_pressure_bitwise():
     c0, p = ctx.init_fields(1, tab, band=g.h, p_mode=1, p_band=band)
     assert np.array_equal(host(c0), c0o) and np.array_equal(host(p), po)
     assert (po > 0).sum() > 0
+
+
+@pytest.mark.parametrize("d,N,c_fill,p_scale", [(3, 1, None, 1e-3), (2, 1, None, 1e-3), (3, 2, 1.0, 1e-3),
+                                                (3, 4, 1.0, 0.0), (2, 3, 0.0, 0.0), (3, 17, 1.0, 1e-3)])
+def test_degenerate_cases(d, N, c_fill, p_scale):
+    """A single element (every node on the boundary), a fully broken field
+    (c = 1: g(c) = k and no pressure work), an intact field and zero
+    pressure."""
+    print(f"case d={d} N={N} c={c_fill} p={p_scale}", flush=True)
+    g, x, p = rand_state(d, N, seed=31 * N + d, p_scale=max(p_scale, 1e-30))
+    if p_scale == 0.0:
+        p[:] = 0.0
+    if c_fill is not None:
+        x.reshape(-1, d + 1)[:, d] = c_fill
+    mat = material(N)
+    ctx = ctx_for(d, N, 1, mat)
+    xd, pd = dev(x), dev(p)
+    E = float(host(ctx.energy(1, xd, pd))[0])
+    assert E == pytest.approx(fem.energy(g, x, p, mat), rel=1e-12)
+    Go = fem.gradient(g, x, p, mat)
+    assert field_rel_err(host(ctx.gradient(1, xd, pd)), Go, d) <= 1e-12
+    v = np.random.default_rng(N).standard_normal(g.n_dofs)
+    HVo = fem.hessian(g, x, p, mat) @ np.where(g.default_dirichlet(), 0.0, v)
+    assert field_rel_err(host(ctx.hessvec(1, xd, pd, dev(v))), HVo, d) <= 1e-12
