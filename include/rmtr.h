@@ -108,6 +108,9 @@ typedef struct {
   const rmtr_nn* nn;       /* host pointer, read during the call         */
   int32_t nn_patience;     /* stop proposing after this many consecutive
                               rejections in a load step (0: never stop)  */
+  int32_t shrink_to_step;  /* 0: Alg. 3 as printed, delta <- gamma1 delta on
+                              rejection; 1: delta <- gamma1 min(delta,
+                              |s|_inf) (the radius follows the rejected step) */
 } rmtr_params;
 
 typedef struct {
@@ -119,7 +122,8 @@ typedef struct {
 /* Fills p with the defaults used throughout: eta = (0.1, 0.75),
    gamma = (0.5, 2), delta0 = 1, delta_max = 10, rtol = 1e-8, mu1 = mu2 = 1,
    3 PGS sweeps, 5 coarse TR steps, MPRGP 500 its / 1e-10, 50 fallback sweeps,
-   200 V-cycles, FP64, f~ = f, no learned proposal (patience 3). */
+   200 V-cycles, FP64, f~ = f, no learned proposal (patience 3), Alg. 3's
+   radius update as printed. */
 void rmtr_default_params(rmtr_params* p);
 
 /* Create a context for the hierarchy of `model`.  Returns RMTR_E_ARG on an

@@ -20,7 +20,8 @@ Readings where the paper is silent (listed in the design notes):
     level tol = 1e-14 |f_ref| / sqrt(n_elements of the level), f_ref the
     energy at the start of the load step; non-finite -> -inf;
   * Alg. 3 literally: accept iff rho > eta1; radius gamma1 D if rho < eta1,
-    unchanged on [eta1, eta2], min(gamma2 D, D_max) if rho > eta2;
+    unchanged on [eta1, eta2], min(gamma2 D, D_max) if rho > eta2 (option:
+    gamma1 min(D, |s|_inf) after a rejection, the usual step-based update);
   * Alg. 2 runs exactly i_max iterations.
 """
 from dataclasses import dataclass, field
@@ -50,6 +51,7 @@ class Params:
     rtol: float = 1e-8
     coarse_model: str = "energy"      # or "zero"
     guard: float = 1e-14
+    shrink_to_step: bool = False      # rejected: gamma1 min(delta, |s|_inf)
 
 
 @dataclass
@@ -156,12 +158,15 @@ class RMTR:
             return -np.inf
         return ared / pred
 
-    def control(self, rho, delta):
-        """Algorithm 3: returns (accept, new radius)."""
+    def control(self, rho, delta, s):
+        """Algorithm 3: returns (accept, new radius).  Variant: with
+        shrink_to_step the radius after a rejection is gamma1 times the
+        smaller of delta and the rejected step's infinity norm."""
         prm = self.prm
         accept = rho > prm.eta1
         if rho < prm.eta1:
-            delta = prm.gamma1 * delta
+            base = min(delta, float(np.max(np.abs(s)))) if prm.shrink_to_step else delta
+            delta = prm.gamma1 * base
         elif rho > prm.eta2:
             delta = min(prm.gamma2 * delta, prm.delta_max)
         return accept, delta
@@ -187,7 +192,7 @@ class RMTR:
         pred = -(float(g @ s) + 0.5 * float(s @ (lev.Hmod @ s)))
         ared = -self.h_diff(lev, x, s)
         rho = self.ratio(ared, pred, lev)
-        accept, delta = self.control(rho, delta)
+        accept, delta = self.control(rho, delta, s)
         if accept:
             self.stats.tr_accepted += 1
             return x + s, delta
@@ -238,7 +243,7 @@ class RMTR:
             ared = -self.h_diff(lev, x, s)
             pred = -self.h_diff(c, c.x0, sc)
             rho = self.ratio(ared, pred, lev)
-            accept, delta = self.control(rho, delta)
+            accept, delta = self.control(rho, delta, s)
             if accept:
                 x = x + s
         x, delta = self.nonlinear_solve(lev, x, delta, self.prm.mu2)

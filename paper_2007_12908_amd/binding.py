@@ -53,7 +53,7 @@ class Params(ctypes.Structure):
                 ("fallback_sweeps", ctypes.c_int32), ("max_vcycles", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("coarse_model", ctypes.c_int32),
                 ("use_learned", ctypes.c_int32), ("nn", ctypes.POINTER(Net)),
-                ("nn_patience", ctypes.c_int32)]
+                ("nn_patience", ctypes.c_int32), ("shrink_to_step", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

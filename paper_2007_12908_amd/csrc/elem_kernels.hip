@@ -173,10 +173,9 @@ constexpr int kTile = 16;
 constexpr int kOwn = kTile - 1;
 
 template <int MODE, typename T>
-__global__ __launch_bounds__(256) void k_elem_scatter3(int N, T h, MatP<double> md, int zchunk,
-                                                       const uint8_t* __restrict__ dir,
-                                                       const T* __restrict__ x, const T* __restrict__ p,
-                                                       const T* __restrict__ v, T* __restrict__ out) {
+__device__ inline void elem_scatter3(int N, T h, const MatP<double>& md, int zchunk, const uint8_t* __restrict__ dir,
+                                     const T* __restrict__ x, const T* __restrict__ p, const T* __restrict__ v,
+                                     T* __restrict__ out) {
   __shared__ T lo_sh[256][4][4];
   __shared__ T hi_sh[256][4][4];
   const MatP<T> m = cast_mat<T>(md);
@@ -249,6 +248,25 @@ __global__ __launch_bounds__(256) void k_elem_scatter3(int N, T h, MatP<double> 
 #pragma unroll
     for (int k = 0; k < 4; ++k) out[4 * n + k] = (mk & (1u << k)) ? T(0) : acc[k];
   }
+}
+
+// FP64: one wavefront per SIMD (the element state does not fit in less than
+// the full register file); FP32: two, which the smaller state allows.
+template <int MODE, typename T>
+__global__ __launch_bounds__(256) void k_elem_scatter3(int N, T h, MatP<double> md, int zchunk,
+                                                       const uint8_t* __restrict__ dir,
+                                                       const T* __restrict__ x, const T* __restrict__ p,
+                                                       const T* __restrict__ v, T* __restrict__ out) {
+  elem_scatter3<MODE, T>(N, h, md, zchunk, dir, x, p, v, out);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256, 2) void k_elem_scatter3_f32(int N, float h, MatP<double> md, int zchunk,
+                                                              const uint8_t* __restrict__ dir,
+                                                              const float* __restrict__ x,
+                                                              const float* __restrict__ p,
+                                                              const float* __restrict__ v, float* __restrict__ out) {
+  elem_scatter3<MODE, float>(N, h, md, zchunk, dir, x, p, v, out);
 }
 
 // Node-centric kernels (any DIM): a thread per node sums the contributions
@@ -430,8 +448,12 @@ static hipError_t launch_scatter(const ElemArgs& a, const T* x, const T* p, cons
     int zchunk = (a.N + 1 + chunks - 1) / chunks;
     if (zchunk < 4) zchunk = 4;
     chunks = (a.N + 1 + zchunk - 1) / zchunk;
-    hipLaunchKernelGGL((k_elem_scatter3<MODE, T>), dim3(tiles, tiles, chunks), dim3(256), 0, st, a.N, T(a.h), a.m,
-                       zchunk, a.dir, x, p, v, out);
+    if constexpr (sizeof(T) == 4)
+      hipLaunchKernelGGL((k_elem_scatter3_f32<MODE>), dim3(tiles, tiles, chunks), dim3(256), 0, st, a.N, T(a.h), a.m,
+                         zchunk, a.dir, x, p, v, out);
+    else
+      hipLaunchKernelGGL((k_elem_scatter3<MODE, T>), dim3(tiles, tiles, chunks), dim3(256), 0, st, a.N, T(a.h), a.m,
+                         zchunk, a.dir, x, p, v, out);
   } else {
     int64_t nn = int64_t(a.N + 1) * (a.N + 1);
     hipLaunchKernelGGL((k_node_gather<2, MODE, T>), dim3(grid_for(nn)), dim3(kBlock), 0, st, a.N, T(a.h), a.m, a.dir,

@@ -42,6 +42,33 @@ __global__ __launch_bounds__(kB) void k_dot(int64_t n, const double* __restrict_
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
+// max |a_i|: per-block maxima, then one block takes the maximum of those
+__global__ __launch_bounds__(kB) void k_amax(int64_t n, const double* __restrict__ a, double* __restrict__ partials) {
+  __shared__ double sh[kB];
+  double m = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * kB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kB) m = fmax(m, fabs(a[i]));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = kB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kB) void k_amax_final(const double* __restrict__ partials, int n, double* __restrict__ out) {
+  __shared__ double sh[kB];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += kB) m = fmax(m, partials[i]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = kB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
 // chi^2 = || P_F(x - g) - x ||^2 over free dofs; F: c_lower <= c <= 1.
 template <int DIM>
 __global__ __launch_bounds__(kB) void k_chi(int N, const double* __restrict__ x, const double* __restrict__ g,
@@ -237,6 +264,13 @@ hipError_t launch_dot(int64_t n, const double* a, const double* b, double* parti
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_reduce_partials(partials, nb, out, st);
+}
+
+hipError_t launch_amax(int64_t n, const double* a, double* partials, double* out, hipStream_t st) {
+  int nb = nblocks(n);
+  hipLaunchKernelGGL(k_amax, dim3(nb), dim3(kB), 0, st, n, a, partials);
+  hipLaunchKernelGGL(k_amax_final, dim3(1), dim3(kB), 0, st, partials, nb, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_chi(int dim, int N, const double* x, const double* g, const double* c_lower, const uint8_t* dir,

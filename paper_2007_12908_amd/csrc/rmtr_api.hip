@@ -297,10 +297,12 @@ struct Run {
     return ared / pred;
   }
 
-  bool control(double rho, double& delta) const {
+  // Alg. 3; with shrink_to_step a rejected step's radius is measured from
+  // the step taken, gamma1 min(delta, |s|_inf)
+  bool control(double rho, double& delta, double snorm) const {
     const bool accept = rho > prm.eta1;
     if (rho < prm.eta1)
-      delta = prm.gamma1 * delta;
+      delta = prm.gamma1 * (prm.shrink_to_step ? fmin(delta, snorm) : delta);
     else if (rho > prm.eta2)
       delta = fmin(prm.gamma2 * delta, prm.delta_max);
     return accept;
@@ -349,10 +351,11 @@ struct Run {
     }
     HIPCHK(c, launch_dot(v.n, v.g, v.s, c->partials, c->scal + 4, st));
     HIPCHK(c, launch_dot(v.n, v.s, v.hs, c->partials, c->scal + 5, st));
+    if (prm.shrink_to_step) HIPCHK(c, launch_amax(v.n, v.s, c->partials, c->scal + 6, st));
     // on levels below the finest h_grad left t1, t2 (t4) for this x and
     // v.hs = S s
     if ((r = h_diff_enqueue(l, x, v.s, 0, l < c->L ? 1 : 0, l < c->L ? v.hs : nullptr)) != RMTR_OK) return r;
-    if ((r = fetch(6, true)) != RMTR_OK) return r;
+    if ((r = fetch(7, true)) != RMTR_OK) return r;
     if (*c->hflag == 0) {
       if (trace) fprintf(stderr, "rmtr:   tr l=%d s=0\n", l);
       return RMTR_OK;
@@ -361,7 +364,7 @@ struct Run {
     const double ared = -h_diff_combine(l, 0);
     const double rho = ratio(ared, pred, l);
     const double d0 = delta;
-    const bool acc = control(rho, delta);
+    const bool acc = control(rho, delta, c->hs[6]);
     if (trace)
       fprintf(stderr, "rmtr:   tr l=%d pred %.3e ared %.3e rho %.3e delta %.2e %s\n", l, pred, ared, rho, d0,
               acc ? "acc" : "rej");
@@ -506,13 +509,14 @@ struct Run {
     // setup_coarse's h_grad(l, x) left t1, t2 (t4) of level l for this x
     if ((r = h_diff_enqueue(l, x, f.s, 0, 1)) != RMTR_OK) return r;
     if ((r = h_diff_enqueue(l - 1, cc.x0, cc.sc, 8, 2)) != RMTR_OK) return r;
-    if ((r = fetch(12, true)) != RMTR_OK) return r;
+    if (prm.shrink_to_step) HIPCHK(c, launch_amax(f.n, f.s, c->partials, c->scal + 12, st));
+    if ((r = fetch(13, true)) != RMTR_OK) return r;
     if (*c->hflag) {
       const double ared = -h_diff_combine(l, 0);
       const double pred = -h_diff_combine(l - 1, 8);
       const double rho = ratio(ared, pred, l);
       const double d0 = delta;
-      const bool acc = control(rho, delta);
+      const bool acc = control(rho, delta, c->hs[12]);
       if (trace)
         fprintf(stderr, "rmtr:   cc l=%d pred %.3e ared %.3e rho %.3e delta %.2e %s\n", l, pred, ared, rho, d0,
                 acc ? "acc" : "rej");
@@ -660,6 +664,7 @@ void rmtr_default_params(rmtr_params* p) {
   p->precision = RMTR_FP64;
   p->coarse_model = 0;
   p->nn_patience = 3;
+  p->shrink_to_step = 0;
 }
 
 rmtr_status rmtr_create(const rmtr_model* m, rmtr_ctx** out) {

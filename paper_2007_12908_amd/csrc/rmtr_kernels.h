@@ -79,6 +79,8 @@ hipError_t launch_init_fields(int dim, int N, const double* table, int n_frac, d
 // ---- vector kernels (linalg_kernels.hip)
 hipError_t launch_dot(int64_t n, const double* a, const double* b, double* partials, double* out,
                       hipStream_t st);
+// out = max_i |a_i| (device scalar)
+hipError_t launch_amax(int64_t n, const double* a, double* partials, double* out, hipStream_t st);
 hipError_t launch_chi(int dim, int N, const double* x, const double* g, const double* c_lower,
                       const uint8_t* dir, double* partials, double* out, hipStream_t st);
 hipError_t launch_axpy(int64_t n, double alpha, const double* x, double* y, hipStream_t st);

@@ -45,17 +45,18 @@ def _gpu_solve(d, N, L, mat, c0, p, x, **prm):
     return host(xd), st
 
 
-@pytest.mark.parametrize("case", ["c1", "3d"])
-def test_loadstep_matches_oracle(case):
+@pytest.mark.parametrize("case,shrink", [("c1", 0), ("3d", 0), ("c1", 1), ("3d", 1)])
+def test_loadstep_matches_oracle(case, shrink):
+    """shrink = 1: the step-based radius update after rejections."""
     if case == "c1":
         g, mat, c0, p, x = _c1()
         d, N, L = 2, 64, 3
     else:
         g, mat, c0, p, x = _small3d(8)
         d, N, L = 3, 8, 2
-    print(f"case {case}", flush=True)
-    xg, st = _gpu_solve(d, N, L, mat, c0, p, x)
-    solver = rmtr.RMTR(d, N, L, mat, p)
+    print(f"case {case} shrink {shrink}", flush=True)
+    xg, st = _gpu_solve(d, N, L, mat, c0, p, x, shrink_to_step=shrink)
+    solver = rmtr.RMTR(d, N, L, mat, p, rmtr.Params(shrink_to_step=bool(shrink)))
     xo, so = solver.solve_loadstep(x.copy(), c0)
     print("gpu", st["vcycles"], st["chi"] / st["chi0"], "oracle", so.vcycles, so.chi / so.chi0, flush=True)
     assert st["code"] == 0
