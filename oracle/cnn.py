@@ -13,6 +13,12 @@ k = (dx+1) + 3 (dy+1) + 9 (dz+1); biases (Cout,).
 
 Loss: mean squared error over the voxels of an interior window and all
 output channels.  Adam (Kingma and Ba) with bias correction.
+
+Option bf16_inputs: each layer's input is rounded to bfloat16 (nearest,
+ties to even, through float32) before its convolution, and the weight
+gradient multiplies bfloat16-rounded layer inputs and output gradients, the
+precision of the matrix-core form; the rounding is otherwise treated as the
+identity (data and bias gradients in full precision).
 """
 import numpy as np
 
@@ -43,13 +49,17 @@ def conv3d(x, W, b):
     return y
 
 
-def conv3d_backward(x, W, dy):
-    """Gradients of sum(dy * conv3d(x, W, b)) w.r.t. x, W and b."""
+def conv3d_backward(x, W, dy, bf16_weight_grad=False):
+    """Gradients of sum(dy * conv3d(x, W, b)) w.r.t. x, W and b.  With
+    bf16_weight_grad the weight gradient takes x and dy rounded to bfloat16
+    (the matrix-core form); dx and db use them unrounded."""
     dW = np.zeros_like(W)
     dx = np.zeros_like(x)
+    xq = bf16_round(x) if bf16_weight_grad else x
+    dyq = bf16_round(dy) if bf16_weight_grad else dy
     for k, d in enumerate(offsets()):
-        xs = shifted(x, d)
-        dW[k] = xs.reshape(-1, x.shape[3]).T @ dy.reshape(-1, dy.shape[3])
+        xs = shifted(xq, d)
+        dW[k] = xs.reshape(-1, x.shape[3]).T @ dyq.reshape(-1, dy.shape[3])
         # y[v] gets x[v + d] W: x[u] feeds y[u - d]
         dx += shifted(dy, (-d[0], -d[1], -d[2])) @ W[k].T
     db = dy.reshape(-1, dy.shape[3]).sum(axis=0)
@@ -66,22 +76,29 @@ def init_params(seed, channels=CHANNELS):
     return params
 
 
-def forward(params, x):
+def bf16_round(a):
+    """Nearest bfloat16 (ties to even) of float32(a), as float64."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward(params, x, bf16_inputs=False):
     """Returns the output and the per-layer activations (inputs of each layer)."""
     acts = [x]
     h = x
     L = len(params)
     for l, (W, b) in enumerate(params):
-        h = conv3d(h, W, b)
+        h = conv3d(bf16_round(h) if bf16_inputs else h, W, b)
         if l < L - 1:
             h = np.maximum(h, 0.0)
         acts.append(h)
     return h, acts
 
 
-def loss_and_grads(params, x, target, window):
+def loss_and_grads(params, x, target, window, bf16_inputs=False):
     """MSE over the window (slices of z, y, x) and channels; gradients."""
-    out, acts = forward(params, x)
+    out, acts = forward(params, x, bf16_inputs)
     diff = np.zeros_like(out)
     sel = (window[0], window[1], window[2], slice(None))
     diff[sel] = out[sel] - target[sel]
@@ -94,7 +111,7 @@ def loss_and_grads(params, x, target, window):
         if l < L - 1:
             dy = dy * (acts[l + 1] > 0.0)
         W, b = params[l]
-        dx, dW, db = conv3d_backward(acts[l], W, dy)
+        dx, dW, db = conv3d_backward(acts[l], W, dy, bf16_inputs)
         grads[l] = (dW, db)
         dy = dx
     return loss, grads

@@ -7,6 +7,8 @@
 // v = x + nx (y + ny z)), the layout of the node-major grid vectors.  Layer
 // weights are [27][Cin][Cout] with offset k = (dx+1) + 3 (dy+1) + 9 (dz+1):
 //   y[v][co] = b[co] + sum_k sum_ci W[k][ci][co] x[v + off(k)][ci].
+#include <algorithm>
+
 #include "rmtr_kernels.h"
 
 namespace rmtr {
@@ -143,6 +145,80 @@ __global__ __launch_bounds__(kB) void k_conv(Box b, const float* __restrict__ in
   }
 }
 
+// Forward convolution as an implicit GEMM on the matrix cores
+// (v_mfma_f32_32x32x8_bf16, FP32 accumulation): a wavefront computes a tile
+// of 32 x-consecutive voxels of one row by 32 output channels; the reduction
+// runs over the 27 offsets times the input channels in chunks of 8.  The
+// A operand is the layer input (FP32 in memory) rounded to BF16 on load,
+// the B operand the layer's BF16 weights, staged in LDS as [k][o][i] so a
+// lane reads its four consecutive input channels with one 8-byte load.
+// Lane l holds A[l % 32][4 (l / 32) + t] and B[4 (l / 32) + t][l % 32]
+// (t = 0..3); accumulator r of lane l is C[8 (r / 4) + 4 (l / 32) + r % 4]
+// [l % 32].  Products of BF16 values are exact in FP32, so the result is
+// the FP32 sum of the exact products.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+template <int NI, int NO, int RELU_OUT>
+__global__ __launch_bounds__(256) void k_conv_mfma(Box b, const float* __restrict__ in,
+                                                   const uint16_t* __restrict__ W, const float* __restrict__ bias,
+                                                   float* __restrict__ out) {
+  static_assert(NI % 8 == 0 && NO <= 32, "input channels in chunks of 8, at most 32 outputs");
+  constexpr int NIP = NI, NOP = 32;
+  __shared__ __align__(16) uint16_t sW[27 * NOP * NIP];
+  for (int e = threadIdx.x; e < 27 * NOP * NIP; e += 256) {
+    const int k = e / (NOP * NIP), o = (e / NIP) % NOP, i = e % NIP;
+    sW[e] = o < NO ? W[(k * NI + i) * NO + o] : uint16_t(0);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 31, lk = lane >> 5;  // A row / B column, K half
+  const int xtiles = (b.nx + 31) / 32;
+  const int64_t ntiles = int64_t(xtiles) * b.ny * b.nz;
+  for (int64_t T = int64_t(blockIdx.x) * 4 + wave; T < ntiles; T += int64_t(gridDim.x) * 4) {
+    const int x0 = 32 * int(T % xtiles);
+    const int64_t row = T / xtiles;
+    const int y = int(row % b.ny), z = int(row / b.ny);
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    for (int k = 0; k < 27; ++k) {
+      const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+      const int Y = y + dy, Z = z + dz;
+      if (Y < 0 || Y >= b.ny || Z < 0 || Z >= b.nz) continue;  // uniform over the wavefront
+      const int X = x0 + li + dx;
+      const bool ok = x0 + li < b.nx && X >= 0 && X < b.nx;
+      const float* src = in + ((int64_t(Z) * b.ny + Y) * b.nx + (ok ? X : 0)) * NI + 4 * lk;
+      const uint16_t* wk = sW + (k * NOP + li) * NIP + 4 * lk;
+#pragma unroll
+      for (int ic = 0; ic < NI / 8; ++ic) {
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (ok) v = *reinterpret_cast<const float4*>(src + 8 * ic);
+        bf16x4 a;
+        a[0] = short(f2bf(v.x));
+        a[1] = short(f2bf(v.y));
+        a[2] = short(f2bf(v.z));
+        a[3] = short(f2bf(v.w));
+        const bf16x4 bw = *reinterpret_cast<const bf16x4*>(wk + 8 * ic);
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bw, acc, 0, 0, 0);
+      }
+    }
+    const int o = li;
+    if (o < NO) {
+      const float bo = bias[o];
+      float* dst = out + ((int64_t(z) * b.ny + y) * b.nx + x0) * NO + o;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = 8 * (r / 4) + 4 * lk + (r % 4);
+        if (x0 + i < b.nx) {
+          const float val = acc[r] + bo;
+          dst[int64_t(i) * NO] = RELU_OUT ? fmaxf(val, 0.0f) : val;
+        }
+      }
+    }
+  }
+}
+
 // Weight and bias gradient, first stage: each block sums over its voxel range
 //   dW[k][ci][co] += X[v + off(k)][ci] dYm[v][co],  db[co] += dYm[v][co]
 // into its own partial row (27 CIN COUT + COUT values).  Per tile of TV
@@ -241,6 +317,84 @@ __global__ __launch_bounds__(kB) void k_conv_bwd_w(Box b, const float* __restric
         for (int c = 0; c < RO; ++c) outp[k * NE + (ci0 + a) * COUT + co0 + c] = acc[k][a][c];
   }
   if (tid < COUT) outp[27 * NE + tid] = accb;
+}
+
+// Weight gradient on the matrix cores: for each offset k,
+//   dW[k][ci][co] = sum_v X[v + off(k)][ci] dYm[v][co]
+// is a 32 x 32 GEMM whose reduction runs over voxels, 8 per MFMA: lane l
+// feeds A[ci = l % 32][voxel 4 (l / 32) + t] and B[voxel 4 (l / 32) + t]
+// [co = l % 32], both rounded to BF16; the four wavefronts of a block split
+// the 27 offsets (7, 7, 7, 6) and share the voxel chunks; partial rows per
+// block as in k_conv_bwd_w (bias partials summed in FP32 by wavefront 0).
+template <int CIN, int COUT, int RELU>
+__global__ __launch_bounds__(256) void k_conv_bwd_w_mfma(Box b, const float* __restrict__ X,
+                                                         const float* __restrict__ dY,
+                                                         const float* __restrict__ Yact, int64_t vox_per_block,
+                                                         float* __restrict__ partial) {
+  static_assert(CIN <= 32 && COUT <= 32, "one 32 x 32 tile per offset");
+  constexpr int NE = CIN * COUT, KW = 7;
+  const int64_t nvox = int64_t(b.nx) * b.ny * b.nz;
+  const int64_t v0 = int64_t(blockIdx.x) * vox_per_block;
+  const int64_t v1 = min(v0 + vox_per_block, nvox);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 31, lk = lane >> 5;
+  f32x16 acc[KW];
+#pragma unroll
+  for (int j = 0; j < KW; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[j][r] = 0.0f;
+  float accb = 0.0f;
+  for (int64_t vt = v0; vt < v1; vt += 8) {
+    int cx[4], cy[4], cz[4];
+    bool vok[4];
+    bf16x4 bb;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t v = vt + 4 * lk + t;
+      vok[t] = v < v1;
+      const int64_t vv = vok[t] ? v : v0;
+      cx[t] = int(vv % b.nx);
+      cy[t] = int((vv / b.nx) % b.ny);
+      cz[t] = int(vv / (int64_t(b.nx) * b.ny));
+      float d = 0.0f;
+      if (vok[t] && li < COUT) {
+        d = dY[vv * COUT + li];
+        if (RELU && !(Yact[vv * COUT + li] > 0.0f)) d = 0.0f;
+      }
+      accb += d;
+      bb[t] = short(f2bf(d));
+    }
+#pragma unroll
+    for (int j = 0; j < KW; ++j) {
+      const int k = wave + 4 * j;
+      if (k >= 27) break;
+      const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+      bf16x4 a;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int xx = cx[t] + dx, yy = cy[t] + dy, zz = cz[t] + dz;
+        float xv = 0.0f;
+        if (vok[t] && li < CIN && xx >= 0 && xx < b.nx && yy >= 0 && yy < b.ny && zz >= 0 && zz < b.nz)
+          xv = X[((int64_t(zz) * b.ny + yy) * b.nx + xx) * CIN + li];
+        a[t] = short(f2bf(xv));
+      }
+      acc[j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bb, acc[j], 0, 0, 0);
+    }
+  }
+  float* outp = partial + int64_t(blockIdx.x) * (27 * NE + COUT);
+#pragma unroll
+  for (int j = 0; j < KW; ++j) {
+    const int k = wave + 4 * j;
+    if (k >= 27) break;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int ci = 8 * (r / 4) + 4 * lk + (r % 4), co = li;
+      if (ci < CIN && co < COUT) outp[k * NE + ci * COUT + co] = acc[j][r];
+    }
+  }
+  // bias partial: lanes l and l + 32 hold the two voxel halves of channel l
+  const float other = __shfl_xor(accb, 32);
+  if (wave == 0 && lk == 0 && li < COUT) outp[27 * NE + li] = accb + other;
 }
 
 // second stage: fixed-order sum of the partial rows
@@ -424,16 +578,14 @@ hipError_t nn_forward(const uint16_t* w, const float* bias, float* const layer[7
     float* Y = layer[l + 1];
     const uint16_t* W = w + w_off(l);
     const float* bb = bias + b_off(l);
-    const int64_t groups = int64_t((nx + 3) / 4) * ny * nz;
+    const int64_t tiles = int64_t((nx + 31) / 32) * ny * nz;
+    const dim3 grid(unsigned(std::min<int64_t>((tiles + 3) / 4, 2048)));
     if (l == 0)
-      hipLaunchKernelGGL((k_conv<8, 32, 1, 0, 1, 1, 0>), dim3(convgrid(groups * 4)), dim3(kB), 0, st, b, X, nullptr,
-                         W, bb, Y);
+      hipLaunchKernelGGL((k_conv_mfma<8, 32, 1>), grid, dim3(256), 0, st, b, X, W, bb, Y);
     else if (l < 5)
-      hipLaunchKernelGGL((k_conv<32, 32, 1, 0, 1, 1, 0>), dim3(convgrid(groups * 4)), dim3(kB), 0, st, b, X,
-                         nullptr, W, bb, Y);
+      hipLaunchKernelGGL((k_conv_mfma<32, 32, 1>), grid, dim3(256), 0, st, b, X, W, bb, Y);
     else
-      hipLaunchKernelGGL((k_conv<32, 4, 1, 0, 1, 0, 0>), dim3(convgrid(groups)), dim3(kB), 0, st, b, X, nullptr, W,
-                         bb, Y);
+      hipLaunchKernelGGL((k_conv_mfma<32, 4, 0>), grid, dim3(256), 0, st, b, X, W, bb, Y);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -470,11 +622,11 @@ hipError_t nn_backward(const uint16_t* w, const float* act, const float* dout, f
     const int64_t len = int64_t(27) * cin * cout + cout;
     // weights: layer 5 has no ReLU on its output
     if (l == 5)
-      hipLaunchKernelGGL((k_conv_bwd_w<32, 4, 0>), dim3(nblk), dim3(kB), 0, st, b, X, dY, Yact, vpb, part);
+      hipLaunchKernelGGL((k_conv_bwd_w_mfma<32, 4, 0>), dim3(nblk), dim3(256), 0, st, b, X, dY, Yact, vpb, part);
     else if (l > 0)
-      hipLaunchKernelGGL((k_conv_bwd_w<32, 32, 1>), dim3(nblk), dim3(kB), 0, st, b, X, dY, Yact, vpb, part);
+      hipLaunchKernelGGL((k_conv_bwd_w_mfma<32, 32, 1>), dim3(nblk), dim3(256), 0, st, b, X, dY, Yact, vpb, part);
     else
-      hipLaunchKernelGGL((k_conv_bwd_w<8, 32, 1>), dim3(nblk), dim3(kB), 0, st, b, X, dY, Yact, vpb, part);
+      hipLaunchKernelGGL((k_conv_bwd_w_mfma<8, 32, 1>), dim3(nblk), dim3(256), 0, st, b, X, dY, Yact, vpb, part);
     hipLaunchKernelGGL(k_sum_partials, dim3(gridn(len)), dim3(kB), 0, st, part, nblk, len, dw + w_off(l),
                        db + b_off(l), int64_t(27) * cin * cout);
     if (l == 0) break;

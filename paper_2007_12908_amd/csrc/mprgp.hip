@@ -200,7 +200,6 @@ hipError_t run_mprgp(int dim, int N, const double* S, const uint8_t* dir, const 
   double* p = beta + n;
   double* Ad = p + n;
   double* part = Ad + n;
-  double* red = part + kNV * 1024;
   const int nb = nblocks(n);
   const dim3 gb(nb), tb(kB);
   hipError_t e;
@@ -209,11 +208,12 @@ hipError_t run_mprgp(int dim, int N, const double* S, const uint8_t* dir, const 
     e = (x);                       \
     if (e != hipSuccess) return e; \
   } while (0)
+  // the final reduction writes straight into the (mapped, coherent) host
+  // scalars; the synchronisation makes them visible
 #define FETCH()                                                                     \
   do {                                                                              \
-    hipLaunchKernelGGL(k_final, dim3(1), tb, 0, st, part, nb, red);                 \
+    hipLaunchKernelGGL(k_final, dim3(1), tb, 0, st, part, nb, hs);                  \
     CK(hipGetLastError());                                                          \
-    CK(hipMemcpyAsync(hs, red, kNV * sizeof(double), hipMemcpyDeviceToHost, st));   \
     CK(hipStreamSynchronize(st));                                                   \
   } while (0)
 #define MATVEC(v, out) CK(launch_st_matvec(dim, N, S, v, out, 0, st))
@@ -224,9 +224,8 @@ hipError_t run_mprgp(int dim, int N, const double* S, const uint8_t* dir, const 
   {
     int nbr = 0;
     CK(launch_st_rowabs(dim, N, S, g, part, &nbr, st));
-    hipLaunchKernelGGL(k_final, dim3(1), tb, 0, st, part, nbr, red);
+    hipLaunchKernelGGL(k_final, dim3(1), tb, 0, st, part, nbr, hs);
     CK(hipGetLastError());
-    CK(hipMemcpyAsync(hs, red, kNV * sizeof(double), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
   }
   const double normA = -hs[kNV - 1];

@@ -116,7 +116,8 @@ rmtr_status ensure_common(rmtr_ctx* c) {
   HIPCHK(c, dalloc(c, &c->scal, kScal));
   HIPCHK(c, dalloc(c, &c->flag, 4));
   void* h = nullptr;
-  HIPCHK(c, hipHostMalloc(&h, kScal * sizeof(double) + 64, hipHostMallocDefault));
+  // coherent: MPRGP's final reductions are written into it by a kernel
+  HIPCHK(c, hipHostMalloc(&h, kScal * sizeof(double) + 64, hipHostMallocCoherent));
   c->hs = static_cast<double*>(h);
   c->hflag = reinterpret_cast<int*>(c->hs + kScal);
   std::vector<double> tab;

@@ -2,10 +2,21 @@
 pass (weight and bias gradients), Adam step, BF16 rounding and input
 features, through the C-ABI.
 
-The oracle runs in FP64 on the same BF16-rounded weights, so the only
-difference is the kernels' FP32 arithmetic (sums of up to 27 x 32 products
-per output): forward and loss agree to 1e-5 relative to the largest output,
-gradients to 1e-4 relative to the largest entry of each layer's gradient."""
+The forward convolutions run on the matrix cores with BF16 operands: the
+oracle rounds each layer's input to BF16 the same way and sums in FP64.
+Layer by layer (the oracle convolving the GPU's own FP32 layer input) the
+only difference is FP32 accumulation order: 2e-6 of the largest output.
+End to end, an FP32 activation next to a BF16 rounding boundary can round
+the other way on the two sides and the difference (one BF16 step, 2^-8
+relative) feeds more such flips downstream, so whole-network outputs agree
+only to BF16 level: 5e-3 in RMS and 3e-2 at the worst voxel.  The backward
+pass is pinned layer by layer the same way: the oracle differentiates the
+GPU's own activations (weight gradient from BF16 layer inputs and output
+gradients as on the matrix cores, data and bias gradients in full
+precision).  Bias gradients agree to 1e-4 of the largest entry of each
+layer; weight gradients to 2e-3, since an output gradient computed in FP32
+on the GPU and in FP64 by the oracle can still round to neighbouring BF16
+values (one flip moves a sum of n products by about 2^-8 / sqrt(n))."""
 import numpy as np
 import pytest
 
@@ -75,18 +86,24 @@ def test_forward_matches_oracle(box):
     print(f"case forward box={box}", flush=True)
     ctx, pq, x, wd, bd, act = setup(box, seed=sum(box))
     ctx.nn_forward(wd, bd, act, box)
-    ref, acts = cnn.forward(pq, x)
-    got = out_of(act, box)
-    scale = np.abs(ref).max()
-    assert np.abs(got - ref).max() <= 1e-5 * scale
-    # hidden layers too (post-ReLU activations)
     nx, ny, nz = box
     nvox = nx * ny * nz
-    off = 8 * nvox
-    for l in range(1, 6):
-        h = host(act[off: off + 32 * nvox]).reshape(nz, ny, nx, 32)
-        assert np.abs(h - acts[l]).max() <= 1e-5 * max(np.abs(acts[l]).max(), 1e-30)
-        off += 32 * nvox
+    chans = cnn.CHANNELS
+    offs = [0]
+    for c in chans:
+        offs.append(offs[-1] + c * nvox)
+    layer = [host(act[offs[l]:offs[l + 1]]).astype(np.float64).reshape(nz, ny, nx, chans[l]) for l in range(7)]
+    # layer by layer on the GPU's own inputs: FP32 accumulation order only
+    for l, (W, b) in enumerate(pq):
+        ref = cnn.conv3d(cnn.bf16_round(layer[l]), W, b)
+        if l < len(pq) - 1:
+            ref = np.maximum(ref, 0.0)
+        assert np.abs(layer[l + 1] - ref).max() <= 2e-6 * np.abs(ref).max(), l
+    # whole network
+    ref, _ = cnn.forward(pq, x, bf16_inputs=True)
+    diff = layer[6] - ref
+    assert np.sqrt(np.mean(diff ** 2)) <= 5e-3 * np.sqrt(np.mean(ref ** 2))
+    assert np.abs(diff).max() <= 3e-2 * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("box", BOXES)
@@ -107,16 +124,37 @@ def test_loss_and_backward_match_oracle(box):
     grad = torch.empty(cnn_param_count(), dtype=torch.float32, device="cuda")
     work = torch.empty(ctx.nn_size(3, nx, ny, nz), dtype=torch.float32, device="cuda")
     ctx.nn_backward(wd, act, dout, grad, work, box)
-    ref_loss, ref_grads = cnn.loss_and_grads(pq, x, target.astype(np.float32).astype(np.float64), window)
-    assert abs(host(loss)[0] - ref_loss) <= 1e-5 * ref_loss
+    # the oracle differentiates the GPU's own activations, layer by layer
+    acts = []
+    off = 0
+    for c in cnn.CHANNELS:
+        acts.append(host(act[off: off + c * nx * ny * nz]).astype(np.float64).reshape(nz, ny, nx, c))
+        off += c * nx * ny * nz
+    tq = target.astype(np.float32).astype(np.float64)
+    diff = np.zeros_like(acts[6])
+    diff[window] = acts[6][window] - tq[window]
+    count = diff[window].size
+    ref_loss = float(np.sum(diff[window] ** 2) / count)
+    assert abs(host(loss)[0] - ref_loss) <= 1e-6 * ref_loss
+    dy = 2.0 * diff / count
+    ref_grads = [None] * 6
+    for l in range(5, -1, -1):
+        if l < 5:
+            dy = dy * (acts[l + 1] > 0.0)
+        dx, dW, db = cnn.conv3d_backward(acts[l], pq[l][0], dy, bf16_weight_grad=True)
+        ref_grads[l] = (dW, db)
+        dy = dx
     g = host(grad).astype(np.float64)
     gw, gb = g[:120960], g[120960:]
     got = unflat_weights(gw, gb)
     for l, ((dW, db), (rW, rb)) in enumerate(zip(got, ref_grads)):
         sw = np.abs(rW).max()
         sb = max(np.abs(rb).max(), 1e-30)
-        assert np.abs(dW - rW).max() <= 1e-4 * sw, (l, np.abs(dW - rW).max() / sw)
+        assert np.abs(dW - rW).max() <= 2e-3 * sw, (l, np.abs(dW - rW).max() / sw)
         assert np.abs(db - rb).max() <= 1e-4 * sb, (l, np.abs(db - rb).max() / sb)
+    # whole network against the oracle's own forward pass: BF16 level
+    loss_e2e, _ = cnn.loss_and_grads(pq, x, tq, window, bf16_inputs=True)
+    assert abs(ref_loss - loss_e2e) <= 3e-2 * loss_e2e
 
 
 def cnn_param_count():
@@ -207,11 +245,11 @@ def test_propose_matches_oracle_and_stays_in_box():
     feat = np.empty((n, 8))
     feat[:, :4] = (x.reshape(n, 4).astype(np.float32) * sc[:4]).astype(np.float64)
     feat[:, 4:] = (g.reshape(n, 4) / rms) * sc[4:8].astype(np.float64)
-    out, _ = cnn.forward(pq, feat.reshape(N + 1, N + 1, N + 1, 8))
+    out, _ = cnn.forward(pq, feat.reshape(N + 1, N + 1, N + 1, 8), bf16_inputs=True)
     raw = out.reshape(n, 4) * sc[8:].astype(np.float64) * rms
     ref = np.clip(raw.ravel(), lo, hi)
     assert np.all(s >= lo) and np.all(s <= hi)
-    assert np.abs(s - ref).max() <= 1e-5 * np.abs(raw).max()
+    assert np.abs(s - ref).max() <= 3e-2 * np.abs(raw).max()
     # non-finite network output (NaN bias) gives a zero step
     bnan = torch.full_like(bd, float("nan"))
     net2 = binding.Net(ctypes.c_void_p(wd.data_ptr()), ctypes.c_void_p(bnan.data_ptr()),

@@ -82,3 +82,16 @@ def test_adam_first_step_moves_by_lr_times_sign():
     g = np.array([0.5, -3.0, 1e-3])
     q, m, v = cnn.adam_step(p, g, np.zeros(3), np.zeros(3), 1, 1e-2)
     assert np.allclose(q, p - 1e-2 * np.sign(g), atol=1e-7)
+
+
+def test_bf16_round_pins():
+    """Round-to-nearest-even on the bfloat16 grid (8 significand bits)."""
+    from oracle import cnn
+    # exact values stay; halfway cases go to the even neighbour
+    assert cnn.bf16_round(np.array([1.0, 3.0, -2.5]))[0] == 1.0
+    one_ulp = 2.0 ** -7                       # bf16 spacing in [1, 2)
+    v = np.array([1.0 + one_ulp / 2, 1.0 + 1.5 * one_ulp, 1.0 + one_ulp / 4, 1.0 + 0.75 * one_ulp])
+    assert np.array_equal(cnn.bf16_round(v), [1.0, 1.0 + 2 * one_ulp, 1.0, 1.0 + one_ulp])
+    x = np.random.default_rng(0).standard_normal(1000)
+    r = cnn.bf16_round(x)
+    assert np.all(np.abs(r - x) <= np.abs(x) * 2.0 ** -8 * (1 + 1e-12))
