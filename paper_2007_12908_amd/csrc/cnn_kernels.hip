@@ -353,9 +353,12 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_mfma(Box b, const float* __r
       const int64_t v = vt + 4 * lk + t;
       vok[t] = v < v1;
       const int64_t vv = vok[t] ? v : v0;
-      cx[t] = int(vv % b.nx);
-      cy[t] = int((vv / b.nx) % b.ny);
-      cz[t] = int(vv / (int64_t(b.nx) * b.ny));
+      // 32-bit division (boxes hold fewer than 2^31 voxels)
+      const uint32_t u = uint32_t(vv), nx = uint32_t(b.nx), nxy = uint32_t(b.nx) * uint32_t(b.ny);
+      cz[t] = int(u / nxy);
+      const uint32_t rxy = u - uint32_t(cz[t]) * nxy;
+      cy[t] = int(rxy / nx);
+      cx[t] = int(rxy - uint32_t(cy[t]) * nx);
       float d = 0.0f;
       if (vok[t] && li < COUT) {
         d = dY[vv * COUT + li];

@@ -1,6 +1,8 @@
 // Matrix-free element kernels on the Q1 grid: energy, energy difference,
 // gradient, Hessian-vector product and node diagonal blocks.  FP64 throughout, with FP32 variants of the
 // Hessian-based operators for the mixed-precision form.
+#include <algorithm>
+
 #include "rmtr_kernels.h"
 
 namespace rmtr {
@@ -44,6 +46,10 @@ __device__ inline MatP<T> cast_mat(const MatP<double>& m) {
   r.ls = T(m.ls);
   r.k = T(m.k);
   r.split = m.split;
+  r.third = T(m.third);
+  r.mu23 = T(m.mu23);
+  r.Gc_ls = T(m.Gc_ls);
+  r.Gc_l = T(m.Gc_l);
   return r;
 }
 
@@ -172,26 +178,22 @@ __global__ __launch_bounds__(kBlock) void k_reduce_partials(const double* __rest
 constexpr int kTile = 16;
 constexpr int kOwn = kTile - 1;
 
+// One column segment: the tile (bx, by) writes its owned nodes of node
+// layers [z0, z1); it computes element layers z0 - 1 .. z1 - 1 (those that
+// touch them).
 template <int MODE, typename T>
-__device__ inline void elem_scatter3(int N, T h, const MatP<double>& md, int zchunk, const uint8_t* __restrict__ dir,
-                                     const T* __restrict__ x, const T* __restrict__ p, const T* __restrict__ v,
-                                     T* __restrict__ out) {
-  __shared__ T lo_sh[256][4][4];
-  __shared__ T hi_sh[256][4][4];
-  const MatP<T> m = cast_mat<T>(md);
+__device__ inline void elem_segment3(int N, const MatP<T>& m, T invh, T w, int bx, int by, int z0, int z1,
+                                     const uint8_t* __restrict__ dir, const T* __restrict__ x,
+                                     const T* __restrict__ p, const T* __restrict__ v, T* __restrict__ out,
+                                     T (*lo_sh)[4][4], T (*hi_sh)[4][4]) {
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
-  const int ex = int(blockIdx.x) * kOwn - 1 + tx;
-  const int ey = int(blockIdx.y) * kOwn - 1 + ty;
+  const int ex = bx * kOwn - 1 + tx;
+  const int ey = by * kOwn - 1 + ty;
   const int ox = ex + 1, oy = ey + 1;
   const bool ecol = ex >= 0 && ex < N && ey >= 0 && ey < N;
   const bool owner = tx < kOwn && ty < kOwn && ox <= N && oy <= N;
   const int64_t nside = N + 1;
-  const T invh = T(1) / h;
-  const T w = h * h * h / T(8);
-  const int z0 = int(blockIdx.z) * zchunk;
-  const int z1 = min(z0 + zchunk, N + 1);
-  if (z0 >= z1) return;
   const int zs = max(z0 - 1, 0), ze = min(z1 - 1, N - 1);
   T acc[4] = {T(0), T(0), T(0), T(0)};
   for (int ez = zs; ez <= ze; ++ez) {
@@ -250,23 +252,50 @@ __device__ inline void elem_scatter3(int N, T h, const MatP<double>& md, int zch
   }
 }
 
+// The work is the tiles x (N + 1) node layers, ordered column by column,
+// and split into gridDim.x equal contiguous ranges, one per workgroup: the
+// grid is sized to the workgroups the chip holds at once, so every compute
+// unit gets the same number of layers (a range that starts inside a column
+// recomputes one element layer).
+template <int MODE, typename T>
+__device__ inline void elem_scatter3(int N, T h, const MatP<double>& md, int tiles,
+                                     const uint8_t* __restrict__ dir, const T* __restrict__ x,
+                                     const T* __restrict__ p, const T* __restrict__ v, T* __restrict__ out) {
+  __shared__ T lo_sh[256][4][4];
+  __shared__ T hi_sh[256][4][4];
+  const MatP<T> m = cast_mat<T>(md);
+  const T invh = T(1) / h;
+  const T w = h * h * h / T(8);
+  const int64_t nz = N + 1;
+  const int64_t work = int64_t(tiles) * tiles * nz;
+  const int64_t u1 = work * (blockIdx.x + 1) / gridDim.x;
+  for (int64_t u = work * blockIdx.x / gridDim.x; u < u1;) {
+    const int64_t col = u / nz;
+    const int z0 = int(u - col * nz);
+    const int z1 = int(min(nz, int64_t(z0) + (u1 - u)));
+    elem_segment3<MODE, T>(N, m, invh, w, int(col % tiles), int(col / tiles), z0, z1, dir, x, p, v, out, lo_sh,
+                           hi_sh);
+    u += z1 - z0;
+  }
+}
+
 // FP64: one wavefront per SIMD (the element state does not fit in less than
 // the full register file); FP32: two, which the smaller state allows.
 template <int MODE, typename T>
-__global__ __launch_bounds__(256) void k_elem_scatter3(int N, T h, MatP<double> md, int zchunk,
+__global__ __launch_bounds__(256) void k_elem_scatter3(int N, T h, MatP<double> md, int tiles,
                                                        const uint8_t* __restrict__ dir,
                                                        const T* __restrict__ x, const T* __restrict__ p,
                                                        const T* __restrict__ v, T* __restrict__ out) {
-  elem_scatter3<MODE, T>(N, h, md, zchunk, dir, x, p, v, out);
+  elem_scatter3<MODE, T>(N, h, md, tiles, dir, x, p, v, out);
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256, 2) void k_elem_scatter3_f32(int N, float h, MatP<double> md, int zchunk,
+__global__ __launch_bounds__(256, 2) void k_elem_scatter3_f32(int N, float h, MatP<double> md, int tiles,
                                                               const uint8_t* __restrict__ dir,
                                                               const float* __restrict__ x,
                                                               const float* __restrict__ p,
                                                               const float* __restrict__ v, float* __restrict__ out) {
-  elem_scatter3<MODE, float>(N, h, md, zchunk, dir, x, p, v, out);
+  elem_scatter3<MODE, float>(N, h, md, tiles, dir, x, p, v, out);
 }
 
 // Node-centric kernels (any DIM): a thread per node sums the contributions
@@ -397,6 +426,19 @@ __global__ __launch_bounds__(kBlock) void k_diag_blocks(int N, T h, MatP<double>
   }
 }
 
+// Compute units of the current device, read once per device.
+int compute_units() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cache[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cache[dev] = n;
+  }
+  return cache[dev];
+}
+
 int grid_for(int64_t work) {
   int64_t b = (work + kBlock - 1) / kBlock;
   if (b < 1) b = 1;
@@ -442,18 +484,17 @@ template <int MODE, typename T>
 static hipError_t launch_scatter(const ElemArgs& a, const T* x, const T* p, const T* v, T* out, hipStream_t st) {
   if (a.dim == 3) {
     const int tiles = (a.N + 1 + kOwn - 1) / kOwn;
-    // enough z chunks for ~4 workgroups per compute unit
-    int chunks = (1024 + tiles * tiles - 1) / (tiles * tiles);
-    if (chunks < 1) chunks = 1;
-    int zchunk = (a.N + 1 + chunks - 1) / chunks;
-    if (zchunk < 4) zchunk = 4;
-    chunks = (a.N + 1 + zchunk - 1) / zchunk;
+    // one workgroup per compute unit (FP64), two (FP32); at least 4 node
+    // layers per workgroup
+    const int64_t work = int64_t(tiles) * tiles * (a.N + 1);
+    int64_t nb = int64_t(compute_units()) * (sizeof(T) == 4 ? 2 : 1);
+    nb = std::max<int64_t>(1, std::min(nb, work / 4));
     if constexpr (sizeof(T) == 4)
-      hipLaunchKernelGGL((k_elem_scatter3_f32<MODE>), dim3(tiles, tiles, chunks), dim3(256), 0, st, a.N, T(a.h), a.m,
-                         zchunk, a.dir, x, p, v, out);
+      hipLaunchKernelGGL((k_elem_scatter3_f32<MODE>), dim3(unsigned(nb)), dim3(256), 0, st, a.N, T(a.h), a.m, tiles,
+                         a.dir, x, p, v, out);
     else
-      hipLaunchKernelGGL((k_elem_scatter3<MODE, T>), dim3(tiles, tiles, chunks), dim3(256), 0, st, a.N, T(a.h), a.m,
-                         zchunk, a.dir, x, p, v, out);
+      hipLaunchKernelGGL((k_elem_scatter3<MODE, T>), dim3(unsigned(nb)), dim3(256), 0, st, a.N, T(a.h), a.m, tiles,
+                         a.dir, x, p, v, out);
   } else {
     int64_t nn = int64_t(a.N + 1) * (a.N + 1);
     hipLaunchKernelGGL((k_node_gather<2, MODE, T>), dim3(grid_for(nn)), dim3(kBlock), 0, st, a.N, T(a.h), a.m, a.dir,

@@ -579,6 +579,7 @@ MatP<Cnt> cnt_mat() {
   m.ls = 0.1;
   m.k = 1e-6;
   m.split = 1;
+  set_derived(m);
   return m;
 }
 
@@ -686,6 +687,7 @@ rmtr_status rmtr_create(const rmtr_model* m, rmtr_ctx** out) {
   c->mat.ls = m->ls;
   c->mat.k = m->k;
   c->mat.split = m->split ? 1 : 0;
+  set_derived(c->mat);
   c->L = m->n_levels;
   c->lv.resize(c->L + 1);
   for (int l = 1; l <= c->L; ++l) {

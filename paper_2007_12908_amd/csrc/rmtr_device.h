@@ -28,7 +28,17 @@ template <typename T>
 struct MatP {
   T lam, mu, K, Gc, ls, k;
   int split;
+  // derived once on the host (set_derived), so no kernel divides
+  T third, mu23, Gc_ls, Gc_l;  // 1/3, 2 mu / 3, Gc / l, Gc l
 };
+
+template <typename T>
+RMTR_FN void set_derived(MatP<T>& m) {
+  m.third = T(1) / T(3);
+  m.mu23 = T(2) * m.mu / T(3);
+  m.Gc_ls = m.Gc / m.ls;
+  m.Gc_l = m.Gc * m.ls;
+}
 
 // One level of the hierarchy: N cells per side, (N+1)^DIM nodes.
 template <typename T>
@@ -105,14 +115,14 @@ RMTR_FN void split_parts(const MatP<T>& m, const T (&G)[DIM][DIM], Split<DIM, T>
   if (m.split) {
     T tp = t > T(0) ? t : T(0);
     T tm = t > T(0) ? T(0) : t;
-    s.psip = T(0.5) * m.K * tp * tp + m.mu * (epsq - t * t / T(3));
+    s.psip = T(0.5) * m.K * tp * tp + m.mu * (epsq - t * t * m.third);
     s.psim = T(0.5) * m.K * tm * tm;
 #pragma unroll
     for (int i = 0; i < DIM; ++i)
 #pragma unroll
       for (int j = 0; j < DIM; ++j) {
         T e = T(0.5) * (G[i][j] + G[j][i]);
-        s.sigp[i][j] = T(2) * m.mu * e + (i == j ? (m.K * tp - T(2) * m.mu * t / T(3)) : T(0));
+        s.sigp[i][j] = T(2) * m.mu * e + (i == j ? (m.K * tp - m.mu23 * t) : T(0));
       }
     s.sigm = m.K * tm;
   } else {
@@ -144,7 +154,7 @@ RMTR_FN T density(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T (&dp)[DIM]
     pi += dp[i] * z.u[i];
     dcq += z.dc[i] * z.dc[i];
   }
-  T crack = T(0.5) * m.Gc * (z.c * z.c / m.ls + m.ls * dcq);
+  T crack = T(0.5) * (m.Gc_ls * z.c * z.c + m.Gc_l * dcq);
   return g * s.psip + s.psim + crack + gp * pi;
 }
 
@@ -165,12 +175,12 @@ RMTR_FN void density_grad(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T (&
 #pragma unroll
   for (int i = 0; i < DIM; ++i) {
     out.u[i] = gp * dp[i];
-    out.dc[i] = m.Gc * m.ls * z.dc[i];
+    out.dc[i] = m.Gc_l * z.dc[i];
 #pragma unroll
     for (int j = 0; j < DIM; ++j)
       out.G[i][j] = g * s.sigp[i][j] + (i == j ? (s.sigm + gp * p) : T(0));
   }
-  out.c = dg * s.psip + m.Gc * z.c / m.ls + dgp * pi;
+  out.c = dg * s.psip + m.Gc_ls * z.c + dgp * pi;
 }
 
 // Coefficients of the second variation at a linearisation point.
@@ -199,7 +209,7 @@ RMTR_FN void hess_coef(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T (&dp)
   for (int i = 0; i < DIM; ++i) pi += dp[i] * z.u[i];
   if (m.split) {
     T Hp = s.t > T(0) ? T(1) : T(0);
-    hc.vol = g * m.K * Hp + m.K * (T(1) - Hp) - g * T(2) * m.mu / T(3);
+    hc.vol = g * m.K * Hp + m.K * (T(1) - Hp) - g * m.mu23;
   } else {
     hc.vol = g * m.lam;
   }
@@ -210,7 +220,7 @@ RMTR_FN void hess_coef(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T (&dp)
 #pragma unroll
     for (int j = 0; j < DIM; ++j) hc.S[i][j] = dg * s.sigp[i][j] + (i == j ? dgp * p : T(0));
   }
-  hc.Ccc = d2g * s.psip + m.Gc / m.ls + T(2) * pi;
+  hc.Ccc = d2g * s.psip + m.Gc_ls + T(2) * pi;
 }
 
 // Second variation applied to a direction v (z-vector of v at the point).
@@ -224,7 +234,7 @@ RMTR_FN void hess_apply(const MatP<T>& m, const HessCoef<DIM, T>& hc, const Zq<D
 #pragma unroll
   for (int i = 0; i < DIM; ++i) {
     out.u[i] = hc.Pc[i] * v.c;
-    out.dc[i] = m.Gc * m.ls * v.dc[i];
+    out.dc[i] = m.Gc_l * v.dc[i];
     oc += hc.Pc[i] * v.u[i];
 #pragma unroll
     for (int j = 0; j < DIM; ++j) {
