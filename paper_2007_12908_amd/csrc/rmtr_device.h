@@ -486,31 +486,223 @@ RMTR_FN void elem_project(const Zq<DIM, T> (&o)[1 << DIM], T invh, T w, T (&r)[1
 }
 
 // ------------------------------------------------ per-element operators
-// MODE 0: gradient of f at x.  MODE 1: Hessian at xl applied to v.
+// 3D element operators on unit-cell derivatives.  With G' = h grad (the
+// derivative on the unit cell) the element's rows are
+//   r = sum_q B'_q^T o_q,
+// where o_q already carries the quadrature weight w and the 1/h of the
+// test-function derivatives: o.u and o.c are scaled by w, o.G and o.dc by
+// w / h.  The pointwise coefficients absorb these factors (a1 = w / h,
+// a2 = w / h^2), so the interpolations and the projection need no scaling.
+template <typename T>
+struct ElemScale {
+  T w, a1, a2;
+};
+
+template <typename T>
+RMTR_FN ElemScale<T> elem_scale(T invh, T w) {
+  ElemScale<T> e;
+  e.w = w;
+  e.a1 = w * invh;
+  e.a2 = e.a1 * invh;
+  return e;
+}
+
+// Split parts on unit-cell strains: psi' = h^2 psi, sig' = h sig, t' = h t.
+template <typename T>
+RMTR_FN void split_unit(const MatP<T>& m, const T (&G)[3][3], T& t, T& psip, T (&sigp)[3][3], T& sigm) {
+  t = G[0][0] + G[1][1] + G[2][2];
+  T e[3][3], epsq = T(0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      e[i][j] = T(0.5) * (G[i][j] + G[j][i]);
+      epsq += e[i][j] * e[i][j];
+    }
+  T diag;
+  if (m.split) {
+    const T tp = t > T(0) ? t : T(0);
+    const T tm = t > T(0) ? T(0) : t;
+    psip = T(0.5) * m.K * tp * tp + m.mu * (epsq - t * t * m.third);
+    diag = m.K * tp - m.mu23 * t;
+    sigm = m.K * tm;
+  } else {
+    psip = T(0.5) * m.lam * t * t + m.mu * epsq;
+    diag = m.lam * t;
+    sigm = T(0);
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) sigp[i][j] = T(2) * m.mu * e[i][j] + (i == j ? diag : T(0));
+}
+
+// Scaled first variation at one point: z holds unit-cell derivatives of
+// u and c, dp the unit-cell gradient of p.
+template <typename T>
+RMTR_FN void density_grad_unit(const MatP<T>& m, const ElemScale<T>& sc, const Zq<3, T>& z, T p,
+                               const T (&dp)[3], Zq<3, T>& o) {
+  T t, psip, sigp[3][3], sigm;
+  split_unit<T>(m, z.G, t, psip, sigp, sigm);
+  const T omc = T(1) - z.c;
+  const T g = (T(1) - m.k) * omc * omc + m.k;
+  const T dg = T(-2) * (T(1) - m.k) * omc;
+  const T gp = omc * omc;
+  const T dgp = T(-2) * omc;
+  T pi = p * t;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) pi += dp[i] * z.u[i];
+  const T a2g = sc.a2 * g;
+  const T dia = sc.a2 * sigm + sc.a1 * gp * p;
+  const T a1gp = sc.a1 * gp;
+  const T cdc = sc.a2 * m.Gc_l;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    o.u[i] = a1gp * dp[i];
+    o.dc[i] = cdc * z.dc[i];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) o.G[i][j] = a2g * sigp[i][j] + (i == j ? dia : T(0));
+  }
+  o.c = sc.a2 * dg * psip + sc.w * m.Gc_ls * z.c + sc.a1 * dgp * pi;
+}
+
+// Scaled second-variation coefficients at the linearisation point.
+template <typename T>
+RMTR_FN void hess_coef_unit(const MatP<T>& m, const ElemScale<T>& sc, const Zq<3, T>& z, T p, const T (&dp)[3],
+                            HessCoef<3, T>& hc) {
+  T t, psip, sigp[3][3], sigm;
+  split_unit<T>(m, z.G, t, psip, sigp, sigm);
+  const T omc = T(1) - z.c;
+  const T g = (T(1) - m.k) * omc * omc + m.k;
+  const T dg = T(-2) * (T(1) - m.k) * omc;
+  const T d2g = T(2) * (T(1) - m.k);
+  const T dgp = T(-2) * omc;
+  T pi = p * t;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) pi += dp[i] * z.u[i];
+  if (m.split) {
+    const T Hp = t > T(0) ? T(1) : T(0);
+    hc.vol = sc.a2 * (g * m.K * Hp + m.K * (T(1) - Hp) - g * m.mu23);
+  } else {
+    hc.vol = sc.a2 * g * m.lam;
+  }
+  hc.shear = sc.a2 * g * m.mu;
+  const T a2dg = sc.a2 * dg;
+  const T a1dgp = sc.a1 * dgp;
+  const T dia = a1dgp * p;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    hc.Pc[i] = a1dgp * dp[i];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) hc.S[i][j] = a2dg * sigp[i][j] + (i == j ? dia : T(0));
+  }
+  hc.Ccc = sc.a2 * d2g * psip + sc.w * m.Gc_ls + T(2) * sc.a1 * pi;
+}
+
+// Scaled second variation applied to v (unit-cell derivatives); cdc = a2 Gc l.
+template <typename T>
+RMTR_FN void hess_apply_unit(const HessCoef<3, T>& hc, T cdc, const Zq<3, T>& v, Zq<3, T>& o) {
+  const T tv = v.G[0][0] + v.G[1][1] + v.G[2][2];
+  T oc = hc.Ccc * v.c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    o.u[i] = hc.Pc[i] * v.c;
+    o.dc[i] = cdc * v.dc[i];
+    oc += hc.Pc[i] * v.u[i];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      o.G[i][j] = hc.shear * (v.G[i][j] + v.G[j][i]) + hc.S[i][j] * v.c + (i == j ? hc.vol * tv : T(0));
+      oc += hc.S[i][j] * v.G[i][j];
+    }
+  }
+  o.c = oc;
+}
+
+// Values and unit-cell derivatives at the 8 points.
+template <typename T>
+RMTR_FN void elem_z_unit(const T (&X)[8][4], Zq<3, T> (&z)[8]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    T f[8], val[8], dx[8], dy[8], dz[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) f[a] = X[a][k];
+    sf_forward3<T>(f, val, dx, dy, dz);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (k < 3) {
+        z[q].u[k] = val[q];
+        z[q].G[k][0] = dx[q];
+        z[q].G[k][1] = dy[q];
+        z[q].G[k][2] = dz[q];
+      } else {
+        z[q].c = val[q];
+        z[q].dc[0] = dx[q];
+        z[q].dc[1] = dy[q];
+        z[q].dc[2] = dz[q];
+      }
+    }
+  }
+}
+
+template <typename T>
+RMTR_FN void elem_project_unit(const Zq<3, T> (&o)[8], T (&r)[8][4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    T cv[8], cx[8], cy[8], cz[8], rr[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (k < 3) {
+        cv[q] = o[q].u[k];
+        cx[q] = o[q].G[k][0];
+        cy[q] = o[q].G[k][1];
+        cz[q] = o[q].G[k][2];
+      } else {
+        cv[q] = o[q].c;
+        cx[q] = o[q].dc[0];
+        cy[q] = o[q].dc[1];
+        cz[q] = o[q].dc[2];
+      }
+      rr[q] = T(0);
+    }
+    sf_backward3<T>(cv, cx, cy, cz, rr);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) r[a][k] = rr[a];
+  }
+}
+
+// MODE 0: gradient of f at X.  MODE 1: Hessian at X applied to V.
 template <int MODE, typename T>
 struct ElemOp3 {
   // computes r[8][4] for one element
   __host__ __device__ static inline void eval(const MatP<T>& m, T invh, T w, const T (&X)[8][4], const T (&V)[8][4],
                                      const T (&P)[8], T (&r)[8][4]) {
-    T pq[8], dpq[8][3];
-    elem_pq<3, T>(P, invh, pq, dpq);
+    const ElemScale<T> sc = elem_scale<T>(invh, w);
+    T pq[8], dpx[8], dpy[8], dpz[8];
+    sf_forward3<T>(P, pq, dpx, dpy, dpz);
     Zq<3, T> o[8];
     {
       Zq<3, T> z[8];
-      elem_z<3, T>(X, invh, z);
+      elem_z_unit<T>(X, z);
       if (MODE == 0) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) density_grad<3, T>(m, z[q], pq[q], dpq[q], o[q]);
+        for (int q = 0; q < 8; ++q) {
+          const T dp[3] = {dpx[q], dpy[q], dpz[q]};
+          density_grad_unit<T>(m, sc, z[q], pq[q], dp, o[q]);
+        }
       } else {
         HessCoef<3, T> hc[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) hess_coef<3, T>(m, z[q], pq[q], dpq[q], hc[q]);
-        elem_z<3, T>(V, invh, z);
+        for (int q = 0; q < 8; ++q) {
+          const T dp[3] = {dpx[q], dpy[q], dpz[q]};
+          hess_coef_unit<T>(m, sc, z[q], pq[q], dp, hc[q]);
+        }
+        elem_z_unit<T>(V, z);
+        const T cdc = sc.a2 * m.Gc_l;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) hess_apply<3, T>(m, hc[q], z[q], o[q]);
+        for (int q = 0; q < 8; ++q) hess_apply_unit<T>(hc[q], cdc, z[q], o[q]);
       }
     }
-    elem_project<3, T>(o, invh, w, r);
+    elem_project_unit<T>(o, r);
   }
 };
 

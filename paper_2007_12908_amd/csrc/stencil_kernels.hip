@@ -164,23 +164,18 @@ __global__ __launch_bounds__(kB) void k_coef(int N, double h, MatP<double> m, co
 // element coefficients they load, and consecutive nodes of a colour give
 // coalesced stores.
 template <int DIM, typename TO>
-__global__ __launch_bounds__(kB) void k_st_node(Colours g, double h, double gcl, const double* __restrict__ C,
-                                                const uint8_t* __restrict__ dir, TO* __restrict__ S) {
+__device__ inline void st_node_item(const Colours& g, double h, double gcl, const double* __restrict__ C,
+                                    const uint8_t* __restrict__ dir, TO* __restrict__ S, int al, int64_t id,
+                                    int pz) {
   constexpr int NL = 1 << DIM, NC = DIM + 1, NK = n_coef<DIM>(), NO = n_off<DIM>(), RB = row_block<DIM>();
   constexpr int NP = DIM == 3 ? 3 : 1, OPP = NO / NP;
   const int N = g.N;
-  const int64_t nodes = g.base[1 << DIM];
   const int64_t ns = N + 1;
   const double invh = 1.0 / h;
   double w = 1.0;
 #pragma unroll
   for (int i = 0; i < DIM; ++i) w *= 0.5 * h;
-  const int64_t work = nodes * NC * NP;
-  for (int64_t it = int64_t(blockIdx.x) * kB + threadIdx.x; it < work; it += int64_t(gridDim.x) * kB) {
-    const int al = int(it % NC);
-    const int64_t r1 = it / NC;
-    const int64_t id = r1 % nodes;
-    const int pz = int(r1 / nodes);
+  {
     int64_t t, n;
     int c[DIM];
     const int col = locate<DIM>(g, id, t, c, n);
@@ -305,6 +300,43 @@ __global__ __launch_bounds__(kB) void k_st_node(Colours g, double h, double gcl,
         const double v = (row_fixed || ((mcol >> be) & 1u)) ? 0.0 : acc[o][be];
         out[((al * NO + of) * NC + be) * kChunk] = TO(v);
       }
+    }
+  }
+}
+
+// Work order.  2D: (al, node, plane) with al fastest over the colour-major
+// node order.  3D: a workgroup takes one 64-node chunk of one colour and
+// one plane (64 nodes x 4 rows); the workgroups that land on one XCD
+// (b % 8) take chunks x, x + 8, ... and, for each, all 8 colours and 3
+// planes in turn, so the element coefficients around a chunk are fetched
+// into that XCD's L2 once and reused by the 24 workgroups that need them.
+constexpr bool kBlockedOrder = true;
+
+template <int DIM, typename TO>
+__global__ __launch_bounds__(kB) void k_st_node(Colours g, double h, double gcl, const double* __restrict__ C,
+                                                const uint8_t* __restrict__ dir, TO* __restrict__ S) {
+  constexpr int NC = DIM + 1, NP = DIM == 3 ? 3 : 1;
+  const int64_t nodes = g.base[1 << DIM];
+  if constexpr (DIM == 3 && kBlockedOrder) {
+    int64_t J = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) J = max(J, (g.cnt[c] + kChunk - 1) / kChunk);
+    const int64_t nblk = 8 * 24 * ((J + 7) / 8);
+    const int al = int(threadIdx.x) & 3;
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+      const int x = int(b & 7);
+      const int64_t k = b >> 3;
+      const int inner = int(k % 24);
+      const int col = inner & 7, pz = inner >> 3;
+      const int64_t t = (x + 8 * (k / 24)) * kChunk + (threadIdx.x >> 2);
+      if (t < g.cnt[col]) st_node_item<DIM, TO>(g, h, gcl, C, dir, S, al, g.base[col] + t, pz);
+    }
+  } else {
+    const int64_t work = nodes * NC * NP;
+    for (int64_t it = int64_t(blockIdx.x) * kB + threadIdx.x; it < work; it += int64_t(gridDim.x) * kB) {
+      const int al = int(it % NC);
+      const int64_t r1 = it / NC;
+      st_node_item<DIM, TO>(g, h, gcl, C, dir, S, al, r1 % nodes, int(r1 / nodes));
     }
   }
 }
