@@ -101,9 +101,9 @@ __device__ inline int64_t st_row(const Colours& g, int col, int64_t t) {
 
 // Second-variation coefficients at the 2^DIM quadrature points of every
 // element, element-major: C[(e 2^DIM + q) n_coef + k].
-template <int DIM>
+template <int DIM, typename TC>
 __global__ __launch_bounds__(kB) void k_coef(int N, double h, MatP<double> m, const double* __restrict__ x,
-                                             const double* __restrict__ p, double* __restrict__ C) {
+                                             const double* __restrict__ p, TC* __restrict__ C) {
   constexpr int NL = 1 << DIM, NC = DIM + 1, NK = n_coef<DIM>();
   int64_t ne = 1;
 #pragma unroll
@@ -139,15 +139,15 @@ __global__ __launch_bounds__(kB) void k_coef(int N, double h, MatP<double> m, co
     for (int q = 0; q < NL; ++q) {
       HessCoef<DIM, double> hc;
       hess_coef<DIM, double>(m, z[q], pq[q], dpq[q], hc);
-      double* o = C + (e * NL + q) * NK;
-      o[0] = hc.vol;
-      o[1] = hc.shear;
-      o[2] = hc.Ccc;
+      TC* o = C + (e * NL + q) * NK;
+      o[0] = TC(hc.vol);
+      o[1] = TC(hc.shear);
+      o[2] = TC(hc.Ccc);
 #pragma unroll
       for (int i = 0; i < DIM; ++i) {
-        o[3 + DIM * DIM + i] = hc.Pc[i];
+        o[3 + DIM * DIM + i] = TC(hc.Pc[i]);
 #pragma unroll
-        for (int j = 0; j < DIM; ++j) o[3 + DIM * i + j] = hc.S[i][j];
+        for (int j = 0; j < DIM; ++j) o[3 + DIM * i + j] = TC(hc.S[i][j]);
       }
     }
   }
@@ -164,28 +164,31 @@ __global__ __launch_bounds__(kB) void k_coef(int N, double h, MatP<double> m, co
 // element coefficients they load, and consecutive nodes of a colour give
 // coalesced stores.
 template <int DIM, typename TO>
-__device__ inline void st_node_item(const Colours& g, double h, double gcl, const double* __restrict__ C,
+__device__ inline void st_node_item(const Colours& g, double h, double gcl_d, const TO* __restrict__ C,
                                     const uint8_t* __restrict__ dir, TO* __restrict__ S, int al, int64_t id,
                                     int pz) {
   constexpr int NL = 1 << DIM, NC = DIM + 1, NK = n_coef<DIM>(), NO = n_off<DIM>(), RB = row_block<DIM>();
   constexpr int NP = DIM == 3 ? 3 : 1, OPP = NO / NP;
   const int N = g.N;
   const int64_t ns = N + 1;
-  const double invh = 1.0 / h;
-  double w = 1.0;
+  using T = TO;  // arithmetic in the stencil's precision
+  const T invh = T(1.0 / h);
+  const T gcl = T(gcl_d);
+  double wd = 1.0;
 #pragma unroll
-  for (int i = 0; i < DIM; ++i) w *= 0.5 * h;
+  for (int i = 0; i < DIM; ++i) wd *= 0.5 * h;
+  const T w = T(wd);
   {
     int64_t t, n;
     int c[DIM];
     const int col = locate<DIM>(g, id, t, c, n);
     const uint8_t mrow = dir ? dir[n] : default_mask<DIM>(c, N);
     const bool row_fixed = (mrow >> al) & 1u;
-    double acc[OPP][NC];
+    T acc[OPP][NC];
 #pragma unroll
     for (int o = 0; o < OPP; ++o)
 #pragma unroll
-      for (int be = 0; be < NC; ++be) acc[o][be] = 0.0;
+      for (int be = 0; be < NC; ++be) acc[o][be] = T(0);
     if (!row_fixed) {
 #pragma unroll
       for (int a = 0; a < NL; ++a) {
@@ -206,25 +209,25 @@ __device__ inline void st_node_item(const Colours& g, double h, double gcl, cons
           eid += int64_t(e[i]) * st;
           st *= N;
         }
-        const double* cfe = C + eid * (NL * NK);
+        const T* cfe = C + eid * (NL * NK);
 #pragma unroll 1
         for (int q = 0; q < NL; ++q) {
-          const double* cf = cfe + q * NK;
-          const double vol = cf[0], shear = cf[1], ccc = cf[2];
-          double Sr[DIM][DIM], Pc[DIM];
+          const T* cf = cfe + q * NK;
+          const T vol = cf[0], shear = cf[1], ccc = cf[2];
+          T Sr[DIM][DIM], Pc[DIM];
 #pragma unroll
           for (int i = 0; i < DIM; ++i) {
             Pc[i] = cf[3 + DIM * DIM + i];
 #pragma unroll
             for (int jj = 0; jj < DIM; ++jj) Sr[i][jj] = cf[3 + DIM * i + jj];
           }
-          const double Na = refN<DIM>(q, a);
-          double dNa[DIM];
+          const T Na = T(refN<DIM>(q, a));
+          T dNa[DIM];
 #pragma unroll
-          for (int jj = 0; jj < DIM; ++jj) dNa[jj] = refdN<DIM>(q, a, jj) * invh;
-          double dNal = 0.0, Sal[DIM], Pcal = 0.0;
+          for (int jj = 0; jj < DIM; ++jj) dNa[jj] = T(refdN<DIM>(q, a, jj)) * invh;
+          T dNal = T(0), Sal[DIM], Pcal = T(0);
 #pragma unroll
-          for (int jj = 0; jj < DIM; ++jj) Sal[jj] = 0.0;
+          for (int jj = 0; jj < DIM; ++jj) Sal[jj] = T(0);
 #pragma unroll
           for (int i = 0; i < DIM; ++i)
             if (i == al) {
@@ -233,7 +236,7 @@ __device__ inline void st_node_item(const Colours& g, double h, double gcl, cons
 #pragma unroll
               for (int jj = 0; jj < DIM; ++jj) Sal[jj] = Sr[i][jj];
             }
-          double SdNa = 0.0;
+          T SdNa = T(0);
 #pragma unroll
           for (int jj = 0; jj < DIM; ++jj) SdNa += Sal[jj] * dNa[jj];
 #pragma unroll
@@ -247,27 +250,27 @@ __device__ inline void st_node_item(const Colours& g, double h, double gcl, cons
               o += (((b >> i) & 1) - ((a >> i) & 1) + 1) * om;
               om *= 3;
             }
-            const double Nb = refN<DIM>(q, b);
-            double dNb[DIM];
-            double dd = 0.0;
+            const T Nb = T(refN<DIM>(q, b));
+            T dNb[DIM];
+            T dd = T(0);
 #pragma unroll
             for (int jj = 0; jj < DIM; ++jj) {
-              dNb[jj] = refdN<DIM>(q, b, jj) * invh;
+              dNb[jj] = T(refdN<DIM>(q, b, jj)) * invh;
               dd += dNa[jj] * dNb[jj];
             }
             if (al < DIM) {
-              double dNbal = 0.0;
+              T dNbal = T(0);
 #pragma unroll
               for (int i = 0; i < DIM; ++i)
                 if (i == al) dNbal = dNb[i];
 #pragma unroll
               for (int be = 0; be < DIM; ++be)
-                acc[o][be] += w * (vol * dNal * dNb[be] + shear * ((al == be ? dd : 0.0) + dNa[be] * dNbal));
+                acc[o][be] += w * (vol * dNal * dNb[be] + shear * ((al == be ? dd : T(0)) + dNa[be] * dNbal));
               acc[o][DIM] += w * (SdNa * Nb + Pcal * Na * Nb);
             } else {
 #pragma unroll
               for (int be = 0; be < DIM; ++be) {
-                double cu = Pc[be] * Na * Nb;
+                T cu = Pc[be] * Na * Nb;
 #pragma unroll
                 for (int jj = 0; jj < DIM; ++jj) cu += Sr[be][jj] * dNb[jj] * Na;
                 acc[o][be] += w * cu;
@@ -297,7 +300,7 @@ __device__ inline void st_node_item(const Colours& g, double h, double gcl, cons
       const uint8_t mcol = inside ? (dir ? dir[mid] : default_mask<DIM>(m, N)) : uint8_t(0xff);
 #pragma unroll
       for (int be = 0; be < NC; ++be) {
-        const double v = (row_fixed || ((mcol >> be) & 1u)) ? 0.0 : acc[o][be];
+        const T v = (row_fixed || ((mcol >> be) & 1u)) ? T(0) : acc[o][be];
         out[((al * NO + of) * NC + be) * kChunk] = TO(v);
       }
     }
@@ -313,7 +316,7 @@ __device__ inline void st_node_item(const Colours& g, double h, double gcl, cons
 constexpr bool kBlockedOrder = true;
 
 template <int DIM, typename TO>
-__global__ __launch_bounds__(kB) void k_st_node(Colours g, double h, double gcl, const double* __restrict__ C,
+__global__ __launch_bounds__(kB) void k_st_node(Colours g, double h, double gcl, const TO* __restrict__ C,
                                                 const uint8_t* __restrict__ dir, TO* __restrict__ S) {
   constexpr int NC = DIM + 1, NP = DIM == 3 ? 3 : 1;
   const int64_t nodes = g.base[1 << DIM];
@@ -746,10 +749,13 @@ static hipError_t st_assemble_t(const ElemArgs& a, const double* xl, const doubl
   for (int i = 0; i < DIM; ++i) ne *= a.N;
   const Colours g = colours(DIM, a.N);
   const double gcl = a.m.Gc * a.m.ls;
-  hipLaunchKernelGGL(k_coef<DIM>, dim3(gridn(ne)), dim3(kB), 0, st, a.N, a.h, a.m, xl, p, coef);
+  // coefficients in the stencil's precision (the FP32 stencil of the mixed
+  // form is assembled from FP32 coefficients in FP32 arithmetic)
+  TO* cf = reinterpret_cast<TO*>(coef);
+  hipLaunchKernelGGL((k_coef<DIM, TO>), dim3(gridn(ne)), dim3(kB), 0, st, a.N, a.h, a.m, xl, p, cf);
   constexpr int NP = DIM == 3 ? 3 : 1;
   const int64_t work = g.base[NL] * NC * NP;
-  hipLaunchKernelGGL((k_st_node<DIM, TO>), dim3(gridn(work)), dim3(kB), 0, st, g, a.h, gcl, coef, a.dir, S);
+  hipLaunchKernelGGL((k_st_node<DIM, TO>), dim3(gridn(work)), dim3(kB), 0, st, g, a.h, gcl, cf, a.dir, S);
   return hipGetLastError();
 }
 
