@@ -129,7 +129,7 @@ def main():
     ap.add_argument("--workload", default="c2_3d_128")
     ap.add_argument("--no-loadstep", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--train-seconds", type=float, default=30.0)
+    ap.add_argument("--train-seconds", type=float, default=60.0)
     ap.add_argument("--learned-target", choices=("pgs", "vcycle"), default="pgs")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernels-only", action="store_true",
