@@ -15,10 +15,11 @@ Loss: mean squared error over the voxels of an interior window and all
 output channels.  Adam (Kingma and Ba) with bias correction.
 
 Option bf16_inputs: each layer's input is rounded to bfloat16 (nearest,
-ties to even, through float32) before its convolution, and the weight
-gradient multiplies bfloat16-rounded layer inputs and output gradients, the
-precision of the matrix-core form; the rounding is otherwise treated as the
-identity (data and bias gradients in full precision).
+ties to even, through float32) before its convolution, and the weight and
+data gradients multiply bfloat16-rounded layer inputs and output gradients
+(with the bfloat16 weights), the precision of the matrix-core form; the
+rounding is otherwise treated as the identity (bias gradients in full
+precision, no gradient through the rounding).
 """
 import numpy as np
 
@@ -52,7 +53,8 @@ def conv3d(x, W, b):
 def conv3d_backward(x, W, dy, bf16_weight_grad=False):
     """Gradients of sum(dy * conv3d(x, W, b)) w.r.t. x, W and b.  With
     bf16_weight_grad the weight gradient takes x and dy rounded to bfloat16
-    (the matrix-core form); dx and db use them unrounded."""
+    and the data gradient dy rounded to bfloat16 (the matrix-core form); db
+    uses dy unrounded."""
     dW = np.zeros_like(W)
     dx = np.zeros_like(x)
     xq = bf16_round(x) if bf16_weight_grad else x
@@ -61,7 +63,7 @@ def conv3d_backward(x, W, dy, bf16_weight_grad=False):
         xs = shifted(xq, d)
         dW[k] = xs.reshape(-1, x.shape[3]).T @ dyq.reshape(-1, dy.shape[3])
         # y[v] gets x[v + d] W: x[u] feeds y[u - d]
-        dx += shifted(dy, (-d[0], -d[1], -d[2])) @ W[k].T
+        dx += shifted(dyq, (-d[0], -d[1], -d[2])) @ W[k].T
     db = dy.reshape(-1, dy.shape[3]).sum(axis=0)
     return dx, dW, db
 

@@ -16,8 +16,6 @@ namespace {
 
 constexpr int kB = 256;
 
-__device__ inline float bf2f(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
-
 // round-to-nearest-even FP32 -> BF16
 __device__ inline uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -30,374 +28,273 @@ struct Box {
   int nx, ny, nz;
 };
 
-__device__ inline bool nb(const Box& b, int x, int y, int z, int k, int64_t& u, int sign) {
-  const int dx = (k % 3 - 1) * sign, dy = ((k / 3) % 3 - 1) * sign, dz = (k / 9 - 1) * sign;
-  const int X = x + dx, Y = y + dy, Z = z + dz;
-  if (X < 0 || X >= b.nx || Y < 0 || Y >= b.ny || Z < 0 || Z >= b.nz) return false;
-  u = int64_t(X) + int64_t(b.nx) * (Y + int64_t(b.ny) * Z);
-  return true;
-}
-
-// Direct 3x3x3 convolution, used for the forward pass and for the data
-// gradient:
-//   out[v][o] = (bias[o]) + sum_k sum_i Wl[k][i][o] m(in)[v + SIGN off(k)][i]
-// Forward: Wl = W (SIGN +1).  Data gradient: Wl[k][i][o] = W[k][o][i]
-// (transposed while staging, SIGN -1) and m(in) = in masked by the ReLU of
-// the layer's output (mask > 0).  Weights of the layer sit in LDS as BF16.
-// A thread computes V consecutive voxels of one x-row for CG consecutive
-// outputs: each LDS weight read (CG values) feeds V CG FMAs and each input
-// load (4 channels of a voxel) feeds 4 CG FMAs.  The waves of a block
-// share the voxels and split the outputs, so weight reads are broadcasts.
-template <int NI, int NO, int SIGN, int TRANS, int BIAS, int RELU_OUT, int MASK_IN>
-__global__ __launch_bounds__(kB) void k_conv(Box b, const float* __restrict__ in, const float* __restrict__ mask,
-                                             const uint16_t* __restrict__ W, const float* __restrict__ bias,
-                                             float* __restrict__ out) {
-  constexpr int V = 4;
-  constexpr int CG = NO < 8 ? NO : 8, NG = NO / CG, VGB = kB / NG;
-  static_assert(NI % 4 == 0 && NO % CG == 0, "channel counts");
-  __shared__ __align__(16) uint16_t sW[27 * NI * NO];
-  for (int e = threadIdx.x; e < 27 * NI * NO; e += kB) {
-    if (TRANS) {
-      // sW[k][i][o] = W[k][o][i] with W of shape [27][NO][NI]
-      const int k = e / (NI * NO), r = e % (NI * NO), i = r / NO, o = r % NO;
-      sW[e] = W[(k * NO + o) * NI + i];
-    } else {
-      sW[e] = W[e];
-    }
-  }
-  __syncthreads();
-  const int gpr = (b.nx + V - 1) / V;
-  const int64_t ngroups = int64_t(gpr) * b.ny * b.nz;
-  const int gq = threadIdx.x / VGB, lv = threadIdx.x % VGB;
-  for (int64_t G = int64_t(blockIdx.x) * VGB + lv; G < ngroups; G += int64_t(gridDim.x) * VGB) {
-    const int x0 = V * int(G % gpr);
-    const int64_t r = G / gpr;
-    const int y = int(r % b.ny), z = int(r / b.ny);
-    float acc[V][CG];
-#pragma unroll
-    for (int j = 0; j < V; ++j)
-#pragma unroll
-      for (int o = 0; o < CG; ++o) acc[j][o] = BIAS ? bias[gq * CG + o] : 0.0f;
-    for (int k = 0; k < 27; ++k) {
-      const int dx = SIGN * (k % 3 - 1), dy = SIGN * ((k / 3) % 3 - 1), dz = SIGN * (k / 9 - 1);
-      const int Y = y + dy, Z = z + dz;
-      if (Y < 0 || Y >= b.ny || Z < 0 || Z >= b.nz) continue;
-      const int64_t row = (int64_t(Z) * b.ny + Y) * b.nx;
-      bool ok[V];
-      int64_t ub[V];
-#pragma unroll
-      for (int j = 0; j < V; ++j) {
-        const int X = x0 + j + dx;
-        ok[j] = (x0 + j < b.nx) && X >= 0 && X < b.nx;
-        ub[j] = (row + (ok[j] ? X : 0)) * NI;
-      }
-      const uint16_t* wk = sW + k * NI * NO + gq * CG;
-      for (int i = 0; i < NI; i += 4) {
-        float xin[V][4];
-#pragma unroll
-        for (int j = 0; j < V; ++j) {
-          float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (ok[j]) {
-            a = *reinterpret_cast<const float4*>(in + ub[j] + i);
-            if (MASK_IN) {
-              const float4 mk = *reinterpret_cast<const float4*>(mask + ub[j] + i);
-              a.x = mk.x > 0.0f ? a.x : 0.0f;
-              a.y = mk.y > 0.0f ? a.y : 0.0f;
-              a.z = mk.z > 0.0f ? a.z : 0.0f;
-              a.w = mk.w > 0.0f ? a.w : 0.0f;
-            }
-          }
-          xin[j][0] = a.x;
-          xin[j][1] = a.y;
-          xin[j][2] = a.z;
-          xin[j][3] = a.w;
-        }
-#pragma unroll
-        for (int ii = 0; ii < 4; ++ii) {
-          float w[CG];
-          const uint16_t* wp = wk + (i + ii) * NO;
-          if (CG == 8) {
-            const uint4 q = *reinterpret_cast<const uint4*>(wp);
-            const uint32_t qq[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-              w[2 * h] = __uint_as_float(qq[h] << 16);
-              w[2 * h + 1] = __uint_as_float(qq[h] & 0xffff0000u);
-            }
-          } else {
-#pragma unroll
-            for (int o = 0; o < CG; ++o) w[o] = bf2f(wp[o]);
-          }
-#pragma unroll
-          for (int j = 0; j < V; ++j)
-#pragma unroll
-            for (int o = 0; o < CG; ++o) acc[j][o] += xin[j][ii] * w[o];
-        }
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < V; ++j) {
-      if (x0 + j >= b.nx) continue;
-      float* op = out + ((int64_t(z) * b.ny + y) * b.nx + x0 + j) * NO + gq * CG;
-#pragma unroll
-      for (int o = 0; o < CG; ++o) op[o] = RELU_OUT ? fmaxf(acc[j][o], 0.0f) : acc[j][o];
-    }
-  }
-}
-
-// Forward convolution as an implicit GEMM on the matrix cores
-// (v_mfma_f32_32x32x8_bf16, FP32 accumulation): a wavefront computes a tile
-// of 32 x-consecutive voxels of one row by 32 output channels; the reduction
-// runs over the 27 offsets times the input channels in chunks of 8.  The
-// A operand is the layer input (FP32 in memory) rounded to BF16 on load,
-// the B operand the layer's BF16 weights, staged in LDS as [k][o][i] so a
-// lane reads its four consecutive input channels with one 8-byte load.
-// Lane l holds A[l % 32][4 (l / 32) + t] and B[4 (l / 32) + t][l % 32]
-// (t = 0..3); accumulator r of lane l is C[8 (r / 4) + 4 (l / 32) + r % 4]
-// [l % 32].  Products of BF16 values are exact in FP32, so the result is
-// the FP32 sum of the exact products.
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-template <int NI, int NO, int RELU_OUT>
-__global__ __launch_bounds__(256) void k_conv_mfma(Box b, const float* __restrict__ in,
-                                                   const uint16_t* __restrict__ W, const float* __restrict__ bias,
-                                                   float* __restrict__ out) {
-  static_assert(NI % 8 == 0 && NO <= 32, "input channels in chunks of 8, at most 32 outputs");
-  constexpr int NIP = NI, NOP = 32;
-  __shared__ __align__(16) uint16_t sW[27 * NOP * NIP];
-  for (int e = threadIdx.x; e < 27 * NOP * NIP; e += 256) {
-    const int k = e / (NOP * NIP), o = (e / NIP) % NOP, i = e % NIP;
-    sW[e] = o < NO ? W[(k * NI + i) * NO + o] : uint16_t(0);
+// 3x3x3 convolution on the matrix cores with the input staged in LDS, for
+// the forward pass and for the data gradient:
+//   out[v][o] = (bias[o]) + sum_k sum_i Wl[k][i][o] m(in)[v + SIGN off(k)][i]
+// (forward: Wl = W, SIGN +1; data gradient: Wl[k][i][o] = W[k][o][i],
+// SIGN -1, m(in) = in where the mask (the layer's ReLU output) is > 0, else
+// 0).  A workgroup computes a tile of 32 x 4 x 2 output voxels: wavefront w
+// the two x-rows (y0 + w, z0) and (y0 + w, z0 + 1), each a 32-voxel x
+// 32-output MFMA tile (v_mfma_f32_32x32x16_bf16, reduction over offsets x
+// input channels in chunks of 16).  The tile's input with its one-voxel halo
+// (34 x 6 x 4 voxels) is converted to BF16 once into LDS, so each input
+// value is read from memory about 3.2 times instead of 27; the weights sit
+// in LDS for the whole kernel.  Voxel and weight rows are padded by eight
+// BF16 values so the 16-byte operand reads of a wavefront hit distinct
+// banks.  Lane l holds A[l % 32][8 (l / 32) + t] and B[8 (l / 32) + t]
+// [l % 32] (t = 0..7); accumulator r of lane l is
+// C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+template <int NI, int NO, int SIGN, int TRANS, int BIAS, int RELU_OUT, int MASK_IN>
+__global__ __launch_bounds__(256) void k_conv_tile(Box b, const float* __restrict__ in,
+                                                   const float* __restrict__ mask, const uint16_t* __restrict__ W,
+                                                   const float* __restrict__ bias, float* __restrict__ out) {
+  constexpr int NIP = NI < 16 ? 16 : NI;  // input channels padded to the MFMA chunk
+  static_assert(NI % 4 == 0 && NIP % 16 == 0 && NO <= 32, "channel counts");
+  constexpr int SP = NIP + 8, WP = NIP + 8;  // padded voxel and weight rows (BF16 values)
+  constexpr int SX = 34, SY = 6, SZ = 4, NG = NIP / 4;
+  __shared__ __align__(16) uint16_t sW[27 * 32 * WP];
+  __shared__ __align__(16) uint16_t sIn[SZ * SY * SX * SP];
+  for (int e = threadIdx.x; e < 27 * 32 * NIP; e += 256) {
+    const int k = e / (32 * NIP), o = (e / NIP) % 32, i = e % NIP;
+    uint16_t wv = 0;
+    if (o < NO && i < NI) wv = TRANS ? W[(k * NO + o) * NI + i] : W[(k * NI + i) * NO + o];
+    sW[(k * 32 + o) * WP + i] = wv;
   }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 31, lk = lane >> 5;  // A row / B column, K half
-  const int xtiles = (b.nx + 31) / 32;
-  const int64_t ntiles = int64_t(xtiles) * b.ny * b.nz;
-  for (int64_t T = int64_t(blockIdx.x) * 4 + wave; T < ntiles; T += int64_t(gridDim.x) * 4) {
-    const int x0 = 32 * int(T % xtiles);
-    const int64_t row = T / xtiles;
-    const int y = int(row % b.ny), z = int(row / b.ny);
-    f32x16 acc;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-    for (int k = 0; k < 27; ++k) {
-      const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
-      const int Y = y + dy, Z = z + dz;
-      if (Y < 0 || Y >= b.ny || Z < 0 || Z >= b.nz) continue;  // uniform over the wavefront
-      const int X = x0 + li + dx;
-      const bool ok = x0 + li < b.nx && X >= 0 && X < b.nx;
-      const float* src = in + ((int64_t(Z) * b.ny + Y) * b.nx + (ok ? X : 0)) * NI + 4 * lk;
-      const uint16_t* wk = sW + (k * NOP + li) * NIP + 4 * lk;
-#pragma unroll
-      for (int ic = 0; ic < NI / 8; ++ic) {
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (ok) v = *reinterpret_cast<const float4*>(src + 8 * ic);
-        bf16x4 a;
-        a[0] = short(f2bf(v.x));
-        a[1] = short(f2bf(v.y));
-        a[2] = short(f2bf(v.z));
-        a[3] = short(f2bf(v.w));
-        const bf16x4 bw = *reinterpret_cast<const bf16x4*>(wk + 8 * ic);
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bw, acc, 0, 0, 0);
-      }
-    }
-    const int o = li;
-    if (o < NO) {
-      const float bo = bias[o];
-      float* dst = out + ((int64_t(z) * b.ny + y) * b.nx + x0) * NO + o;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int i = 8 * (r / 4) + 4 * lk + (r % 4);
-        if (x0 + i < b.nx) {
-          const float val = acc[r] + bo;
-          dst[int64_t(i) * NO] = RELU_OUT ? fmaxf(val, 0.0f) : val;
-        }
-      }
-    }
-  }
-}
-
-// Weight and bias gradient, first stage: each block sums over its voxel range
-//   dW[k][ci][co] += X[v + off(k)][ci] dYm[v][co],  db[co] += dYm[v][co]
-// into its own partial row (27 CIN COUT + COUT values).  Per tile of TV
-// voxels, dYm is staged in LDS once and the shifted inputs once per offset;
-// a thread owns an RI x RO block of the (ci, co) plane for all 27 offsets.
-template <int CIN, int COUT, int RELU>
-__global__ __launch_bounds__(kB) void k_conv_bwd_w(Box b, const float* __restrict__ X, const float* __restrict__ dY,
-                                                   const float* __restrict__ Yact, int64_t vox_per_block,
-                                                   float* __restrict__ partial) {
-  constexpr int TV = 64, NE = CIN * COUT;
-  constexpr int RI = NE >= 4 * kB ? 2 : 1, RO = RI;
-  constexpr int TI = CIN / RI, TO = COUT / RO;
-  static_assert(TI * TO <= kB && (TV * CIN) % kB == 0, "tiling");
-  constexpr int XPT = TV * CIN / kB;
-  __shared__ __align__(16) float sD[TV][COUT];
-  __shared__ __align__(16) float sX[TV][CIN];
-  const int64_t nvox = int64_t(b.nx) * b.ny * b.nz;
-  const int64_t v0 = int64_t(blockIdx.x) * vox_per_block;
-  const int64_t v1 = min(v0 + vox_per_block, nvox);
-  const int tid = threadIdx.x;
-  const bool owner = tid < TI * TO;
-  const int ci0 = RI * (tid / TO), co0 = RO * (tid % TO);
-  float acc[27][RI][RO];
-#pragma unroll
-  for (int k = 0; k < 27; ++k)
-#pragma unroll
-    for (int a = 0; a < RI; ++a)
-#pragma unroll
-      for (int c = 0; c < RO; ++c) acc[k][a][c] = 0.0f;
-  float accb = 0.0f;
-  for (int64_t vt = v0; vt < v1; vt += TV) {
-    // coordinates of this thread's gather elements
-    int gx[XPT], gy[XPT], gz[XPT];
-#pragma unroll
-    for (int j = 0; j < XPT; ++j) {
-      const int64_t v = vt + (tid + kB * j) / CIN;
-      if (v < v1) {
-        gx[j] = int(v % b.nx);
-        gy[j] = int((v / b.nx) % b.ny);
-        gz[j] = int(v / (int64_t(b.nx) * b.ny));
-      } else {
-        gx[j] = -4;  // outside for every offset
-        gy[j] = 0;
-        gz[j] = 0;
-      }
-    }
-    __syncthreads();
-    for (int e = tid; e < TV * COUT; e += kB) {
-      const int64_t v = vt + e / COUT;
-      float d = 0.0f;
-      if (v < v1) {
-        d = dY[v * COUT + e % COUT];
-        if (RELU && !(Yact[v * COUT + e % COUT] > 0.0f)) d = 0.0f;
-      }
-      sD[e / COUT][e % COUT] = d;
-    }
-    __syncthreads();
-    if (tid < COUT)
-      for (int t = 0; t < TV; ++t) accb += sD[t][tid];
-#pragma unroll
-    for (int k = 0; k < 27; ++k) {
-      const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
-      if (k > 0) __syncthreads();
-#pragma unroll
-      for (int j = 0; j < XPT; ++j) {
-        const int e = tid + kB * j;
-        const int xx = gx[j] + dx, yy = gy[j] + dy, zz = gz[j] + dz;
-        float xv = 0.0f;
-        if (xx >= 0 && xx < b.nx && yy >= 0 && yy < b.ny && zz >= 0 && zz < b.nz)
-          xv = X[((int64_t(zz) * b.ny + yy) * b.nx + xx) * CIN + e % CIN];
-        sX[e / CIN][e % CIN] = xv;
-      }
-      __syncthreads();
-      if (owner) {
-        for (int t = 0; t < TV; ++t) {
-          float xa[RI], da[RO];
-#pragma unroll
-          for (int a = 0; a < RI; ++a) xa[a] = sX[t][ci0 + a];
-#pragma unroll
-          for (int c = 0; c < RO; ++c) da[c] = sD[t][co0 + c];
-#pragma unroll
-          for (int a = 0; a < RI; ++a)
-#pragma unroll
-            for (int c = 0; c < RO; ++c) acc[k][a][c] += xa[a] * da[c];
-        }
-      }
-    }
-  }
-  float* outp = partial + int64_t(blockIdx.x) * (27 * NE + COUT);
-  if (owner) {
-#pragma unroll
-    for (int k = 0; k < 27; ++k)
-#pragma unroll
-      for (int a = 0; a < RI; ++a)
-#pragma unroll
-        for (int c = 0; c < RO; ++c) outp[k * NE + (ci0 + a) * COUT + co0 + c] = acc[k][a][c];
-  }
-  if (tid < COUT) outp[27 * NE + tid] = accb;
-}
-
-// Weight gradient on the matrix cores: for each offset k,
-//   dW[k][ci][co] = sum_v X[v + off(k)][ci] dYm[v][co]
-// is a 32 x 32 GEMM whose reduction runs over voxels, 8 per MFMA: lane l
-// feeds A[ci = l % 32][voxel 4 (l / 32) + t] and B[voxel 4 (l / 32) + t]
-// [co = l % 32], both rounded to BF16; the four wavefronts of a block split
-// the 27 offsets (7, 7, 7, 6) and share the voxel chunks; partial rows per
-// block as in k_conv_bwd_w (bias partials summed in FP32 by wavefront 0).
-template <int CIN, int COUT, int RELU>
-__global__ __launch_bounds__(256) void k_conv_bwd_w_mfma(Box b, const float* __restrict__ X,
-                                                         const float* __restrict__ dY,
-                                                         const float* __restrict__ Yact, int64_t vox_per_block,
-                                                         float* __restrict__ partial) {
-  static_assert(CIN <= 32 && COUT <= 32, "one 32 x 32 tile per offset");
-  constexpr int NE = CIN * COUT, KW = 7;
-  const int64_t nvox = int64_t(b.nx) * b.ny * b.nz;
-  const int64_t v0 = int64_t(blockIdx.x) * vox_per_block;
-  const int64_t v1 = min(v0 + vox_per_block, nvox);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 31, lk = lane >> 5;
-  f32x16 acc[KW];
+  const int xt = (b.nx + 31) / 32, yt = (b.ny + 3) / 4, zt = (b.nz + 1) / 2;
+  const int64_t ntiles = int64_t(xt) * yt * zt;
+  // the tile's input (with halo) is loaded into registers one tile ahead, so
+  // the loads of tile T + gridDim.x are in flight while tile T is computed
+  constexpr int NST = SZ * SY * SX * NG, NIT = (NST + 255) / 256;
+  float4 buf[NIT];
+  auto load_tile = [&](int64_t T) {
+    const int x0 = 32 * int(T % xt);
+    const int y0 = 4 * int((T / xt) % yt);
+    const int z0 = 2 * int(T / (int64_t(xt) * yt));
 #pragma unroll
-  for (int j = 0; j < KW; ++j)
+    for (int j = 0; j < NIT; ++j) {
+      const int e = int(threadIdx.x) + 256 * j;
+      const int g = e % NG, vs = e / NG;
+      const int sx = vs % SX, sy = (vs / SX) % SY, sz = vs / (SX * SY);
+      const int X = x0 - 1 + sx, Y = y0 - 1 + sy, Z = z0 - 1 + sz;
+      float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e < NST && 4 * g < NI && X >= 0 && X < b.nx && Y >= 0 && Y < b.ny && Z >= 0 && Z < b.nz) {
+        const int64_t off = ((int64_t(Z) * b.ny + Y) * b.nx + X) * NI + 4 * g;
+        a = *reinterpret_cast<const float4*>(in + off);
+        if (MASK_IN) {
+          const float4 mk = *reinterpret_cast<const float4*>(mask + off);
+          a.x = mk.x > 0.0f ? a.x : 0.0f;
+          a.y = mk.y > 0.0f ? a.y : 0.0f;
+          a.z = mk.z > 0.0f ? a.z : 0.0f;
+          a.w = mk.w > 0.0f ? a.w : 0.0f;
+        }
+      }
+      buf[j] = a;
+    }
+  };
+  if (int64_t(blockIdx.x) < ntiles) load_tile(blockIdx.x);
+  for (int64_t T = blockIdx.x; T < ntiles; T += gridDim.x) {
+    const int x0 = 32 * int(T % xt);
+    const int y0 = 4 * int((T / xt) % yt);
+    const int z0 = 2 * int(T / (int64_t(xt) * yt));
+    __syncthreads();  // the previous tile's reads of sIn are done (and sW is staged)
+#pragma unroll
+    for (int j = 0; j < NIT; ++j) {
+      const int e = int(threadIdx.x) + 256 * j;
+      if (e < NST) {
+        const int g = e % NG, vs = e / NG;
+        bf16x4 q;
+        q[0] = short(f2bf(buf[j].x));
+        q[1] = short(f2bf(buf[j].y));
+        q[2] = short(f2bf(buf[j].z));
+        q[3] = short(f2bf(buf[j].w));
+        *reinterpret_cast<bf16x4*>(sIn + vs * SP + 4 * g) = q;
+      }
+    }
+    __syncthreads();
+    if (T + gridDim.x < ntiles) load_tile(T + gridDim.x);
+    f32x16 acc0, acc1;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      acc0[r] = 0.0f;
+      acc1[r] = 0.0f;
+    }
+    for (int k = 0; k < 27; ++k) {
+      const int dx = SIGN * (k % 3 - 1), dy = SIGN * ((k / 3) % 3 - 1), dz = SIGN * (k / 9 - 1);
+      const uint16_t* wk = sW + (k * 32 + li) * WP + 8 * lk;
+      const uint16_t* a0 = sIn + (((1 + dz) * SY + (wave + 1 + dy)) * SX + (li + 1 + dx)) * SP + 8 * lk;
+      const uint16_t* a1 = a0 + SY * SX * SP;
+#pragma unroll
+      for (int ic = 0; ic < NIP / 16; ++ic) {
+        const bf16x8 bw = *reinterpret_cast<const bf16x8*>(wk + 16 * ic);
+        const bf16x8 v0 = *reinterpret_cast<const bf16x8*>(a0 + 16 * ic);
+        const bf16x8 v1 = *reinterpret_cast<const bf16x8*>(a1 + 16 * ic);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(v0, bw, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(v1, bw, acc1, 0, 0, 0);
+      }
+    }
+    const int o = li, y = y0 + wave;
+    if (o < NO && y < b.ny) {
+      const float bo = BIAS ? bias[o] : 0.0f;
+#pragma unroll
+      for (int zr = 0; zr < 2; ++zr) {
+        const int z = z0 + zr;
+        if (z >= b.nz) continue;
+        float* dst = out + ((int64_t(z) * b.ny + y) * b.nx + x0) * NO + o;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int i = 8 * (r / 4) + 4 * lk + (r % 4);
+          if (x0 + i < b.nx) {
+            const float val = (zr ? acc1[r] : acc0[r]) + bo;
+            dst[int64_t(i) * NO] = RELU_OUT ? fmaxf(val, 0.0f) : val;
+          }
+        }
+      }
+    }
+  }
+}
+
+// Weight and bias gradient on the matrix cores with LDS tiles: for each
+// offset k,
+//   dW[k][ci][co] = sum_v X[v + off(k)][ci] dYm[v][co],   db[co] = sum_v dYm[v][co]
+// (dYm = dY masked by the layer's ReLU) is a 32 x 32 GEMM reduced over
+// voxels, 16 per v_mfma_f32_32x32x16_bf16.  A workgroup takes tiles of
+// 32 x 4 x 2 voxels (as k_conv_tile); per tile it stores in LDS, as BF16,
+// the tile's dYm transposed ([row][co][x]) and the input with its halo
+// transposed ([z][y][ci][x], x 16-byte aligned), so a lane's eight
+// voxel-consecutive operand values are one aligned 16-byte read.  Nine
+// wavefronts, one per (dy, dz); each keeps the three offsets dx = -1, 0, 1
+// and builds their operands from one aligned read and its two neighbours
+// (byte alignment of register pairs).  Every workgroup writes one partial
+// row (27 CIN COUT + COUT values); the bias sums are FP32 over the unrounded
+// dYm, per thread and then across threads in a fixed order.
+template <int CIN, int COUT, int RELU>
+__global__ __launch_bounds__(576) void k_conv_bwd_w_tile(Box b, const float* __restrict__ X,
+                                                         const float* __restrict__ dY,
+                                                         const float* __restrict__ Yact,
+                                                         float* __restrict__ partial) {
+  static_assert(CIN % 4 == 0 && COUT % 4 == 0 && CIN <= 32 && COUT <= 32, "channel counts");
+  constexpr int NT = 576, NE = CIN * COUT;
+  constexpr int SX = 34, SY = 6, SZ = 4, XW = 48, DW = 40;
+  constexpr int NGI = CIN / 4, NGO = COUT / 4;
+  static_assert(NT % NGO == 0, "fixed channel group per thread");
+  __shared__ __align__(16) uint16_t sX[SZ * SY * 32 * XW];  // [z][y][ci][x + 7]
+  __shared__ __align__(16) uint16_t sD[8 * 32 * DW];        // [row][co][x]
+  __shared__ float sB[NT][4];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, lk = lane >> 5;
+  // channel rows beyond CIN / COUT stay zero
+  for (int e = tid; e < SZ * SY * 32 * XW; e += NT) sX[e] = 0;
+  for (int e = tid; e < 8 * 32 * DW; e += NT) sD[e] = 0;
+  f32x16 acc[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[j][r] = 0.0f;
-  float accb = 0.0f;
-  for (int64_t vt = v0; vt < v1; vt += 8) {
-    int cx[4], cy[4], cz[4];
-    bool vok[4];
-    bf16x4 bb;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int64_t v = vt + 4 * lk + t;
-      vok[t] = v < v1;
-      const int64_t vv = vok[t] ? v : v0;
-      // 32-bit division (boxes hold fewer than 2^31 voxels)
-      const uint32_t u = uint32_t(vv), nx = uint32_t(b.nx), nxy = uint32_t(b.nx) * uint32_t(b.ny);
-      cz[t] = int(u / nxy);
-      const uint32_t rxy = u - uint32_t(cz[t]) * nxy;
-      cy[t] = int(rxy / nx);
-      cx[t] = int(rxy - uint32_t(cy[t]) * nx);
-      float d = 0.0f;
-      if (vok[t] && li < COUT) {
-        d = dY[vv * COUT + li];
-        if (RELU && !(Yact[vv * COUT + li] > 0.0f)) d = 0.0f;
+  float bacc[4] = {0.f, 0.f, 0.f, 0.f};
+  const int dyw = wave % 3 - 1, dzw = wave / 3 - 1;
+  const int xt = (b.nx + 31) / 32, yt = (b.ny + 3) / 4, zt = (b.nz + 1) / 2;
+  const int64_t ntiles = int64_t(xt) * yt * zt;
+  for (int64_t T = blockIdx.x; T < ntiles; T += gridDim.x) {
+    const int x0 = 32 * int(T % xt);
+    const int y0 = 4 * int((T / xt) % yt);
+    const int z0 = 2 * int(T / (int64_t(xt) * yt));
+    __syncthreads();  // the previous tile's operand reads are done
+    // output gradient of the tile's 256 voxels, masked, transposed
+    for (int e = tid; e < 256 * NGO; e += NT) {
+      const int g = e % NGO, vt = e / NGO;
+      const int xx = vt & 31, r = vt >> 5;  // r = zr * 4 + yw
+      const int x = x0 + xx, y = y0 + (r & 3), z = z0 + (r >> 2);
+      float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (x < b.nx && y < b.ny && z < b.nz) {
+        const int64_t off = ((int64_t(z) * b.ny + y) * b.nx + x) * COUT + 4 * g;
+        d = *reinterpret_cast<const float4*>(dY + off);
+        if (RELU) {
+          const float4 a = *reinterpret_cast<const float4*>(Yact + off);
+          d.x = a.x > 0.0f ? d.x : 0.0f;
+          d.y = a.y > 0.0f ? d.y : 0.0f;
+          d.z = a.z > 0.0f ? d.z : 0.0f;
+          d.w = a.w > 0.0f ? d.w : 0.0f;
+        }
       }
-      accb += d;
-      bb[t] = short(f2bf(d));
+      bacc[0] += d.x;
+      bacc[1] += d.y;
+      bacc[2] += d.z;
+      bacc[3] += d.w;
+      uint16_t* dst = sD + (r * 32 + 4 * g) * DW + xx;
+      dst[0] = f2bf(d.x);
+      dst[DW] = f2bf(d.y);
+      dst[2 * DW] = f2bf(d.z);
+      dst[3 * DW] = f2bf(d.w);
     }
+    // the layer input with its halo, transposed
+    for (int e = tid; e < SZ * SY * SX * NGI; e += NT) {
+      const int g = e % NGI, vs = e / NGI;
+      const int sx = vs % SX, sy = (vs / SX) % SY, sz = vs / (SX * SY);
+      const int x = x0 - 1 + sx, y = y0 - 1 + sy, z = z0 - 1 + sz;
+      float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (x >= 0 && x < b.nx && y >= 0 && y < b.ny && z >= 0 && z < b.nz)
+        a = *reinterpret_cast<const float4*>(X + ((int64_t(z) * b.ny + y) * b.nx + x) * CIN + 4 * g);
+      uint16_t* dst = sX + ((sz * SY + sy) * 32 + 4 * g) * XW + sx + 7;
+      dst[0] = f2bf(a.x);
+      dst[XW] = f2bf(a.y);
+      dst[2 * XW] = f2bf(a.z);
+      dst[3 * XW] = f2bf(a.w);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int r = 0; r < 8; ++r) {
+      const int yw = r & 3, zr = r >> 2;
+      const uint16_t* xrow = sX + (((zr + 1 + dzw) * SY + (yw + 1 + dyw)) * 32 + li) * XW;
+      const uint16_t* drow = sD + (r * 32 + li) * DW;
 #pragma unroll
-    for (int j = 0; j < KW; ++j) {
-      const int k = wave + 4 * j;
-      if (k >= 27) break;
-      const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
-      bf16x4 a;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int xx = cx[t] + dx, yy = cy[t] + dy, zz = cz[t] + dz;
-        float xv = 0.0f;
-        if (vok[t] && li < CIN && xx >= 0 && xx < b.nx && yy >= 0 && yy < b.ny && zz >= 0 && zz < b.nz)
-          xv = X[((int64_t(zz) * b.ny + yy) * b.nx + xx) * CIN + li];
-        a[t] = short(f2bf(xv));
+      for (int c = 0; c < 2; ++c) {
+        const int xp = 8 + 16 * c + 8 * lk;  // first of the lane's eight voxels (dx = 0)
+        const bf16x8 bd = *reinterpret_cast<const bf16x8*>(drow + 16 * c + 8 * lk);
+        const uint4 m = *reinterpret_cast<const uint4*>(xrow + xp);
+        const uint32_t lft = *reinterpret_cast<const uint32_t*>(xrow + xp - 2);
+        const uint32_t rgt = *reinterpret_cast<const uint32_t*>(xrow + xp + 8);
+        // dx = -1: elements xp - 1 .. xp + 6;  dx = +1: xp + 1 .. xp + 8
+        const uint32_t n0 = __builtin_amdgcn_alignbyte(m.x, lft, 2);
+        const uint32_t n1 = __builtin_amdgcn_alignbyte(m.y, m.x, 2);
+        const uint32_t n2 = __builtin_amdgcn_alignbyte(m.z, m.y, 2);
+        const uint32_t n3 = __builtin_amdgcn_alignbyte(m.w, m.z, 2);
+        const uint32_t p3 = __builtin_amdgcn_alignbyte(rgt, m.w, 2);
+        const uint4 am = make_uint4(n0, n1, n2, n3);
+        const uint4 ap = make_uint4(n1, n2, n3, p3);
+        acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf16x8*>(&am), bd, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf16x8*>(&m), bd, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf16x8*>(&ap), bd, acc[2], 0, 0, 0);
       }
-      acc[j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bb, acc[j], 0, 0, 0);
     }
   }
   float* outp = partial + int64_t(blockIdx.x) * (27 * NE + COUT);
 #pragma unroll
-  for (int j = 0; j < KW; ++j) {
-    const int k = wave + 4 * j;
-    if (k >= 27) break;
+  for (int j = 0; j < 3; ++j) {
+    const int k = j + 3 * (dyw + 1) + 9 * (dzw + 1);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int ci = 8 * (r / 4) + 4 * lk + (r % 4), co = li;
       if (ci < CIN && co < COUT) outp[k * NE + ci * COUT + co] = acc[j][r];
     }
   }
-  // bias partial: lanes l and l + 32 hold the two voxel halves of channel l
-  const float other = __shfl_xor(accb, 32);
-  if (wave == 0 && lk == 0 && li < COUT) outp[27 * NE + li] = accb + other;
+  // bias: thread t holds channel group t % NGO; sum over the threads of a
+  // group in thread order
+#pragma unroll
+  for (int q = 0; q < 4; ++q) sB[tid][q] = bacc[q];
+  __syncthreads();
+  if (tid < COUT) {
+    const int g = tid / 4, q = tid % 4;
+    float sum = 0.0f;
+    for (int t = g; t < NT; t += NGO) sum += sB[t][q];
+    outp[27 * NE + tid] = sum;
+  }
 }
 
 // second stage: fixed-order sum of the partial rows
@@ -525,11 +422,11 @@ int gridn(int64_t work) {
   return int(b);
 }
 
-// convolution grids: persistent blocks (each stages the layer's weights in
-// LDS once), about four per compute unit
-int convgrid(int64_t work) {
-  const int g = gridn(work);
-  return g < 1024 ? g : 1024;
+// k_conv_tile grid: persistent workgroups (each stages the layer's weights
+// once), at most 512
+int conv_tile_grid(const Box& b) {
+  const int64_t tiles = int64_t((b.nx + 31) / 32) * ((b.ny + 3) / 4) * ((b.nz + 1) / 2);
+  return int(std::max<int64_t>(1, std::min<int64_t>(tiles, 512)));
 }
 
 }  // namespace
@@ -581,14 +478,13 @@ hipError_t nn_forward(const uint16_t* w, const float* bias, float* const layer[7
     float* Y = layer[l + 1];
     const uint16_t* W = w + w_off(l);
     const float* bb = bias + b_off(l);
-    const int64_t tiles = int64_t((nx + 31) / 32) * ny * nz;
-    const dim3 grid(unsigned(std::min<int64_t>((tiles + 3) / 4, 2048)));
+    const dim3 grid(conv_tile_grid(b));
     if (l == 0)
-      hipLaunchKernelGGL((k_conv_mfma<8, 32, 1>), grid, dim3(256), 0, st, b, X, W, bb, Y);
+      hipLaunchKernelGGL((k_conv_tile<8, 32, 1, 0, 1, 1, 0>), grid, dim3(256), 0, st, b, X, nullptr, W, bb, Y);
     else if (l < 5)
-      hipLaunchKernelGGL((k_conv_mfma<32, 32, 1>), grid, dim3(256), 0, st, b, X, W, bb, Y);
+      hipLaunchKernelGGL((k_conv_tile<32, 32, 1, 0, 1, 1, 0>), grid, dim3(256), 0, st, b, X, nullptr, W, bb, Y);
     else
-      hipLaunchKernelGGL((k_conv_mfma<32, 4, 0>), grid, dim3(256), 0, st, b, X, W, bb, Y);
+      hipLaunchKernelGGL((k_conv_tile<32, 4, 1, 0, 1, 0, 0>), grid, dim3(256), 0, st, b, X, nullptr, W, bb, Y);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -613,9 +509,8 @@ hipError_t nn_backward(const uint16_t* w, const float* act, const float* dout, f
   float* gA = work;
   float* gB = work + nvox * 32;
   float* part = work + 2 * nvox * 32;
-  int nblk = 512;
-  if (nvox < 512 * 64) nblk = int((nvox + 63) / 64);
-  const int64_t vpb = (nvox + nblk - 1) / nblk;
+  // one partial row per weight-gradient workgroup (at most 512)
+  const int nblk = conv_tile_grid(b);
   const float* dY = dout;
   for (int l = 5; l >= 0; --l) {
     const int cin = kCh[l], cout = kCh[l + 1];
@@ -625,24 +520,23 @@ hipError_t nn_backward(const uint16_t* w, const float* act, const float* dout, f
     const int64_t len = int64_t(27) * cin * cout + cout;
     // weights: layer 5 has no ReLU on its output
     if (l == 5)
-      hipLaunchKernelGGL((k_conv_bwd_w_mfma<32, 4, 0>), dim3(nblk), dim3(256), 0, st, b, X, dY, Yact, vpb, part);
+      hipLaunchKernelGGL((k_conv_bwd_w_tile<32, 4, 0>), dim3(nblk), dim3(576), 0, st, b, X, dY, Yact, part);
     else if (l > 0)
-      hipLaunchKernelGGL((k_conv_bwd_w_mfma<32, 32, 1>), dim3(nblk), dim3(256), 0, st, b, X, dY, Yact, vpb, part);
+      hipLaunchKernelGGL((k_conv_bwd_w_tile<32, 32, 1>), dim3(nblk), dim3(576), 0, st, b, X, dY, Yact, part);
     else
-      hipLaunchKernelGGL((k_conv_bwd_w_mfma<8, 32, 1>), dim3(nblk), dim3(256), 0, st, b, X, dY, Yact, vpb, part);
+      hipLaunchKernelGGL((k_conv_bwd_w_tile<8, 32, 1>), dim3(nblk), dim3(576), 0, st, b, X, dY, Yact, part);
     hipLaunchKernelGGL(k_sum_partials, dim3(gridn(len)), dim3(kB), 0, st, part, nblk, len, dw + w_off(l),
                        db + b_off(l), int64_t(27) * cin * cout);
     if (l == 0) break;
     float* dX = (l % 2) ? gA : gB;
     // data gradient: inputs dY (cout channels, masked by the layer's ReLU),
     // outputs cin channels, transposed weights, mirrored offsets
-    const int64_t groups = int64_t((nx + 3) / 4) * ny * nz;
     if (l == 5)
-      hipLaunchKernelGGL((k_conv<4, 32, -1, 1, 0, 0, 0>), dim3(convgrid(groups * 4)), dim3(kB), 0, st, b, dY,
+      hipLaunchKernelGGL((k_conv_tile<4, 32, -1, 1, 0, 0, 0>), dim3(conv_tile_grid(b)), dim3(256), 0, st, b, dY,
                          nullptr, W, nullptr, dX);
     else
-      hipLaunchKernelGGL((k_conv<32, 32, -1, 1, 0, 0, 1>), dim3(convgrid(groups * 4)), dim3(kB), 0, st, b, dY, Yact,
-                         W, nullptr, dX);
+      hipLaunchKernelGGL((k_conv_tile<32, 32, -1, 1, 0, 0, 1>), dim3(conv_tile_grid(b)), dim3(256), 0, st, b, dY,
+                         Yact, W, nullptr, dX);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dY = dX;

@@ -11,8 +11,8 @@ the other way on the two sides and the difference (one BF16 step, 2^-8
 relative) feeds more such flips downstream, so whole-network outputs agree
 only to BF16 level: 5e-3 in RMS and 3e-2 at the worst voxel.  The backward
 pass is pinned layer by layer the same way: the oracle differentiates the
-GPU's own activations (weight gradient from BF16 layer inputs and output
-gradients as on the matrix cores, data and bias gradients in full
+GPU's own activations (weight and data gradients from BF16 layer inputs and
+output gradients as on the matrix cores, bias gradients in full
 precision).  Bias gradients agree to 1e-4 of the largest entry of each
 layer; weight gradients to 2e-3, since an output gradient computed in FP32
 on the GPU and in FP64 by the oracle can still round to neighbouring BF16
