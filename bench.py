@@ -109,7 +109,7 @@ def learned_leg(ctx, wl, P, W, torch, train_seconds, target):
     t_harvest = time.perf_counter() - t0
     net = learned.ProposalNet(ctx, seed=0)
     learned.fit_scales(net, samples)
-    tr = learned.Trainer(net, L, lr=1e-3)
+    tr = learned.Trainer(net, L, lr=3e-4)
     tr.add(samples)
     del samples
     loss0 = tr.mean_loss()
@@ -119,6 +119,35 @@ def learned_leg(ctx, wl, P, W, torch, train_seconds, target):
             "loss_initial": loss0, "loss_final": loss1}
     tr.data = []
     return net, info
+
+
+PEAK_BF16 = 2500.0    # TFLOP/s, dense BF16 matrix cores
+
+
+def cnn_leg(ctx, L, torch, reps):
+    """Forward and backward pass of the proposal network over the finest node
+    grid (one whole-grid training step without Adam), timed with HIP events;
+    flops count the multiply-adds of the convolutions (forward 120,960 per
+    voxel; backward: weight gradient of every layer plus data gradient of
+    layers 2-6)."""
+    from paper_2007_12908_amd import learned
+    n = ctx.level_cells(L) + 1
+    box = (n, n, n)
+    nvox = n ** 3
+    net = learned.ProposalNet(ctx, seed=0)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    act = torch.zeros(ctx.nn_size(2, *box), dtype=torch.float32, device="cuda")
+    act[: 8 * nvox].normal_(generator=gen)
+    work = torch.empty(ctx.nn_size(3, *box), dtype=torch.float32, device="cuda")
+    dout = torch.empty(4 * nvox, dtype=torch.float32, device="cuda").normal_(generator=gen)
+    grad = torch.empty(learned.NW + learned.NB, dtype=torch.float32, device="cuda")
+    t_f = time_calls(lambda: ctx.nn_forward(net.w, net.bias, act, box), reps, torch)
+    t_b = time_calls(lambda: ctx.nn_backward(net.w, act, dout, grad, work, box), reps, torch)
+    mac_f = 120960 * nvox
+    mac_b = (120960 + 120960 - 27 * 8 * 32) * nvox
+    tf_f, tf_b = 2 * mac_f / t_f / 1e9, 2 * mac_b / t_b / 1e9
+    return {"box": n, "forward_ms": t_f, "backward_ms": t_b, "forward_TFLOP/s": tf_f, "backward_TFLOP/s": tf_b,
+            "forward_frac_bf16": tf_f / PEAK_BF16, "backward_frac_bf16": tf_b / PEAK_BF16}
 
 
 def main():
@@ -134,6 +163,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernels-only", action="store_true",
                     help="time only the kernel triple (for profiler runs)")
+    ap.add_argument("--cnn-only", action="store_true",
+                    help="time only the network's forward and backward passes (for profiler runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -171,6 +202,10 @@ def main():
     g = torch.empty_like(x)
     hv = torch.empty_like(x)
     hv32 = torch.empty_like(x32)
+
+    if args.cnn_only:
+        log(json.dumps({"cnn": cnn_leg(ctx, L, torch, max(args.steps, 5))}))
+        return
 
     def step():
         ctx.energy(L, x, p, out=E)
@@ -223,6 +258,8 @@ def main():
                                      "hessvec": 104 * n_nodes / t_h / 1e6,
                                      "hessvec_fp32": 52 * n_nodes / t_h32 / 1e6}}
 
+    cnn = None if args.no_learned else cnn_leg(ctx, L, torch, 10)
+
     rmtr = None
     if not args.no_loadstep:
         import ctypes
@@ -272,6 +309,7 @@ def main():
                    "step": "energy + gradient + Hv (FP64) on the finest level"},
         "kernels": per,
         "roofline": roof,
+        "cnn": cnn,
         "rmtr": rmtr,
         "cpu_baseline": cpu,
     }

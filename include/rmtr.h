@@ -234,14 +234,15 @@ rmtr_status rmtr_chi(rmtr_ctx* ctx, int32_t level, const double* x, const double
    max_vcycles.  With params->use_learned, each V-cycle first tries the
    learned proposal on the finest level: it is projected onto the step box,
    scaled by the model minimiser beta in (0, 1] along it (it must be a
-   descent direction of the model, with beta >= 1/2), required to predict
-   at least the decrease of the last accepted finest-level smoother step
-   (if any), judged by the FP64 ratio of
-   eq. (rho_tr) against the lagged model, and
-   taken in place of the first PGS pre-smoothing step if rho > eta1 and its
-   predicted decrease is at least that of a Cauchy step (d = P(-t g),
+   descent direction of the model, with beta >= 1/2), judged by the FP64
+   ratio of eq. (rho_tr) against the lagged model (rho > eta1), required to
+   predict at least the decrease of a Cauchy step (d = P(-t g),
    t = g^T g / g^T H g, projected onto the box, scaled by the exact model
-   minimiser alpha in [0, 1]); otherwise the PGS step runs.  A rejected proposal leaves delta unchanged.  p: fine nodal pressure; c_lower: c^{t-1} per fine node;
+   minimiser alpha in [0, 1]), and taken in place of the first PGS
+   pre-smoothing step only if it lowers the energy at least as much as
+   that PGS step from the same state would (or the PGS step would fail its
+   ratio test); otherwise the PGS step runs.  A rejected proposal leaves x
+   and delta unchanged.  p: fine nodal pressure; c_lower: c^{t-1} per fine node;
    x_inout must be feasible.  chi_history (host, may be NULL) receives chi
    after each V-cycle (max_vcycles entries).  Returns RMTR_OK,
    RMTR_NOT_CONVERGED (x still feasible) or an error.  Synchronises. */

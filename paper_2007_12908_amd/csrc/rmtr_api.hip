@@ -201,7 +201,6 @@ struct Run {
   double f_ref = 1.0;
   int accepted = 0, rejected = 0;
   int nn_proposed = 0, nn_accepted = 0, nn_misses = 0;
-  double fine_pred = -1.0;  // predicted decrease of the last accepted finest-level smoother step
   rmtr_status status = RMTR_OK;
   bool trace = false;  // per-step log on stderr (RMTR_VERBOSE=2)
 
@@ -371,7 +370,6 @@ struct Run {
               acc ? "acc" : "rej");
     if (acc) {
       ++accepted;
-      if (l == c->L) fine_pred = pred;
       HIPCHK(c, launch_axpy(v.n, 1.0, v.s, x, st));
     } else {
       ++rejected;
@@ -382,14 +380,15 @@ struct Run {
   // learned proposal on the finest level, judged like a TR step on the
   // lagged model.  The box-projected proposal s is a direction: the step is
   // beta s with beta in (0, 1] the model minimiser along it (s must be a
-  // descent direction).  It is taken if beta >= 1/2 (the proposal's length is
-  // within a factor two of the best along it), it predicts at least the
-  // decrease of the last accepted finest-level smoother step when there is
-  // one (so it replaces the smoother only where it does as well), the ratio
-  // test accepts it and
-  // its predicted decrease is at least that of the Cauchy step (d = P(-t g) with
-  // t = g^T g / g^T H g, projected onto the step box, then the exact model
-  // minimiser alpha d, alpha in [0, 1]).  A rejection leaves delta unchanged.
+  // descent direction).  It is a candidate if beta >= 1/2 (the proposal's
+  // length is within a factor two of the best along it), the ratio test
+  // accepts it and its predicted decrease is at least that of the Cauchy
+  // step (d = P(-t g) with t = g^T g / g^T H g, projected onto the step box,
+  // then the exact model minimiser alpha d, alpha in [0, 1]).  A candidate
+  // replaces the smoother step only if it lowers the energy at least as much
+  // as the smoother step from the same state does (or that step would be
+  // rejected); the smoother step is computed for the comparison and then
+  // discarded.  A rejection leaves x and delta unchanged.
   rmtr_status nn_step(double* x, double delta, bool& taken) {
     taken = false;
     const int L = c->L;
@@ -441,13 +440,35 @@ struct Run {
     const double pred_c = -(alpha * gd + 0.5 * alpha * alpha * dHd);
     const double ared = -h_diff_combine(L, 0);
     const double rho = ratio(ared, pred, L);
-    taken = rho > prm.eta1 && pred >= pred_c && beta >= 0.5 && (fine_pred <= 0.0 || pred >= fine_pred);
+    taken = rho > prm.eta1 && pred >= pred_c && beta >= 0.5;
+    double ared_s = 0.0, rho_s = 0.0;
+    bool smoother_ok = false;
+    if (taken) {
+      // the smoother step from the same state (as the TR step would compute
+      // it), its energy decrease and ratio; the proposal waits in t2
+      HIPCHK(c, hipMemcpyAsync(v.t2, v.s, size_t(v.n) * sizeof(double), hipMemcpyDeviceToDevice, st));
+      if ((r = solve_qp(L, false)) != RMTR_OK) return r;
+      HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), st));
+      HIPCHK(c, launch_any_nonzero(v.n, v.s, c->flag, st));
+      HIPCHK(c, launch_hessvec(eargs(c, L, fdir), v.x0, v.p, v.s, v.hs, 0, st));
+      HIPCHK(c, launch_dot(v.n, v.g, v.s, c->partials, c->scal + 4, st));
+      HIPCHK(c, launch_dot(v.n, v.s, v.hs, c->partials, c->scal + 5, st));
+      if ((r = h_diff_enqueue(L, x, v.s, 0)) != RMTR_OK) return r;
+      if ((r = fetch(6, true)) != RMTR_OK) return r;
+      if (*c->hflag) {
+        const double pred_s = -(c->hs[4] + 0.5 * c->hs[5]);
+        ared_s = -h_diff_combine(L, 0);
+        rho_s = ratio(ared_s, pred_s, L);
+        smoother_ok = rho_s > prm.eta1;
+      }
+      taken = !smoother_ok || ared >= ared_s;
+    }
     if (trace)
-      fprintf(stderr, "rmtr:   nn l=%d beta %.3e pred %.3e cauchy %.3e smoother %.3e ared %.3e rho %.3e %s\n", L,
-              beta, pred, pred_c, fine_pred, ared, rho, taken ? "acc" : "rej");
+      fprintf(stderr, "rmtr:   nn l=%d beta %.3e pred %.3e cauchy %.3e ared %.3e rho %.3e smoother ared %.3e rho %.3e %s\n",
+              L, beta, pred, pred_c, ared, rho, ared_s, rho_s, taken ? "acc" : "rej");
     if (taken) {
       ++nn_accepted;
-      HIPCHK(c, launch_axpy(v.n, 1.0, v.s, x, st));
+      HIPCHK(c, launch_axpy(v.n, 1.0, v.t2, x, st));
     }
     return RMTR_OK;
   }

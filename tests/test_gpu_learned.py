@@ -1,8 +1,9 @@
 """The learned finest-level proposal inside the RMTR load step (GPU).
 
 A proposal never weakens the method: it is projected onto the step box and
-taken only if the FP64 trust-region ratio accepts it and it reaches the
-Cauchy decrease of the model, and the smoother runs otherwise.  So a network
+taken only if the FP64 trust-region ratio accepts it, it reaches the Cauchy
+decrease of the model and it lowers the energy at least as much as the
+smoother step from the same state, and the smoother runs otherwise.  So a network
 whose output is not finite, or absurdly large, must leave the run bit for
 bit identical to the plain one; and a trained network
 is compared with the untrained one and with the plain method on a held-out
