@@ -16,13 +16,10 @@ namespace {
 
 constexpr int kB = 256;
 
-// round-to-nearest-even FP32 -> BF16
-__device__ inline uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);  // NaN stays NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return uint16_t(u >> 16);
-}
+// round-to-nearest-even FP32 -> BF16 (NaN stays a quiet NaN), one hardware
+// conversion on gfx950 (checked against the bit-level definition over all
+// 2^32 inputs)
+__device__ inline uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 struct Box {
   int nx, ny, nz;
