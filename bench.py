@@ -273,7 +273,7 @@ def main():
         for name, prec, nn in legs:
             xs = torch.zeros_like(x)
             xs.view(-1, 4)[:, 3] = c0
-            prm = P.default_params(precision=prec)
+            prm = P.default_params(precision=prec, **wl.solver)
             if nn is not None:
                 nnv = nn.net()
                 prm.use_learned = 1

@@ -34,6 +34,8 @@ class Workload:
     seed: int = 0
     n_frac: int = 0
     extra: dict = field(default_factory=dict)
+    # solver settings that differ from the defaults (rmtr_params fields)
+    solver: dict = field(default_factory=dict)
 
     @property
     def h(self):
@@ -75,11 +77,15 @@ WORKLOADS = {
     "c2_3d_128": Workload("c2_3d_128", 3, 128, 4, seed=2, n_frac=10,
                           extra=dict(centre_lo=0.2, centre_hi=0.8, r_lo=0.03, r_hi=0.08)),
     # 3D, 256^3 cells, 100 discs, radii log-U[0.01, 0.06], centres U[0.1, 0.9]^3.
+    # Smoothing: 2 pre- and 2 post-smoothing TR steps of 6 PGS sweeps, and
+    # the radius of a rejected step measured from the step taken.
     "c3_3d_256": Workload("c3_3d_256", 3, 256, 5, seed=3, n_frac=100,
                           extra=dict(centre_lo=0.1, centre_hi=0.9, r_lo=0.01, r_hi=0.06,
-                                     log_radius=True)),
+                                     log_radius=True),
+                          solver=dict(mu1=2, mu2=2, pgs_sweeps=6, shrink_to_step=1)),
     # 3D, 384^3 cells, 1000 discs, radii log-U[0.005, 0.04], p_f U[5e-4, 2e-3].
     "c4_3d_384": Workload("c4_3d_384", 3, 384, 5, seed=4, n_frac=1000,
                           extra=dict(centre_lo=0.1, centre_hi=0.9, r_lo=0.005, r_hi=0.04,
-                                     log_radius=True, p_lo=5e-4, p_hi=2e-3)),
+                                     log_radius=True, p_lo=5e-4, p_hi=2e-3),
+                          solver=dict(mu1=2, mu2=2, pgs_sweeps=6, shrink_to_step=1)),
 }
