@@ -31,10 +31,12 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // 3x3x3 convolution on the matrix cores with the input staged in LDS, for
 // the forward pass and for the data gradient:
-//   out[v][o] = (bias[o]) + sum_k sum_i Wl[k][i][o] m(in)[v + SIGN off(k)][i]
+//   out[v][o] = (bias[o]) + sum_k sum_i Wl[k][i][o] in[v + SIGN off(k)][i]
 // (forward: Wl = W, SIGN +1; data gradient: Wl[k][i][o] = W[k][o][i],
-// SIGN -1, m(in) = in where the mask (the layer's ReLU output) is > 0, else
-// 0).  A workgroup computes a tile of 32 x 4 x 2 output voxels: wavefront w
+// SIGN -1).  With MASK_OUT the result is zeroed where mask <= 0: the data
+// gradient of layer l is stored already multiplied by the ReLU derivative
+// of layer l - 1's output (mask = that output), which is how both passes
+// of layer l - 1 consume it.  A workgroup computes a tile of 32 x 4 x 2 output voxels: wavefront w
 // the two x-rows (y0 + w, z0) and (y0 + w, z0 + 1), each a 32-voxel x
 // 32-output MFMA tile (v_mfma_f32_32x32x16_bf16, reduction over offsets x
 // input channels in chunks of 16).  The tile's input with its one-voxel halo
@@ -45,7 +47,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // banks.  Lane l holds A[l % 32][8 (l / 32) + t] and B[8 (l / 32) + t]
 // [l % 32] (t = 0..7); accumulator r of lane l is
 // C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
-template <int NI, int NO, int SIGN, int TRANS, int BIAS, int RELU_OUT, int MASK_IN>
+template <int NI, int NO, int SIGN, int TRANS, int BIAS, int RELU_OUT, int MASK_OUT>
 __global__ __launch_bounds__(256) void k_conv_tile(Box b, const float* __restrict__ in,
                                                    const float* __restrict__ mask, const uint16_t* __restrict__ W,
                                                    const float* __restrict__ bias, float* __restrict__ out) {
@@ -83,13 +85,6 @@ __global__ __launch_bounds__(256) void k_conv_tile(Box b, const float* __restric
       if (e < NST && 4 * g < NI && X >= 0 && X < b.nx && Y >= 0 && Y < b.ny && Z >= 0 && Z < b.nz) {
         const int64_t off = ((int64_t(Z) * b.ny + Y) * b.nx + X) * NI + 4 * g;
         a = *reinterpret_cast<const float4*>(in + off);
-        if (MASK_IN) {
-          const float4 mk = *reinterpret_cast<const float4*>(mask + off);
-          a.x = mk.x > 0.0f ? a.x : 0.0f;
-          a.y = mk.y > 0.0f ? a.y : 0.0f;
-          a.z = mk.z > 0.0f ? a.z : 0.0f;
-          a.w = mk.w > 0.0f ? a.w : 0.0f;
-        }
       }
       buf[j] = a;
     }
@@ -142,13 +137,15 @@ __global__ __launch_bounds__(256) void k_conv_tile(Box b, const float* __restric
       for (int zr = 0; zr < 2; ++zr) {
         const int z = z0 + zr;
         if (z >= b.nz) continue;
-        float* dst = out + ((int64_t(z) * b.ny + y) * b.nx + x0) * NO + o;
+        const int64_t base = ((int64_t(z) * b.ny + y) * b.nx + x0) * NO + o;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int i = 8 * (r / 4) + 4 * lk + (r % 4);
           if (x0 + i < b.nx) {
-            const float val = (zr ? acc1[r] : acc0[r]) + bo;
-            dst[int64_t(i) * NO] = RELU_OUT ? fmaxf(val, 0.0f) : val;
+            float val = (zr ? acc1[r] : acc0[r]) + bo;
+            if (RELU_OUT) val = fmaxf(val, 0.0f);
+            if (MASK_OUT && !(mask[base + int64_t(i) * NO] > 0.0f)) val = 0.0f;
+            out[base + int64_t(i) * NO] = val;
           }
         }
       }
@@ -159,7 +156,8 @@ __global__ __launch_bounds__(256) void k_conv_tile(Box b, const float* __restric
 // Weight and bias gradient on the matrix cores with LDS tiles: for each
 // offset k,
 //   dW[k][ci][co] = sum_v X[v + off(k)][ci] dYm[v][co],   db[co] = sum_v dYm[v][co]
-// (dYm = dY masked by the layer's ReLU) is a 32 x 32 GEMM reduced over
+// (dYm = the output gradient times the layer's ReLU derivative, as the data
+// gradient of the next layer stores it) is a 32 x 32 GEMM reduced over
 // voxels, 16 per v_mfma_f32_32x32x16_bf16.  A workgroup takes tiles of
 // 32 x 4 x 2 voxels (as k_conv_tile); per tile it stores in LDS, as BF16,
 // the tile's dYm transposed ([row][co][x]) and the input with its halo
@@ -170,10 +168,9 @@ __global__ __launch_bounds__(256) void k_conv_tile(Box b, const float* __restric
 // (byte alignment of register pairs).  Every workgroup writes one partial
 // row (27 CIN COUT + COUT values); the bias sums are FP32 over the unrounded
 // dYm, per thread and then across threads in a fixed order.
-template <int CIN, int COUT, int RELU>
+template <int CIN, int COUT>
 __global__ __launch_bounds__(576) void k_conv_bwd_w_tile(Box b, const float* __restrict__ X,
                                                          const float* __restrict__ dY,
-                                                         const float* __restrict__ Yact,
                                                          float* __restrict__ partial) {
   static_assert(CIN % 4 == 0 && COUT % 4 == 0 && CIN <= 32 && COUT <= 32, "channel counts");
   constexpr int NT = 576, NE = CIN * COUT;
@@ -203,7 +200,7 @@ __global__ __launch_bounds__(576) void k_conv_bwd_w_tile(Box b, const float* __r
     const int y0 = 4 * int((T / xt) % yt);
     const int z0 = 2 * int(T / (int64_t(xt) * yt));
     __syncthreads();  // the previous tile's operand reads are done
-    // output gradient of the tile's 256 voxels, masked, transposed
+    // output gradient of the tile's 256 voxels, transposed
     for (int e = tid; e < 256 * NGO; e += NT) {
       const int g = e % NGO, vt = e / NGO;
       const int xx = vt & 31, r = vt >> 5;  // r = zr * 4 + yw
@@ -212,13 +209,6 @@ __global__ __launch_bounds__(576) void k_conv_bwd_w_tile(Box b, const float* __r
       if (x < b.nx && y < b.ny && z < b.nz) {
         const int64_t off = ((int64_t(z) * b.ny + y) * b.nx + x) * COUT + 4 * g;
         d = *reinterpret_cast<const float4*>(dY + off);
-        if (RELU) {
-          const float4 a = *reinterpret_cast<const float4*>(Yact + off);
-          d.x = a.x > 0.0f ? d.x : 0.0f;
-          d.y = a.y > 0.0f ? d.y : 0.0f;
-          d.z = a.z > 0.0f ? d.z : 0.0f;
-          d.w = a.w > 0.0f ? d.w : 0.0f;
-        }
       }
       bacc[0] += d.x;
       bacc[1] += d.y;
@@ -512,28 +502,29 @@ hipError_t nn_backward(const uint16_t* w, const float* act, const float* dout, f
   for (int l = 5; l >= 0; --l) {
     const int cin = kCh[l], cout = kCh[l + 1];
     const float* X = act + a_off(l, nvox);
-    const float* Yact = act + a_off(l + 1, nvox);
     const uint16_t* W = w + w_off(l);
     const int64_t len = int64_t(27) * cin * cout + cout;
-    // weights: layer 5 has no ReLU on its output
+    // weights (dY arrives multiplied by the ReLU derivative already, see
+    // the data gradient below; layer 5 has no ReLU on its output)
     if (l == 5)
-      hipLaunchKernelGGL((k_conv_bwd_w_tile<32, 4, 0>), dim3(nblk), dim3(576), 0, st, b, X, dY, Yact, part);
+      hipLaunchKernelGGL((k_conv_bwd_w_tile<32, 4>), dim3(nblk), dim3(576), 0, st, b, X, dY, part);
     else if (l > 0)
-      hipLaunchKernelGGL((k_conv_bwd_w_tile<32, 32, 1>), dim3(nblk), dim3(576), 0, st, b, X, dY, Yact, part);
+      hipLaunchKernelGGL((k_conv_bwd_w_tile<32, 32>), dim3(nblk), dim3(576), 0, st, b, X, dY, part);
     else
-      hipLaunchKernelGGL((k_conv_bwd_w_tile<8, 32, 1>), dim3(nblk), dim3(576), 0, st, b, X, dY, Yact, part);
+      hipLaunchKernelGGL((k_conv_bwd_w_tile<8, 32>), dim3(nblk), dim3(576), 0, st, b, X, dY, part);
     hipLaunchKernelGGL(k_sum_partials, dim3(gridn(len)), dim3(kB), 0, st, part, nblk, len, dw + w_off(l),
                        db + b_off(l), int64_t(27) * cin * cout);
     if (l == 0) break;
     float* dX = (l % 2) ? gA : gB;
-    // data gradient: inputs dY (cout channels, masked by the layer's ReLU),
-    // outputs cin channels, transposed weights, mirrored offsets
+    // data gradient: input dY (cout channels), output cin channels,
+    // transposed weights, mirrored offsets; stored multiplied by the ReLU
+    // derivative of layer l - 1 (its output X > 0)
     if (l == 5)
-      hipLaunchKernelGGL((k_conv_tile<4, 32, -1, 1, 0, 0, 0>), dim3(conv_tile_grid(b)), dim3(256), 0, st, b, dY,
-                         nullptr, W, nullptr, dX);
+      hipLaunchKernelGGL((k_conv_tile<4, 32, -1, 1, 0, 0, 1>), dim3(conv_tile_grid(b)), dim3(256), 0, st, b, dY,
+                         X, W, nullptr, dX);
     else
       hipLaunchKernelGGL((k_conv_tile<32, 32, -1, 1, 0, 0, 1>), dim3(conv_tile_grid(b)), dim3(256), 0, st, b, dY,
-                         Yact, W, nullptr, dX);
+                         X, W, nullptr, dX);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dY = dX;
