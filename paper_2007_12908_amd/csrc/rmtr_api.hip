@@ -36,6 +36,7 @@ struct Level {
   double* S = nullptr;      // lagged Hessian as a block stencil (FP64)
   float* Sf = nullptr;      // the same in FP32 (finest level, mixed precision)
   double* coef = nullptr;   // per-element second-variation coefficients (finest level)
+  size_t coef_cap = 0;      // doubles held by coef (FP32 coefficients take half)
   double* Sop = nullptr;    // stencil scratch of rmtr_smooth / rmtr_em_smooth
   float* Sopf = nullptr;
   double* coefop = nullptr;
@@ -137,7 +138,6 @@ rmtr_status ensure_solver_level(rmtr_ctx* c, int l, bool mixed) {
                        &v.t1, &v.t2, &v.t3, &v.t4};
     for (double** b : vecs) HIPCHK(c, dalloc(c, b, n));
     HIPCHK(c, dalloc(c, &v.p, size_t(v.nodes)));
-    if (l == c->L) HIPCHK(c, dalloc(c, &v.coef, coef_values(c->model.dim, v.N)));
     v.solver_ready = true;
   }
   // stencil of the lagged Hessian: FP32 on the finest level in mixed mode
@@ -871,7 +871,7 @@ rmtr_status rmtr_coarse_hessvec(rmtr_ctx* c, int32_t level, const double* xl, co
     Sm = f.Sop;
   }
   HIPCHK(c, launch_st_assemble(eargs(c, L, dir), xl, p, f.coefop, Sm, f32, S(stream)));
-  HIPCHK(c, grow(c, &c->rap_work, &c->rap_cap, st_rap_work_doubles(d, f.N)));
+  HIPCHK(c, grow(c, &c->rap_work, &c->rap_cap, st_rap_work_doubles(d, f.N, f32 ? 1 : 0)));
   const void* src = Sm;
   int src32 = f32 ? 1 : 0;
   for (int l = L - 1; l >= level; --l) {
@@ -964,7 +964,15 @@ rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lo
   for (int l = 1; l <= c->L; ++l)
     if ((r = ensure_solver_level(c, l, mixed)) != RMTR_OK) return r;
   if (!c->mprgp_work) HIPCHK(c, dalloc(c, &c->mprgp_work, mprgp_work_doubles(c->model.dim, c->lv[1].N)));
-  if (c->L > 1) HIPCHK(c, grow(c, &c->rap_work, &c->rap_cap, st_rap_work_doubles(c->model.dim, c->lv[c->L].N)));
+  // the finest level's stencil and its coefficients are FP32 in the mixed
+  // form (with more than one level): half the memory
+  const bool fine32 = mixed && c->L > 1;
+  if (c->L > 1)
+    HIPCHK(c, grow(c, &c->rap_work, &c->rap_cap, st_rap_work_doubles(c->model.dim, c->lv[c->L].N, fine32 ? 1 : 0)));
+  {
+    const size_t cv = coef_values(c->model.dim, c->lv[c->L].N);
+    HIPCHK(c, grow(c, &c->lv[c->L].coef, &c->lv[c->L].coef_cap, fine32 ? (cv + 1) / 2 : cv));
+  }
   Run run{c, *prm, st, dir, mixed, prm->coarse_model == 0};
   const int L = c->L, d = c->model.dim;
   Level& f = c->lv[L];

@@ -56,8 +56,9 @@ hipError_t launch_em_to_st(int dim, int N, const double* K, void* S, int fp32, h
 // Galerkin coarse stencil Sc (level with Nf/2 cells, FP64) = R Sf I of the
 // fine stencil Sf (FP64, or FP32 if fp32), rows and columns of the coarse
 // Dirichlet dofs (mask dirc, null: default set) zero; work holds
-// st_rap_work_doubles(dim, Nf) doubles
-size_t st_rap_work_doubles(int dim, int Nf);
+// st_rap_work_doubles(dim, Nf, fp32) doubles (the intermediate stencils are
+// kept in the fine stencil's precision)
+size_t st_rap_work_doubles(int dim, int Nf, int fp32);
 hipError_t launch_st_rap(int dim, int Nf, const void* Sf, int fp32, double* Sc, const uint8_t* dirc, double* work,
                          hipStream_t st);
 hipError_t launch_st_matvec(int dim, int N, const void* S, const void* v, void* y, int fp32, hipStream_t st);

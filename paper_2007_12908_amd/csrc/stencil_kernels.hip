@@ -388,9 +388,9 @@ __device__ inline int64_t box_index(const Box3& b, const int (&a)[DIM]) {
   return id;
 }
 
-template <int DIM, int D, typename TI, int IN_COL, int OUT_COL>
+template <int DIM, int D, typename TI, typename TO, int IN_COL, int OUT_COL>
 __global__ __launch_bounds__(kB) void k_st_rap1(Colours gin, Box3 bin, Colours gout, Box3 bout,
-                                                const TI* __restrict__ Sin, double* __restrict__ Sout,
+                                                const TI* __restrict__ Sin, TO* __restrict__ Sout,
                                                 const uint8_t* __restrict__ dirc) {
   constexpr int NC = DIM + 1, NO = n_off<DIM>(), NOTH = NO / 3;
   int64_t nin = 1, nout = 1;
@@ -493,9 +493,9 @@ __global__ __launch_bounds__(kB) void k_st_rap1(Colours gin, Box3 bin, Colours g
         double val = acc[J][be];
         if (OUT_COL) {
           if (row_fixed || !inside || ((mcol >> be) & 1u)) val = 0.0;
-          Sout[colour_index<DIM>(gout, C, k)] = val;
+          Sout[colour_index<DIM>(gout, C, k)] = TO(val);
         } else {
-          Sout[k * nout + node] = val;
+          Sout[k * nout + node] = TO(val);
         }
       }
     }
@@ -854,7 +854,7 @@ hipError_t launch_st_pgs(int dim, int N, const void* S, const uint8_t* dir, cons
                               (double*)s, n_sweeps, st);
 }
 
-size_t st_rap_work_doubles(int dim, int Nf) {
+size_t st_rap_work_doubles(int dim, int Nf, int fp32) {
   const int Nc = Nf / 2;
   const size_t rb = size_t(dim == 3 ? row_block<3>() : row_block<2>());
   size_t a = 1, b = 1;
@@ -862,9 +862,12 @@ size_t st_rap_work_doubles(int dim, int Nf) {
     a *= size_t(i == 0 ? Nc + 1 : Nf + 1);
     b *= size_t(i <= 1 ? Nc + 1 : Nf + 1);
   }
-  return (a + (dim == 3 ? b : 0)) * rb;
+  const size_t vals = (a + (dim == 3 ? b : 0)) * rb;
+  return fp32 ? (vals + 1) / 2 : vals;
 }
 
+// intermediates in the fine stencil's precision (FP32 from an FP32 fine
+// stencil: half the work memory; the sums are FP64 in every pass)
 template <int DIM, typename TI>
 static hipError_t st_rap_t(int Nf, const TI* Sf, double* Sc, const uint8_t* dirc, double* work, hipStream_t st) {
   const int Nc = Nf / 2;
@@ -878,15 +881,17 @@ static hipError_t st_rap_t(int Nf, const TI* Sf, double* Sc, const uint8_t* dirc
     int64_t n = int64_t(b.n[0]) * b.n[1] * b.n[2];
     return dim3(gridn(n * NC * NOTH));
   };
-  double* T1 = work;
+  TI* T1 = reinterpret_cast<TI*>(work);
   if constexpr (DIM == 3) {
-    double* T2 = work + int64_t(b1.n[0]) * b1.n[1] * b1.n[2] * row_block<DIM>();
-    hipLaunchKernelGGL((k_st_rap1<DIM, 0, TI, 1, 0>), grid(b1), dim3(kB), 0, st, gf, b0, gc, b1, Sf, T1, dirc);
-    hipLaunchKernelGGL((k_st_rap1<DIM, 1, double, 0, 0>), grid(b2), dim3(kB), 0, st, gf, b1, gc, b2, T1, T2, dirc);
-    hipLaunchKernelGGL((k_st_rap1<DIM, 2, double, 0, 1>), grid(b3), dim3(kB), 0, st, gf, b2, gc, b3, T2, Sc, dirc);
+    TI* T2 = T1 + int64_t(b1.n[0]) * b1.n[1] * b1.n[2] * row_block<DIM>();
+    hipLaunchKernelGGL((k_st_rap1<DIM, 0, TI, TI, 1, 0>), grid(b1), dim3(kB), 0, st, gf, b0, gc, b1, Sf, T1, dirc);
+    hipLaunchKernelGGL((k_st_rap1<DIM, 1, TI, TI, 0, 0>), grid(b2), dim3(kB), 0, st, gf, b1, gc, b2, T1, T2, dirc);
+    hipLaunchKernelGGL((k_st_rap1<DIM, 2, TI, double, 0, 1>), grid(b3), dim3(kB), 0, st, gf, b2, gc, b3, T2, Sc,
+                       dirc);
   } else {
-    hipLaunchKernelGGL((k_st_rap1<DIM, 0, TI, 1, 0>), grid(b1), dim3(kB), 0, st, gf, b0, gc, b1, Sf, T1, dirc);
-    hipLaunchKernelGGL((k_st_rap1<DIM, 1, double, 0, 1>), grid(b3), dim3(kB), 0, st, gf, b1, gc, b3, T1, Sc, dirc);
+    hipLaunchKernelGGL((k_st_rap1<DIM, 0, TI, TI, 1, 0>), grid(b1), dim3(kB), 0, st, gf, b0, gc, b1, Sf, T1, dirc);
+    hipLaunchKernelGGL((k_st_rap1<DIM, 1, TI, double, 0, 1>), grid(b3), dim3(kB), 0, st, gf, b1, gc, b3, T1, Sc,
+                       dirc);
   }
   return hipGetLastError();
 }
