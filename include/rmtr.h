@@ -260,8 +260,9 @@ rmtr_status rmtr_step_box(rmtr_ctx* ctx, int32_t level, const double* x, const d
 /* ------------------------------------------------------------------------
    Learned proposal (not part of the paper's method: a learned form of the
    finest-level smoother, gated by the unchanged trust-region ratio test of
-   eq. (rho_tr), a Cauchy sufficient-decrease check and the bound
-   projection, with the PGS smoother of Sec. 3.2.1 as fallback).
+   eq. (rho_tr), a Cauchy sufficient-decrease check, a comparison with the
+   smoother step's energy decrease and the bound projection, with the PGS
+   smoother of Sec. 3.2.1 as fallback).
 
    Network: six 3x3x3 convolutions with zero padding on the node grid,
    channels 8 -> 32 -> 32 -> 32 -> 32 -> 32 -> 4, ReLU after the first five:
@@ -269,7 +270,9 @@ rmtr_status rmtr_step_box(rmtr_ctx* ctx, int32_t level, const double* x, const d
    off(k) = (k%3 - 1, (k/3)%3 - 1, k/9 - 1) in (x, y, z).  Tensors are
    channels-last FP32 on nx*ny*nz voxels, voxel v = i + nx (j + ny k).
    Weights are BF16 (round-to-nearest-even of FP32 masters), [27][Cin][Cout]
-   per layer, layers concatenated; FP32 arithmetic.
+   per layer, layers concatenated.  Every convolution runs on the BF16
+   matrix cores: layer inputs, output gradients and weights rounded to BF16
+   (round-to-nearest-even), products summed in FP32.
    Input channels: (u, c) of x times scales[0..3], then g_k / rms(g_k) times
    scales[4..7], rms(g_k) the root mean square of component k of g over the
    level's nodes (the input is 0 where it vanishes); output channel k times

@@ -1,7 +1,8 @@
 // The learned fine-level proposal: a 3D convolutional network (six 3x3x3
 // layers, channels 8 -> 32 -> 32 -> 32 -> 32 -> 32 -> 4, ReLU after the
-// first five, zero padding), with BF16 weights and FP32 arithmetic, and the
-// kernels that train it (backward passes, MSE loss, Adam).
+// first five, zero padding), with BF16 weights and BF16 matrix-core
+// products summed in FP32, and the kernels that train it (backward passes,
+// MSE loss, Adam).
 //
 // Tensors are channels-last FP32 on a box of nx x ny x nz voxels (voxel
 // v = x + nx (y + ny z)), the layout of the node-major grid vectors.  Layer
