@@ -169,6 +169,12 @@ __global__ __launch_bounds__(256) void k_conv_tile(Box b, const float* __restric
 // (byte alignment of register pairs).  Every workgroup writes one partial
 // row (27 CIN COUT + COUT values); the bias sums are FP32 over the unrounded
 // dYm, per thread and then across threads in a fixed order.
+// Position of x-entry xq (0..47, six blocks of eight) in the LDS row of
+// input channel ci: the blocks of a row are rotated by ci / 8, which spreads
+// the transposing stores of a wavefront (eight 4-channel groups) over all
+// bank groups; a block stays 16-byte aligned for the operand reads.
+__device__ inline int xslot(int ci, int xq) { return ((((xq >> 3) + (ci >> 3)) % 6) << 3) | (xq & 7); }
+
 template <int CIN, int COUT>
 __global__ __launch_bounds__(576) void k_conv_bwd_w_tile(Box b, const float* __restrict__ X,
                                                          const float* __restrict__ dY,
@@ -229,7 +235,7 @@ __global__ __launch_bounds__(576) void k_conv_bwd_w_tile(Box b, const float* __r
       float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
       if (x >= 0 && x < b.nx && y >= 0 && y < b.ny && z >= 0 && z < b.nz)
         a = *reinterpret_cast<const float4*>(X + ((int64_t(z) * b.ny + y) * b.nx + x) * CIN + 4 * g);
-      uint16_t* dst = sX + ((sz * SY + sy) * 32 + 4 * g) * XW + sx + 7;
+      uint16_t* dst = sX + ((sz * SY + sy) * 32 + 4 * g) * XW + xslot(4 * g, sx + 7);
       dst[0] = f2bf(a.x);
       dst[XW] = f2bf(a.y);
       dst[2 * XW] = f2bf(a.z);
@@ -245,9 +251,9 @@ __global__ __launch_bounds__(576) void k_conv_bwd_w_tile(Box b, const float* __r
       for (int c = 0; c < 2; ++c) {
         const int xp = 8 + 16 * c + 8 * lk;  // first of the lane's eight voxels (dx = 0)
         const bf16x8 bd = *reinterpret_cast<const bf16x8*>(drow + 16 * c + 8 * lk);
-        const uint4 m = *reinterpret_cast<const uint4*>(xrow + xp);
-        const uint32_t lft = *reinterpret_cast<const uint32_t*>(xrow + xp - 2);
-        const uint32_t rgt = *reinterpret_cast<const uint32_t*>(xrow + xp + 8);
+        const uint4 m = *reinterpret_cast<const uint4*>(xrow + xslot(li, xp));
+        const uint32_t lft = *reinterpret_cast<const uint32_t*>(xrow + xslot(li, xp - 2));
+        const uint32_t rgt = *reinterpret_cast<const uint32_t*>(xrow + xslot(li, xp + 8));
         // dx = -1: elements xp - 1 .. xp + 6;  dx = +1: xp + 1 .. xp + 8
         const uint32_t n0 = __builtin_amdgcn_alignbyte(m.x, lft, 2);
         const uint32_t n1 = __builtin_amdgcn_alignbyte(m.y, m.x, 2);
