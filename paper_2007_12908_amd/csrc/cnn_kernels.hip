@@ -416,11 +416,11 @@ int gridn(int64_t work) {
   return int(b);
 }
 
-// k_conv_tile grid: persistent workgroups (each stages the layer's weights
-// once), at most 512
-int conv_tile_grid(const Box& b) {
+// Tiled-kernel grids: persistent workgroups (each stages the layer's weights
+// once, or writes one partial row), at most cap
+int conv_tile_grid(const Box& b, int cap = 512) {
   const int64_t tiles = int64_t((b.nx + 31) / 32) * ((b.ny + 3) / 4) * ((b.nz + 1) / 2);
-  return int(std::max<int64_t>(1, std::min<int64_t>(tiles, 512)));
+  return int(std::max<int64_t>(1, std::min<int64_t>(tiles, cap)));
 }
 
 }  // namespace
@@ -503,8 +503,9 @@ hipError_t nn_backward(const uint16_t* w, const float* act, const float* dout, f
   float* gA = work;
   float* gB = work + nvox * 32;
   float* part = work + 2 * nvox * 32;
-  // one partial row per weight-gradient workgroup (at most 512)
-  const int nblk = conv_tile_grid(b);
+  // one partial row per weight-gradient workgroup: 256 workgroups (one per
+  // compute unit, as their LDS allows) keep the fixed-order sum short
+  const int nblk = conv_tile_grid(b, 256);
   const float* dY = dout;
   for (int l = 5; l >= 0; --l) {
     const int cin = kCh[l], cout = kCh[l + 1];
