@@ -250,6 +250,9 @@ __device__ inline void st_node_item(const Colours& g, double h, double gcl_d, co
               o += (((b >> i) & 1) - ((a >> i) & 1) + 1) * om;
               om *= 3;
             }
+            // 3D: blocks towards lower neighbours are the mirror image of
+            // blocks the neighbour computes (k_st_mirror fills them)
+            if (DIM == 3 && pz == 1 && o < 4) continue;
             const T Nb = T(refN<DIM>(q, b));
             T dNb[DIM];
             T dd = T(0);
@@ -284,6 +287,7 @@ __device__ inline void st_node_item(const Colours& g, double h, double gcl_d, co
     TO* out = S + st_row<DIM>(g, col, t);
 #pragma unroll
     for (int o = 0; o < OPP; ++o) {
+      if (DIM == 3 && pz == 1 && o < 4) continue;
       const int of = o + OPP * pz;
       int m[DIM];
       bool inside = true;
@@ -332,7 +336,8 @@ __global__ __launch_bounds__(kB) void k_st_node(Colours g, double h, double gcl,
       const int inner = int(k % 24);
       const int col = inner & 7, pz = inner >> 3;
       const int64_t t = (x + 8 * (k / 24)) * kChunk + (threadIdx.x >> 2);
-      if (t < g.cnt[col]) st_node_item<DIM, TO>(g, h, gcl, C, dir, S, al, g.base[col] + t, pz);
+      // plane dz = -1 holds mirror images only
+      if (pz > 0 && t < g.cnt[col]) st_node_item<DIM, TO>(g, h, gcl, C, dir, S, al, g.base[col] + t, pz);
     }
   } else {
     const int64_t work = nodes * NC * NP;
@@ -340,6 +345,44 @@ __global__ __launch_bounds__(kB) void k_st_node(Colours g, double h, double gcl,
       const int al = int(it % NC);
       const int64_t r1 = it / NC;
       st_node_item<DIM, TO>(g, h, gcl, C, dir, S, al, r1 % nodes, int(r1 / nodes));
+    }
+  }
+}
+
+// The stencil is symmetric: the block of row node n towards neighbour
+// m = n + off(k) is the transpose of m's block towards n (offset 26 - k).
+// k_st_node computes the 14 blocks towards n itself and its upper
+// neighbours (dz = 1; dz = 0 with dy = 1, or dy = 0 and dx = 1); this pass
+// fills the other 13 from the neighbours' rows.  Thread per (node, row al);
+// Dirichlet rows and columns are zero on both sides already, and blocks
+// towards missing neighbours are written as zero.
+template <typename TO>
+__global__ __launch_bounds__(kB) void k_st_mirror(Colours g, TO* __restrict__ S) {
+  constexpr int NC = 4, NO = 27;
+  const int N = g.N;
+  const int64_t nodes = g.base[8];
+  for (int64_t it = int64_t(blockIdx.x) * kB + threadIdx.x; it < nodes * NC; it += int64_t(gridDim.x) * kB) {
+    const int al = int(it % NC);
+    const int64_t id = it / NC;
+    int64_t t, n;
+    int c[3];
+    const int col = locate<3>(g, id, t, c, n);
+    TO* out = S + st_row<3>(g, col, t);
+#pragma unroll
+    for (int k = 0; k < 13; ++k) {
+      const int m[3] = {c[0] + k % 3 - 1, c[1] + (k / 3) % 3 - 1, c[2] + k / 9 - 1};
+      const bool inside = m[0] >= 0 && m[0] <= N && m[1] >= 0 && m[1] <= N && m[2] >= 0 && m[2] <= N;
+      TO v[NC] = {TO(0), TO(0), TO(0), TO(0)};
+      if (inside) {
+        const int cm = (m[0] & 1) + 2 * (m[1] & 1) + 4 * (m[2] & 1);
+        const int64_t tm = int64_t(m[0] >> 1) +
+                           int64_t(g.len[cm][0]) * (int64_t(m[1] >> 1) + int64_t(g.len[cm][1]) * (m[2] >> 1));
+        const TO* src = S + st_row<3>(g, cm, tm);
+#pragma unroll
+        for (int be = 0; be < NC; ++be) v[be] = src[((be * NO + (26 - k)) * NC + al) * kChunk];
+      }
+#pragma unroll
+      for (int be = 0; be < NC; ++be) out[((al * NO + k) * NC + be) * kChunk] = v[be];
     }
   }
 }
@@ -756,6 +799,8 @@ static hipError_t st_assemble_t(const ElemArgs& a, const double* xl, const doubl
   constexpr int NP = DIM == 3 ? 3 : 1;
   const int64_t work = g.base[NL] * NC * NP;
   hipLaunchKernelGGL((k_st_node<DIM, TO>), dim3(gridn(work)), dim3(kB), 0, st, g, a.h, gcl, cf, a.dir, S);
+  if constexpr (DIM == 3)
+    hipLaunchKernelGGL(k_st_mirror<TO>, dim3(gridn(g.base[NL] * NC)), dim3(kB), 0, st, g, S);
   return hipGetLastError();
 }
 
