@@ -4,46 +4,30 @@
 // The level's element matrices are first assembled into a 3^d-point block
 // stencil (stencil_kernels.hip), so every matrix-vector product is a
 // row-parallel pass over contiguous rows.  The
-// host drives the iteration; every reduction is a fixed-order two-stage tree,
-// so the scalars (and the branch taken) do not depend on scheduling.
+// host drives the iteration and reads two sets of reduced scalars per
+// iteration.  The products A d are fused with the row-local work that
+// consumes them, and every reduction ends in the kernel that produces it:
+// each workgroup writes its partial sums, and the last workgroup to finish
+// adds all partials in a fixed order and writes the scalars to host-mapped
+// memory, so the scalars (and the branch taken) do not depend on scheduling.
 #include <math.h>
 
 #include "rmtr_kernels.h"
+#include "stencil_layout.h"
 
 namespace rmtr {
 namespace {
 
 constexpr int kB = 256;
-constexpr int kNV = 5;  // reduced values per pass: four sums and one min
+constexpr int kMvB = 3 * kChunk;  // fused products: one wavefront per neighbour plane
+constexpr int kNV = 5;            // reduced values per pass: four sums and one min
+constexpr int kMaxBlocks = 1024;
 
-template <int DIM>
-constexpr int n_off() {
-  return DIM == 3 ? 27 : 9;
-}
-
-int nblocks(int64_t n) {
-  int64_t b = (n + kB - 1) / kB;
+int nblocks(int64_t n, int per_block) {
+  int64_t b = (n + per_block - 1) / per_block;
   if (b < 1) b = 1;
-  if (b > 1024) b = 1024;
+  if (b > kMaxBlocks) b = kMaxBlocks;
   return int(b);
-}
-
-__device__ inline void bred(double (&v)[kNV], double (*sh)[kB], double* out) {
-  const int t = threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < kNV; ++k) sh[k][t] = v[k];
-  __syncthreads();
-  for (int s = kB / 2; s > 0; s >>= 1) {
-    if (t < s) {
-#pragma unroll
-      for (int k = 0; k < kNV - 1; ++k) sh[k][t] += sh[k][t + s];
-      sh[kNV - 1][t] = fmin(sh[kNV - 1][t], sh[kNV - 1][t + s]);
-    }
-    __syncthreads();
-  }
-  if (t == 0)
-#pragma unroll
-    for (int k = 0; k < kNV; ++k) out[k] = sh[k][0];
 }
 
 __device__ inline void vinit(double (&v)[kNV]) {
@@ -52,16 +36,74 @@ __device__ inline void vinit(double (&v)[kNV]) {
   v[kNV - 1] = INFINITY;
 }
 
+__device__ inline double vop(int k, double a, double b) { return k == kNV - 1 ? fmin(a, b) : a + b; }
+
+// reduce v over the workgroup (butterfly in each wavefront, then the
+// wavefronts in order); the result is valid in thread 0
+template <int NW>
+__device__ inline void block_reduce(double (&v)[kNV], double (*sh)[kNV]) {
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+#pragma unroll
+  for (int k = 0; k < kNV; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] = vop(k, v[k], __shfl_xor(v[k], off));
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) sh[w][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) {
+      double r = sh[0][k];
+#pragma unroll
+      for (int i = 1; i < NW; ++i) r = vop(k, r, sh[i][k]);
+      v[k] = r;
+    }
+}
+
+// Workgroup partials of v, then in the last workgroup to arrive the
+// fixed-order sum of all partials into out[0 .. kNV) (host-mapped); the
+// counter is left at zero for the next pass.
+template <int NW>
+__device__ inline void reduce_to_host(double (&v)[kNV], double* __restrict__ partials, unsigned* ctr,
+                                      double* out) {
+  __shared__ double sh[NW][kNV];
+  __shared__ int last;
+  block_reduce<NW>(v, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) partials[kNV * blockIdx.x + k] = v[k];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned prev = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    last = prev == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  vinit(v);
+  for (int b = threadIdx.x; b < int(gridDim.x); b += NW * 64)
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) v[k] = vop(k, v[k], partials[kNV * b + k]);
+  __syncthreads();  // sh is reused
+  block_reduce<NW>(v, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) out[k] = v[k];
+    __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 __global__ __launch_bounds__(kB) void k_final(const double* __restrict__ partials, int nb, double* __restrict__ out) {
-  __shared__ double sh[kNV][kB];
+  __shared__ double sh[kB / 64][kNV];
   double v[kNV];
   vinit(v);
-  for (int i = threadIdx.x; i < nb; i += kB) {
+  for (int i = threadIdx.x; i < nb; i += kB)
 #pragma unroll
-    for (int k = 0; k < kNV - 1; ++k) v[k] += partials[kNV * i + k];
-    v[kNV - 1] = fmin(v[kNV - 1], partials[kNV * i + kNV - 1]);
-  }
-  bred(v, sh, out);
+    for (int k = 0; k < kNV; ++k) v[k] = vop(k, v[k], partials[kNV * i + k]);
+  block_reduce<kB / 64>(v, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) out[k] = v[k];
 }
 
 __device__ inline bool is_free(double s, double lo, double hi) { return s > lo && s < hi; }
@@ -75,13 +117,15 @@ __device__ inline double chop(double s, double g, double lo, double hi) {
 }
 
 // state sums of (s, gr): ||phi + beta||^2, beta^T beta, phit^T phi, and
-// phi^T Ad (when Ad is given); phi and beta are written.
-__device__ inline void state_terms(double abar, double si, double gi, double l, double h, double* phi,
-                                   double* beta, int64_t i, const double* Ad, double (&v)[kNV]) {
+// phi^T Ad (when Ad is given); phi and beta are written, and phi also to
+// pout when given.
+__device__ inline void state_terms(double abar, double si, double gi, double l, double h, double* phi, double* beta,
+                                   double* pout, int64_t i, const double* Ad, double (&v)[kNV]) {
   const double f = is_free(si, l, h) ? gi : 0.0;
   const double b = chop(si, gi, l, h);
   phi[i] = f;
   beta[i] = b;
+  if (pout) pout[i] = f;
   const double ft = f > 0.0 ? fmin((si - l) / abar, f) : fmax((si - h) / abar, f);
   v[0] += (f + b) * (f + b);
   v[1] += b * b;
@@ -89,45 +133,82 @@ __device__ inline void state_terms(double abar, double si, double gi, double l, 
   if (Ad) v[3] += f * Ad[i];
 }
 
+struct Red {
+  double* partials;
+  unsigned* ctr;
+  double* out;
+};
+
 __global__ __launch_bounds__(kB) void k_state(int64_t n, double abar, const double* __restrict__ s,
                                               const double* __restrict__ gr, const double* __restrict__ lo,
                                               const double* __restrict__ hi, double* __restrict__ phi,
-                                              double* __restrict__ beta, double* __restrict__ partials) {
-  __shared__ double sh[kNV][kB];
+                                              double* __restrict__ beta, double* __restrict__ p, Red red) {
   double v[kNV];
   vinit(v);
   for (int64_t i = int64_t(blockIdx.x) * kB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kB)
-    state_terms(abar, s[i], gr[i], lo[i], hi[i], phi, beta, i, nullptr, v);
-  bred(v, sh, partials + kNV * blockIdx.x);
+    state_terms(abar, s[i], gr[i], lo[i], hi[i], phi, beta, p, i, nullptr, v);
+  reduce_to_host<kB / 64>(v, red.partials, red.ctr, red.out);
 }
 
-// d^T A d, g^T d (slots 0, 1) and the largest feasible step along -d (min).
-__global__ __launch_bounds__(kB) void k_dir(int64_t n, const double* __restrict__ s, const double* __restrict__ gr,
-                                            const double* __restrict__ d, const double* __restrict__ Ad,
-                                            const double* __restrict__ lo, const double* __restrict__ hi,
-                                            double* __restrict__ partials) {
-  __shared__ double sh[kNV][kB];
+// Fused product and row-local pass over the rows of A (al-major order, 64
+// rows per workgroup, one wavefront per neighbour plane):
+//   MODE 0: Ad = A d; d^T A d, g^T d (slots 0, 1) and the largest feasible
+//           step along -d (min slot);
+//   MODE 1: gr = A d + g (d = s); the state sums of (s, gr), phi also to p.
+template <int DIM, int MODE>
+__global__ __launch_bounds__(kMvB) void k_mv_fused(Colours cg, const double* __restrict__ S,
+                                                   const double* __restrict__ d, double* __restrict__ Ad,
+                                                   const double* __restrict__ g, const double* __restrict__ s,
+                                                   double* __restrict__ gr, const double* __restrict__ lo,
+                                                   const double* __restrict__ hi, double abar,
+                                                   double* __restrict__ phi, double* __restrict__ beta,
+                                                   double* __restrict__ p, Red red) {
+  constexpr int NC = DIM + 1;
+  __shared__ double part[2][kChunk];
+  const int64_t nodes = cg.base[1 << DIM], rows = nodes * NC;
+  const int lane = threadIdx.x % kChunk, pl = threadIdx.x / kChunk;
   double v[kNV];
   vinit(v);
-  for (int64_t i = int64_t(blockIdx.x) * kB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kB) {
-    const double di = d[i];
-    v[0] += di * Ad[i];
-    v[1] += gr[i] * di;
-    if (di > 0.0) v[kNV - 1] = fmin(v[kNV - 1], (s[i] - lo[i]) / di);
-    if (di < 0.0) v[kNV - 1] = fmin(v[kNV - 1], (s[i] - hi[i]) / di);
+  for (int64_t r0 = int64_t(blockIdx.x) * kChunk; r0 < rows; r0 += int64_t(gridDim.x) * kChunk) {
+    const int64_t it = r0 + lane;
+    double acc = 0.0;
+    int64_t n = 0;
+    int al = 0;
+    if (it < rows) {
+      al = int(it / nodes);
+      acc = st_row_plane<DIM>(cg, S, d, it % nodes, al, pl, n);
+    }
+    if (pl > 0) part[pl - 1][lane] = acc;
+    __syncthreads();
+    if (pl == 0 && it < rows) {
+      const int64_t i = NC * n + al;
+      const double a = (acc + part[0][lane]) + part[1][lane];
+      if (MODE == 0) {
+        Ad[i] = a;
+        const double di = d[i];
+        v[0] += di * a;
+        v[1] += gr[i] * di;
+        if (di > 0.0) v[kNV - 1] = fmin(v[kNV - 1], (s[i] - lo[i]) / di);
+        if (di < 0.0) v[kNV - 1] = fmin(v[kNV - 1], (s[i] - hi[i]) / di);
+      } else {
+        const double gi = a + g[i];
+        gr[i] = gi;
+        state_terms(abar, s[i], gi, lo[i], hi[i], phi, beta, p, i, nullptr, v);
+      }
+    }
+    __syncthreads();
   }
-  bred(v, sh, partials + kNV * blockIdx.x);
+  reduce_to_host<kMvB / 64>(v, red.partials, red.ctr, red.out);
 }
 
 // s -= a d (clipped to the box if clip); gr -= a Ad; then the state sums
-// of the new point, with phi^T Ad in slot 3.
-__global__ __launch_bounds__(kB) void k_step_state(int64_t n, double a, int clip, double abar,
-                                                   const double* __restrict__ d, const double* __restrict__ Ad,
-                                                   const double* __restrict__ lo, const double* __restrict__ hi,
-                                                   double* __restrict__ s, double* __restrict__ gr,
-                                                   double* __restrict__ phi, double* __restrict__ beta,
-                                                   double* __restrict__ partials) {
-  __shared__ double sh[kNV][kB];
+// of the new point, with phi^T Ad in slot 3 (phi also to p when given).
+// d may be beta: each element is read before it is rewritten.
+__global__ __launch_bounds__(kB) void k_step_state(int64_t n, double a, int clip, double abar, const double* d,
+                                                   const double* __restrict__ Ad, const double* __restrict__ lo,
+                                                   const double* __restrict__ hi, double* __restrict__ s,
+                                                   double* __restrict__ gr, double* __restrict__ phi, double* beta,
+                                                   double* p, Red red) {
   double v[kNV];
   vinit(v);
   for (int64_t i = int64_t(blockIdx.x) * kB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kB) {
@@ -136,9 +217,9 @@ __global__ __launch_bounds__(kB) void k_step_state(int64_t n, double a, int clip
     const double gi = gr[i] - a * Ad[i];
     s[i] = si;
     gr[i] = gi;
-    state_terms(abar, si, gi, lo[i], hi[i], phi, beta, i, Ad, v);
+    state_terms(abar, si, gi, lo[i], hi[i], phi, beta, p, i, Ad, v);
   }
-  bred(v, sh, partials + kNV * blockIdx.x);
+  reduce_to_host<kB / 64>(v, red.partials, red.ctr, red.out);
 }
 
 // expansion step: s -= af p, then s = P(s - abar phi(s, gr - af Ap))
@@ -154,23 +235,6 @@ __global__ __launch_bounds__(kB) void k_expand(int64_t n, double af, double abar
   }
 }
 
-// gr = A s + g (A s given), then the state sums
-__global__ __launch_bounds__(kB) void k_regrad_state(int64_t n, double abar, const double* __restrict__ As,
-                                                     const double* __restrict__ g, const double* __restrict__ s,
-                                                     const double* __restrict__ lo, const double* __restrict__ hi,
-                                                     double* __restrict__ gr, double* __restrict__ phi,
-                                                     double* __restrict__ beta, double* __restrict__ partials) {
-  __shared__ double sh[kNV][kB];
-  double v[kNV];
-  vinit(v);
-  for (int64_t i = int64_t(blockIdx.x) * kB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kB) {
-    const double gi = As[i] + g[i];
-    gr[i] = gi;
-    state_terms(abar, s[i], gi, lo[i], hi[i], phi, beta, i, nullptr, v);
-  }
-  bred(v, sh, partials + kNV * blockIdx.x);
-}
-
 // p = phi - bet p
 __global__ __launch_bounds__(kB) void k_pupd(int64_t n, double bet, const double* __restrict__ phi,
                                              double* __restrict__ p) {
@@ -178,14 +242,13 @@ __global__ __launch_bounds__(kB) void k_pupd(int64_t n, double bet, const double
     p[i] = phi[i] - bet * p[i];
 }
 
-
 }  // namespace
 
 size_t mprgp_work_doubles(int dim, int N) {
   int64_t nn = 1;
   for (int i = 0; i < dim; ++i) nn *= (N + 1);
   const int64_t n = nn * (dim + 1);
-  return size_t(5 * n + kNV * 1024 + 2 * kNV + 16);
+  return size_t(5 * n + kNV * kMaxBlocks + 2 * kNV + 16);
 }
 
 hipError_t run_mprgp(int dim, int N, const double* S, const uint8_t* dir, const double* g, const double* lo,
@@ -200,33 +263,33 @@ hipError_t run_mprgp(int dim, int N, const double* S, const uint8_t* dir, const 
   double* p = beta + n;
   double* Ad = p + n;
   double* part = Ad + n;
-  const int nb = nblocks(n);
-  const dim3 gb(nb), tb(kB);
+  // arrival counter of the in-kernel reductions (zero between passes)
+  double* ctr_slot = part + kNV * kMaxBlocks;
+  unsigned* ctr = reinterpret_cast<unsigned*>(ctr_slot);
+  const Red red{part, ctr, hs};
+  const Colours cg = colours(dim, N);
+  const dim3 ge(nblocks(n, kB)), te(kB);
+  const dim3 gm(nblocks(n, kChunk)), tm(kMvB);
   hipError_t e;
 #define CK(x)                      \
   do {                             \
     e = (x);                       \
     if (e != hipSuccess) return e; \
   } while (0)
-  // the final reduction writes straight into the (mapped, coherent) host
-  // scalars; the synchronisation makes them visible
-#define FETCH()                                                                     \
-  do {                                                                              \
-    hipLaunchKernelGGL(k_final, dim3(1), tb, 0, st, part, nb, hs);                  \
-    CK(hipGetLastError());                                                          \
-    CK(hipStreamSynchronize(st));                                                   \
-  } while (0)
-#define MATVEC(v, out) CK(launch_st_matvec(dim, N, S, v, out, 0, st))
+  // the scalars of a pass are written straight into the (mapped, coherent)
+  // host memory hs; the synchronisation makes them visible
+#define SYNC() CK(hipStreamSynchronize(st))
   res->iterations = 0;
   res->status = 1;
   CK(launch_fill(n, 0.0, s, st));
+  CK(launch_fill(1, 0.0, ctr_slot, st));
   // ||A|| bound and ||b||
   {
     int nbr = 0;
     CK(launch_st_rowabs(dim, N, S, g, part, &nbr, st));
-    hipLaunchKernelGGL(k_final, dim3(1), tb, 0, st, part, nbr, hs);
+    hipLaunchKernelGGL(k_final, dim3(1), te, 0, st, part, nbr, hs);
     CK(hipGetLastError());
-    CK(hipStreamSynchronize(st));
+    SYNC();
   }
   const double normA = -hs[kNV - 1];
   const double bnorm = sqrt(hs[0]);
@@ -236,12 +299,31 @@ hipError_t run_mprgp(int dim, int N, const double* S, const uint8_t* dir, const 
   }
   const double abar = 1.9 / normA;
   const double tol = rtol * fmax(bnorm, 1e-300);
-  // s = 0: gr = A s - b = g
+  // Ad = A d with the direction sums (mode 0), or gr = A s + g with the
+  // state sums and p = phi (mode 1)
+  auto fused = [&](int mode, const double* dv) -> hipError_t {
+    if (dim == 3) {
+      if (mode == 0)
+        hipLaunchKernelGGL((k_mv_fused<3, 0>), gm, tm, 0, st, cg, S, dv, Ad, g, s, gr, lo, hi, abar, phi, beta, p,
+                           red);
+      else
+        hipLaunchKernelGGL((k_mv_fused<3, 1>), gm, tm, 0, st, cg, S, dv, Ad, g, s, gr, lo, hi, abar, phi, beta, p,
+                           red);
+    } else {
+      if (mode == 0)
+        hipLaunchKernelGGL((k_mv_fused<2, 0>), gm, tm, 0, st, cg, S, dv, Ad, g, s, gr, lo, hi, abar, phi, beta, p,
+                           red);
+      else
+        hipLaunchKernelGGL((k_mv_fused<2, 1>), gm, tm, 0, st, cg, S, dv, Ad, g, s, gr, lo, hi, abar, phi, beta, p,
+                           red);
+    }
+    return hipGetLastError();
+  };
+  // s = 0: gr = A s - b = g; p = phi
   CK(hipMemcpyAsync(gr, g, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-  hipLaunchKernelGGL(k_state, gb, tb, 0, st, n, abar, s, gr, lo, hi, phi, beta, part);
+  hipLaunchKernelGGL(k_state, ge, te, 0, st, n, abar, s, gr, lo, hi, phi, beta, p, red);
   CK(hipGetLastError());
-  CK(hipMemcpyAsync(p, phi, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-  FETCH();
+  SYNC();
   int it = 0;
   bool negcurv = false;
   while (it < max_it) {
@@ -252,10 +334,8 @@ hipError_t run_mprgp(int dim, int N, const double* S, const uint8_t* dir, const 
     }
     ++it;
     if (bb <= pf) {
-      MATVEC(p, Ad);
-      hipLaunchKernelGGL(k_dir, gb, tb, 0, st, n, s, gr, p, Ad, lo, hi, part);
-      CK(hipGetLastError());
-      FETCH();
+      CK(fused(0, p));
+      SYNC();
       const double pAp = hs[0], gp = hs[1], af = hs[kNV - 1];
       if (!(pAp > 0.0)) {
         negcurv = true;
@@ -263,39 +343,32 @@ hipError_t run_mprgp(int dim, int N, const double* S, const uint8_t* dir, const 
       }
       const double acg = gp / pAp;
       if (acg <= af) {
-        hipLaunchKernelGGL(k_step_state, gb, tb, 0, st, n, acg, 0, abar, p, Ad, lo, hi, s, gr, phi, beta, part);
+        hipLaunchKernelGGL(k_step_state, ge, te, 0, st, n, acg, 0, abar, p, Ad, lo, hi, s, gr, phi, beta,
+                           (double*)nullptr, red);
         CK(hipGetLastError());
-        FETCH();
+        SYNC();
         const double bet = hs[3] / pAp;
-        hipLaunchKernelGGL(k_pupd, gb, tb, 0, st, n, bet, phi, p);
+        hipLaunchKernelGGL(k_pupd, ge, te, 0, st, n, bet, phi, p);
         CK(hipGetLastError());
       } else {
-        hipLaunchKernelGGL(k_expand, gb, tb, 0, st, n, af, abar, p, Ad, lo, hi, s, gr);
+        hipLaunchKernelGGL(k_expand, ge, te, 0, st, n, af, abar, p, Ad, lo, hi, s, gr);
         CK(hipGetLastError());
-        MATVEC(s, Ad);
-        hipLaunchKernelGGL(k_regrad_state, gb, tb, 0, st, n, abar, Ad, g, s, lo, hi, gr, phi, beta, part);
-        CK(hipGetLastError());
-        CK(hipMemcpyAsync(p, phi, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-        FETCH();
+        CK(fused(1, s));
+        SYNC();
       }
     } else {
       // proportioning step along the chopped gradient, kept inside the box
-      MATVEC(beta, Ad);
-      hipLaunchKernelGGL(k_dir, gb, tb, 0, st, n, s, gr, beta, Ad, lo, hi, part);
-      CK(hipGetLastError());
-      FETCH();
+      CK(fused(0, beta));
+      SYNC();
       const double dAd = hs[0], gd = hs[1], af = hs[kNV - 1];
       if (!(dAd > 0.0)) {
         negcurv = true;
         break;
       }
       const double a = fmin(gd / dAd, af);
-      // beta is rewritten by the new state: step along a copy in p
-      CK(hipMemcpyAsync(p, beta, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-      hipLaunchKernelGGL(k_step_state, gb, tb, 0, st, n, a, 1, abar, p, Ad, lo, hi, s, gr, phi, beta, part);
+      hipLaunchKernelGGL(k_step_state, ge, te, 0, st, n, a, 1, abar, beta, Ad, lo, hi, s, gr, phi, beta, p, red);
       CK(hipGetLastError());
-      CK(hipMemcpyAsync(p, phi, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-      FETCH();
+      SYNC();
     }
   }
   res->iterations = it;
@@ -307,8 +380,7 @@ hipError_t run_mprgp(int dim, int N, const double* S, const uint8_t* dir, const 
   }
   return hipSuccess;
 #undef CK
-#undef FETCH
-#undef MATVEC
+#undef SYNC
 }
 
 }  // namespace rmtr

@@ -16,6 +16,7 @@
 // keeps value k of its row block (k = (al 3^d + o)(d+1) + be) at
 //   S[(pbase[c] + 64 (t / 64)) RB + 64 k + t % 64],   RB = (d+1) 3^d (d+1).
 #include "rmtr_kernels.h"
+#include "stencil_layout.h"
 
 namespace rmtr {
 namespace {
@@ -23,18 +24,8 @@ namespace {
 constexpr int kB = 256;
 
 template <int DIM>
-constexpr int n_off() {
-  return DIM == 3 ? 27 : 9;
-}
-
-template <int DIM>
 constexpr int n_coef() {
   return 3 + DIM * DIM + DIM;  // vol, shear, Ccc, S (DIM x DIM), Pc (DIM)
-}
-
-template <int DIM>
-constexpr int row_block() {
-  return (DIM + 1) * n_off<DIM>() * (DIM + 1);
 }
 
 int gridn(int64_t work) {
@@ -42,61 +33,6 @@ int gridn(int64_t work) {
   if (b < 1) b = 1;
   if (b > 262140) b = 262140;
   return int(b);
-}
-
-// Colour geometry of one level.
-constexpr int kChunk = 64;  // nodes per stencil chunk (one wavefront)
-
-struct Colours {
-  int N;
-  int64_t cnt[8];    // nodes per colour
-  int64_t base[9];   // prefix sums of cnt
-  int64_t pbase[9];  // prefix sums of cnt rounded up to kChunk
-  int len[8][3];     // nodes per direction within a colour
-};
-
-Colours colours(int dim, int N) {
-  Colours g{};
-  g.N = N;
-  g.base[0] = 0;
-  g.pbase[0] = 0;
-  for (int c = 0; c < (1 << dim); ++c) {
-    int64_t n = 1;
-    for (int i = 0; i < dim; ++i) {
-      g.len[c][i] = (N - ((c >> i) & 1)) / 2 + 1;
-      n *= g.len[c][i];
-    }
-    g.cnt[c] = n;
-    g.base[c + 1] = g.base[c] + n;
-    g.pbase[c + 1] = g.pbase[c] + (n + kChunk - 1) / kChunk * kChunk;
-  }
-  return g;
-}
-
-// thread index -> (colour, index within colour, node coordinates, node id)
-template <int DIM>
-__device__ inline int locate(const Colours& g, int64_t id, int64_t& t, int (&c)[DIM], int64_t& n) {
-  int col = 0;
-#pragma unroll
-  for (int k = 1; k < (1 << DIM); ++k)
-    if (id >= g.base[k]) col = k;
-  t = id - g.base[col];
-  int64_t r = t, s = 1;
-  n = 0;
-#pragma unroll
-  for (int i = 0; i < DIM; ++i) {
-    c[i] = 2 * int(r % g.len[col][i]) + ((col >> i) & 1);
-    r /= g.len[col][i];
-    n += int64_t(c[i]) * s;
-    s *= (g.N + 1);
-  }
-  return col;
-}
-
-// start of the row block of node t of colour col; value k sits at + kChunk k
-template <int DIM>
-__device__ inline int64_t st_row(const Colours& g, int col, int64_t t) {
-  return (g.pbase[col] + (t & ~int64_t(kChunk - 1))) * row_block<DIM>() + (t & (kChunk - 1));
 }
 
 // Second-variation coefficients at the 2^DIM quadrature points of every
@@ -162,7 +98,11 @@ __global__ __launch_bounds__(kB) void k_coef(int N, double h, MatP<double> m, co
 // and towards missing neighbours), so no zeroing pass or read-modify-write
 // is needed.  Work items run al fastest: the four rows of a node share the
 // element coefficients they load, and consecutive nodes of a colour give
-// coalesced stores.
+// coalesced stores.  The lagged Hessian is symmetric: in 3D only the 14
+// blocks towards n itself and its upper neighbours (dz = 1; dz = 0 with
+// dy = 1, or dy = 0 and dx = 1) are summed, and each of the 13 off-diagonal
+// ones is stored twice, in n's row and, transposed, in the row of the
+// neighbour m = n + off(o) towards n (offset 26 - o).
 template <int DIM, typename TO>
 __device__ inline void st_node_item(const Colours& g, double h, double gcl_d, const TO* __restrict__ C,
                                     const uint8_t* __restrict__ dir, TO* __restrict__ S, int al, int64_t id,
@@ -250,8 +190,8 @@ __device__ inline void st_node_item(const Colours& g, double h, double gcl_d, co
               o += (((b >> i) & 1) - ((a >> i) & 1) + 1) * om;
               om *= 3;
             }
-            // 3D: blocks towards lower neighbours are the mirror image of
-            // blocks the neighbour computes (k_st_mirror fills them)
+            // 3D: blocks towards lower neighbours are the transposes of
+            // blocks the neighbour computes and stores for this node too
             if (DIM == 3 && pz == 1 && o < 4) continue;
             const T Nb = T(refN<DIM>(q, b));
             T dNb[DIM];
@@ -302,10 +242,31 @@ __device__ inline void st_node_item(const Colours& g, double h, double gcl_d, co
         s2 *= ns;
       }
       const uint8_t mcol = inside ? (dir ? dir[mid] : default_mask<DIM>(m, N)) : uint8_t(0xff);
+      // 3D: the value is also the transposed entry of neighbour m's row be
+      // towards n (offset 26 - of), which no work item computes
+      TO* tr = nullptr;
+      if (DIM == 3 && of > NO / 2 && inside) {
+        const int cm = (m[0] & 1) + 2 * (m[1] & 1) + 4 * (m[2 % DIM] & 1);
+        const int64_t tm = int64_t(m[0] >> 1) + int64_t(g.len[cm][0]) *
+                                                    (int64_t(m[1] >> 1) + int64_t(g.len[cm][1]) * (m[2 % DIM] >> 1));
+        tr = S + st_row<DIM>(g, cm, tm) + int64_t((NO - 1 - of) * NC + al) * kChunk;
+      }
 #pragma unroll
       for (int be = 0; be < NC; ++be) {
         const T v = (row_fixed || ((mcol >> be) & 1u)) ? T(0) : acc[o][be];
         out[((al * NO + of) * NC + be) * kChunk] = TO(v);
+        if (tr) tr[int64_t(be * NO * NC) * kChunk] = TO(v);
+      }
+    }
+    // 3D: blocks towards missing lower neighbours get no transposed value;
+    // the plane-1 item writes them as zero
+    if (DIM == 3 && pz == 1) {
+#pragma unroll
+      for (int k = 0; k < NO / 2; ++k) {
+        const int d0 = c[0] + k % 3 - 1, d1 = c[1] + (k / 3) % 3 - 1, d2 = c[2 % DIM] + k / 9 - 1;
+        if (d0 >= 0 && d0 <= N && d1 >= 0 && d1 <= N && d2 >= 0 && d2 <= N) continue;
+#pragma unroll
+        for (int be = 0; be < NC; ++be) out[((al * NO + k) * NC + be) * kChunk] = TO(0);
       }
     }
   }
@@ -336,7 +297,7 @@ __global__ __launch_bounds__(kB) void k_st_node(Colours g, double h, double gcl,
       const int inner = int(k % 24);
       const int col = inner & 7, pz = inner >> 3;
       const int64_t t = (x + 8 * (k / 24)) * kChunk + (threadIdx.x >> 2);
-      // plane dz = -1 holds mirror images only
+      // plane dz = -1 holds transposes of blocks computed elsewhere only
       if (pz > 0 && t < g.cnt[col]) st_node_item<DIM, TO>(g, h, gcl, C, dir, S, al, g.base[col] + t, pz);
     }
   } else {
@@ -345,44 +306,6 @@ __global__ __launch_bounds__(kB) void k_st_node(Colours g, double h, double gcl,
       const int al = int(it % NC);
       const int64_t r1 = it / NC;
       st_node_item<DIM, TO>(g, h, gcl, C, dir, S, al, r1 % nodes, int(r1 / nodes));
-    }
-  }
-}
-
-// The stencil is symmetric: the block of row node n towards neighbour
-// m = n + off(k) is the transpose of m's block towards n (offset 26 - k).
-// k_st_node computes the 14 blocks towards n itself and its upper
-// neighbours (dz = 1; dz = 0 with dy = 1, or dy = 0 and dx = 1); this pass
-// fills the other 13 from the neighbours' rows.  Thread per (node, row al);
-// Dirichlet rows and columns are zero on both sides already, and blocks
-// towards missing neighbours are written as zero.
-template <typename TO>
-__global__ __launch_bounds__(kB) void k_st_mirror(Colours g, TO* __restrict__ S) {
-  constexpr int NC = 4, NO = 27;
-  const int N = g.N;
-  const int64_t nodes = g.base[8];
-  for (int64_t it = int64_t(blockIdx.x) * kB + threadIdx.x; it < nodes * NC; it += int64_t(gridDim.x) * kB) {
-    const int al = int(it % NC);
-    const int64_t id = it / NC;
-    int64_t t, n;
-    int c[3];
-    const int col = locate<3>(g, id, t, c, n);
-    TO* out = S + st_row<3>(g, col, t);
-#pragma unroll
-    for (int k = 0; k < 13; ++k) {
-      const int m[3] = {c[0] + k % 3 - 1, c[1] + (k / 3) % 3 - 1, c[2] + k / 9 - 1};
-      const bool inside = m[0] >= 0 && m[0] <= N && m[1] >= 0 && m[1] <= N && m[2] >= 0 && m[2] <= N;
-      TO v[NC] = {TO(0), TO(0), TO(0), TO(0)};
-      if (inside) {
-        const int cm = (m[0] & 1) + 2 * (m[1] & 1) + 4 * (m[2] & 1);
-        const int64_t tm = int64_t(m[0] >> 1) +
-                           int64_t(g.len[cm][0]) * (int64_t(m[1] >> 1) + int64_t(g.len[cm][1]) * (m[2] >> 1));
-        const TO* src = S + st_row<3>(g, cm, tm);
-#pragma unroll
-        for (int be = 0; be < NC; ++be) v[be] = src[((be * NO + (26 - k)) * NC + al) * kChunk];
-      }
-#pragma unroll
-      for (int be = 0; be < NC; ++be) out[((al * NO + k) * NC + be) * kChunk] = v[be];
     }
   }
 }
@@ -607,41 +530,32 @@ __global__ __launch_bounds__(kB) void k_em_to_st(Colours g, const double* __rest
   }
 }
 
-// y = H v: thread per row (node, al); the rows of one component al form
-// consecutive work items, so lanes read consecutive stencil values.
+// y = H v: a workgroup takes 64 consecutive rows of the al-major work order
+// (so lanes read consecutive stencil values) and gives each of the three
+// neighbour planes of the rows to one wavefront; the plane sums are added
+// in LDS in a fixed order.
+constexpr int kMvB = 3 * kChunk;
+
 template <int DIM, typename T>
-__global__ __launch_bounds__(kB) void k_st_mv(Colours g, const T* __restrict__ S, const T* __restrict__ v,
-                                              T* __restrict__ y) {
-  constexpr int NC = DIM + 1, NO = n_off<DIM>(), RB = row_block<DIM>();
-  const int N = g.N;
-  const int64_t nodes = g.base[1 << DIM];
-  const int64_t ns = N + 1;
-  for (int64_t it = int64_t(blockIdx.x) * kB + threadIdx.x; it < nodes * NC; it += int64_t(gridDim.x) * kB) {
-    const int64_t id = it % nodes;
-    const int al = int(it / nodes);
-    int64_t t, n;
-    int c[DIM];
-    const int col = locate<DIM>(g, id, t, c, n);
-    const T* Sn = S + st_row<DIM>(g, col, t) + al * NO * NC * kChunk;
+__global__ __launch_bounds__(kMvB) void k_st_mv(Colours g, const T* __restrict__ S, const T* __restrict__ v,
+                                                T* __restrict__ y) {
+  constexpr int NC = DIM + 1;
+  __shared__ T part[2][kChunk];
+  const int64_t nodes = g.base[1 << DIM], rows = nodes * NC;
+  const int lane = threadIdx.x % kChunk, pl = threadIdx.x / kChunk;
+  for (int64_t r0 = int64_t(blockIdx.x) * kChunk; r0 < rows; r0 += int64_t(gridDim.x) * kChunk) {
+    const int64_t it = r0 + lane;
     T acc = T(0);
-#pragma unroll
-    for (int o = 0; o < NO; ++o) {
-      int64_t m = 0, st = 1;
-      bool ok = true;
-      int oo = o;
-#pragma unroll
-      for (int i = 0; i < DIM; ++i) {
-        const int mi = c[i] + oo % 3 - 1;
-        oo /= 3;
-        ok &= (mi >= 0) & (mi <= N);
-        m += int64_t(mi) * st;
-        st *= ns;
-      }
-      if (!ok) continue;
-#pragma unroll
-      for (int be = 0; be < NC; ++be) acc += Sn[(o * NC + be) * kChunk] * v[NC * m + be];
+    int64_t n = 0;
+    int al = 0;
+    if (it < rows) {
+      al = int(it / nodes);
+      acc = st_row_plane<DIM>(g, S, v, it % nodes, al, pl, n);
     }
-    y[NC * n + al] = acc;
+    if (pl > 0) part[pl - 1][lane] = acc;
+    __syncthreads();
+    if (pl == 0 && it < rows) y[NC * n + al] = (acc + part[0][lane]) + part[1][lane];
+    __syncthreads();
   }
 }
 
@@ -799,8 +713,6 @@ static hipError_t st_assemble_t(const ElemArgs& a, const double* xl, const doubl
   constexpr int NP = DIM == 3 ? 3 : 1;
   const int64_t work = g.base[NL] * NC * NP;
   hipLaunchKernelGGL((k_st_node<DIM, TO>), dim3(gridn(work)), dim3(kB), 0, st, g, a.h, gcl, cf, a.dir, S);
-  if constexpr (DIM == 3)
-    hipLaunchKernelGGL(k_st_mirror<TO>, dim3(gridn(g.base[NL] * NC)), dim3(kB), 0, st, g, S);
   return hipGetLastError();
 }
 
@@ -832,18 +744,20 @@ hipError_t launch_em_to_st(int dim, int N, const double* K, void* S, int fp32, h
 
 hipError_t launch_st_matvec(int dim, int N, const void* S, const void* v, void* y, int fp32, hipStream_t st) {
   const Colours g = colours(dim, N);
-  const dim3 gd(gridn(g.base[1 << dim] * (dim + 1)));
+  int64_t nb = (g.base[1 << dim] * (dim + 1) + kChunk - 1) / kChunk;
+  if (nb > 262140) nb = 262140;
+  const dim3 gd(static_cast<uint32_t>(nb)), tb(kMvB);
   if (dim == 3) {
     if (fp32)
-      hipLaunchKernelGGL((k_st_mv<3, float>), gd, dim3(kB), 0, st, g, (const float*)S, (const float*)v, (float*)y);
+      hipLaunchKernelGGL((k_st_mv<3, float>), gd, tb, 0, st, g, (const float*)S, (const float*)v, (float*)y);
     else
-      hipLaunchKernelGGL((k_st_mv<3, double>), gd, dim3(kB), 0, st, g, (const double*)S, (const double*)v,
+      hipLaunchKernelGGL((k_st_mv<3, double>), gd, tb, 0, st, g, (const double*)S, (const double*)v,
                          (double*)y);
   } else {
     if (fp32)
-      hipLaunchKernelGGL((k_st_mv<2, float>), gd, dim3(kB), 0, st, g, (const float*)S, (const float*)v, (float*)y);
+      hipLaunchKernelGGL((k_st_mv<2, float>), gd, tb, 0, st, g, (const float*)S, (const float*)v, (float*)y);
     else
-      hipLaunchKernelGGL((k_st_mv<2, double>), gd, dim3(kB), 0, st, g, (const double*)S, (const double*)v,
+      hipLaunchKernelGGL((k_st_mv<2, double>), gd, tb, 0, st, g, (const double*)S, (const double*)v,
                          (double*)y);
   }
   return hipGetLastError();
