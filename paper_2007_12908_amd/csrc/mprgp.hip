@@ -6,10 +6,9 @@
 // row-parallel pass over contiguous rows.  The
 // host drives the iteration and reads two sets of reduced scalars per
 // iteration.  The products A d are fused with the row-local work that
-// consumes them, and every reduction ends in the kernel that produces it:
-// each workgroup writes its partial sums, and the last workgroup to finish
-// adds all partials in a fixed order and writes the scalars to host-mapped
-// memory, so the scalars (and the branch taken) do not depend on scheduling.
+// consumes them; each workgroup writes its partial sums, and a
+// one-workgroup kernel adds them in a fixed order into host-mapped memory,
+// so the scalars (and the branch taken) do not depend on scheduling.
 #include <math.h>
 
 #include "rmtr_kernels.h"
@@ -61,36 +60,14 @@ __device__ inline void block_reduce(double (&v)[kNV], double (*sh)[kNV]) {
     }
 }
 
-// Workgroup partials of v, then in the last workgroup to arrive the
-// fixed-order sum of all partials into out[0 .. kNV) (host-mapped); the
-// counter is left at zero for the next pass.
+// workgroup partials of v at partials[kNV blockIdx.x + k]
 template <int NW>
-__device__ inline void reduce_to_host(double (&v)[kNV], double* __restrict__ partials, unsigned* ctr,
-                                      double* out) {
+__device__ inline void block_partials(double (&v)[kNV], double* __restrict__ partials) {
   __shared__ double sh[NW][kNV];
-  __shared__ int last;
   block_reduce<NW>(v, sh);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0)
 #pragma unroll
     for (int k = 0; k < kNV; ++k) partials[kNV * blockIdx.x + k] = v[k];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const unsigned prev = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    last = prev == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!last) return;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  vinit(v);
-  for (int b = threadIdx.x; b < int(gridDim.x); b += NW * 64)
-#pragma unroll
-    for (int k = 0; k < kNV; ++k) v[k] = vop(k, v[k], partials[kNV * b + k]);
-  __syncthreads();  // sh is reused
-  block_reduce<NW>(v, sh);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < kNV; ++k) out[k] = v[k];
-    __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
 }
 
 __global__ __launch_bounds__(kB) void k_final(const double* __restrict__ partials, int nb, double* __restrict__ out) {
@@ -133,21 +110,15 @@ __device__ inline void state_terms(double abar, double si, double gi, double l, 
   if (Ad) v[3] += f * Ad[i];
 }
 
-struct Red {
-  double* partials;
-  unsigned* ctr;
-  double* out;
-};
-
 __global__ __launch_bounds__(kB) void k_state(int64_t n, double abar, const double* __restrict__ s,
                                               const double* __restrict__ gr, const double* __restrict__ lo,
                                               const double* __restrict__ hi, double* __restrict__ phi,
-                                              double* __restrict__ beta, double* __restrict__ p, Red red) {
+                                              double* __restrict__ beta, double* __restrict__ p, double* __restrict__ partials) {
   double v[kNV];
   vinit(v);
   for (int64_t i = int64_t(blockIdx.x) * kB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kB)
     state_terms(abar, s[i], gr[i], lo[i], hi[i], phi, beta, p, i, nullptr, v);
-  reduce_to_host<kB / 64>(v, red.partials, red.ctr, red.out);
+  block_partials<kB / 64>(v, partials);
 }
 
 // Fused product and row-local pass over the rows of A (al-major order, 64
@@ -162,7 +133,7 @@ __global__ __launch_bounds__(kMvB) void k_mv_fused(Colours cg, const double* __r
                                                    double* __restrict__ gr, const double* __restrict__ lo,
                                                    const double* __restrict__ hi, double abar,
                                                    double* __restrict__ phi, double* __restrict__ beta,
-                                                   double* __restrict__ p, Red red) {
+                                                   double* __restrict__ p, double* __restrict__ partials) {
   constexpr int NC = DIM + 1;
   __shared__ double part[2][kChunk];
   const int64_t nodes = cg.base[1 << DIM], rows = nodes * NC;
@@ -198,7 +169,7 @@ __global__ __launch_bounds__(kMvB) void k_mv_fused(Colours cg, const double* __r
     }
     __syncthreads();
   }
-  reduce_to_host<kMvB / 64>(v, red.partials, red.ctr, red.out);
+  block_partials<kMvB / 64>(v, partials);
 }
 
 // s -= a d (clipped to the box if clip); gr -= a Ad; then the state sums
@@ -208,7 +179,7 @@ __global__ __launch_bounds__(kB) void k_step_state(int64_t n, double a, int clip
                                                    const double* __restrict__ Ad, const double* __restrict__ lo,
                                                    const double* __restrict__ hi, double* __restrict__ s,
                                                    double* __restrict__ gr, double* __restrict__ phi, double* beta,
-                                                   double* p, Red red) {
+                                                   double* p, double* __restrict__ partials) {
   double v[kNV];
   vinit(v);
   for (int64_t i = int64_t(blockIdx.x) * kB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kB) {
@@ -219,7 +190,7 @@ __global__ __launch_bounds__(kB) void k_step_state(int64_t n, double a, int clip
     gr[i] = gi;
     state_terms(abar, si, gi, lo[i], hi[i], phi, beta, p, i, Ad, v);
   }
-  reduce_to_host<kB / 64>(v, red.partials, red.ctr, red.out);
+  block_partials<kB / 64>(v, partials);
 }
 
 // expansion step: s -= af p, then s = P(s - abar phi(s, gr - af Ap))
@@ -263,10 +234,6 @@ hipError_t run_mprgp(int dim, int N, const double* S, const uint8_t* dir, const 
   double* p = beta + n;
   double* Ad = p + n;
   double* part = Ad + n;
-  // arrival counter of the in-kernel reductions (zero between passes)
-  double* ctr_slot = part + kNV * kMaxBlocks;
-  unsigned* ctr = reinterpret_cast<unsigned*>(ctr_slot);
-  const Red red{part, ctr, hs};
   const Colours cg = colours(dim, N);
   const dim3 ge(nblocks(n, kB)), te(kB);
   const dim3 gm(nblocks(n, kChunk)), tm(kMvB);
@@ -276,20 +243,22 @@ hipError_t run_mprgp(int dim, int N, const double* S, const uint8_t* dir, const 
     e = (x);                       \
     if (e != hipSuccess) return e; \
   } while (0)
-  // the scalars of a pass are written straight into the (mapped, coherent)
-  // host memory hs; the synchronisation makes them visible
-#define SYNC() CK(hipStreamSynchronize(st))
+  // the final sum of a pass's nbk partials is written straight into the
+  // (mapped, coherent) host memory hs; the synchronisation makes it visible
+#define FETCH(nbk)                                                       \
+  do {                                                                   \
+    hipLaunchKernelGGL(k_final, dim3(1), te, 0, st, part, int(nbk), hs); \
+    CK(hipGetLastError());                                               \
+    CK(hipStreamSynchronize(st));                                        \
+  } while (0)
   res->iterations = 0;
   res->status = 1;
   CK(launch_fill(n, 0.0, s, st));
-  CK(launch_fill(1, 0.0, ctr_slot, st));
   // ||A|| bound and ||b||
   {
     int nbr = 0;
     CK(launch_st_rowabs(dim, N, S, g, part, &nbr, st));
-    hipLaunchKernelGGL(k_final, dim3(1), te, 0, st, part, nbr, hs);
-    CK(hipGetLastError());
-    SYNC();
+    FETCH(nbr);
   }
   const double normA = -hs[kNV - 1];
   const double bnorm = sqrt(hs[0]);
@@ -305,25 +274,25 @@ hipError_t run_mprgp(int dim, int N, const double* S, const uint8_t* dir, const 
     if (dim == 3) {
       if (mode == 0)
         hipLaunchKernelGGL((k_mv_fused<3, 0>), gm, tm, 0, st, cg, S, dv, Ad, g, s, gr, lo, hi, abar, phi, beta, p,
-                           red);
+                           part);
       else
         hipLaunchKernelGGL((k_mv_fused<3, 1>), gm, tm, 0, st, cg, S, dv, Ad, g, s, gr, lo, hi, abar, phi, beta, p,
-                           red);
+                           part);
     } else {
       if (mode == 0)
         hipLaunchKernelGGL((k_mv_fused<2, 0>), gm, tm, 0, st, cg, S, dv, Ad, g, s, gr, lo, hi, abar, phi, beta, p,
-                           red);
+                           part);
       else
         hipLaunchKernelGGL((k_mv_fused<2, 1>), gm, tm, 0, st, cg, S, dv, Ad, g, s, gr, lo, hi, abar, phi, beta, p,
-                           red);
+                           part);
     }
     return hipGetLastError();
   };
   // s = 0: gr = A s - b = g; p = phi
   CK(hipMemcpyAsync(gr, g, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-  hipLaunchKernelGGL(k_state, ge, te, 0, st, n, abar, s, gr, lo, hi, phi, beta, p, red);
+  hipLaunchKernelGGL(k_state, ge, te, 0, st, n, abar, s, gr, lo, hi, phi, beta, p, part);
   CK(hipGetLastError());
-  SYNC();
+  FETCH(ge.x);
   int it = 0;
   bool negcurv = false;
   while (it < max_it) {
@@ -335,7 +304,7 @@ hipError_t run_mprgp(int dim, int N, const double* S, const uint8_t* dir, const 
     ++it;
     if (bb <= pf) {
       CK(fused(0, p));
-      SYNC();
+      FETCH(gm.x);
       const double pAp = hs[0], gp = hs[1], af = hs[kNV - 1];
       if (!(pAp > 0.0)) {
         negcurv = true;
@@ -344,9 +313,9 @@ hipError_t run_mprgp(int dim, int N, const double* S, const uint8_t* dir, const 
       const double acg = gp / pAp;
       if (acg <= af) {
         hipLaunchKernelGGL(k_step_state, ge, te, 0, st, n, acg, 0, abar, p, Ad, lo, hi, s, gr, phi, beta,
-                           (double*)nullptr, red);
+                           (double*)nullptr, part);
         CK(hipGetLastError());
-        SYNC();
+        FETCH(ge.x);
         const double bet = hs[3] / pAp;
         hipLaunchKernelGGL(k_pupd, ge, te, 0, st, n, bet, phi, p);
         CK(hipGetLastError());
@@ -354,21 +323,21 @@ hipError_t run_mprgp(int dim, int N, const double* S, const uint8_t* dir, const 
         hipLaunchKernelGGL(k_expand, ge, te, 0, st, n, af, abar, p, Ad, lo, hi, s, gr);
         CK(hipGetLastError());
         CK(fused(1, s));
-        SYNC();
+        FETCH(gm.x);
       }
     } else {
       // proportioning step along the chopped gradient, kept inside the box
       CK(fused(0, beta));
-      SYNC();
+      FETCH(gm.x);
       const double dAd = hs[0], gd = hs[1], af = hs[kNV - 1];
       if (!(dAd > 0.0)) {
         negcurv = true;
         break;
       }
       const double a = fmin(gd / dAd, af);
-      hipLaunchKernelGGL(k_step_state, ge, te, 0, st, n, a, 1, abar, beta, Ad, lo, hi, s, gr, phi, beta, p, red);
+      hipLaunchKernelGGL(k_step_state, ge, te, 0, st, n, a, 1, abar, beta, Ad, lo, hi, s, gr, phi, beta, p, part);
       CK(hipGetLastError());
-      SYNC();
+      FETCH(ge.x);
     }
   }
   res->iterations = it;
@@ -380,7 +349,7 @@ hipError_t run_mprgp(int dim, int N, const double* S, const uint8_t* dir, const 
   }
   return hipSuccess;
 #undef CK
-#undef SYNC
+#undef FETCH
 }
 
 }  // namespace rmtr
