@@ -70,7 +70,11 @@ __device__ inline void block_partials(double (&v)[kNV], double* __restrict__ par
     for (int k = 0; k < kNV; ++k) partials[kNV * blockIdx.x + k] = v[k];
 }
 
-__global__ __launch_bounds__(kB) void k_final(const double* __restrict__ partials, int nb, double* __restrict__ out) {
+// fixed-order sum of nb partials into out[0 .. kNV) (host-mapped), then the
+// pass's sequence number q into *seq (host-mapped), released at system
+// scope after the sums
+__global__ __launch_bounds__(kB) void k_final(const double* __restrict__ partials, int nb, double* __restrict__ out,
+                                              unsigned long long* seq, unsigned long long q) {
   __shared__ double sh[kB / 64][kNV];
   double v[kNV];
   vinit(v);
@@ -78,9 +82,11 @@ __global__ __launch_bounds__(kB) void k_final(const double* __restrict__ partial
 #pragma unroll
     for (int k = 0; k < kNV; ++k) v[k] = vop(k, v[k], partials[kNV * i + k]);
   block_reduce<kB / 64>(v, sh);
-  if (threadIdx.x == 0)
+  if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < kNV; ++k) out[k] = v[k];
+    __hip_atomic_store(seq, q, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 __device__ inline bool is_free(double s, double lo, double hi) { return s > lo && s < hi; }
@@ -213,6 +219,16 @@ __global__ __launch_bounds__(kB) void k_pupd(int64_t n, double bet, const double
     p[i] = phi[i] - bet * p[i];
 }
 
+// Wait until k_final has published sequence number q: a bounded busy wait on
+// the host-mapped word, which ends sooner than a stream synchronisation for
+// these short passes; after the bound the stream is synchronised, so a failed
+// launch still reports its error.
+hipError_t wait_for(const unsigned long long* seq, unsigned long long q, hipStream_t st) {
+  for (int i = 0; i < (1 << 22); ++i)
+    if (__atomic_load_n(seq, __ATOMIC_ACQUIRE) == q) return hipSuccess;
+  return hipStreamSynchronize(st);
+}
+
 }  // namespace
 
 size_t mprgp_work_doubles(int dim, int N) {
@@ -244,12 +260,16 @@ hipError_t run_mprgp(int dim, int N, const double* S, const uint8_t* dir, const 
     if (e != hipSuccess) return e; \
   } while (0)
   // the final sum of a pass's nbk partials is written straight into the
-  // (mapped, coherent) host memory hs; the synchronisation makes it visible
-#define FETCH(nbk)                                                       \
-  do {                                                                   \
-    hipLaunchKernelGGL(k_final, dim3(1), te, 0, st, part, int(nbk), hs); \
-    CK(hipGetLastError());                                               \
-    CK(hipStreamSynchronize(st));                                        \
+  // (mapped, coherent) host memory hs[0 .. kNV), followed by the pass's
+  // sequence number in hs[8]
+  unsigned long long* seq = reinterpret_cast<unsigned long long*>(hs + 8);
+  unsigned long long q = __atomic_load_n(seq, __ATOMIC_ACQUIRE);
+#define FETCH(nbk)                                                                  \
+  do {                                                                              \
+    ++q;                                                                            \
+    hipLaunchKernelGGL(k_final, dim3(1), te, 0, st, part, int(nbk), hs, seq, q);    \
+    CK(hipGetLastError());                                                          \
+    CK(wait_for(seq, q, st));                                                       \
   } while (0)
   res->iterations = 0;
   res->status = 1;

@@ -98,12 +98,14 @@ hipError_t launch_clamp(int64_t n, const double* lo, const double* hi, double* s
 hipError_t launch_inject_scalar(int dim, int Nc, const double* fine, double* coarse, hipStream_t st);
 hipError_t launch_any_nonzero(int64_t n, const double* v, int* flag, hipStream_t st);
 
-// ---- MPRGP (mprgp_kernels.hip)
+// ---- MPRGP (mprgp.hip)
 struct MprgpResult {
   int iterations;
   int status;  // 0 converged, 1 max iterations, 2 negative curvature (fallback applied)
 };
-// S: the level's assembled block stencil (FP64)
+// S: the level's assembled block stencil (FP64); host_scalars: at least 10
+// doubles of host-mapped coherent memory (slots 0-4 take reduced scalars,
+// slot 8 a pass sequence word)
 hipError_t run_mprgp(int dim, int N, const double* S, const uint8_t* dir, const double* g, const double* lo,
                      const double* hi, double* s, int max_it, double rtol, int fallback_sweeps, double* work,
                      double* host_scalars, MprgpResult* res, hipStream_t st);
