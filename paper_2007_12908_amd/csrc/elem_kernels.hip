@@ -484,11 +484,12 @@ template <int MODE, typename T>
 static hipError_t launch_scatter(const ElemArgs& a, const T* x, const T* p, const T* v, T* out, hipStream_t st) {
   if (a.dim == 3) {
     const int tiles = (a.N + 1 + kOwn - 1) / kOwn;
-    // one workgroup per compute unit (FP64), two (FP32); at least 4 node
-    // layers per workgroup
+    // one workgroup per compute unit (FP64), two (FP32); a coarse level with
+    // fewer node layers than that gets one layer per workgroup (latency, not
+    // the recomputed element layer, bounds it there)
     const int64_t work = int64_t(tiles) * tiles * (a.N + 1);
     int64_t nb = int64_t(compute_units()) * (sizeof(T) == 4 ? 2 : 1);
-    nb = std::max<int64_t>(1, std::min(nb, work / 4));
+    nb = std::max<int64_t>(1, std::min(nb, work));
     if constexpr (sizeof(T) == 4)
       hipLaunchKernelGGL((k_elem_scatter3_f32<MODE>), dim3(unsigned(nb)), dim3(256), 0, st, a.N, T(a.h), a.m, tiles,
                          a.dir, x, p, v, out);
