@@ -67,6 +67,8 @@ struct rmtr_ctx {
   size_t rap_cap = 0;
   double* op_st = nullptr;      // stencil scratch of rmtr_mprgp
   size_t op_cap = 0;
+  double* op_work = nullptr;    // iteration vectors of rmtr_mprgp
+  size_t op_work_cap = 0;
   std::vector<void*> allocs;
   std::string err;
 };
@@ -748,10 +750,7 @@ rmtr_status rmtr_init_fields(rmtr_ctx* c, int32_t level, const double* table, in
   if (p_mode == 1 && c->model.dim != 3) return fail(c, RMTR_E_ARG, "rmtr_init_fields: per-fracture p needs 3D");
   const int cols = c->model.dim == 3 ? 8 : 7;
   const size_t need = size_t(n_frac) * cols + 1;
-  if (need > c->table_cap) {
-    HIPCHK(c, dalloc(c, &c->table, need));
-    c->table_cap = need;
-  }
+  HIPCHK(c, grow(c, &c->table, &c->table_cap, need));
   if (n_frac > 0)
     HIPCHK(c, hipMemcpyAsync(c->table, table, size_t(n_frac) * cols * sizeof(double), hipMemcpyHostToDevice, S(stream)));
   HIPCHK(c, launch_init_fields(c->model.dim, c->lv[level].N, c->table, n_frac, band, p_mode, p_value, p_band, c0, p,
@@ -909,13 +908,12 @@ rmtr_status rmtr_mprgp(rmtr_ctx* c, int32_t level, const double* K, const double
     return fail(c, RMTR_E_ARG, "rmtr_mprgp: bad arguments");
   rmtr_status r = ensure_common(c);
   if (r != RMTR_OK) return r;
-  double* work = nullptr;
-  HIPCHK(c, dalloc(c, &work, mprgp_work_doubles(c->model.dim, c->lv[level].N)));
+  HIPCHK(c, grow(c, &c->op_work, &c->op_work_cap, mprgp_work_doubles(c->model.dim, c->lv[level].N)));
   HIPCHK(c, grow(c, &c->op_st, &c->op_cap, stencil_values(c->model.dim, c->lv[level].N)));
   HIPCHK(c, launch_em_to_st(c->model.dim, c->lv[level].N, K, c->op_st, 0, S(stream)));
   MprgpResult res;
   HIPCHK(c, run_mprgp(c->model.dim, c->lv[level].N, c->op_st, nullptr, g, lo, hi, s, max_it, rtol, fallback_sweeps,
-                      work, c->hs + 48, &res, S(stream)));
+                      c->op_work, c->hs + 48, &res, S(stream)));
   HIPCHK(c, hipStreamSynchronize(S(stream)));
   if (iterations) *iterations = res.iterations;
   if (status) *status = res.status;
