@@ -242,8 +242,8 @@ __device__ inline void st_node_item(const Colours& g, double h, double gcl_d, co
         s2 *= ns;
       }
       const uint8_t mcol = inside ? (dir ? dir[mid] : default_mask<DIM>(m, N)) : uint8_t(0xff);
-      // 3D: the value is also the transposed entry of neighbour m's row be
-      // towards n (offset 26 - of), which no work item computes
+      // 3D: the value is also entry (be, 26 - of, al) of neighbour m's row
+      // block, a lower block that m's own work items skip
       TO* tr = nullptr;
       if (DIM == 3 && of > NO / 2 && inside) {
         const int cm = (m[0] & 1) + 2 * (m[1] & 1) + 4 * (m[2 % DIM] & 1);
