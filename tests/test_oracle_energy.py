@@ -252,3 +252,29 @@ def test_local_rows_match_global():
     HV = fem.hessvec(g, x, p, mat, np.where(g.default_dirichlet(), 0.0, v))
     assert np.allclose(gr, G[want], rtol=1e-13, atol=1e-17)
     assert np.allclose(hv, HV[want], rtol=1e-13, atol=1e-17)
+
+
+@pytest.mark.parametrize("d,N", [(2, 3), (3, 2)])
+def test_energy_difference_is_a_difference_and_matches_taylor(d, N):
+    """The per-element energy difference f(x + s) - f(x) equals the difference
+    of the two totals up to rounding, and, on the unsplit (smooth) density,
+    differs from the FD-pinned second-order model g^T s + 1/2 s^T H s by a
+    third-order term: halving the step divides the gap by about 8."""
+    g = fem.Grid(d, N)
+    mat = _mat(False, N)
+    rng = np.random.default_rng(2024 + d)
+    x = rng.standard_normal(g.n_dofs) * 0.1
+    x.reshape(-1, d + 1)[:, d] = rng.uniform(0.0, 1.0, g.n_nodes)
+    p = rng.uniform(0.5, 1.5, g.n_nodes) * 0.05
+    nodir = np.zeros(g.n_dofs, bool)
+    gr = fem.gradient(g, x, p, mat, nodir)
+    H = fem.hessian(g, x, p, mat, nodir)
+    v = rng.standard_normal(g.n_dofs)
+    f0 = fem.energy(g, x, p, mat)
+    gaps = []
+    for eps in (2e-3, 1e-3):
+        s = eps * v
+        de = fem.energy_diff(g, x, s, p, mat)
+        assert abs(de - (fem.energy(g, x + s, p, mat) - f0)) <= 1e-13 * abs(f0)
+        gaps.append(abs(de - (gr @ s + 0.5 * s @ (H @ s))))
+    assert gaps[1] > 0 and 7.0 <= gaps[0] / gaps[1] <= 9.0
