@@ -104,3 +104,29 @@ def test_pgs_nonpositive_curvature_moves_to_better_bound():
     # dof 0: m(t) = 0.5 t - 0.5 t^2: m(-1) = -1, m(2) = -1 -> tie -> lo
     # dof 1: m(t) = -0.25 t: best at hi = 1
     assert s[0] == -1.0 and s[1] == 1.0
+
+
+def test_mprgp_negative_curvature_falls_back_to_separable_minimiser():
+    """On a separable QP with indefinite diagonal H the first CG direction
+    has p^T H p < 0: MPRGP must report it, and the PGS fallback must land on
+    the closed-form box minimiser (per coordinate: clamp(-g/h) where h > 0,
+    else the bound with the lower value g t + h t^2 / 2)."""
+    from scipy.sparse import diags
+    h = np.array([2.0, -1.0, 0.5, -3.0, 1.0, 0.0])
+    gv = np.array([0.1, 1.0, -0.2, -2.0, 0.3, 0.4])
+    lo = np.array([-1.0, -1.0, -0.1, -1.0, -2.0, -0.5])
+    hi = np.array([1.0, 1.0, 0.3, 1.0, 2.0, 0.25])
+    H = diags(h).tocsr()
+    want = np.empty(h.size)
+    for i in range(h.size):
+        if h[i] > 0:
+            want[i] = min(max(-gv[i] / h[i], lo[i]), hi[i])
+        else:
+            m = lambda t: gv[i] * t + 0.5 * h[i] * t * t  # noqa: E731
+            want[i] = hi[i] if m(hi[i]) < m(lo[i]) else lo[i]
+    blocks = [np.array([i]) for i in range(h.size)]
+    s, its, status = qp.mprgp(H, gv, lo, hi, rtol=1e-12, max_it=100,
+                              fallback=lambda s0: qp.pgs(H, gv, lo, hi, s0, blocks, 1))
+    assert status == "negative_curvature" and its == 1
+    assert np.allclose(s, want, rtol=0, atol=1e-15)
+    assert qp.model_value(H, gv, s) < 0.0
