@@ -170,7 +170,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "decomposition is not part of this build.", file=sys.stderr)
+              "decomposition is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
