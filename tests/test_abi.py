@@ -65,3 +65,21 @@ def test_nn_sizes_without_gpu():
     assert nw + nb == 121124
     assert lib.rmtr_nn_size(2, 3, 4, 5) == 60 * sum(cnn.CHANNELS)
     assert lib.rmtr_nn_size(2, 0, 4, 5) == -1 and lib.rmtr_nn_size(7, 1, 1, 1) == -1
+
+
+def test_host_arrays_are_refused_without_a_fallback():
+    """The product path has no CPU fallback: host tensors are refused before
+    the library is called (no GPU call is made)."""
+    import torch
+    from paper_2007_12908_amd import binding
+    assert binding._ptr(None) is None
+    with pytest.raises(ValueError, match="device tensors"):
+        binding._ptr(torch.zeros(4, dtype=torch.float64))
+    ctx = binding.Context(3, 4, 2, 1.0, 1.0, 1e-3, 0.5)
+    x = torch.zeros(4 * 5 ** 3, dtype=torch.float64)
+    p = torch.zeros(5 ** 3, dtype=torch.float64)
+    out = torch.zeros(1, dtype=torch.float64)
+    for call in (lambda: ctx.energy(2, x, p, out=out), lambda: ctx.gradient(2, x, p, out=torch.zeros_like(x)),
+                 lambda: ctx.hessvec(2, x, p, x, out=torch.zeros_like(x))):
+        with pytest.raises(ValueError, match="device tensors"):
+            call()
