@@ -36,9 +36,11 @@
  *     that return host values synchronise that stream.
  *   - Errors: no exception crosses this interface.  A negative status means
  *     the outputs are undefined; rmtr_last_error() describes the failure.
- *   - The library allocates its own device workspace (on first use of an
- *     operation on a level) and frees it in rmtr_destroy().  A context is not
- *     thread safe.
+ *   - Device workspace: by default the library allocates its buffers on
+ *     first use of an operation on a level and frees them in rmtr_destroy().
+ *     A caller that owns the memory binds one buffer instead
+ *     (rmtr_workspace_bytes, rmtr_bind_workspace) and the library then makes
+ *     no device allocation.  A context is not thread safe.
  */
 #ifndef RMTR_H
 #define RMTR_H
@@ -57,6 +59,7 @@ typedef int32_t rmtr_status;
 #define RMTR_NOT_CONVERGED 1 /* warning: outputs valid, tolerance not met */
 #define RMTR_E_ARG (-1)
 #define RMTR_E_HIP (-2)
+#define RMTR_E_WORKSPACE (-3) /* the bound workspace is too small for the call */
 #define RMTR_E_NONFINITE (-4)
 
 #define RMTR_FP64 0
@@ -111,12 +114,18 @@ typedef struct {
   int32_t shrink_to_step;  /* 0: Alg. 3 as printed, delta <- gamma1 delta on
                               rejection; 1: delta <- gamma1 min(delta,
                               |s|_inf) (the radius follows the rejected step) */
+  int32_t gs_mode;         /* Gauss-Seidel order of the smoother (Sec. 3.2.1,
+                              Sec. 4.2.2): 0 = global 2^d node colours (the
+                              sequential order within a colour); 1 = the
+                              hybrid Jacobi/Gauss-Seidel over tiles, not built
+                              (RMTR_E_ARG) */
 } rmtr_params;
 
 typedef struct {
   int32_t vcycles, tr_accepted, tr_rejected, status;
   double chi0, chi, energy, seconds;
   int32_t nn_proposed, nn_accepted; /* learned proposals made / accepted */
+  double delta;                     /* finest-level TR radius at the end */
 } rmtr_stats;
 
 /* Fills p with the defaults used throughout: eta = (0.1, 0.75),
@@ -133,6 +142,27 @@ void rmtr_destroy(rmtr_ctx* ctx);
 const char* rmtr_last_error(const rmtr_ctx* ctx);
 /* Nodes of level `level` ((N_l+1)^d), or -1 for an invalid level. */
 int64_t rmtr_level_nodes(const rmtr_ctx* ctx, int32_t level);
+
+/* Caller-owned device workspace (host-only computation, no GPU call).
+   rmtr_workspace_bytes(ctx, params): bytes of device memory that
+   rmtr_solve_loadstep with these parameters needs on a fresh context
+   (precision and use_learned matter), which also covers every later
+   rmtr_energy, rmtr_energy_diff, rmtr_gradient, rmtr_hessvec,
+   rmtr_diag_blocks, rmtr_restrict, rmtr_prolong, rmtr_dot and rmtr_chi
+   call; params == NULL: the bytes those calls alone need.  The other entry
+   points (rmtr_smooth, rmtr_coarse_hessvec, rmtr_mprgp, rmtr_step_box,
+   rmtr_init_fields, the rmtr_nn_* calls) carve their scratch from what is
+   left and return RMTR_E_WORKSPACE when it does not fit.
+   rmtr_bind_workspace: from now on every device buffer of the context is
+   carved, in call order, from [dev, dev + bytes) (256-byte aligned, device
+   memory owned by the caller, kept alive until rmtr_destroy); the library
+   makes no device allocation.  Bind once, before the context's first device
+   call (RMTR_E_ARG otherwise).  A few hundred bytes of pinned host memory for
+   returned scalars are still allocated on first use.
+   rmtr_workspace_used: bytes carved so far. */
+size_t rmtr_workspace_bytes(const rmtr_ctx* ctx, const rmtr_params* params);
+rmtr_status rmtr_bind_workspace(rmtr_ctx* ctx, void* dev, size_t bytes);
+size_t rmtr_workspace_used(const rmtr_ctx* ctx);
 
 /* Nodal inclusion initialisation (Sec. 5, first paragraph; Sec. 5.2):
    c0[n] = 1 if node n lies inside a fracture's volumetric description
@@ -190,14 +220,6 @@ rmtr_status rmtr_restrict(rmtr_ctx* ctx, int32_t fine_level, int32_t mode, const
 rmtr_status rmtr_prolong(rmtr_ctx* ctx, int32_t coarse_level, const void* coarse, void* fine, int32_t precision,
                          void* stream);
 
-/* Galerkin coarse Hessian (eq. (delta_terms): R grad^2 h I) as one dense
-   ((d+1) 2^d)^2 row-major FP64 matrix per element of level coarse_level,
-   Dirichlet rows/columns zero.  If coarse_level == L-1 it is built from the
-   matrix-free Hessian at x_lin (fine p, fine Dirichlet mask); otherwise from
-   the element matrices K_fine of level coarse_level+1 (x_lin, p, dirichlet
-   ignored). */
-rmtr_status rmtr_galerkin(rmtr_ctx* ctx, int32_t coarse_level, const double* x_lin, const double* p,
-                          const uint8_t* dirichlet, const double* K_fine, double* K_coarse, void* stream);
 /* Hv with the Galerkin coarse Hessian of `level` < L as the load step
    builds it (eq. (delta_terms), Alg. 1, lagged at x_lin): the finest-level
    Hessian at x_lin (FP64 x_lin and p; stored FP64, or FP32 if precision is
@@ -208,12 +230,6 @@ rmtr_status rmtr_galerkin(rmtr_ctx* ctx, int32_t coarse_level, const double* x_l
 rmtr_status rmtr_coarse_hessvec(rmtr_ctx* ctx, int32_t level, const double* x_lin, const double* p,
                                 const uint8_t* dirichlet, const double* v, double* Hv, int32_t precision,
                                 void* stream);
-
-/* Hv and symmetric PGS with element matrices K of `level` (FP64). */
-rmtr_status rmtr_em_hessvec(rmtr_ctx* ctx, int32_t level, const double* K, const double* v, double* Hv,
-                            void* stream);
-rmtr_status rmtr_em_smooth(rmtr_ctx* ctx, int32_t level, const double* K, const double* g, const double* lo,
-                           const double* hi, double* s_inout, int32_t n_sweeps, void* stream);
 
 /* MPRGP (Sec. 3.2.1, coarsest level) for min g^T s + 1/2 s^T K s,
    lo <= s <= hi, from s = 0.  iterations/status (host, may be NULL):
@@ -319,6 +335,24 @@ rmtr_status rmtr_nn_to_bf16(rmtr_ctx* ctx, int64_t n, const float* master, uint1
    scales[k] (k < 4), g[4 n + k - 4] / rms(g_{k-4}) * scales[k] (k >= 4). */
 rmtr_status rmtr_nn_features(rmtr_ctx* ctx, int32_t level, const double* x, const double* g, const float* scales,
                              float* in8, void* stream);
+
+/* rms[k] = root mean square of component k of the nodal 4-vector v over
+   the level's nodes (4 device doubles; 3D levels). */
+rmtr_status rmtr_nn_channel_rms(rmtr_ctx* ctx, int32_t level, const double* v, double* rms, void* stream);
+
+/* Training target of a harvested step s at gradient g (the inverse of the
+   proposal's output scaling): t[4 n + k] = s[4 n + k] / (scales[8+k]
+   rms(g_k)), 0 where the denominator vanishes; t FP32. */
+rmtr_status rmtr_nn_target(rmtr_ctx* ctx, int32_t level, const double* g, const double* s, const float* scales,
+                           float* t, void* stream);
+
+/* Normalisation constants of the network from n_samples harvested (x, g, s)
+   triples of `level` (x, g, s: host arrays of n_samples device pointers):
+   scales[k] = 1 / mean rms(x_k), scales[4+k] = 1 (g enters divided by its
+   own RMS), scales[8+k] = mean over samples of rms(s_k) / rms(g_k) (0 for a
+   sample with rms(g_k) = 0); a constant that comes out 0 is set to 1. */
+rmtr_status rmtr_nn_fit_scales(rmtr_ctx* ctx, int32_t level, int32_t n_samples, const double* const* x,
+                               const double* const* g, const double* const* s, float* scales, void* stream);
 
 /* Proposed step of `level` (3D): features of (x, g), forward pass, output
    channel k times scales[8+k] rms(g_k), projected onto [lo, hi] (non-finite

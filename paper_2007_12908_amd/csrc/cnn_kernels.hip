@@ -409,6 +409,38 @@ __global__ __launch_bounds__(kB) void k_proposal(int64_t n, const float* __restr
   }
 }
 
+// Training target: t = s_k / (sc[8 + k] rms(g)_k), 0 where that vanishes
+// (the inverse of the output scaling of k_proposal).
+__global__ __launch_bounds__(kB) void k_target(int64_t n, const double* __restrict__ s,
+                                               const float* __restrict__ sc, const double* __restrict__ rms,
+                                               float* __restrict__ t) {
+  for (int64_t i = int64_t(blockIdx.x) * kB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kB) {
+    const double den = double(sc[8 + i % 4]) * rms[i % 4];
+    t[i] = den > 0.0 ? float(s[i] / den) : 0.0f;
+  }
+}
+
+// Normalisation constants from the per-sample RMS values r[12 i + j]
+// (j < 4: state x, 4..7: gradient g, 8..11: step s) of ns samples, in sample
+// order: sc[k] = 1 / mean_i rms(x_k), sc[4 + k] = 1 (g is divided by its own
+// RMS at run time), sc[8 + k] = mean_i rms(s_k) / rms(g_k) (samples with
+// rms(g_k) = 0 count as 0); a constant that comes out 0 becomes 1.
+__global__ void k_fit_scales(int ns, const double* __restrict__ r, float* __restrict__ sc) {
+  const int k = threadIdx.x;
+  if (k >= 4) return;
+  double xs = 0.0, ratio = 0.0;
+  for (int i = 0; i < ns; ++i) {
+    xs += r[12 * i + k];
+    const double rg = r[12 * i + 4 + k];
+    ratio += rg > 0.0 ? r[12 * i + 8 + k] / rg : 0.0;
+  }
+  xs /= double(ns);
+  ratio /= double(ns);
+  sc[k] = xs > 0.0 ? float(1.0 / xs) : 1.0f;
+  sc[4 + k] = 1.0f;
+  sc[8 + k] = ratio > 0.0 ? float(ratio) : 1.0f;
+}
+
 int gridn(int64_t work) {
   int64_t b = (work + kB - 1) / kB;
   if (b < 1) b = 1;
@@ -586,6 +618,16 @@ hipError_t nn_features(int64_t nn, const double* x, const double* g, const float
 hipError_t nn_proposal(int64_t n, const float* out, const float* scales, const double* rms, const double* lo,
                        const double* hi, double* s, hipStream_t st) {
   hipLaunchKernelGGL(k_proposal, dim3(gridn(n)), dim3(kB), 0, st, n, out, scales, rms, lo, hi, s);
+  return hipGetLastError();
+}
+
+hipError_t nn_target(int64_t n, const double* s, const float* scales, const double* rms, float* t, hipStream_t st) {
+  hipLaunchKernelGGL(k_target, dim3(gridn(n)), dim3(kB), 0, st, n, s, scales, rms, t);
+  return hipGetLastError();
+}
+
+hipError_t nn_fit_scales(int ns, const double* rms_samples, float* scales, hipStream_t st) {
+  hipLaunchKernelGGL(k_fit_scales, dim3(1), dim3(64), 0, st, ns, rms_samples, scales);
   return hipGetLastError();
 }
 

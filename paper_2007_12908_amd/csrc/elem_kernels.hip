@@ -454,12 +454,17 @@ hipError_t launch_reduce_partials(const double* partials, int n, double* out, hi
   return hipGetLastError();
 }
 
-hipError_t launch_energy(const ElemArgs& a, const double* x, const void* s, int s_fp32, const double* p,
-                         double* partials, double* out, hipStream_t st) {
-  int64_t ne = int64_t(a.N) * a.N * (a.dim == 3 ? a.N : 1);
-  int nb = int((ne + kBlock - 1) / kBlock);
+int energy_partials(const ElemArgs& a) {
+  const int64_t ne = int64_t(a.N) * a.N * (a.dim == 3 ? a.N : 1);
+  int64_t nb = (ne + kBlock - 1) / kBlock;
   if (nb > kMaxPartials) nb = kMaxPartials;
   if (nb < 1) nb = 1;
+  return int(nb);
+}
+
+hipError_t launch_energy(const ElemArgs& a, const double* x, const void* s, int s_fp32, const double* p,
+                         double* partials, double* out, hipStream_t st) {
+  const int nb = energy_partials(a);
   if (a.dim == 3) {
     if (s_fp32)
       hipLaunchKernelGGL((k_energy<3, float>), dim3(nb), dim3(kBlock), 0, st, a.N, a.h, a.m, x, (const float*)s, p,

@@ -37,7 +37,7 @@ struct Level {
   float* Sf = nullptr;      // the same in FP32 (finest level, mixed precision)
   double* coef = nullptr;   // per-element second-variation coefficients (finest level)
   size_t coef_cap = 0;      // doubles held by coef (FP32 coefficients take half)
-  double* Sop = nullptr;    // stencil scratch of rmtr_smooth / rmtr_em_smooth
+  double* Sop = nullptr;    // stencil scratch of rmtr_smooth / rmtr_coarse_hessvec
   float* Sopf = nullptr;
   double* coefop = nullptr;
   bool solver_ready = false;
@@ -58,7 +58,6 @@ struct rmtr_ctx {
   double* table = nullptr;
   size_t table_cap = 0;
   double* mprgp_work = nullptr;
-  double* fineq_tab = nullptr;  // coarse basis at fine quadrature points
   double* box_tmp = nullptr;    // bounds scratch of rmtr_step_box
   size_t box_cap = 0;
   float* nn_buf = nullptr;      // inference tensors of the proposal network
@@ -69,7 +68,13 @@ struct rmtr_ctx {
   size_t op_cap = 0;
   double* op_work = nullptr;    // iteration vectors of rmtr_mprgp
   size_t op_work_cap = 0;
+  double* fit_buf = nullptr;    // per-sample RMS values of rmtr_nn_fit_scales
+  size_t fit_cap = 0;
   std::vector<void*> allocs;
+  // caller-bound workspace (rmtr_bind_workspace): every device buffer is
+  // carved from it in order and nothing is allocated
+  char* ws = nullptr;
+  size_t ws_bytes = 0, ws_used = 0;
   std::string err;
 };
 
@@ -82,17 +87,34 @@ rmtr_status fail(rmtr_ctx* c, rmtr_status s, const std::string& msg) {
   return s;
 }
 
+// A shortfall of a bound workspace surfaces as hipErrorOutOfMemory from
+// dalloc and is reported as RMTR_E_WORKSPACE.
 #define HIPCHK(ctx, expr)                                                                        \
   do {                                                                                           \
     hipError_t e__ = (expr);                                                                     \
-    if (e__ != hipSuccess)                                                                       \
+    if (e__ != hipSuccess) {                                                                     \
+      if (e__ == hipErrorOutOfMemory && (ctx)->ws)                                               \
+        return fail(ctx, RMTR_E_WORKSPACE, std::string(#expr) + ": bound workspace too small");  \
       return fail(ctx, RMTR_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e__));         \
+    }                                                                                            \
   } while (0)
+
+// Bytes one buffer of `bytes` takes: 256 bytes of slack past the end (vector
+// loads of a last partial chunk stay inside the allocation), rounded up to
+// the 256-byte alignment every buffer starts at.
+size_t buf_bytes(size_t bytes) { return (bytes + 256 + 255) & ~size_t(255); }
 
 template <typename T>
 hipError_t dalloc(rmtr_ctx* c, T** p, size_t count) {
+  const size_t bytes = buf_bytes(count * sizeof(T));
+  if (c->ws) {
+    if (c->ws_used + bytes > c->ws_bytes) return hipErrorOutOfMemory;
+    *p = reinterpret_cast<T*>(c->ws + c->ws_used);
+    c->ws_used += bytes;
+    return hipSuccess;
+  }
   void* q = nullptr;
-  hipError_t e = hipMalloc(&q, count * sizeof(T) + 256);
+  hipError_t e = hipMalloc(&q, bytes);
   if (e != hipSuccess) return e;
   c->allocs.push_back(q);
   *p = static_cast<T*>(q);
@@ -123,10 +145,6 @@ rmtr_status ensure_common(rmtr_ctx* c) {
   HIPCHK(c, hipHostMalloc(&h, kScal * sizeof(double) + 64, hipHostMallocCoherent));
   c->hs = static_cast<double*>(h);
   c->hflag = reinterpret_cast<int*>(c->hs + kScal);
-  std::vector<double> tab;
-  galerkin_fineq_table(c->model.dim, tab);
-  HIPCHK(c, dalloc(c, &c->fineq_tab, tab.size()));
-  HIPCHK(c, hipMemcpy(c->fineq_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
   return RMTR_OK;
 }
 
@@ -155,15 +173,45 @@ rmtr_status ensure_solver_level(rmtr_ctx* c, int l, bool mixed) {
   return RMTR_OK;
 }
 
+// Device bytes of the buffers above: the common scalars and reduction
+// partials, and (with a load step) everything rmtr_solve_loadstep allocates
+// for its hierarchy, in the same sizes and rounding as dalloc.
+size_t common_bytes() {
+  return buf_bytes(kMaxPartials * sizeof(double)) + buf_bytes(kScal * sizeof(double)) + buf_bytes(4 * sizeof(int));
+}
+
+size_t loadstep_bytes(const rmtr_ctx* c, bool mixed, bool learned) {
+  const int d = c->model.dim, L = c->L;
+  size_t b = common_bytes();
+  for (int l = 1; l <= L; ++l) {
+    const Level& v = c->lv[l];
+    b += 15 * buf_bytes(size_t(v.n) * sizeof(double)) + buf_bytes(size_t(v.nodes) * sizeof(double));
+    const bool f32 = mixed && l == L && L > 1;
+    b += buf_bytes(stencil_values(d, v.N) * (f32 ? sizeof(float) : sizeof(double)));
+    if (mixed && l == L) b += 5 * buf_bytes(size_t(v.n) * sizeof(float)) + buf_bytes(size_t(v.nodes) * sizeof(float));
+  }
+  b += buf_bytes(mprgp_work_doubles(d, c->lv[1].N) * sizeof(double));
+  const bool fine32 = mixed && L > 1;
+  if (L > 1) b += buf_bytes(st_rap_work_doubles(d, c->lv[L].N, fine32 ? 1 : 0) * sizeof(double));
+  const size_t cv = coef_values(d, c->lv[L].N);
+  b += buf_bytes((fine32 ? (cv + 1) / 2 : cv) * sizeof(double));
+  if (learned) b += buf_bytes(size_t(c->lv[L].nodes) * (8 + 32 + 32 + 4) * sizeof(float));
+  return b;
+}
+
 // grows a context-owned buffer, freeing the previous one
 template <typename T>
 hipError_t grow(rmtr_ctx* c, T** buf, size_t* cap, size_t count) {
   if (*cap >= count) return hipSuccess;
   if (*buf) {
-    for (auto& a : c->allocs)
-      if (a == *buf) a = nullptr;
-    hipError_t e = hipFree(*buf);
-    if (e != hipSuccess) return e;
+    // a buffer carved from a bound workspace stays where it is (its space is
+    // not reused); an allocated one is freed
+    if (!c->ws) {
+      for (auto& a : c->allocs)
+        if (a == *buf) a = nullptr;
+      hipError_t e = hipFree(*buf);
+      if (e != hipSuccess) return e;
+    }
     *buf = nullptr;
     *cap = 0;
   }
@@ -690,6 +738,7 @@ void rmtr_default_params(rmtr_params* p) {
   p->coarse_model = 0;
   p->nn_patience = 3;
   p->shrink_to_step = 0;
+  p->gs_mode = 0;
 }
 
 rmtr_status rmtr_create(const rmtr_model* m, rmtr_ctx** out) {
@@ -768,6 +817,26 @@ rmtr_status rmtr_energy(rmtr_ctx* c, int32_t level, const double* x, const doubl
   return RMTR_OK;
 }
 
+size_t rmtr_workspace_bytes(const rmtr_ctx* c, const rmtr_params* prm) {
+  if (!c) return 0;
+  if (!prm) return common_bytes();
+  return loadstep_bytes(c, prm->precision == RMTR_FP32, prm->use_learned != 0);
+}
+
+rmtr_status rmtr_bind_workspace(rmtr_ctx* c, void* dev, size_t bytes) {
+  if (!c) return RMTR_E_ARG;
+  if (!dev || bytes == 0 || (reinterpret_cast<uintptr_t>(dev) & 255u) != 0)
+    return fail(c, RMTR_E_ARG, "rmtr_bind_workspace: needs a non-empty, 256-byte aligned device buffer");
+  if (c->ws || c->partials || !c->allocs.empty())
+    return fail(c, RMTR_E_ARG, "rmtr_bind_workspace: bind once, before the context's first device call");
+  c->ws = static_cast<char*>(dev);
+  c->ws_bytes = bytes;
+  c->ws_used = 0;
+  return RMTR_OK;
+}
+
+size_t rmtr_workspace_used(const rmtr_ctx* c) { return c ? c->ws_used : 0; }
+
 rmtr_status rmtr_energy_diff(rmtr_ctx* c, int32_t level, const double* x, const void* s, int32_t s_precision,
                              const double* p, double* out, void* stream) {
   if (!valid_level(c, level) || !x || !s || !p || !out) return fail(c, RMTR_E_ARG, "rmtr_energy_diff: bad arguments");
@@ -837,22 +906,6 @@ rmtr_status rmtr_prolong(rmtr_ctx* c, int32_t coarse_level, const void* coarse, 
   return RMTR_OK;
 }
 
-rmtr_status rmtr_galerkin(rmtr_ctx* c, int32_t coarse_level, const double* xl, const double* p, const uint8_t* dir,
-                          const double* Kf, double* Kc, void* stream) {
-  if (!valid_level(c, coarse_level) || coarse_level >= c->L || !Kc)
-    return fail(c, RMTR_E_ARG, "rmtr_galerkin: bad arguments");
-  if (coarse_level == c->L - 1) {
-    if (!xl || !p) return fail(c, RMTR_E_ARG, "rmtr_galerkin: x_lin and p needed below the finest level");
-    rmtr_status r = ensure_common(c);
-    if (r != RMTR_OK) return r;
-    HIPCHK(c, launch_galerkin_from_matfree(eargs(c, c->L, dir), xl, p, Kc, 0, nullptr, c->fineq_tab, S(stream)));
-  } else {
-    if (!Kf) return fail(c, RMTR_E_ARG, "rmtr_galerkin: K_fine needed");
-    HIPCHK(c, launch_galerkin_from_em(c->model.dim, c->lv[coarse_level].N, Kf, Kc, nullptr, S(stream)));
-  }
-  return RMTR_OK;
-}
-
 rmtr_status rmtr_coarse_hessvec(rmtr_ctx* c, int32_t level, const double* xl, const double* p, const uint8_t* dir,
                                 const double* v, double* hv, int32_t precision, void* stream) {
   if (!valid_level(c, level) || level >= c->L || !xl || !p || !v || !hv || v == hv)
@@ -881,23 +934,6 @@ rmtr_status rmtr_coarse_hessvec(rmtr_ctx* c, int32_t level, const double* xl, co
     src32 = 0;
   }
   HIPCHK(c, launch_st_matvec(d, c->lv[level].N, c->lv[level].Sop, v, hv, 0, S(stream)));
-  return RMTR_OK;
-}
-
-rmtr_status rmtr_em_hessvec(rmtr_ctx* c, int32_t level, const double* K, const double* v, double* hv, void* stream) {
-  if (!valid_level(c, level) || !K || !v || !hv || v == hv) return fail(c, RMTR_E_ARG, "rmtr_em_hessvec: bad arguments");
-  HIPCHK(c, launch_em_hessvec(c->model.dim, c->lv[level].N, K, v, hv, nullptr, 0, S(stream)));
-  return RMTR_OK;
-}
-
-rmtr_status rmtr_em_smooth(rmtr_ctx* c, int32_t level, const double* K, const double* g, const double* lo,
-                           const double* hi, double* s, int32_t n_sweeps, void* stream) {
-  if (!valid_level(c, level) || !K || !g || !lo || !hi || !s || n_sweeps < 0)
-    return fail(c, RMTR_E_ARG, "rmtr_em_smooth: bad arguments");
-  Level& v = c->lv[level];
-  if (!v.Sop) HIPCHK(c, dalloc(c, &v.Sop, stencil_values(c->model.dim, v.N)));
-  HIPCHK(c, launch_em_to_st(c->model.dim, v.N, K, v.Sop, 0, S(stream)));
-  HIPCHK(c, launch_st_pgs(c->model.dim, v.N, v.Sop, nullptr, g, lo, hi, s, n_sweeps, 0, S(stream)));
   return RMTR_OK;
 }
 
@@ -951,6 +987,8 @@ rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lo
       prm->eta1 > prm->eta2 || !(prm->gamma1 > 0.0) || prm->gamma1 > 1.0 || prm->gamma2 < 1.0 ||
       !(prm->delta0 > 0.0))
     return fail(c, RMTR_E_ARG, "rmtr_solve_loadstep: invalid parameters");
+  if (prm->gs_mode != 0)
+    return fail(c, RMTR_E_ARG, "rmtr_solve_loadstep: only gs_mode 0 (global node colours) is built");
   if (prm->use_learned &&
       (c->model.dim != 3 || c->L < 2 || !prm->nn || !prm->nn->w || !prm->nn->bias || !prm->nn->scales))
     return fail(c, RMTR_E_ARG, "rmtr_solve_loadstep: the learned proposal needs 3D, L >= 2 and a network");
@@ -1028,6 +1066,7 @@ rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lo
   out.tr_rejected = run.rejected;
   out.nn_proposed = run.nn_proposed;
   out.nn_accepted = run.nn_accepted;
+  out.delta = delta;
   out.status = (chi0 == 0.0 || out.chi <= prm->rtol * chi0) ? RMTR_OK : RMTR_NOT_CONVERGED;
   out.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (stats) *stats = out;
@@ -1117,6 +1156,46 @@ rmtr_status rmtr_nn_features(rmtr_ctx* c, int32_t level, const double* x, const 
   double* rms = c->scal + 40;
   HIPCHK(c, nn_grad_rms(c->lv[level].nodes, g, c->partials, rms, S(stream)));
   HIPCHK(c, nn_features(c->lv[level].nodes, x, g, scales, rms, in8, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_nn_channel_rms(rmtr_ctx* c, int32_t level, const double* v, double* rms, void* stream) {
+  if (!valid_level(c, level) || c->model.dim != 3 || !v || !rms)
+    return fail(c, RMTR_E_ARG, "rmtr_nn_channel_rms: bad arguments (3D only)");
+  rmtr_status r = ensure_common(c);
+  if (r != RMTR_OK) return r;
+  HIPCHK(c, nn_grad_rms(c->lv[level].nodes, v, c->partials, rms, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_nn_target(rmtr_ctx* c, int32_t level, const double* g, const double* s, const float* scales,
+                           float* t, void* stream) {
+  if (!valid_level(c, level) || c->model.dim != 3 || !g || !s || !scales || !t)
+    return fail(c, RMTR_E_ARG, "rmtr_nn_target: bad arguments (3D only)");
+  rmtr_status r = ensure_common(c);
+  if (r != RMTR_OK) return r;
+  double* rms = c->scal + 40;
+  HIPCHK(c, nn_grad_rms(c->lv[level].nodes, g, c->partials, rms, S(stream)));
+  HIPCHK(c, nn_target(c->lv[level].n, s, scales, rms, t, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_nn_fit_scales(rmtr_ctx* c, int32_t level, int32_t n_samples, const double* const* x,
+                               const double* const* g, const double* const* s, float* scales, void* stream) {
+  if (!valid_level(c, level) || c->model.dim != 3 || n_samples < 1 || !x || !g || !s || !scales)
+    return fail(c, RMTR_E_ARG, "rmtr_nn_fit_scales: bad arguments (3D only)");
+  for (int i = 0; i < n_samples; ++i)
+    if (!x[i] || !g[i] || !s[i]) return fail(c, RMTR_E_ARG, "rmtr_nn_fit_scales: null sample");
+  rmtr_status r = ensure_common(c);
+  if (r != RMTR_OK) return r;
+  HIPCHK(c, grow(c, &c->fit_buf, &c->fit_cap, size_t(12) * n_samples));
+  const int64_t nn = c->lv[level].nodes;
+  for (int i = 0; i < n_samples; ++i) {
+    HIPCHK(c, nn_grad_rms(nn, x[i], c->partials, c->fit_buf + 12 * i, S(stream)));
+    HIPCHK(c, nn_grad_rms(nn, g[i], c->partials, c->fit_buf + 12 * i + 4, S(stream)));
+    HIPCHK(c, nn_grad_rms(nn, s[i], c->partials, c->fit_buf + 12 * i + 8, S(stream)));
+  }
+  HIPCHK(c, nn_fit_scales(n_samples, c->fit_buf, scales, S(stream)));
   return RMTR_OK;
 }
 

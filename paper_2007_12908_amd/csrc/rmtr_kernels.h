@@ -22,6 +22,8 @@ struct ElemArgs {
 };
 
 // ---- element kernels (elem_kernels.hip)
+// workgroups of the energy kernel = partial sums it writes (<= kMaxPartials)
+int energy_partials(const ElemArgs& a);
 hipError_t launch_energy(const ElemArgs& a, const double* x, const void* s, int s_fp32, const double* p,
                          double* partials, double* out, hipStream_t st);
 hipError_t launch_gradient(const ElemArgs& a, const double* x, const double* p, double* g, hipStream_t st);
@@ -30,20 +32,6 @@ hipError_t launch_hessvec(const ElemArgs& a, const void* xl, const void* p, cons
 hipError_t launch_diag_blocks(const ElemArgs& a, const void* xl, const void* p, void* D, int fp32,
                               hipStream_t st);
 hipError_t launch_reduce_partials(const double* partials, int n, double* out, hipStream_t st);
-
-// ---- element-matrix (Galerkin) operators (galerkin_kernels.hip)
-// same_level: element matrices of the level's own Hessian (no coarsening);
-// dirc: Dirichlet mask of the output level (null: default set).
-// fineq_tab: coarse basis values/gradients at the fine quadrature points
-// (galerkin_fineq_table), used on the fast path (default Dirichlet sets).
-hipError_t launch_galerkin_from_matfree(const ElemArgs& fine, const double* xl, const double* p,
-                                        double* Kc, int same_level, const uint8_t* dirc,
-                                        const double* fineq_tab, hipStream_t st);
-void galerkin_fineq_table(int dim, std::vector<double>& out);
-hipError_t launch_galerkin_from_em(int dim, int Nc, const double* Kf, double* Kc, const uint8_t* dirc,
-                                   hipStream_t st);
-hipError_t launch_em_hessvec(int dim, int N, const void* K, const void* v, void* hv, const uint8_t* dir,
-                             int fp32, hipStream_t st);
 
 // ---- assembled block stencils (stencil_kernels.hip)
 size_t stencil_values(int dim, int N);
@@ -134,5 +122,9 @@ hipError_t nn_features(int64_t nn, const double* x, const double* g, const float
                        float* feat, hipStream_t st);
 hipError_t nn_proposal(int64_t n, const float* out, const float* scales, const double* rms, const double* lo,
                        const double* hi, double* s, hipStream_t st);
+// training target s_k / (scales[8+k] rms_k) of a step s (n values, 4 per node)
+hipError_t nn_target(int64_t n, const double* s, const float* scales, const double* rms, float* t, hipStream_t st);
+// the 12 normalisation constants from ns samples' RMS values (12 per sample)
+hipError_t nn_fit_scales(int ns, const double* rms_samples, float* scales, hipStream_t st);
 
 }  // namespace rmtr

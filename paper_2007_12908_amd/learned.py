@@ -12,8 +12,8 @@ GPU through the library's own forward, backward, loss and Adam kernels
 projected onto the step box and must pass the FP64 trust-region ratio test;
 the smoother is the fallback (rmtr_solve_loadstep with use_learned).
 
-Torch is used for device memory, copies between buffers and the per-channel
-RMS normalisation constants of the harvested data.
+Torch is used for device memory and copies between buffers; the
+normalisation constants, features and targets are library calls.
 """
 import ctypes
 import time
@@ -99,25 +99,13 @@ def harvest_run(ctx, x, p, c_lower, n_states, sweeps=3, params=None, dirichlet=N
     return out
 
 
-def channel_rms(t):
-    v = t.view(-1, 4)
-    return v.pow(2).mean(0).sqrt()
-
-
-def fit_scales(net, samples):
-    """Normalisation constants: x channels by their RMS over the samples;
-    g enters divided by its own per-component RMS (done by the library), so
-    its scale is 1; output channel k is scaled by the mean ratio
+def fit_scales(net, samples, level=None):
+    """Normalisation constants (rmtr_nn_fit_scales): x channels by their RMS
+    over the samples; g enters divided by its own per-component RMS, so its
+    scale is 1; output channel k is scaled by the mean ratio
     rms(s_k) / rms(g_k) of the samples (and, at run time, by rms(g_k))."""
-    xs = torch.stack([channel_rms(x) for x, _, _ in samples]).mean(0)
-    ratios = []
-    for _, g, s in samples:
-        rg, rs = channel_rms(g), channel_rms(s)
-        ratios.append(torch.where(rg > 0, rs / torch.where(rg > 0, rg, torch.ones_like(rg)), torch.zeros_like(rg)))
-    ss = torch.stack(ratios).mean(0)
-    one = torch.ones_like(xs)
-    xs, ss = (torch.where(t > 0, t, one) for t in (xs, ss))
-    net.scales.copy_(torch.cat([1.0 / xs, one, ss]).float())
+    ctx = net.ctx
+    ctx.nn_fit_scales(ctx.L if level is None else level, samples, net.scales)
 
 
 class Trainer:
@@ -139,13 +127,10 @@ class Trainer:
 
     def add(self, samples):
         """Scaled features and targets of (x, g, s) samples (after fit_scales):
-        the target of channel k is s_k / (scale_k rms(g_k))."""
+        the target of channel k is s_k / (scale_k rms(g_k)) (rmtr_nn_target)."""
         for x, g, s in samples:
             feat = self.ctx.nn_features(self.level, x, g, self.net.scales)
-            rg = channel_rms(g)
-            den = self.net.scales[8:].double() * rg
-            inv = torch.where(den > 0, 1.0 / torch.where(den > 0, den, torch.ones_like(den)), torch.zeros_like(den))
-            tgt = (s.view(-1, 4) * inv).float().reshape(-1).contiguous()
+            tgt = self.ctx.nn_target(self.level, g, s, self.net.scales)
             self.data.append((feat, tgt))
 
     def forward_loss(self, i):

@@ -2,21 +2,26 @@
 pass (weight and bias gradients), Adam step, BF16 rounding and input
 features, through the C-ABI.
 
-The forward convolutions run on the matrix cores with BF16 operands: the
-oracle rounds each layer's input to BF16 the same way and sums in FP64.
-Layer by layer (the oracle convolving the GPU's own FP32 layer input) the
-only difference is FP32 accumulation order: 2e-6 of the largest output.
-End to end, an FP32 activation next to a BF16 rounding boundary can round
-the other way on the two sides and the difference (one BF16 step, 2^-8
-relative) feeds more such flips downstream, so whole-network outputs agree
-only to BF16 level: 5e-3 in RMS and 3e-2 at the worst voxel.  The backward
-pass is pinned layer by layer the same way: the oracle differentiates the
-GPU's own activations (weight and data gradients from BF16 layer inputs and
-output gradients as on the matrix cores, bias gradients in full
-precision).  Bias gradients agree to 1e-4 of the largest entry of each
-layer; weight gradients to 2e-3, since an output gradient computed in FP32
-on the GPU and in FP64 by the oracle can still round to neighbouring BF16
-values (one flip moves a sum of n products by about 2^-8 / sqrt(n))."""
+Primary check, against the plain FP64 network (BF16 weights, the
+configured parameter precision, and FP64 activations, products and sums):
+whole-network outputs, losses and the proposal within 1e-2 relative (the
+BF16 tolerance of the learned form), gradients within 1e-2 normwise over the
+whole parameter vector on boxes of realistic size (thousands of voxels per
+sum).  The matrix-core instruction multiplies BF16 operands, so activations
+and output gradients are rounded to BF16 (8-bit significand) on their way
+into each product; that rounding, not an error, is what separates the two
+and is what these tolerances allow for.
+
+Secondary, tight checks (the same rounding applied by the oracle to the
+GPU's own layer inputs, layer by layer): the only difference left is FP32
+accumulation order, 2e-6 of the largest output.  The backward pass is
+pinned layer by layer the same way: the oracle differentiates the GPU's own
+activations with BF16 layer inputs and output gradients as on the matrix
+cores (bias gradients in full precision).  Bias gradients agree to 1e-4 of
+the largest entry of each layer; weight gradients to 2e-3, since an output
+gradient computed in FP32 on the GPU and in FP64 by the oracle can still
+round to neighbouring BF16 values (one flip moves a sum of n products by
+about 2^-8 / sqrt(n))."""
 import numpy as np
 import pytest
 
@@ -99,11 +104,11 @@ def test_forward_matches_oracle(box):
         if l < len(pq) - 1:
             ref = np.maximum(ref, 0.0)
         assert np.abs(layer[l + 1] - ref).max() <= 2e-6 * np.abs(ref).max(), l
-    # whole network
-    ref, _ = cnn.forward(pq, x, bf16_inputs=True)
+    # whole network against the plain FP64 network (unrounded activations)
+    ref, _ = cnn.forward(pq, x)
     diff = layer[6] - ref
-    assert np.sqrt(np.mean(diff ** 2)) <= 5e-3 * np.sqrt(np.mean(ref ** 2))
-    assert np.abs(diff).max() <= 3e-2 * np.abs(ref).max()
+    assert np.sqrt(np.mean(diff ** 2)) <= 1e-2 * np.sqrt(np.mean(ref ** 2))
+    assert np.abs(diff).max() <= 1e-2 * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("box", BOXES)
@@ -152,9 +157,17 @@ def test_loss_and_backward_match_oracle(box):
         sb = max(np.abs(rb).max(), 1e-30)
         assert np.abs(dW - rW).max() <= 2e-3 * sw, (l, np.abs(dW - rW).max() / sw)
         assert np.abs(db - rb).max() <= 1e-4 * sb, (l, np.abs(db - rb).max() / sb)
-    # whole network against the oracle's own forward pass: BF16 level
-    loss_e2e, _ = cnn.loss_and_grads(pq, x, tq, window, bf16_inputs=True)
-    assert abs(ref_loss - loss_e2e) <= 3e-2 * loss_e2e
+    # whole network against the plain FP64 network (unrounded activations
+    # and gradients): the loss to 1e-2, and on boxes of realistic size the
+    # whole gradient to 1e-2 normwise
+    loss64, grads64 = cnn.loss_and_grads(pq, x, tq, window)
+    assert abs(host(loss)[0] - loss64) <= 1e-2 * loss64
+    if nx * ny * nz >= 10000:
+        v64 = np.concatenate([np.concatenate([gw_.ravel(), gb_]) for gw_, gb_ in grads64])
+        vg = np.concatenate([np.concatenate([gw_.ravel(), gb_]) for gw_, gb_ in got])
+        rel = np.linalg.norm(vg - v64) / np.linalg.norm(v64)
+        print(f"gradient vs FP64: {rel:.2e} normwise", flush=True)
+        assert rel <= 1e-2
 
 
 def cnn_param_count():
@@ -245,14 +258,52 @@ def test_propose_matches_oracle_and_stays_in_box():
     feat = np.empty((n, 8))
     feat[:, :4] = (x.reshape(n, 4).astype(np.float32) * sc[:4]).astype(np.float64)
     feat[:, 4:] = (g.reshape(n, 4) / rms) * sc[4:8].astype(np.float64)
-    out, _ = cnn.forward(pq, feat.reshape(N + 1, N + 1, N + 1, 8), bf16_inputs=True)
+    out, _ = cnn.forward(pq, feat.reshape(N + 1, N + 1, N + 1, 8))
     raw = out.reshape(n, 4) * sc[8:].astype(np.float64) * rms
     ref = np.clip(raw.ravel(), lo, hi)
     assert np.all(s >= lo) and np.all(s <= hi)
-    assert np.abs(s - ref).max() <= 3e-2 * np.abs(raw).max()
+    assert np.abs(s - ref).max() <= 1e-2 * np.abs(raw).max()
     # non-finite network output (NaN bias) gives a zero step
     bnan = torch.full_like(bd, float("nan"))
     net2 = binding.Net(ctypes.c_void_p(wd.data_ptr()), ctypes.c_void_p(bnan.data_ptr()),
                        ctypes.c_void_p(scd.data_ptr()))
     s2 = host(ctx.nn_propose(1, net2, dev(x), dev(g), dev(lo), dev(hi)))
     assert np.all(s2 == np.clip(0.0, lo, hi))
+
+
+def test_normalisation_calls():
+    """rmtr_nn_channel_rms, rmtr_nn_target and rmtr_nn_fit_scales against
+    their definitions (per-component RMS over the nodes; target = s_k /
+    (scale_k rms(g_k)); scales from means over samples)."""
+    import torch
+    N = 6
+    ctx = ctx_for(3, N, 1, material(N))
+    n = (N + 1) ** 3
+    rng = np.random.default_rng(17)
+    samples, ref_x, ref_ratio = [], [], []
+    for i in range(3):
+        x = rng.standard_normal(4 * n) * np.array([1e-3, 2e-3, 5e-4, 0.3] * n)
+        g = rng.standard_normal(4 * n) * np.array([1e-5, 2e-5, 3e-6, 1e-7] * n)
+        s = rng.standard_normal(4 * n) * np.array([1e-4, 1e-4, 2e-4, 1e-2] * n)
+        if i == 1:
+            g[3::4] = 0.0                                  # a channel with rms(g) = 0
+        samples.append((dev(x), dev(g), dev(s)))
+        rx = np.sqrt((x.reshape(n, 4) ** 2).mean(axis=0))
+        rg = np.sqrt((g.reshape(n, 4) ** 2).mean(axis=0))
+        rs = np.sqrt((s.reshape(n, 4) ** 2).mean(axis=0))
+        ref_x.append(rx)
+        ref_ratio.append(np.where(rg > 0, rs / np.where(rg > 0, rg, 1.0), 0.0))
+        got = host(ctx.nn_channel_rms(1, samples[-1][1]))
+        assert np.allclose(got, rg, rtol=1e-13, atol=0)
+    sc = torch.empty(12, dtype=torch.float32, device="cuda")
+    ctx.nn_fit_scales(1, samples, sc)
+    want = np.concatenate([1.0 / np.mean(ref_x, axis=0), np.ones(4), np.mean(ref_ratio, axis=0)])
+    assert np.allclose(host(sc), want.astype(np.float32), rtol=1e-6, atol=0)
+    x, g, s = samples[0]
+    t = host(ctx.nn_target(1, g, s, sc)).astype(np.float64)
+    rg = np.sqrt((host(g).reshape(n, 4) ** 2).mean(axis=0))
+    tw = host(s).reshape(n, 4) / (host(sc)[8:].astype(np.float64) * rg)
+    assert np.allclose(t.reshape(n, 4), tw, rtol=1e-6, atol=0)
+    _, g1, s1 = samples[1]
+    t1 = host(ctx.nn_target(1, g1, s1, sc)).reshape(n, 4)
+    assert np.all(t1[:, 3] == 0.0)

@@ -45,18 +45,21 @@ def _gpu_solve(d, N, L, mat, c0, p, x, **prm):
     return host(xd), st
 
 
-@pytest.mark.parametrize("case,shrink", [("c1", 0), ("3d", 0), ("c1", 1), ("3d", 1)])
-def test_loadstep_matches_oracle(case, shrink):
-    """shrink = 1: the step-based radius update after rejections."""
+@pytest.mark.parametrize("case,shrink,model", [("c1", 0, 0), ("3d", 0, 0), ("c1", 1, 0), ("3d", 1, 0),
+                                               ("c1", 0, 1), ("3d", 0, 1)])
+def test_loadstep_matches_oracle(case, shrink, model):
+    """shrink = 1: the step-based radius update after rejections; model = 1:
+    the coarse levels minimise the pure Galerkin quadratic (f~ = 0)."""
     if case == "c1":
         g, mat, c0, p, x = _c1()
         d, N, L = 2, 64, 3
     else:
         g, mat, c0, p, x = _small3d(8)
         d, N, L = 3, 8, 2
-    print(f"case {case} shrink {shrink}", flush=True)
-    xg, st = _gpu_solve(d, N, L, mat, c0, p, x, shrink_to_step=shrink)
-    solver = rmtr.RMTR(d, N, L, mat, p, rmtr.Params(shrink_to_step=bool(shrink)))
+    print(f"case {case} shrink {shrink} coarse_model {model}", flush=True)
+    xg, st = _gpu_solve(d, N, L, mat, c0, p, x, shrink_to_step=shrink, coarse_model=model)
+    solver = rmtr.RMTR(d, N, L, mat, p, rmtr.Params(shrink_to_step=bool(shrink),
+                                                    coarse_model=("energy", "zero")[model]))
     xo, so = solver.solve_loadstep(x.copy(), c0)
     print("gpu", st["vcycles"], st["chi"] / st["chi0"], "oracle", so.vcycles, so.chi / so.chi0, flush=True)
     assert st["code"] == 0
@@ -115,3 +118,77 @@ def test_mixed_precision_reaches_fp64_tolerance_c1():
     assert fem.chi(g, xg, gr, c0) <= 1e-8 * chi0 * (1 + 1e-6)
     c = xg[2::3]
     assert np.all(c >= c0) and np.all(c <= 1.0)
+
+
+def test_capped_vcycles_returns_not_converged_with_a_feasible_iterate():
+    """max_vcycles = 2 on C1: status RMTR_NOT_CONVERGED, the iterate feasible
+    (c_lower <= c <= 1, Dirichlet values untouched) and equal to the
+    oracle's after the same two V-cycles."""
+    g, mat, c0, p, x = _c1()
+    xg, st = _gpu_solve(2, 64, 3, mat, c0, p, x, max_vcycles=2)
+    solver = rmtr.RMTR(2, 64, 3, mat, p, rmtr.Params(max_vcycles=2))
+    xo, so = solver.solve_loadstep(x.copy(), c0)
+    assert st["code"] == 1 and st["status"] == 1 and st["vcycles"] == 2 == so.vcycles
+    assert st["chi"] > 1e-8 * st["chi0"]
+    c = xg[2::3]
+    assert np.all(c >= c0) and np.all(c <= 1.0)
+    assert np.all(xg[g.default_dirichlet()] == 0.0)
+    assert np.abs(xg - xo).max() <= 1e-6 * np.abs(xo).max()
+    assert st["delta"] == so.history[-1][1]
+
+
+@pytest.mark.parametrize("case", ["c1", "3d"])
+def test_forced_rejections_shrink_the_radius(case):
+    """eta1 = eta2 = 1e6: no step can pass Alg. 3, so every decision rejects,
+    the iterate stays bit for bit where it started and the radius halves at
+    each finest-level decision: after two V-cycles of one pre- and one
+    post-smoothing step (the coarse corrections are all zero) it is
+    delta0 / 2^4, the same as the oracle's."""
+    if case == "c1":
+        g, mat, c0, p, x = _c1()
+        d, N, L = 2, 64, 3
+    else:
+        g, mat, c0, p, x = _small3d(8)
+        d, N, L = 3, 8, 2
+    kw = dict(eta1=1e6, eta2=1e6, max_vcycles=2)
+    xg, st = _gpu_solve(d, N, L, mat, c0, p, x, **kw)
+    solver = rmtr.RMTR(d, N, L, mat, p, rmtr.Params(**kw))
+    xo, so = solver.solve_loadstep(x.copy(), c0)
+    assert st["code"] == 1 and st["vcycles"] == 2
+    assert st["tr_accepted"] == 0 == so.tr_accepted
+    assert st["tr_rejected"] == so.tr_rejected > 0
+    assert np.array_equal(xg, x) and np.array_equal(xo, x)
+    assert [h[1] for h in so.history] == [0.25, 0.0625]
+    assert st["delta"] == 0.0625
+
+
+def test_load_step_sequence_irreversibility():
+    """Three load steps with the pressure ramped (Sec. 4.1 workflow step 7:
+    each step starts from the previous solution, with c_lower <- c, the
+    irreversibility bound of eq. (space_pf)).  Every GPU step is certified by
+    the oracle's chi with its own c_lower, the phase field never decreases,
+    and the energies agree with the oracle's own three-step sequence."""
+    g, mat, c0, p, x = _small3d(8)
+    d, N, L = 3, 8, 2
+    import paper_2007_12908_amd as P
+    ctx = ctx_for(d, N, L, mat)
+    xd = dev(x.copy())
+    xo = x.copy()
+    cl_g, cl_o = c0.copy(), c0.copy()
+    for t, pt in enumerate((2e-3, 3e-3, 4e-3)):
+        print(f"load step {t} p={pt}", flush=True)
+        pv = np.full(g.n_nodes, pt)
+        x_start = host(xd)
+        chi0 = fem.chi(g, x_start, fem.gradient(g, x_start, pv, mat), cl_g)
+        st = ctx.solve_loadstep(xd, dev(pv), dev(cl_g), P.default_params())
+        xg = host(xd)
+        solver = rmtr.RMTR(d, N, L, mat, pv, rmtr.Params())
+        xo, so = solver.solve_loadstep(xo, cl_o)
+        assert st["code"] == 0
+        c = xg[d::d + 1]
+        assert np.all(c >= cl_g) and np.all(c <= 1.0)
+        gr = fem.gradient(g, xg, pv, mat)
+        assert fem.chi(g, xg, gr, cl_g) <= 1e-8 * chi0 * (1 + 1e-6)
+        assert st["energy"] == pytest.approx(so.energy, rel=1e-9)
+        cl_g = c.copy()                     # c_old <- c
+        cl_o = xo[d::d + 1].copy()

@@ -1,5 +1,6 @@
 """GPU vs oracle: projected Gauss-Seidel, transfers (bitwise), Galerkin
-coarse operators, MPRGP, reductions."""
+coarse operators, MPRGP (convex, and its negative-curvature fallback),
+reductions."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -71,35 +72,6 @@ def _masked_galerkin(d, Nc, Hf):
     return (Dc @ (R @ Hf @ I) @ Dc).tocsr(), gc
 
 
-@pytest.mark.parametrize("d,N,L", [(2, 8, 3), (2, 16, 2), (3, 4, 2), (3, 16, 3)])
-def test_galerkin_element_matrices(d, N, L):
-    print(f"case d={d} N={N} L={L}", flush=True)
-    g, x, p = rand_state(d, N, seed=N + L)
-    mat = material(N)
-    ctx = ctx_for(d, N, L, mat)
-    H = fem.hessian(g, x, p, mat)
-    K = ctx.galerkin(L - 1, dev(x), dev(p))
-    Hc, gc = _masked_galerkin(d, N // 2, H)
-    rng = np.random.default_rng(1)
-    v = rng.standard_normal(gc.n_dofs)
-    assert field_rel_err(host(ctx.em_hessvec(L - 1, K, dev(v))), Hc @ v, d) <= 1e-12
-    if L >= 3:
-        K2 = ctx.galerkin(L - 2, K_fine=K)
-        Hcc, gcc = _masked_galerkin(d, N // 4, Hc)
-        w = rng.standard_normal(gcc.n_dofs)
-        assert field_rel_err(host(ctx.em_hessvec(L - 2, K2, dev(w))), Hcc @ w, d) <= 1e-12
-    # element-matrix PGS on the coarse level
-    gv = rng.standard_normal(gc.n_dofs) * 1e-4
-    gv[gc.default_dirichlet()] = 0.0
-    xc = transfer.injection(d, N // 2, d + 1) @ x
-    lo, hi = _box(gc, xc, 2e-3, rng)
-    blocks = qp.colour_blocks(gc.node_colour(), gc.nc, 2 ** d)
-    so = qp.pgs(Hc, gv, lo, hi, np.zeros(gc.n_dofs), blocks, 2, ~gc.default_dirichlet())
-    s = dev(np.zeros(gc.n_dofs))
-    ctx.em_smooth(L - 1, K, dev(gv), dev(lo), dev(hi), s, 2)
-    assert field_rel_err(host(s), so, d) <= 1e-11
-
-
 @pytest.mark.parametrize("d,N,L", [(2, 16, 3), (2, 14, 2), (3, 8, 3), (3, 12, 2), (3, 16, 4)])
 def test_coarse_hessvec_is_dense_rap(d, N, L):
     """The load step's coarse Hessians (finest stencil coarsened direction by
@@ -122,25 +94,87 @@ def test_coarse_hessvec_is_dense_rap(d, N, L):
         assert field_rel_err(got32, ref, d) <= 1e-5
 
 
+def _masked_element_matrices(g, x, p, mat):
+    """The level's own Hessian as element matrices (the oracle's), rows and
+    columns of the default Dirichlet dofs zeroed: the input format of
+    rmtr_mprgp."""
+    dofs, Ke = fem.element_matrices(g, x, p, mat)
+    free = (~g.default_dirichlet())[dofs].astype(float)
+    return Ke * free[:, :, None] * free[:, None, :]
+
+
 @pytest.mark.parametrize("d,N", [(2, 8), (3, 4), (3, 8)])
 def test_mprgp_matches_oracle_on_convex_qp(d, N):
+    print(f"case d={d} N={N}", flush=True)
     g, x, p = rand_state(d, N, seed=3 * N, u_scale=1e-5, p_scale=1e-6, c_max=0.3)
     mat = material(N)
-    ctx = ctx_for(d, N, 2, mat)
+    ctx = ctx_for(d, N, 1, mat)
     H = fem.hessian(g, x, p, mat)
-    K = ctx.galerkin(1, dev(x), dev(p))
-    Hc, gc = _masked_galerkin(d, N // 2, H)
+    K = _masked_element_matrices(g, x, p, mat)
     rng = np.random.default_rng(2)
-    gv = rng.standard_normal(gc.n_dofs) * 1e-4
-    gv[gc.default_dirichlet()] = 0.0
-    xc = transfer.injection(d, N // 2, d + 1) @ x
-    lo, hi = _box(gc, xc, 1e-3, rng)
-    so, its_o, st_o = qp.mprgp(Hc, gv, lo, hi, rtol=1e-12, max_it=3000)
-    s, its, st = ctx.mprgp(1, K, dev(gv), dev(lo), dev(hi), max_it=3000, rtol=1e-12)
+    gv = rng.standard_normal(g.n_dofs) * 1e-4
+    gv[g.default_dirichlet()] = 0.0
+    lo, hi = _box(g, x, 1e-3, rng)
+    so, its_o, st_o = qp.mprgp(H, gv, lo, hi, rtol=1e-12, max_it=3000)
+    s, its, st = ctx.mprgp(1, dev(K.reshape(-1)), dev(gv), dev(lo), dev(hi), max_it=3000, rtol=1e-12)
     assert st_o == "converged" and st == 0
     sh = host(s)
     assert np.all(sh >= lo) and np.all(sh <= hi)
     assert np.abs(sh - so).max() <= 1e-8 * np.abs(so).max()
+
+
+@pytest.mark.parametrize("d,N", [(2, 4), (3, 2)])
+def test_mprgp_negative_curvature_pgs_fallback(d, N):
+    """Separable QP with an indefinite diagonal (Sec. 3.2.1, reading 16): the
+    first MPRGP direction has p^T A p < 0, so the GPU must report status 2
+    after one iteration and its PGS fallback must land on the closed-form box
+    minimiser: clamp(-g/h) where h > 0, otherwise the bound with the lower
+    value of g t + h t^2 / 2 (ties: lo), exactly as the oracle's fallback."""
+    from scipy.sparse import diags
+    print(f"case d={d} N={N}", flush=True)
+    g = fem.Grid(d, N)
+    mat = material(N)
+    rng = np.random.default_rng(40 + d)
+    dirm = g.default_dirichlet()
+    h = rng.uniform(0.5, 2.0, g.n_dofs)
+    neg = rng.uniform(0, 1, g.n_dofs) < 0.4
+    h[neg] = -rng.uniform(0.5, 2.0, neg.sum())
+    h[rng.uniform(0, 1, g.n_dofs) < 0.1] = 0.0
+    h[dirm] = 1.0
+    gv = rng.uniform(-1.0, 1.0, g.n_dofs) * np.where(h <= 0.0, 10.0, 0.1)
+    lo = -rng.uniform(0.2, 1.0, g.n_dofs)
+    hi = rng.uniform(0.2, 1.0, g.n_dofs)
+    gv[dirm] = 0.0
+    lo[dirm] = hi[dirm] = 0.0
+    free = ~dirm
+    assert np.sum(h[free] * gv[free] ** 2) < 0.0          # the first CG direction is g
+    want = np.zeros(g.n_dofs)
+    for i in np.nonzero(free)[0]:
+        if h[i] > 0:
+            want[i] = min(max(-gv[i] / h[i], lo[i]), hi[i])
+        else:
+            m = lambda t: gv[i] * t + 0.5 * h[i] * t * t  # noqa: E731
+            want[i] = hi[i] if m(hi[i]) < m(lo[i]) else lo[i]
+    # element matrices: each node's diagonal split evenly over the elements
+    # around it (1, 2, 4 or 8 of them: exact in binary)
+    ijk = g.node_ijk()
+    count = np.prod(np.where((ijk == 0) | (ijk == N), 1, 2), axis=1)
+    hs = (h.reshape(-1, d + 1) / count[:, None]).reshape(-1)
+    dofs = g.elem_dofs()
+    K = np.zeros((g.n_elems, dofs.shape[1], dofs.shape[1]))
+    K[:, np.arange(dofs.shape[1]), np.arange(dofs.shape[1])] = hs[dofs]
+    K *= free[dofs][:, :, None] * free[dofs][:, None, :]
+    H = diags(np.where(free, h, 0.0)).tocsr()
+    blocks = qp.colour_blocks(g.node_colour(), g.nc, 2 ** d)
+    so, its_o, st_o = qp.mprgp(H, gv, lo, hi, rtol=1e-12, max_it=100,
+                               fallback=lambda s0: qp.pgs(H, gv, lo, hi, s0, blocks, 50, free))
+    assert st_o == "negative_curvature" and its_o == 1
+    assert np.allclose(so, want, rtol=1e-14, atol=0)
+    ctx = ctx_for(d, N, 1, mat)
+    s, its, st = ctx.mprgp(1, dev(K.reshape(-1)), dev(gv), dev(lo), dev(hi), max_it=100, rtol=1e-12,
+                           fallback_sweeps=50)
+    assert st == 2 and its == 1
+    assert np.allclose(host(s), want, rtol=1e-14, atol=0)
 
 
 def test_dot_and_chi():
