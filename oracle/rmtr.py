@@ -13,7 +13,12 @@ in post-smoothing.
 Readings where the paper is silent (listed in the design notes):
   * h^l(x) = f~^l(x) + <dg, x - x0> + 1/2 <x - x0, dH (x - x0)>, with f~^l the
     same discrete functional on the level-l grid (p injected, l_s unchanged),
-    or f~^l = 0 ("zero" coarse model);
+    or f~^l = 0 ("zero" coarse model), or f~^l(x) = f(I_{l->L} x), the finest
+    functional of the prolongated coarse iterate ("fine" coarse model);
+  * first-order variant (ablation): dH = 0, so the coarse model is
+    f~^l(x) + <dg, x - x0> and its Hessian, lagged like every other, is the
+    level's own grad^2 f~^l(x0) instead of the Galerkin product (needs a
+    coarse functional: not with the "zero" model);
   * coarse feasible set: x0 + box_restrict(fine correction box);
   * ratio guards: pred <= 0 with s != 0 -> rho = -inf; s = 0 -> skip;
     |pred| <= tol -> rho = 1 if ared >= -tol else -inf, with the round-off
@@ -49,7 +54,8 @@ class Params:
     fallback_sweeps: int = 50
     max_vcycles: int = 200
     rtol: float = 1e-8
-    coarse_model: str = "energy"      # or "zero"
+    coarse_model: str = "energy"      # or "zero", or "fine" (f o I)
+    first_order: bool = False         # coarse models without the dH term
     guard: float = 1e-14
     shrink_to_step: bool = False      # rejected: gamma1 min(delta, |s|_inf)
 
@@ -106,19 +112,65 @@ class RMTR:
                 nodeP = transfer.injection(d, Nc, 1)
                 p = nodeP @ p
         self.levels[n_levels].finest = True
+        # composite prolongations I_{l -> L} for the "fine" coarse model
+        self.IL = {n_levels: None}
+        for l in range(n_levels - 1, 0, -1):
+            nxt = self.IL[l + 1]
+            self.IL[l] = self.I[l] if nxt is None else (nxt @ self.I[l]).tocsr()
+        if self.prm.coarse_model not in ("energy", "zero", "fine"):
+            raise ValueError(f"unknown coarse model {self.prm.coarse_model!r}")
+        if self.prm.first_order and self.prm.coarse_model == "zero":
+            raise ValueError("the first-order coarse model needs a coarse functional")
         self.stats = Stats()
         self.f_ref = 1.0
 
     # ---------------------------------------------------------- level h
     def _ftilde_active(self, lev):
-        return lev.finest or self.prm.coarse_model == "energy"
+        return lev.finest or self.prm.coarse_model != "zero"
+
+    def _fine(self):
+        return self.levels[self.L]
+
+    def ft_grad(self, lev, x):
+        """grad f~ of a coarse level (Dirichlet rows zeroed)."""
+        if self.prm.coarse_model == "fine":
+            f = self._fine()
+            IL = self.IL[self._level_index(lev)]
+            g = IL.T @ fem.gradient(f.grid, IL @ x, f.p, f.mat, f.dirichlet)
+            g[lev.dirichlet] = 0.0
+            return g
+        return fem.gradient(lev.grid, x, lev.p, lev.mat, lev.dirichlet)
+
+    def ft_hessian(self, lev, x):
+        """grad^2 f~ of a coarse level at x (Dirichlet rows and columns zeroed)."""
+        if self.prm.coarse_model == "fine":
+            f = self._fine()
+            IL = self.IL[self._level_index(lev)]
+            H = IL.T @ fem.hessian(f.grid, IL @ x, f.p, f.mat, f.dirichlet) @ IL
+            D = sp.diags(lev.free.astype(np.float64))
+            return (D @ H @ D).tocsr()
+        return fem.hessian(lev.grid, x, lev.p, lev.mat, lev.dirichlet)
+
+    def ft_diff(self, lev, x, s):
+        """f~(x + s) - f~(x) of any level."""
+        if not lev.finest and self.prm.coarse_model == "fine":
+            f = self._fine()
+            IL = self.IL[self._level_index(lev)]
+            return fem.energy_diff(f.grid, IL @ x, IL @ s, f.p, f.mat)
+        return fem.energy_diff(lev.grid, x, s, lev.p, lev.mat)
+
+    def _level_index(self, lev):
+        for l, v in self.levels.items():
+            if v is lev:
+                return l
+        raise KeyError("level not in this hierarchy")
 
     def h_grad(self, lev, x):
         if lev.finest:
             return fem.gradient(lev.grid, x, lev.p, lev.mat, lev.dirichlet)
         g = lev.dg + lev.Hmod @ (x - lev.x0)
         if self._ftilde_active(lev):
-            g = g + fem.gradient(lev.grid, x, lev.p, lev.mat, lev.dirichlet) - lev.Hf0 @ (x - lev.x0)
+            g = g + self.ft_grad(lev, x) - lev.Hf0 @ (x - lev.x0)
         g[lev.dirichlet] = 0.0
         return g
 
@@ -126,7 +178,7 @@ class RMTR:
         """h(x + s) - h(x)."""
         out = 0.0
         if self._ftilde_active(lev):
-            out += fem.energy_diff(lev.grid, x, s, lev.p, lev.mat)
+            out += self.ft_diff(lev, x, s)
         if not lev.finest:
             dx = x - lev.x0
             dHdx = lev.Hmod @ dx
@@ -216,17 +268,22 @@ class RMTR:
         c.Lb = c.x0 + loH
         c.Ub = c.x0 + hiH
         g = self.h_grad(lev, x)
-        # Galerkin product restricted to the coarse free dofs (the coarse
-        # problem, like the fine one, has no displacement dofs on the boundary)
-        Dc = sp.diags(c.free.astype(np.float64))
-        c.Hmod = (Dc @ (R @ lev.Hmod @ I) @ Dc).tocsr()
-        c.Hmod.sort_indices()
-        if self.prm.coarse_model == "energy":
-            c.Hf0 = fem.hessian(c.grid, c.x0, c.p, c.mat, c.dirichlet)
-            c.dg = R @ g - fem.gradient(c.grid, c.x0, c.p, c.mat, c.dirichlet)
+        if self.prm.coarse_model != "zero":
+            c.Hf0 = self.ft_hessian(c, c.x0)
+            c.dg = R @ g - self.ft_grad(c, c.x0)
         else:
             c.Hf0 = None
             c.dg = R @ g
+        if self.prm.first_order:
+            # dH = 0: the coarse model's Hessian is grad^2 f~ at x0
+            c.Hmod = c.Hf0.copy()
+        else:
+            # Galerkin product restricted to the coarse free dofs (the coarse
+            # problem, like the fine one, has no displacement dofs on the
+            # boundary)
+            Dc = sp.diags(c.free.astype(np.float64))
+            c.Hmod = (Dc @ (R @ lev.Hmod @ I) @ Dc).tocsr()
+        c.Hmod.sort_indices()
         c.dg[c.dirichlet] = 0.0
 
     def vcycle(self, l, x, delta):

@@ -30,7 +30,7 @@ def _setup(d, N, L, p0=1e-3, seed=0):
 
 
 @pytest.mark.parametrize("d,N,L", [(2, 8, 2), (3, 4, 2)])
-@pytest.mark.parametrize("model", ["energy", "zero"])
+@pytest.mark.parametrize("model", ["energy", "zero", "fine"])
 def test_level_objective_first_and_second_order_consistency(d, N, L, model):
     g, mat, c0, p, x = _setup(d, N, L)
     x = x + RNG.standard_normal(x.shape) * 1e-3
@@ -248,3 +248,65 @@ def test_sneddon_opening_c1():
     assert 0.5 * sned < cod[32] < 2.0 * sned
     assert np.allclose(cod, cod[::-1], rtol=1e-6, atol=1e-12)
     assert cod[32] > cod[26] > cod[20]
+
+
+@pytest.mark.parametrize("d,N,L", [(2, 8, 3), (3, 4, 2)])
+@pytest.mark.parametrize("model", ["energy", "fine"])
+def test_first_order_coarse_model(d, N, L, model):
+    """First-order variant: grad h^{l-1}(x0) = R grad f(x) still holds, but
+    the coarse Hessian is grad^2 f~ at x0 (by central differences of the
+    coarse functional's own gradient), not R H I; for the "fine" model
+    f~(x) = f(I x), whose gradient is I^T grad f(I x) (central differences
+    of its energy differences)."""
+    g, mat, c0, p, x = _setup(d, N, L)
+    x = x + RNG.standard_normal(x.shape) * 1e-3
+    x[g.default_dirichlet()] = 0.0
+    x[d::d + 1] = np.clip(x[d::d + 1], c0, 1.0)
+    s = rmtr.RMTR(d, N, L, mat, p, rmtr.Params(coarse_model=model, first_order=True))
+    fine = s.levels[L]
+    fine.Lb = np.full(g.n_dofs, -np.inf); fine.Ub = np.full(g.n_dofs, np.inf)
+    fine.x0 = x.copy()
+    fine.Hmod = fem.hessian(g, x, p, mat)
+    s.setup_coarse(L, x, 0.5)
+    c = s.levels[L - 1]
+    Rg = s.R[L - 1] @ fem.gradient(g, x, p, mat)
+    Rg[c.dirichlet] = 0.0
+    assert np.allclose(s.h_grad(c, c.x0), Rg, rtol=0, atol=1e-13 * np.abs(Rg).max())
+    v = RNG.standard_normal(c.x0.shape)
+    v[c.dirichlet] = 0.0
+    eta = 1e-6
+    fd = (s.h_grad(c, c.x0 + eta * v) - s.h_grad(c, c.x0 - eta * v)) / (2 * eta)
+    fdf = (s.ft_grad(c, c.x0 + eta * v) - s.ft_grad(c, c.x0 - eta * v)) / (2 * eta)
+    assert np.abs(fd - fdf).max() <= 1e-7 * np.abs(fdf).max()
+    assert np.abs(c.Hmod @ v - fdf).max() <= 1e-6 * np.abs(fdf).max()
+    RHIv = s.R[L - 1] @ (fine.Hmod @ (s.I[L - 1] @ v))
+    RHIv[c.dirichlet] = 0.0
+    assert np.abs(fd - RHIv).max() > 1e-3 * np.abs(RHIv).max()   # not the Galerkin product
+    # grad f~ is the derivative of f~ (energy differences along w)
+    w = RNG.standard_normal(c.x0.shape) * 1e-3
+    w[c.dirichlet] = 0.0
+    xa = c.x0 + w
+    dfd = (s.ft_diff(c, xa, eta * v) - s.ft_diff(c, xa, -eta * v)) / (2 * eta)
+    assert dfd == pytest.approx(float(s.ft_grad(c, xa) @ v), rel=1e-6)
+
+
+@pytest.mark.parametrize("model,first", [("fine", False), ("energy", True), ("fine", True), ("zero", False)])
+def test_coarse_model_variants_converge(model, first):
+    """Every coarse-model variant keeps RMTR's guarantees: the energy never
+    rises at the end of a V-cycle, the iterates stay feasible and chi reaches
+    1e-8 chi0."""
+    d, N, L = 2, 16, 3
+    g, mat, c0, p, x = _setup(d, N, L, p0=2e-3)
+    solver = rmtr.RMTR(d, N, L, mat, p, rmtr.Params(coarse_model=model, first_order=first, max_vcycles=150))
+    xs, st = solver.solve_loadstep(x.copy(), c0)
+    assert st.chi <= 1e-8 * st.chi0
+    c = xs[d::d + 1]
+    assert np.all(c >= c0) and np.all(c <= 1.0)
+    assert np.all(xs[g.default_dirichlet()] == 0.0)
+    assert st.energy <= fem.energy(g, x, p, mat)
+
+
+def test_first_order_needs_a_coarse_functional():
+    g, mat, c0, p, x = _setup(2, 8, 2)
+    with pytest.raises(ValueError):
+        rmtr.RMTR(2, 8, 2, mat, p, rmtr.Params(coarse_model="zero", first_order=True))
