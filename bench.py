@@ -5,10 +5,11 @@ One step = energy, gradient and Hessian-vector product (FP64, matrix-free)
 over the fine level of the workload, inputs resident in HBM.  `value` is the
 fine-level dofs passed through that triple per second (GDoF/s).  The same run
 reports each kernel's own rate, the mixed-precision (FP32) Hv, the roofline
-of the dominant kernel (HIP events on the launch stream), the RMTR load step
-to 1e-8 (plain FP64, mixed precision, and mixed precision with the learned
-proposal, whose harvesting and training are timed apart), and the CPU oracle
-on a bounded sample.
+of the dominant kernel (HIP events on the launch stream) on the 256^3
+workload, whose working set is larger than the Infinity Cache, the RMTR load
+step to 1e-8 (plain FP64, mixed precision, and mixed precision with the
+learned proposal, whose harvesting and training are timed apart), and the
+CPU oracle on a bounded sample at one core and at the host's cores.
 """
 import argparse
 import hashlib
@@ -22,9 +23,24 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GDoF/s energy/grad/Hv; RMTR s/load-step plain vs mixed+learned at 1e-8"
 PEAK_FP64 = 78.6      # TFLOP/s, MI355X FP64 vector (= FP64 matrix)
+PEAK_FP32 = 157.3     # TFLOP/s, MI355X FP32 vector
 PEAK_HBM = 8000.0     # GB/s
 KERNEL_SOURCES = ["paper_2007_12908_amd/csrc/elem_kernels.hip", "paper_2007_12908_amd/csrc/rmtr_device.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hessvec_c2_3d_128.json")
+ROOFLINE_WORKLOAD = "c3_3d_256"   # x alone (543 MB) is twice the 256 MB Infinity Cache
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", f"traffic_hessvec_{ROOFLINE_WORKLOAD}.json")
+
+# Algorithmic work of the 3D element kernels, per fine node (bytes that must
+# cross HBM once: x 32, p 8, v 32, and the output) and per element (flops of
+# a sum-factorised evaluation: interpolation of the nodal fields to the 8
+# Gauss points, the pointwise density terms, the adjoint back to the nodes).
+# The flop figures are the hot-path scope estimates, not the executed
+# instruction count (which includes recomputed subexpressions).
+ALGO = {
+    "energy": {"bytes_per_node": 40, "flops_per_element": 700, "peak": PEAK_FP64},
+    "gradient": {"bytes_per_node": 72, "flops_per_element": 1300, "peak": PEAK_FP64},
+    "hessvec": {"bytes_per_node": 104, "flops_per_element": 1800, "peak": PEAK_FP64},
+    "hessvec_fp32": {"bytes_per_node": 52, "flops_per_element": 1800, "peak": PEAK_FP32},
+}
 
 
 def log(*a):
@@ -40,8 +56,9 @@ def source_hash():
 
 
 def measured_traffic():
-    """Per-launch HBM bytes of the Hv kernel from committed PMC counters, or
-    None when the kernel sources changed since they were taken."""
+    """Per-launch HBM bytes of the Hv kernel at the roofline workload from
+    committed PMC counters, or None when the kernel sources changed since
+    they were taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -65,28 +82,127 @@ def time_calls(fn, n, torch):
     return s.elapsed_time(e) / n
 
 
-def cpu_baseline(wl, x_np, p_np, v_np, budget_s=20.0):
-    """The oracle, as it is, on the first z-layers of the workload grid."""
+_CPU = {}
+
+
+def _cpu_init(shm_names, shapes, n_cells, mat_args):
+    from multiprocessing import shared_memory
     import numpy as np
     from oracle import fem
-    g = fem.Grid(3, wl.n_cells)
-    mat = fem.material_from_E_nu(wl.E, wl.nu, wl.Gc, wl.ls, wl.k)
-    ne = 256
-    while True:
-        elems = np.arange(ne)
-        t0 = time.perf_counter()
-        fem.energy(g, x_np, p_np, mat, elems)
-        fem.gradient(g, x_np, p_np, mat, None, elems)
-        H = fem.hessian(g, x_np, p_np, mat, None, elems)
-        _ = H @ v_np
-        dt = time.perf_counter() - t0
-        if dt * 4 > budget_s or ne >= wl.n_cells ** 3:
-            break
-        ne *= 2
+    arrs = []
+    for name, n in zip(shm_names, shapes):
+        sh = shared_memory.SharedMemory(name=name)
+        arrs.append((sh, np.ndarray((n,), dtype=np.float64, buffer=sh.buf)))
+    _CPU["arrs"] = arrs
+    _CPU["grid"] = fem.Grid(3, n_cells)
+    _CPU["mat"] = fem.material_from_E_nu(*mat_args)
+
+
+def _cpu_chunk(elems):
+    """The oracle's energy, gradient and assembled Hessian times v over a
+    chunk of elements (one process, one thread)."""
+    from oracle import fem
+    (_, x), (_, p), (_, v) = _CPU["arrs"]
+    g, mat = _CPU["grid"], _CPU["mat"]
+    fem.energy(g, x, p, mat, elems)
+    fem.gradient(g, x, p, mat, None, elems)
+    H = fem.hessian(g, x, p, mat, None, elems)
+    H @ v
+    return len(elems)
+
+
+def cpu_baseline(wl, x_np, p_np, v_np, budget_s=12.0):
+    """The oracle, as it is, timed on the host: energy, gradient and Hv over
+    the first elements of the workload grid, in one process (one core) and in
+    as many single-threaded processes as the host offers (at most 16), each
+    over its own chunk of elements.  The 1-core sample is grown until it
+    takes about budget_s; the parallel sample is that size times the process
+    count."""
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+    import numpy as np
+    os.environ["OMP_NUM_THREADS"] = "1"
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    shms = []
+    for a in (x_np, p_np, v_np):
+        sh = shared_memory.SharedMemory(create=True, size=a.nbytes)
+        np.ndarray(a.shape, dtype=np.float64, buffer=sh.buf)[:] = a
+        shms.append(sh)
+    try:
+        args = ([sh.name for sh in shms], [a.size for a in (x_np, p_np, v_np)], wl.n_cells,
+                (wl.E, wl.nu, wl.Gc, wl.ls, wl.k))
+        ctxmp = mp.get_context("spawn")
+        ne_max = wl.n_cells ** 3
+        with ctxmp.Pool(cores, initializer=_cpu_init, initargs=args) as pool:
+            pool.map(_cpu_chunk, [np.arange(64)] * cores)          # imports and warm-up
+            ne = 1024
+            while True:
+                t0 = time.perf_counter()
+                pool.apply(_cpu_chunk, (np.arange(ne),))
+                t1 = time.perf_counter() - t0
+                if t1 * 2 > budget_s or 2 * ne > ne_max // cores:
+                    break
+                ne *= 2
+            chunk = ne
+            work = [np.arange(i * chunk, (i + 1) * chunk) for i in range(cores)]
+            t0 = time.perf_counter()
+            pool.map(_cpu_chunk, work, chunksize=1)
+            tp = time.perf_counter() - t0
+    finally:
+        for sh in shms:
+            sh.close()
+            sh.unlink()
     # one element per node in the large-grid limit: 4 dofs per element
-    return {"value": 4 * ne / dt / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
-            "sample": f"energy+gradient+Hv over the first {ne} elements of the {wl.n_cells}^3 grid "
-                      f"(4 dofs per element), numpy/scipy FP64 single thread, {dt:.1f} s"}
+    one = 4 * ne / t1 / 1e9
+    par = 4 * chunk * cores / tp / 1e9
+    return {"value": par, "unit": "GDoF/s", "cores": cores, "kind": "oracle",
+            "value_1core": one,
+            "sample": f"energy + gradient + assembled-Hessian Hv (numpy/scipy FP64, one thread per process) over "
+                      f"the first {chunk * cores} elements of the {wl.n_cells}^3 grid in {cores} processes of "
+                      f"{chunk} elements ({tp:.1f} s); one process over {ne} elements: {t1:.1f} s; "
+                      f"4 dofs per element"}
+
+
+def kernel_leg(ctx, wl, c0, p, reps, torch):
+    """Energy, gradient and Hv (FP64 and FP32) on the finest level of a
+    workload, each timed with HIP events over `reps` launches on the launch
+    stream, with its algorithmic HBM rate and arithmetic rate."""
+    import numpy as np
+    N, L = wl.n_cells, wl.n_levels
+    n_nodes = (N + 1) ** 3
+    n_dofs = 4 * n_nodes
+    ne = N ** 3
+    gen = torch.Generator(device="cuda").manual_seed(1234)
+    x = torch.empty(n_dofs, dtype=torch.float64, device="cuda").normal_(0.0, 1e-4, generator=gen)
+    xv = x.view(-1, 4)
+    xv[:, 3] = c0
+    idx = torch.arange(n_nodes, device="cuda")
+    i, j, k = idx % (N + 1), (idx // (N + 1)) % (N + 1), idx // ((N + 1) ** 2)
+    bnd = (i == 0) | (i == N) | (j == 0) | (j == N) | (k == 0) | (k == N)
+    xv[bnd, :3] = 0.0
+    v = torch.empty(n_dofs, dtype=torch.float64, device="cuda").normal_(generator=gen)
+    x32, p32, v32 = x.float(), p.float(), v.float()
+    E = torch.empty(1, dtype=torch.float64, device="cuda")
+    g, hv, hv32 = torch.empty_like(x), torch.empty_like(x), torch.empty_like(x32)
+    calls = {
+        "energy": lambda: ctx.energy(L, x, p, out=E),
+        "gradient": lambda: ctx.gradient(L, x, p, out=g),
+        "hessvec": lambda: ctx.hessvec(L, x, p, v, out=hv),
+        "hessvec_fp32": lambda: ctx.hessvec(L, x32, p32, v32, out=hv32),
+    }
+    out = {}
+    for name, fn in calls.items():
+        fn()
+        ms = time_calls(fn, reps, torch)
+        a = ALGO[name]
+        gbs = a["bytes_per_node"] * n_nodes / ms / 1e6
+        tfs = a["flops_per_element"] * ne / ms / 1e9
+        out[name] = {"ms": ms, "GDoF/s": n_dofs / ms / 1e6, "GB/s": gbs, "hbm_frac": gbs / PEAK_HBM,
+                     "TFLOP/s": tfs, "alu_frac": tfs / a["peak"],
+                     "bound": "alu" if a["flops_per_element"] / a["bytes_per_node"] > a["peak"] * 1e3 / PEAK_HBM
+                     else "hbm"}
+    del x, v, x32, p32, v32, g, hv, hv32
+    return out
 
 
 def learned_leg(ctx, wl, P, W, torch, train_seconds, target):
@@ -150,6 +266,21 @@ def cnn_leg(ctx, L, torch, reps):
             "forward_frac_bf16": tf_f / PEAK_BF16, "backward_frac_bf16": tf_b / PEAK_BF16}
 
 
+def roofline_of(kernels, wl, traffic):
+    """Roofline of the dominant (slowest) FP64 kernel of a kernel leg."""
+    dom = max(("energy", "gradient", "hessvec"), key=lambda k: kernels[k]["ms"])
+    k = kernels[dom]
+    a = ALGO[dom]
+    alu = k["bound"] == "alu"
+    return {"kernel": dom, "workload": wl.name, "bound": k["bound"],
+            "achieved": k["TFLOP/s"] if alu else k["GB/s"], "peak": a["peak"] if alu else PEAK_HBM,
+            "unit": "TFLOP/s" if alu else "GB/s", "frac": k["alu_frac"] if alu else k["hbm_frac"],
+            "traffic": traffic if dom == "hessvec" else None,
+            "flops_per_element": a["flops_per_element"], "elements": wl.n_cells ** 3,
+            "bytes_per_node": a["bytes_per_node"], "nodes": (wl.n_cells + 1) ** 3,
+            "hbm_frac": k["hbm_frac"], "ms": k["ms"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,8 +292,12 @@ def main():
     ap.add_argument("--train-seconds", type=float, default=60.0)
     ap.add_argument("--learned-target", choices=("pgs", "vcycle"), default="pgs")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-roofline-leg", action="store_true",
+                    help="skip the kernel leg on the roofline workload")
     ap.add_argument("--kernels-only", action="store_true",
                     help="time only the kernel triple (for profiler runs)")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="time only the kernels on the roofline workload (for profiler runs)")
     ap.add_argument("--cnn-only", action="store_true",
                     help="time only the network's forward and backward passes (for profiler runs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -177,7 +312,28 @@ def main():
     import torch
     import workloads as W
     import paper_2007_12908_amd as P
-    from paper_2007_12908_amd import binding
+
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float64, device="cuda")   # 2 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    def roofline_leg():
+        rw = W.WORKLOADS[ROOFLINE_WORKLOAD]
+        rctx = P.Context(3, rw.n_cells, rw.n_levels, rw.lam, rw.mu, rw.Gc, rw.ls, rw.k)
+        rc0, rp = rctx.init_fields(rw.n_levels, rw.fractures(), band=rw.h, p_mode=0, p_value=rw.p)
+        ker = kernel_leg(rctx, rw, rc0, rp, max(args.steps // 2, 5), torch)
+        del rctx, rc0, rp
+        torch.cuda.synchronize()
+        return rw, ker
+
+    if args.roofline_only:
+        rw, ker = roofline_leg()
+        log(json.dumps({"workload": rw.name, "kernels": ker}))
+        return
 
     wl = W.WORKLOADS[args.workload]
     assert wl.dim == 3
@@ -197,11 +353,9 @@ def main():
     v_np = rng.standard_normal(n_dofs)
     x = torch.from_numpy(x_np).cuda()
     v = torch.from_numpy(v_np).cuda()
-    x32, p32, v32 = x.float(), p.float(), v.float()
     E = torch.empty(1, dtype=torch.float64, device="cuda")
     g = torch.empty_like(x)
     hv = torch.empty_like(x)
-    hv32 = torch.empty_like(x32)
 
     if args.cnn_only:
         log(json.dumps({"cnn": cnn_leg(ctx, L, torch, max(args.steps, 5))}))
@@ -212,14 +366,6 @@ def main():
         ctx.gradient(L, x, p, out=g)
         ctx.hessvec(L, x, p, v, out=hv)
 
-    if args.copy_probe:
-        a = torch.empty(1 << 28, dtype=torch.float64, device="cuda")   # 2 GiB
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -229,34 +375,19 @@ def main():
     torch.cuda.synchronize()
     ms_step = (time.perf_counter() - t0) / args.steps * 1e3
 
-    reps = max(args.steps, 5)
-    t_e = time_calls(lambda: ctx.energy(L, x, p, out=E), reps, torch)
-    t_g = time_calls(lambda: ctx.gradient(L, x, p, out=g), reps, torch)
-    t_h = time_calls(lambda: ctx.hessvec(L, x, p, v, out=hv), reps, torch)
-    t_h32 = time_calls(lambda: ctx.hessvec(L, x32, p32, v32, out=hv32), reps, torch)
+    per = kernel_leg(ctx, wl, c0, p, max(args.steps, 5), torch)
     if args.kernels_only:
-        log(json.dumps({"ms": {"energy": t_e, "gradient": t_g, "hessvec": t_h, "hessvec_fp32": t_h32}}))
+        log(json.dumps({"ms": {k: v_["ms"] for k, v_ in per.items()}}))
         return
 
-    ne = N ** 3
-    fl = {k: binding.element_flops(3, kk) for k, kk in (("energy", 0), ("gradient", 2), ("hessvec", 3))}
-    per = {
-        "energy": {"ms": t_e, "GDoF/s": n_dofs / t_e / 1e6, "TFLOP/s": fl["energy"] * ne / t_e / 1e9},
-        "gradient": {"ms": t_g, "GDoF/s": n_dofs / t_g / 1e6, "TFLOP/s": fl["gradient"] * ne / t_g / 1e9},
-        "hessvec": {"ms": t_h, "GDoF/s": n_dofs / t_h / 1e6, "TFLOP/s": fl["hessvec"] * ne / t_h / 1e9},
-        "hessvec_fp32": {"ms": t_h32, "GDoF/s": n_dofs / t_h32 / 1e6,
-                         "TFLOP/s": fl["hessvec"] * ne / t_h32 / 1e9},
-    }
-    # dominant kernel of the step: the slowest of the three FP64 kernels
-    dom = max(("energy", "gradient", "hessvec"), key=lambda k: per[k]["ms"])
-    achieved = per[dom]["TFLOP/s"]
-    traffic = measured_traffic() if dom == "hessvec" else None
-    roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_FP64, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64, "traffic": traffic,
-            "flops_per_element": fl[dom], "elements": ne,
-            "hbm_GB/s_algorithmic": {"energy": 40 * n_nodes / t_e / 1e6, "gradient": 72 * n_nodes / t_g / 1e6,
-                                     "hessvec": 104 * n_nodes / t_h / 1e6,
-                                     "hessvec_fp32": 52 * n_nodes / t_h32 / 1e6}}
+    # the roofline is taken where the working set does not fit the
+    # Infinity Cache (the benchmark workload's x does)
+    if args.no_roofline_leg:
+        rw, rker = wl, per
+    else:
+        rw, rker = roofline_leg()
+    roof = roofline_of(rker, rw, measured_traffic() if rw.name == ROOFLINE_WORKLOAD else None)
+    log("roofline", json.dumps(roof))
 
     cnn = None if args.no_learned else cnn_leg(ctx, L, torch, 10)
 
@@ -306,8 +437,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: 3D Q1 {N}^3 cells, {wl.n_frac} penny fractures, "
                                f"{L} levels, p={wl.p} uniform", "n_cells": N, "n_dofs": n_dofs,
-                   "step": "energy + gradient + Hv (FP64) on the finest level"},
+                   "step": "energy + gradient + Hv (FP64) on the finest level",
+                   "roofline_workload": f"{rw.name}: 3D Q1 {rw.n_cells}^3 cells, {rw.n_frac} penny fractures"},
         "kernels": per,
+        "kernels_roofline_workload": rker,
         "roofline": roof,
         "cnn": cnn,
         "rmtr": rmtr,

@@ -105,7 +105,11 @@ typedef struct {
   int32_t fallback_sweeps; /* PGS sweeps after MPRGP meets p^T A p <= 0 */
   int32_t max_vcycles;
   int32_t precision;       /* RMTR_FP64 or RMTR_FP32 (fine Hv + PGS)    */
-  int32_t coarse_model;    /* 0: f~ = f on the coarse grid, 1: f~ = 0   */
+  int32_t coarse_model;    /* f~^l of the coarse models (eq. (second_order_consistency)):
+                              0: the same functional on the level-l grid,
+                              1: f~ = 0 (the pure Galerkin quadratic),
+                              2: f~^l(x) = f(I_{l->L} x), the finest functional
+                              of the prolongated iterate */
   int32_t use_learned;     /* 1: learned proposal before the first finest-level
                               pre-smoothing step of each V-cycle (3D; needs nn) */
   const rmtr_nn* nn;       /* host pointer, read during the call         */
@@ -119,6 +123,10 @@ typedef struct {
                               sequential order within a colour); 1 = the
                               hybrid Jacobi/Gauss-Seidel over tiles, not built
                               (RMTR_E_ARG) */
+  int32_t first_order;     /* 1: first-order coarse models (ablation): no dH
+                              term, each coarse level smooths with its own
+                              lagged Hessian grad^2 f~^l(x0) instead of the
+                              Galerkin product; needs coarse_model 0 */
 } rmtr_params;
 
 typedef struct {

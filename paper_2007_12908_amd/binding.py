@@ -57,7 +57,7 @@ class Params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("coarse_model", ctypes.c_int32),
                 ("use_learned", ctypes.c_int32), ("nn", ctypes.POINTER(Net)),
                 ("nn_patience", ctypes.c_int32), ("shrink_to_step", ctypes.c_int32),
-                ("gs_mode", ctypes.c_int32)]
+                ("gs_mode", ctypes.c_int32), ("first_order", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -40,6 +40,8 @@ struct Level {
   double* Sop = nullptr;    // stencil scratch of rmtr_smooth / rmtr_coarse_hessvec
   float* Sopf = nullptr;
   double* coefop = nullptr;
+  // prolongation / restriction chains of the coarse model f~ = f o I
+  double *ca = nullptr, *cb = nullptr, *cc = nullptr;
   bool solver_ready = false;
 };
 
@@ -150,8 +152,13 @@ rmtr_status ensure_common(rmtr_ctx* c) {
 
 int ndof_elem(int dim) { return (1 << dim) * (dim + 1); }
 
-rmtr_status ensure_solver_level(rmtr_ctx* c, int l, bool mixed) {
+rmtr_status ensure_solver_level(rmtr_ctx* c, int l, bool mixed, bool fine_model) {
   Level& v = c->lv[l];
+  if (fine_model && l >= 2 && !v.ca) {
+    HIPCHK(c, dalloc(c, &v.ca, size_t(v.n)));
+    HIPCHK(c, dalloc(c, &v.cb, size_t(v.n)));
+    if (l == c->L) HIPCHK(c, dalloc(c, &v.cc, size_t(v.n)));
+  }
   if (!v.solver_ready) {
     const size_t n = size_t(v.n);
     double** vecs[] = {&v.x0, &v.xs, &v.Lb, &v.Ub, &v.dg, &v.g, &v.lo, &v.hi, &v.s, &v.sc, &v.hs,
@@ -180,11 +187,12 @@ size_t common_bytes() {
   return buf_bytes(kMaxPartials * sizeof(double)) + buf_bytes(kScal * sizeof(double)) + buf_bytes(4 * sizeof(int));
 }
 
-size_t loadstep_bytes(const rmtr_ctx* c, bool mixed, bool learned) {
+size_t loadstep_bytes(const rmtr_ctx* c, bool mixed, bool learned, bool fine_model) {
   const int d = c->model.dim, L = c->L;
   size_t b = common_bytes();
   for (int l = 1; l <= L; ++l) {
     const Level& v = c->lv[l];
+    if (fine_model && l >= 2) b += (l == L ? 3 : 2) * buf_bytes(size_t(v.n) * sizeof(double));
     b += 15 * buf_bytes(size_t(v.n) * sizeof(double)) + buf_bytes(size_t(v.nodes) * sizeof(double));
     const bool f32 = mixed && l == L && L > 1;
     b += buf_bytes(stencil_values(d, v.N) * (f32 ? sizeof(float) : sizeof(double)));
@@ -247,7 +255,9 @@ struct Run {
   hipStream_t st;
   const uint8_t* fdir;
   bool mixed;
-  bool energy_model;
+  bool energy_model;       // coarse levels carry f~ (coarse_model 0 or 2)
+  bool fine_model;         // f~^l = f o I_{l->L} (coarse_model 2)
+  bool first_order;        // coarse models without dH
   double f_ref = 1.0;
   int accepted = 0, rejected = 0;
   int nn_proposed = 0, nn_accepted = 0, nn_misses = 0;
@@ -266,6 +276,74 @@ struct Run {
 
   bool ftilde(int l) const { return l == c->L || energy_model; }
 
+  // ---- the coarse functional f~^l of a level l < L
+  // x of level l prolongated to the finest level, through the chain buf
+  rmtr_status to_finest(int l, const double* x, double* Level::*buf) {
+    const double* src = x;
+    for (int k = l; k < c->L; ++k) {
+      double* dst = c->lv[k + 1].*buf;
+      HIPCHK(c, launch_prolong(dim(), c->lv[k].N, src, dst, 0, st));
+      src = dst;
+    }
+    return RMTR_OK;
+  }
+  // a finest-level vector restricted (R = I^T) to level l into out, through
+  // the ca chain of the levels in between
+  rmtr_status from_finest(int l, const double* fine, double* out) {
+    const double* src = fine;
+    for (int k = c->L - 1; k >= l; --k) {
+      double* dst = k == l ? out : c->lv[k].ca;
+      HIPCHK(c, launch_restrict(dim(), c->lv[k].N, RMTR_R_DUAL, src, dst, 0, st));
+      src = dst;
+    }
+    return RMTR_OK;
+  }
+  // out = grad f~^l(x)
+  rmtr_status ft_grad(int l, const double* x, double* out) {
+    Level& v = c->lv[l];
+    if (!fine_model) {
+      HIPCHK(c, launch_gradient(eargs(c, l, nullptr), x, v.p, out, st));
+      return RMTR_OK;
+    }
+    Level& f = c->lv[c->L];
+    rmtr_status r;
+    if ((r = to_finest(l, x, &Level::ca)) != RMTR_OK) return r;
+    HIPCHK(c, launch_gradient(eargs(c, c->L, fdir), f.ca, f.p, f.cc, st));
+    if ((r = from_finest(l, f.cc, out)) != RMTR_OK) return r;
+    HIPCHK(c, launch_zero_masked(dim(), v.N, out, nullptr, st));
+    return RMTR_OK;
+  }
+  // out = grad^2 f~^l(x0^l) w
+  rmtr_status ft_hv(int l, const double* w, double* out) {
+    Level& v = c->lv[l];
+    if (!fine_model) {
+      HIPCHK(c, launch_hessvec(eargs(c, l, nullptr), v.x0, v.p, w, out, 0, st));
+      return RMTR_OK;
+    }
+    Level& f = c->lv[c->L];
+    rmtr_status r;
+    if ((r = to_finest(l, v.x0, &Level::ca)) != RMTR_OK) return r;
+    if ((r = to_finest(l, w, &Level::cb)) != RMTR_OK) return r;
+    HIPCHK(c, launch_hessvec(eargs(c, c->L, fdir), f.ca, f.p, f.cb, f.cc, 0, st));
+    if ((r = from_finest(l, f.cc, out)) != RMTR_OK) return r;
+    HIPCHK(c, launch_zero_masked(dim(), v.N, out, nullptr, st));
+    return RMTR_OK;
+  }
+  // f~^l(x + s) - f~^l(x) into the device scalar out
+  rmtr_status ft_diff(int l, const double* x, const double* s, double* out) {
+    Level& v = c->lv[l];
+    if (!fine_model || l == c->L) {
+      HIPCHK(c, launch_energy(eargs(c, l, dir(l)), x, s, 0, v.p, c->partials, out, st));
+      return RMTR_OK;
+    }
+    Level& f = c->lv[c->L];
+    rmtr_status r;
+    if ((r = to_finest(l, x, &Level::ca)) != RMTR_OK) return r;
+    if ((r = to_finest(l, s, &Level::cb)) != RMTR_OK) return r;
+    HIPCHK(c, launch_energy(eargs(c, c->L, fdir), f.ca, f.cb, 0, f.p, c->partials, out, st));
+    return RMTR_OK;
+  }
+
   // out = grad h^l(x)
   rmtr_status h_grad(int l, const double* x, double* out) {
     Level& v = c->lv[l];
@@ -273,12 +351,20 @@ struct Run {
       HIPCHK(c, launch_gradient(eargs(c, l, fdir), x, v.p, out, st));
       return RMTR_OK;
     }
+    rmtr_status r;
+    if (first_order) {
+      // h = f~ + <dg, x - x0>: its Hessian is the lagged grad^2 f~ itself
+      if ((r = ft_grad(l, x, v.t3)) != RMTR_OK) return r;
+      HIPCHK(c, launch_add_scaled(v.n, v.dg, 1.0, v.t3, 1.0, nullptr, out, st));
+      HIPCHK(c, launch_zero_masked(dim(), v.N, out, nullptr, st));
+      return RMTR_OK;
+    }
     HIPCHK(c, launch_add_scaled(v.n, x, 1.0, v.x0, -1.0, nullptr, v.t1, st));
     HIPCHK(c, launch_st_matvec(dim(), v.N, v.S, v.t1, v.t2, 0, st));
     HIPCHK(c, launch_add_scaled(v.n, v.dg, 1.0, v.t2, 1.0, nullptr, out, st));
     if (energy_model) {
-      HIPCHK(c, launch_gradient(eargs(c, l, nullptr), x, v.p, v.t3, st));
-      HIPCHK(c, launch_hessvec(eargs(c, l, nullptr), v.x0, v.p, v.t1, v.t4, 0, st));
+      if ((r = ft_grad(l, x, v.t3)) != RMTR_OK) return r;
+      if ((r = ft_hv(l, v.t1, v.t4)) != RMTR_OK) return r;
       HIPCHK(c, launch_add_scaled(v.n, v.t3, 1.0, v.t4, -1.0, out, out, st));
     }
     HIPCHK(c, launch_zero_masked(dim(), v.N, out, nullptr, st));
@@ -295,13 +381,19 @@ struct Run {
                              const double* Ss = nullptr) {
     Level& v = c->lv[l];
     double* sc = c->scal + base;
+    rmtr_status r;
     if (ftilde(l)) {
-      HIPCHK(c, launch_energy(eargs(c, l, dir(l)), x, s, 0, v.p, c->partials, sc, st));
+      if ((r = ft_diff(l, x, s, sc)) != RMTR_OK) return r;
     } else {
       HIPCHK(c, launch_fill(1, 0.0, sc, st));
     }
     if (l == c->L) return RMTR_OK;
     HIPCHK(c, launch_dot(v.n, v.dg, s, c->partials, sc + 1, st));
+    if (first_order) {
+      // no dH terms
+      HIPCHK(c, launch_fill(2, 0.0, sc + 2, st));
+      return RMTR_OK;
+    }
     // t2 = (S - H~) (x - x0)
     if (kind == 2) {
       HIPCHK(c, launch_fill(1, 0.0, sc + 2, st));
@@ -309,7 +401,7 @@ struct Run {
       if (kind == 0) {
         HIPCHK(c, launch_add_scaled(v.n, x, 1.0, v.x0, -1.0, nullptr, v.t1, st));
         HIPCHK(c, launch_st_matvec(dim(), v.N, v.S, v.t1, v.t2, 0, st));
-        if (energy_model) HIPCHK(c, launch_hessvec(eargs(c, l, nullptr), v.x0, v.p, v.t1, v.t4, 0, st));
+        if (energy_model && (r = ft_hv(l, v.t1, v.t4)) != RMTR_OK) return r;
       }
       if (energy_model) HIPCHK(c, launch_add_scaled(v.n, v.t4, -1.0, nullptr, 0.0, v.t2, v.t2, st));
       HIPCHK(c, launch_dot(v.n, s, v.t2, c->partials, sc + 2, st));
@@ -321,7 +413,7 @@ struct Run {
       Sv = v.t3;
     }
     if (energy_model) {
-      HIPCHK(c, launch_hessvec(eargs(c, l, nullptr), v.x0, v.p, s, v.t4, 0, st));
+      if ((r = ft_hv(l, s, v.t4)) != RMTR_OK) return r;
       HIPCHK(c, launch_add_scaled(v.n, v.t4, -1.0, nullptr, 0.0, Sv, v.t3, st));
       Sv = v.t3;
     }
@@ -543,14 +635,21 @@ struct Run {
     HIPCHK(c, launch_add_scaled(cc.n, cc.x0, 1.0, cc.hi, 1.0, nullptr, cc.Ub, st));
     rmtr_status r = h_grad(l, x, f.g);
     if (r != RMTR_OK) return r;
-    // lagged coarse Hessian R H I (default coarse Dirichlet set) from the
-    // level's stencil
-    const bool f32 = l == c->L && mixed;
-    HIPCHK(c, launch_st_rap(d, f.N, f32 ? static_cast<const void*>(f.Sf) : static_cast<const void*>(f.S), f32 ? 1 : 0,
-                            cc.S, nullptr, c->rap_work, st));
+    if (first_order) {
+      // the coarse level's own Hessian at x0 (rediscretised, lagged); the
+      // finest level's coefficient buffer is free once its stencil is built
+      // and holds the coarse level's coefficients
+      HIPCHK(c, launch_st_assemble(eargs(c, l - 1, nullptr), cc.x0, cc.p, c->lv[c->L].coef, cc.S, 0, st));
+    } else {
+      // lagged coarse Hessian R H I (default coarse Dirichlet set) from the
+      // level's stencil
+      const bool f32 = l == c->L && mixed;
+      HIPCHK(c, launch_st_rap(d, f.N, f32 ? static_cast<const void*>(f.Sf) : static_cast<const void*>(f.S),
+                              f32 ? 1 : 0, cc.S, nullptr, c->rap_work, st));
+    }
     HIPCHK(c, launch_restrict(d, cc.N, RMTR_R_DUAL, f.g, cc.dg, 0, st));
     if (energy_model) {
-      HIPCHK(c, launch_gradient(eargs(c, l - 1, nullptr), cc.x0, cc.p, cc.t3, st));
+      if ((r = ft_grad(l - 1, cc.x0, cc.t3)) != RMTR_OK) return r;
       HIPCHK(c, launch_add_scaled(cc.n, cc.t3, -1.0, nullptr, 0.0, cc.dg, cc.dg, st));
     }
     HIPCHK(c, launch_zero_masked(d, cc.N, cc.dg, nullptr, st));
@@ -739,6 +838,7 @@ void rmtr_default_params(rmtr_params* p) {
   p->nn_patience = 3;
   p->shrink_to_step = 0;
   p->gs_mode = 0;
+  p->first_order = 0;
 }
 
 rmtr_status rmtr_create(const rmtr_model* m, rmtr_ctx** out) {
@@ -820,7 +920,7 @@ rmtr_status rmtr_energy(rmtr_ctx* c, int32_t level, const double* x, const doubl
 size_t rmtr_workspace_bytes(const rmtr_ctx* c, const rmtr_params* prm) {
   if (!c) return 0;
   if (!prm) return common_bytes();
-  return loadstep_bytes(c, prm->precision == RMTR_FP32, prm->use_learned != 0);
+  return loadstep_bytes(c, prm->precision == RMTR_FP32, prm->use_learned != 0, prm->coarse_model == 2);
 }
 
 rmtr_status rmtr_bind_workspace(rmtr_ctx* c, void* dev, size_t bytes) {
@@ -989,6 +1089,10 @@ rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lo
     return fail(c, RMTR_E_ARG, "rmtr_solve_loadstep: invalid parameters");
   if (prm->gs_mode != 0)
     return fail(c, RMTR_E_ARG, "rmtr_solve_loadstep: only gs_mode 0 (global node colours) is built");
+  if (prm->coarse_model < 0 || prm->coarse_model > 2)
+    return fail(c, RMTR_E_ARG, "rmtr_solve_loadstep: coarse_model must be 0, 1 or 2");
+  if (prm->first_order && prm->coarse_model != 0)
+    return fail(c, RMTR_E_ARG, "rmtr_solve_loadstep: first_order needs coarse_model 0 (the level's own functional)");
   if (prm->use_learned &&
       (c->model.dim != 3 || c->L < 2 || !prm->nn || !prm->nn->w || !prm->nn->bias || !prm->nn->scales))
     return fail(c, RMTR_E_ARG, "rmtr_solve_loadstep: the learned proposal needs 3D, L >= 2 and a network");
@@ -998,7 +1102,7 @@ rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lo
   if (r != RMTR_OK) return r;
   const bool mixed = prm->precision == RMTR_FP32;
   for (int l = 1; l <= c->L; ++l)
-    if ((r = ensure_solver_level(c, l, mixed)) != RMTR_OK) return r;
+    if ((r = ensure_solver_level(c, l, mixed, prm->coarse_model == 2)) != RMTR_OK) return r;
   if (!c->mprgp_work) HIPCHK(c, dalloc(c, &c->mprgp_work, mprgp_work_doubles(c->model.dim, c->lv[1].N)));
   // the finest level's stencil and its coefficients are FP32 in the mixed
   // form (with more than one level): half the memory
@@ -1009,7 +1113,7 @@ rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lo
     const size_t cv = coef_values(c->model.dim, c->lv[c->L].N);
     HIPCHK(c, grow(c, &c->lv[c->L].coef, &c->lv[c->L].coef_cap, fine32 ? (cv + 1) / 2 : cv));
   }
-  Run run{c, *prm, st, dir, mixed, prm->coarse_model == 0};
+  Run run{c, *prm, st, dir, mixed, prm->coarse_model != 1, prm->coarse_model == 2, prm->first_order != 0};
   const int L = c->L, d = c->model.dim;
   Level& f = c->lv[L];
   // pressure on every level: fine copy, then injection

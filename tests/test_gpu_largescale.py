@@ -104,20 +104,23 @@ def test_fields_and_rows_at_scale(name):
     del torch
 
 
-def test_c3_loadstep_mixed_with_workload_settings():
-    """One c3 load step in the mixed form (2 + 2 smoothing steps of 6 PGS
-    sweeps, radius measured from a rejected step) reaches chi <= 1e-8 chi0;
-    the bounds and the Dirichlet values hold exactly; the gradient rows of
-    the final iterate that chi is made of agree with the oracle's."""
+@pytest.mark.parametrize("precision", [1, 0])
+def test_c3_loadstep_with_workload_settings(precision):
+    """One c3 load step, in the mixed form (precision 1) and in plain FP64
+    (precision 0), with the workload's smoothing (2 + 2 smoothing steps of 6
+    PGS sweeps, radius measured from a rejected step), reaches
+    chi <= 1e-8 chi0; the bounds and the Dirichlet values hold exactly; the
+    gradient rows of the final iterate that chi is made of agree with the
+    oracle's."""
     import torch
     import paper_2007_12908_amd as P
     wl = W.WORKLOADS["c3_3d_256"]
     N = wl.n_cells
-    print("case c3_3d_256 mixed load step", flush=True)
+    print(f"case c3_3d_256 load step, precision {precision}", flush=True)
     ctx, c0d, pd = _setup(wl)
     x = torch.zeros(4 * (N + 1) ** 3, dtype=torch.float64, device="cuda")
     x.view(-1, 4)[:, 3] = c0d
-    st = ctx.solve_loadstep(x, pd, c0d, P.default_params(precision=1, max_vcycles=200, **wl.solver))
+    st = ctx.solve_loadstep(x, pd, c0d, P.default_params(precision=precision, max_vcycles=200, **wl.solver))
     print({k: st[k] for k in ("code", "vcycles", "chi0", "chi", "seconds")}, flush=True)
     assert st["code"] == 0 and st["chi"] <= 1e-8 * st["chi0"]
     xs, c0 = host(x), host(c0d)

@@ -45,21 +45,24 @@ def _gpu_solve(d, N, L, mat, c0, p, x, **prm):
     return host(xd), st
 
 
-@pytest.mark.parametrize("case,shrink,model", [("c1", 0, 0), ("3d", 0, 0), ("c1", 1, 0), ("3d", 1, 0),
-                                               ("c1", 0, 1), ("3d", 0, 1)])
-def test_loadstep_matches_oracle(case, shrink, model):
+@pytest.mark.parametrize("case,shrink,model,first", [
+    ("c1", 0, 0, 0), ("3d", 0, 0, 0), ("c1", 1, 0, 0), ("3d", 1, 0, 0),
+    ("c1", 0, 1, 0), ("3d", 0, 1, 0), ("3d", 0, 2, 0), ("c1", 0, 0, 1), ("3d", 0, 0, 1)])
+def test_loadstep_matches_oracle(case, shrink, model, first):
     """shrink = 1: the step-based radius update after rejections; model = 1:
-    the coarse levels minimise the pure Galerkin quadratic (f~ = 0)."""
+    the coarse levels minimise the pure Galerkin quadratic (f~ = 0); model =
+    2: f~^l = f o I_{l->L}; first = 1: first-order coarse models (no dH, the
+    level's own lagged Hessian)."""
     if case == "c1":
         g, mat, c0, p, x = _c1()
         d, N, L = 2, 64, 3
     else:
         g, mat, c0, p, x = _small3d(8)
         d, N, L = 3, 8, 2
-    print(f"case {case} shrink {shrink} coarse_model {model}", flush=True)
-    xg, st = _gpu_solve(d, N, L, mat, c0, p, x, shrink_to_step=shrink, coarse_model=model)
-    solver = rmtr.RMTR(d, N, L, mat, p, rmtr.Params(shrink_to_step=bool(shrink),
-                                                    coarse_model=("energy", "zero")[model]))
+    print(f"case {case} shrink {shrink} coarse_model {model} first_order {first}", flush=True)
+    xg, st = _gpu_solve(d, N, L, mat, c0, p, x, shrink_to_step=shrink, coarse_model=model, first_order=first)
+    solver = rmtr.RMTR(d, N, L, mat, p, rmtr.Params(shrink_to_step=bool(shrink), first_order=bool(first),
+                                                    coarse_model=("energy", "zero", "fine")[model]))
     xo, so = solver.solve_loadstep(x.copy(), c0)
     print("gpu", st["vcycles"], st["chi"] / st["chi0"], "oracle", so.vcycles, so.chi / so.chi0, flush=True)
     assert st["code"] == 0

@@ -118,3 +118,33 @@ def test_c2_fracture_table_and_inclusion():
     vol = c0.sum() * g.h ** 3
     est = np.sum(2 * g.h * np.pi * tab[:, 6] ** 2)
     assert 0.3 * est < vol < 3.0 * est
+
+
+def test_2d_network_statistics():
+    """The 2D stochastic network of the geoscience application (Sec. 5.2):
+    hypocentres uniform in the unit square, orientations uniform in
+    [-80, 80] degrees, lengths from the power law n(l) ~ l^-2 on [0.01, 0.2],
+    whose CDF is F(l) = (1/l_min - 1/l) / (1/l_min - 1/l_max); width 2h."""
+    wl = W.WORKLOADS["f2_2d_2048"]
+    tab = wl.fractures()
+    assert tab.shape == (1000, 7)
+    cx, cy, tx, ty, a, w = (tab[:, i] for i in range(6))
+    assert np.all((cx >= 0) & (cx < 1) & (cy >= 0) & (cy < 1))
+    assert np.allclose(tx * tx + ty * ty, 1.0, atol=1e-15)
+    ang = np.degrees(np.arctan2(ty, tx))
+    assert np.all(np.abs(ang) <= 80.0)
+    length = 2.0 * a
+    assert np.all((length >= 0.01) & (length <= 0.2))
+    assert np.all(w == 1.0 / 2048)
+    F = lambda l: (100.0 - 1.0 / l) / (100.0 - 5.0)  # noqa: E731
+    for q in (0.012, 0.02, 0.05, 0.1):
+        assert abs(np.mean(length <= q) - F(q)) < 0.05, q
+    for q in (-40.0, 0.0, 40.0):
+        assert abs(np.mean(ang <= q) - (q + 80.0) / 160.0) < 0.05
+    assert abs(np.mean(cx <= 0.5) - 0.5) < 0.05
+    # the same seed gives the same table; inclusion marks the rectangles
+    assert np.array_equal(tab, wl.fractures())
+    g = fem.Grid(2, 128)
+    c0, p = fields.initial_fields(g, W.rect_network_table(30, 16, 80.0, 0.05, 0.3, 2.0, 1.0 / 128, 1e-3),
+                                  p_uniform=1e-3)
+    assert 500 < c0.sum() < 2000 and np.all(p == 1e-3)

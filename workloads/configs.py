@@ -2,7 +2,7 @@
 fracture-network runs).  Sizes count cells per side on the finest level."""
 from dataclasses import dataclass, field
 
-from .fractures import disc_table, c1_crack
+from .fractures import disc_table, rect_network_table, c1_crack
 
 
 def hierarchy_nodes_per_side(coarse_nodes, n_levels):
@@ -63,7 +63,11 @@ class Workload:
 
     def fractures(self):
         if self.dim == 2:
-            return c1_crack(self.n_cells, self.p)
+            if self.n_frac == 0:
+                return c1_crack(self.n_cells, self.p)
+            e = self.extra
+            return rect_network_table(self.n_frac, self.seed, e["angle_deg"], e["l_min"], e["l_max"],
+                                      e["exponent"], self.h, self.p)
         e = self.extra
         return disc_table(self.n_frac, self.seed, e["centre_lo"], e["centre_hi"],
                           e["r_lo"], e["r_hi"], log_radius=e.get("log_radius", False),
@@ -73,6 +77,12 @@ class Workload:
 WORKLOADS = {
     # 2D, 64x64 cells, one straight crack, uniform p, 3 levels.
     "c1_2d_64": Workload("c1_2d_64", 2, 64, 3),
+    # 2D stochastic network (Sec. 5.2): 2048^2 cells (12.6 M dofs, near the
+    # paper's 13.6 M), 1000 line fractures of width 2h, hypocentres uniform,
+    # orientation U[-80, 80] degrees, lengths from n(l) ~ l^-2 on
+    # [0.01, 0.2]; p uniform; 8 levels (coarsest 16^2).
+    "f2_2d_2048": Workload("f2_2d_2048", 2, 2048, 8, seed=6, n_frac=1000,
+                           extra=dict(angle_deg=80.0, l_min=0.01, l_max=0.2, exponent=2.0)),
     # 3D, 128^3 cells, 10 discs, radii U[0.03, 0.08], centres U[0.2, 0.8]^3.
     "c2_3d_128": Workload("c2_3d_128", 3, 128, 4, seed=2, n_frac=10,
                           extra=dict(centre_lo=0.2, centre_hi=0.8, r_lo=0.03, r_hi=0.08)),

@@ -58,6 +58,27 @@ def rect_table(rows):
     return tab
 
 
+def rect_network_table(n, seed, angle_deg, l_min, l_max, exponent, half_width, p_const=0.0):
+    """n random line fractures as thin rectangles (the 2D stochastic network
+    of the paper's geoscience application, Sec. 5.2): hypocentres uniform over
+    the unit square, orientation uniform in [-angle_deg, angle_deg] degrees
+    from the x axis, length from the scale-invariant power law
+    n(l) ~ l^-exponent on [l_min, l_max] (inverse-CDF draw), width 2 half_width.
+    Draw order per fracture: centre x, y; angle; length."""
+    rng = SplitMix64(seed)
+    tab = np.zeros((n, len(RECT_COLS)), dtype=np.float64)
+    a1 = 1.0 - exponent
+    lo_p, hi_p = l_min ** a1, l_max ** a1
+    for f in range(n):
+        cx = rng.uniform()
+        cy = rng.uniform()
+        ang = math.radians(-angle_deg + 2.0 * angle_deg * rng.uniform())
+        u = rng.uniform()
+        length = (lo_p + u * (hi_p - lo_p)) ** (1.0 / a1)
+        tab[f] = (cx, cy, math.cos(ang), math.sin(ang), 0.5 * length, half_width, p_const)
+    return tab
+
+
 def c1_crack(n_cells, p=1e-3):
     """The straight 2D crack along y = 0.5 for x in [0.4, 0.6], of width 2h."""
     h = 1.0 / n_cells
