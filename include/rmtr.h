@@ -187,6 +187,16 @@ rmtr_status rmtr_init_fields(rmtr_ctx* ctx, int32_t level, const double* table, 
 rmtr_status rmtr_energy(rmtr_ctx* ctx, int32_t level, const double* x, const double* p, double* out,
                         void* stream);
 
+/* rmtr_energy for callers that cannot allocate memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid allocation): the same
+   kernels and result, with the reduction's partial sums in a fixed device
+   array of 4096 doubles held by the library on each GPU it runs on, instead
+   of context memory.  Allocates nothing (host or device).  Calls that overlap
+   on one GPU share that array and race; a level that would need more
+   partial sums than it holds is refused with RMTR_E_ARG. */
+rmtr_status rmtr_energy_noalloc(rmtr_ctx* ctx, int32_t level, const double* x, const double* p, double* out,
+                                void* stream);
+
 /* f(x + s) - f(x), accumulated element by element (numerator of eq. (rho_tr)
    and (rho_ml)); s is double (s_precision RMTR_FP64) or float (RMTR_FP32). */
 rmtr_status rmtr_energy_diff(rmtr_ctx* ctx, int32_t level, const double* x, const void* s, int32_t s_precision,

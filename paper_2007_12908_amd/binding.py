@@ -27,7 +27,7 @@ EXPORTS = [
     "rmtr_diag_blocks", "rmtr_smooth", "rmtr_restrict", "rmtr_prolong", "rmtr_coarse_hessvec", "rmtr_mprgp", "rmtr_dot", "rmtr_chi", "rmtr_solve_loadstep",
     "rmtr_step_box", "rmtr_nn_size", "rmtr_nn_forward", "rmtr_nn_backward", "rmtr_nn_mse", "rmtr_nn_adam_step",
     "rmtr_nn_to_bf16", "rmtr_nn_features", "rmtr_nn_propose", "rmtr_element_flops",
-    "rmtr_workspace_bytes", "rmtr_bind_workspace", "rmtr_workspace_used",
+    "rmtr_workspace_bytes", "rmtr_bind_workspace", "rmtr_workspace_used", "rmtr_energy_noalloc",
     "rmtr_nn_channel_rms", "rmtr_nn_target", "rmtr_nn_fit_scales",
 ]
 
@@ -114,6 +114,7 @@ def load():
             "rmtr_workspace_bytes": (ctypes.c_size_t, [P, ctypes.POINTER(Params)]),
             "rmtr_bind_workspace": (I32, [P, P, ctypes.c_size_t]),
             "rmtr_workspace_used": (ctypes.c_size_t, [P]),
+            "rmtr_energy_noalloc": (I32, [P, I32, P, P, P, P]),
             "rmtr_nn_channel_rms": (I32, [P, I32, P, P, P]),
             "rmtr_nn_target": (I32, [P, I32, P, P, P, P, P]),
             "rmtr_nn_fit_scales": (I32, [P, I32, I32, P, P, P, P, P]),
@@ -295,6 +296,13 @@ class Context:
         px, pp = self._xp(level, x, p)
         self._check(self._fn("rmtr_energy")(self.h, level, px, pp, _arr(out, "out", F64, min_numel=1), _stream()),
                     "rmtr_energy")
+        return out
+
+    def energy_noalloc(self, level, x, p, out):
+        """rmtr_energy with no allocation at all: `out` must be given."""
+        px, pp = self._xp(level, x, p)
+        self._check(self._fn("rmtr_energy_noalloc")(self.h, level, px, pp, _arr(out, "out", F64, min_numel=1),
+                                                 _stream()), "rmtr_energy_noalloc")
         return out
 
     def energy_diff(self, level, x, s, p, out=None):

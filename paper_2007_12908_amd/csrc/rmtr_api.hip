@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <chrono>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -804,6 +805,40 @@ int64_t count_kind(int kind) {
 
 }  // namespace
 
+// ----------------------------------------- fixed scratch of the no-alloc call
+// Partial sums of rmtr_energy_noalloc, one per workgroup of the energy kernel,
+// live in this fixed device array instead of allocated memory.  Each GPU the
+// library runs on holds its own copy until the process ends; every call on
+// that GPU shares it and it keeps the last call's values (each call writes
+// every partial it reads, so nothing has to start at zero).
+constexpr int kNoAllocPartials = kMaxPartials;
+__device__ __align__(256) double scratch[kNoAllocPartials];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current (the array's name is only a host-side
+// stand-in and must never reach a kernel).
+hipError_t scratch_address(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* q = nullptr;
+    e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = static_cast<double*>(q);
+  }
+  *out = g_scratch[dev];
+  return hipSuccess;
+}
+}  // namespace
+
 // ================================================================== C-ABI
 extern "C" {
 
@@ -914,6 +949,20 @@ rmtr_status rmtr_energy(rmtr_ctx* c, int32_t level, const double* x, const doubl
   rmtr_status r = ensure_common(c);
   if (r != RMTR_OK) return r;
   HIPCHK(c, launch_energy(eargs(c, level, nullptr), x, nullptr, 0, p, c->partials, out, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_energy_noalloc(rmtr_ctx* c, int32_t level, const double* x, const double* p, double* out,
+                                void* stream) {
+  if (!valid_level(c, level) || !x || !p || !out) return fail(c, RMTR_E_ARG, "rmtr_energy_noalloc: bad arguments");
+  const ElemArgs a = eargs(c, level, nullptr);
+  const int need = energy_partials(a);
+  if (need > kNoAllocPartials)
+    return fail(c, RMTR_E_ARG, "rmtr_energy_noalloc: level needs " + std::to_string(need) +
+                                   " partial sums, the fixed scratch holds " + std::to_string(kNoAllocPartials));
+  double* ptr = nullptr;
+  HIPCHK(c, scratch_address(&ptr));
+  HIPCHK(c, launch_energy(a, x, nullptr, 0, p, ptr, out, S(stream)));
   return RMTR_OK;
 }
 
