@@ -277,12 +277,29 @@ rmtr_status rmtr_chi(rmtr_ctx* ctx, int32_t level, const double* x, const double
    that PGS step from the same state would (or the PGS step would fail its
    ratio test); otherwise the PGS step runs.  A rejected proposal leaves x
    and delta unchanged.  p: fine nodal pressure; c_lower: c^{t-1} per fine node;
-   x_inout must be feasible.  chi_history (host, may be NULL) receives chi
-   after each V-cycle (max_vcycles entries).  Returns RMTR_OK,
-   RMTR_NOT_CONVERGED (x still feasible) or an error.  Synchronises. */
+   x_inout must be feasible; its Dirichlet values (the data g^t of V_u^t,
+   e.g. a prescribed displacement for displacement-driven loading) are kept.
+   f_ext (device, may be NULL): external load on the finest level (the
+   Neumann terms, rmtr_neumann_load); the functional minimised is then
+   f(x) - f_ext . x, and stats->energy reports it.  chi_history (host, may be
+   NULL) receives chi after each V-cycle (max_vcycles entries).  Returns
+   RMTR_OK, RMTR_NOT_CONVERGED (x still feasible) or an error.  Synchronises. */
 rmtr_status rmtr_solve_loadstep(rmtr_ctx* ctx, const double* p, const double* c_lower, const uint8_t* dirichlet,
-                                const rmtr_params* params, double* x_inout, rmtr_stats* stats,
-                                double* chi_history, void* stream);
+                                const double* f_ext, const rmtr_params* params, double* x_inout,
+                                rmtr_stats* stats, double* chi_history, void* stream);
+
+/* External load of the Neumann terms of eq. (pressurized) (Sec. 2.1, the
+   boundary part Gamma_N where the displacement is free):
+     b[(d+1) n + i] = int_{Gamma_N} (tbar_i + p n_i) N_n ds,  b[(d+1) n + d] = 0,
+   over the faces in face_mask (bit f = face f = 2 axis + side: x = 0, x = 1,
+   y = 0, y = 1[, z = 0, z = 1]), n the outward normal.  traction (host,
+   2d x d doubles, row f = the constant traction tbar of face f).  With the
+   pressure work of the density written as + gp(c) div(p u), the boundary
+   term of the divergence theorem enters the energy as - int p n . u, so
+   the functional with these terms is f(x) - b . x (pass b as f_ext).  Face
+   cells by the (d-1)-dimensional 2-point Gauss rule (exact). */
+rmtr_status rmtr_neumann_load(rmtr_ctx* ctx, int32_t level, int32_t face_mask, const double* traction,
+                              const double* p, double* b, void* stream);
 
 /* Trust-region step box of Alg. 3 on the finest level (Sec. 3, the
    constraints of eq. (model_qp)): lo = max(-delta, L - x), hi = min(delta,

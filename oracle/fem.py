@@ -430,6 +430,62 @@ def local_rows(grid, x, p, mat, nodes, v=None, dirichlet=None):
     return want, g_rows, hv_rows
 
 
+def face_nodes(grid, face):
+    """Nodes of boundary face `face` = 2 axis + side (side 0: coordinate 0,
+    side 1: coordinate 1) and the face's outward unit normal."""
+    axis, side = divmod(face, 2)
+    ijk = grid.node_ijk()
+    n = np.zeros(grid.d)
+    n[axis] = 1.0 if side else -1.0
+    return np.nonzero(ijk[:, axis] == side * grid.N)[0], n
+
+
+def neumann_load(grid, faces, traction, p):
+    """External load vector of the Neumann terms of eq. (pressurized) on the
+    boundary faces listed in `faces` (the part Gamma_N of the boundary where
+    the displacement is free):
+
+        b[(d+1) a + i] = int_{Gamma_N} (tbar_i + p n_i) N_a ds,
+
+    so that the functional is f(x) - b . x.  tbar: traction per face
+    (shape (2d, d), constant on a face); p: nodal pressure (Q1 on the face).
+    Reading: with the pressure work written as + int g_p div(p u) (the sign
+    that opens a pressurised crack), the boundary term of the divergence
+    theorem enters as - int_{Gamma_N} p n . u, next to - int tbar . u.
+    Face cells are integrated with the (d-1)-dimensional 2-point Gauss rule,
+    exact for the bilinear integrand."""
+    d, N, h = grid.d, grid.N, grid.h
+    b = np.zeros(grid.n_dofs)
+    gp = gauss_points_01()
+    ijk = grid.node_ijk()
+    index = {tuple(c): k for k, c in enumerate(ijk)}
+    for face in faces:
+        axis, side = divmod(face, 2)
+        tan = [i for i in range(d) if i != axis]
+        nvec = np.zeros(d)
+        nvec[axis] = 1.0 if side else -1.0
+        tb = np.asarray(traction[face], dtype=np.float64)
+        # face cells: lower corner over the tangential directions
+        for cell in np.ndindex(*([N] * (d - 1))):
+            corners = []
+            for a in range(1 << (d - 1)):
+                c = [0] * d
+                c[axis] = side * N
+                for t, ti in enumerate(tan):
+                    c[ti] = cell[t] + ((a >> t) & 1)
+                corners.append(index[tuple(c)])
+            for q in range(1 << (d - 1)):
+                xi = [gp[(q >> t) & 1] for t in range(d - 1)]
+                Na = np.array([np.prod([xi[t] if (a >> t) & 1 else 1.0 - xi[t] for t in range(d - 1)])
+                               for a in range(1 << (d - 1))])
+                wq = h ** (d - 1) / (1 << (d - 1))
+                pq = float(Na @ p[corners])
+                load = tb + pq * nvec
+                for a, node in enumerate(corners):
+                    b[(d + 1) * node:(d + 1) * node + d] += wq * Na[a] * load
+    return b
+
+
 def diag_blocks(H, grid):
     """(d+1) x (d+1) diagonal block of every node, from an assembled Hessian."""
     nc = grid.nc

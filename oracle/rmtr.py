@@ -15,6 +15,9 @@ Readings where the paper is silent (listed in the design notes):
     same discrete functional on the level-l grid (p injected, l_s unchanged),
     or f~^l = 0 ("zero" coarse model), or f~^l(x) = f(I_{l->L} x), the finest
     functional of the prolongated coarse iterate ("fine" coarse model);
+  * a caller's Dirichlet set on the finest level is injected to the
+    coarse levels (fine node (2i, 2j, 2k) -> coarse node (i, j, k)); the
+    default set (every boundary displacement) is its own injection;
   * first-order variant (ablation): dH = 0, so the coarse model is
     f~^l(x) + <dg, x - x0> and its Hessian, lagged like every other, is the
     level's own grad^2 f~^l(x0) instead of the Galerkin product (needs a
@@ -92,8 +95,11 @@ class Level:
 class RMTR:
     """RMTR on the hierarchy N_l = N_L / 2^(L-l), l = 1 (coarsest) .. L."""
 
-    def __init__(self, d, n_cells, n_levels, mat, p_fine, params=None, dirichlet=None):
+    def __init__(self, d, n_cells, n_levels, mat, p_fine, params=None, dirichlet=None, f_ext=None):
+        """f_ext: external load vector of the finest level (the Neumann terms,
+        fem.neumann_load); the finest functional is then f(x) - f_ext . x."""
         self.prm = params or Params()
+        self.f_ext = f_ext
         self.L = n_levels
         self.d = d
         Ns = [n_cells >> (n_levels - l) for l in range(1, n_levels + 1)]
@@ -101,8 +107,9 @@ class RMTR:
         self.levels = {}
         p = p_fine
         self.I, self.R, self.P = {}, {}, {}
+        mask = dirichlet
         for l in range(n_levels, 0, -1):
-            lev = Level(d, Ns[l - 1], mat, p, dirichlet if l == n_levels else None)
+            lev = Level(d, Ns[l - 1], mat, p, mask)
             self.levels[l] = lev
             if l > 1:
                 Nc = Ns[l - 2]
@@ -111,6 +118,12 @@ class RMTR:
                 self.P[l - 1] = transfer.injection(d, Nc, d + 1)
                 nodeP = transfer.injection(d, Nc, 1)
                 p = nodeP @ p
+                # a caller's Dirichlet set reaches the coarse levels by
+                # injection (the coarse dof is fixed where the fine dof it
+                # coincides with is); otherwise every level has the default
+                # set
+                if dirichlet is not None:
+                    mask = (self.P[l - 1] @ lev.dirichlet.astype(np.float64)) > 0.5
         self.levels[n_levels].finest = True
         # composite prolongations I_{l -> L} for the "fine" coarse model
         self.IL = {n_levels: None}
@@ -131,12 +144,30 @@ class RMTR:
     def _fine(self):
         return self.levels[self.L]
 
+    # ------------------------------------------------- finest functional
+    def fine_energy(self, x):
+        f = self._fine()
+        e = fem.energy(f.grid, x, f.p, f.mat)
+        return e if self.f_ext is None else e - float(self.f_ext @ x)
+
+    def fine_energy_diff(self, x, s):
+        f = self._fine()
+        e = fem.energy_diff(f.grid, x, s, f.p, f.mat)
+        return e if self.f_ext is None else e - float(self.f_ext @ s)
+
+    def fine_gradient(self, x):
+        f = self._fine()
+        g = fem.gradient(f.grid, x, f.p, f.mat, f.dirichlet)
+        if self.f_ext is not None:
+            g = g - self.f_ext
+            g[f.dirichlet] = 0.0
+        return g
+
     def ft_grad(self, lev, x):
         """grad f~ of a coarse level (Dirichlet rows zeroed)."""
         if self.prm.coarse_model == "fine":
-            f = self._fine()
             IL = self.IL[self._level_index(lev)]
-            g = IL.T @ fem.gradient(f.grid, IL @ x, f.p, f.mat, f.dirichlet)
+            g = IL.T @ self.fine_gradient(IL @ x)
             g[lev.dirichlet] = 0.0
             return g
         return fem.gradient(lev.grid, x, lev.p, lev.mat, lev.dirichlet)
@@ -153,10 +184,11 @@ class RMTR:
 
     def ft_diff(self, lev, x, s):
         """f~(x + s) - f~(x) of any level."""
-        if not lev.finest and self.prm.coarse_model == "fine":
-            f = self._fine()
+        if lev.finest:
+            return self.fine_energy_diff(x, s)
+        if self.prm.coarse_model == "fine":
             IL = self.IL[self._level_index(lev)]
-            return fem.energy_diff(f.grid, IL @ x, IL @ s, f.p, f.mat)
+            return self.fine_energy_diff(IL @ x, IL @ s)
         return fem.energy_diff(lev.grid, x, s, lev.p, lev.mat)
 
     def _level_index(self, lev):
@@ -167,7 +199,7 @@ class RMTR:
 
     def h_grad(self, lev, x):
         if lev.finest:
-            return fem.gradient(lev.grid, x, lev.p, lev.mat, lev.dirichlet)
+            return self.fine_gradient(x)
         g = lev.dg + lev.Hmod @ (x - lev.x0)
         if self._ftilde_active(lev):
             g = g + self.ft_grad(lev, x) - lev.Hf0 @ (x - lev.x0)
@@ -319,9 +351,9 @@ class RMTR:
         fine.Ub[self.d::nc] = 1.0
         self.stats = Stats()
         delta = prm.delta0
-        g = fem.gradient(fine.grid, x, fine.p, fine.mat, fine.dirichlet)
+        g = self.fine_gradient(x)
         chi0 = fem.chi(fine.grid, x, g, c_lower, fine.dirichlet)
-        self.f_ref = fem.energy(fine.grid, x, fine.p, fine.mat)
+        self.f_ref = self.fine_energy(x)
         self.stats.chi0 = self.stats.chi = chi0
         if chi0 == 0.0:
             return x, self.stats
@@ -329,12 +361,12 @@ class RMTR:
             fine.x0 = x.copy()
             fine.Hmod = fem.hessian(fine.grid, x, fine.p, fine.mat, fine.dirichlet)
             x, delta = self.vcycle(self.L, x, delta)
-            g = fem.gradient(fine.grid, x, fine.p, fine.mat, fine.dirichlet)
+            g = self.fine_gradient(x)
             chi = fem.chi(fine.grid, x, g, c_lower, fine.dirichlet)
             self.stats.vcycles = v + 1
             self.stats.chi = chi
             self.stats.history.append((chi, delta))
             if chi <= prm.rtol * chi0:
                 break
-        self.stats.energy = fem.energy(fine.grid, x, fine.p, fine.mat)
+        self.stats.energy = self.fine_energy(x)
         return x, self.stats

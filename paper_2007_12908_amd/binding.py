@@ -28,7 +28,7 @@ EXPORTS = [
     "rmtr_step_box", "rmtr_nn_size", "rmtr_nn_forward", "rmtr_nn_backward", "rmtr_nn_mse", "rmtr_nn_adam_step",
     "rmtr_nn_to_bf16", "rmtr_nn_features", "rmtr_nn_propose", "rmtr_element_flops",
     "rmtr_workspace_bytes", "rmtr_bind_workspace", "rmtr_workspace_used", "rmtr_energy_noalloc",
-    "rmtr_nn_channel_rms", "rmtr_nn_target", "rmtr_nn_fit_scales",
+    "rmtr_nn_channel_rms", "rmtr_nn_target", "rmtr_nn_fit_scales", "rmtr_neumann_load",
 ]
 
 NN_WEIGHTS = 120960
@@ -99,8 +99,9 @@ def load():
                                  ctypes.POINTER(I32), P]),
             "rmtr_dot": (I32, [P, I64, P, P, P, P]),
             "rmtr_chi": (I32, [P, I32, P, P, P, P, P, P]),
-            "rmtr_solve_loadstep": (I32, [P, P, P, P, ctypes.POINTER(Params), P, ctypes.POINTER(Stats),
+            "rmtr_solve_loadstep": (I32, [P, P, P, P, P, ctypes.POINTER(Params), P, ctypes.POINTER(Stats),
                                           P, P]),
+            "rmtr_neumann_load": (I32, [P, I32, I32, P, P, P, P]),
             "rmtr_element_flops": (I64, [I32, I32]),
             "rmtr_step_box": (I32, [P, I32, P, P, D, P, P, P, P]),
             "rmtr_nn_size": (I64, [I32, I32, I32, I32]),
@@ -514,16 +515,33 @@ class Context:
         return out
 
     # -- load step
-    def solve_loadstep(self, x, p, c_lower, params=None, dirichlet=None, history=False):
+    def neumann_load(self, level, faces, traction, p):
+        """External load of the Neumann terms on the listed faces (face =
+        2 axis + side); traction: (2d, d) array of constant face tractions."""
+        import numpy as np
+        mask = 0
+        for f in faces:
+            mask |= 1 << int(f)
+        tr = np.ascontiguousarray(traction, dtype=np.float64)
+        if tr.shape != (2 * self.dim, self.dim):
+            raise ValueError(f"traction: shape {tr.shape}, expected {(2 * self.dim, self.dim)}")
+        b = torch.empty(self.level_dofs(level), dtype=torch.float64, device=p.device)
+        self._check(self._fn("rmtr_neumann_load")(self.h, level, mask, tr.ctypes.data_as(ctypes.c_void_p),
+                                                  _arr(p, "p", F64, self.level_nodes(level)), _ptr(b), _stream()),
+                    "rmtr_neumann_load")
+        return b
+
+    def solve_loadstep(self, x, p, c_lower, params=None, dirichlet=None, history=False, f_ext=None):
         import numpy as np
         prm = params if params is not None else default_params()
         L = self.L
         px = _arr(x, "x", F64, self.level_dofs(L))
         pp = _arr(p, "p", F64, self.level_nodes(L))
         pc = _arr(c_lower, "c_lower", F64, self.level_nodes(L))
+        pf = _arr(f_ext, "f_ext", F64, self.level_dofs(L), optional=True)
         st = Stats()
         hist = np.zeros(max(prm.max_vcycles, 1), dtype=np.float64)
-        code = self._check(self._fn("rmtr_solve_loadstep")(self.h, pp, pc, self._dir(L, dirichlet),
+        code = self._check(self._fn("rmtr_solve_loadstep")(self.h, pp, pc, self._dir(L, dirichlet), pf,
                                                         ctypes.byref(prm), px, ctypes.byref(st),
                                                         hist.ctypes.data_as(ctypes.c_void_p), _stream()),
                            "rmtr_solve_loadstep")

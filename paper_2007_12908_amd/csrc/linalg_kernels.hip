@@ -223,8 +223,8 @@ __global__ __launch_bounds__(kB) void k_clamp(int64_t n, const double* __restric
 }
 
 // coarse scalar nodal field = fine values at nodes (2i, 2j, 2k)
-template <int DIM>
-__global__ __launch_bounds__(kB) void k_inject_scalar(int Nc, const double* __restrict__ f, double* __restrict__ c) {
+template <int DIM, typename T>
+__global__ __launch_bounds__(kB) void k_inject_scalar(int Nc, const T* __restrict__ f, T* __restrict__ c) {
   const int64_t nsc = Nc + 1, nsf = 2 * Nc + 1;
   int64_t nn = 1;
 #pragma unroll
@@ -252,9 +252,19 @@ hipError_t launch_inject_scalar(int dim, int Nc, const double* fine, double* coa
   int64_t nn = 1;
   for (int i = 0; i < dim; ++i) nn *= (Nc + 1);
   if (dim == 3)
-    hipLaunchKernelGGL(k_inject_scalar<3>, dim3(gridn(nn)), dim3(kB), 0, st, Nc, fine, coarse);
+    hipLaunchKernelGGL((k_inject_scalar<3, double>), dim3(gridn(nn)), dim3(kB), 0, st, Nc, fine, coarse);
   else
-    hipLaunchKernelGGL(k_inject_scalar<2>, dim3(gridn(nn)), dim3(kB), 0, st, Nc, fine, coarse);
+    hipLaunchKernelGGL((k_inject_scalar<2, double>), dim3(gridn(nn)), dim3(kB), 0, st, Nc, fine, coarse);
+  return hipGetLastError();
+}
+
+hipError_t launch_inject_mask(int dim, int Nc, const uint8_t* fine, uint8_t* coarse, hipStream_t st) {
+  int64_t nn = 1;
+  for (int i = 0; i < dim; ++i) nn *= (Nc + 1);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_inject_scalar<3, uint8_t>), dim3(gridn(nn)), dim3(kB), 0, st, Nc, fine, coarse);
+  else
+    hipLaunchKernelGGL((k_inject_scalar<2, uint8_t>), dim3(gridn(nn)), dim3(kB), 0, st, Nc, fine, coarse);
   return hipGetLastError();
 }
 

@@ -43,6 +43,9 @@ struct Level {
   double* coefop = nullptr;
   // prolongation / restriction chains of the coarse model f~ = f o I
   double *ca = nullptr, *cb = nullptr, *cc = nullptr;
+  // Dirichlet bits of a coarse level when the finest level has its own
+  // set (injected from the level above)
+  uint8_t* mask = nullptr;
   bool solver_ready = false;
 };
 
@@ -166,6 +169,7 @@ rmtr_status ensure_solver_level(rmtr_ctx* c, int l, bool mixed, bool fine_model)
                        &v.t1, &v.t2, &v.t3, &v.t4};
     for (double** b : vecs) HIPCHK(c, dalloc(c, b, n));
     HIPCHK(c, dalloc(c, &v.p, size_t(v.nodes)));
+    if (l < c->L) HIPCHK(c, dalloc(c, &v.mask, size_t(v.nodes)));
     v.solver_ready = true;
   }
   // stencil of the lagged Hessian: FP32 on the finest level in mixed mode
@@ -195,6 +199,7 @@ size_t loadstep_bytes(const rmtr_ctx* c, bool mixed, bool learned, bool fine_mod
     const Level& v = c->lv[l];
     if (fine_model && l >= 2) b += (l == L ? 3 : 2) * buf_bytes(size_t(v.n) * sizeof(double));
     b += 15 * buf_bytes(size_t(v.n) * sizeof(double)) + buf_bytes(size_t(v.nodes) * sizeof(double));
+    if (l < L) b += buf_bytes(size_t(v.nodes));
     const bool f32 = mixed && l == L && L > 1;
     b += buf_bytes(stencil_values(d, v.N) * (f32 ? sizeof(float) : sizeof(double)));
     if (mixed && l == L) b += 5 * buf_bytes(size_t(v.n) * sizeof(float)) + buf_bytes(size_t(v.nodes) * sizeof(float));
@@ -255,6 +260,7 @@ struct Run {
   rmtr_params prm;
   hipStream_t st;
   const uint8_t* fdir;
+  const double* fext;      // external load of the finest level (may be null)
   bool mixed;
   bool energy_model;       // coarse levels carry f~ (coarse_model 0 or 2)
   bool fine_model;         // f~^l = f o I_{l->L} (coarse_model 2)
@@ -265,7 +271,9 @@ struct Run {
   rmtr_status status = RMTR_OK;
   bool trace = false;  // per-step log on stderr (RMTR_VERBOSE=2)
 
-  const uint8_t* dir(int l) const { return l == c->L ? fdir : nullptr; }
+  // Dirichlet bits of level l: the caller's on the finest level and, when
+  // it gave one, their injection on the coarse levels; else the default set
+  const uint8_t* dir(int l) const { return l == c->L ? fdir : (fdir ? c->lv[l].mask : nullptr); }
   int dim() const { return c->model.dim; }
 
   rmtr_status fetch(int k, bool with_flag) {
@@ -276,6 +284,29 @@ struct Run {
   }
 
   bool ftilde(int l) const { return l == c->L || energy_model; }
+
+  // ---- the finest functional f(x) - f_ext . x
+  // out = grad of the finest functional at x (Dirichlet rows zero)
+  rmtr_status fine_grad(const double* x, double* out) {
+    Level& f = c->lv[c->L];
+    HIPCHK(c, launch_gradient(eargs(c, c->L, fdir), x, f.p, out, st));
+    if (fext) {
+      HIPCHK(c, launch_add_scaled(f.n, out, 1.0, fext, -1.0, nullptr, out, st));
+      HIPCHK(c, launch_zero_masked(dim(), f.N, out, fdir, st));
+    }
+    return RMTR_OK;
+  }
+  // out (device scalar) = f(x + s) - f(x) on the finest level; tmp: one
+  // more device scalar
+  rmtr_status fine_diff(const double* x, const double* s, double* out, double* tmp) {
+    Level& f = c->lv[c->L];
+    HIPCHK(c, launch_energy(eargs(c, c->L, fdir), x, s, 0, f.p, c->partials, out, st));
+    if (fext) {
+      HIPCHK(c, launch_dot(f.n, fext, s, c->partials, tmp, st));
+      HIPCHK(c, launch_add_scaled(1, out, 1.0, tmp, -1.0, nullptr, out, st));
+    }
+    return RMTR_OK;
+  }
 
   // ---- the coarse functional f~^l of a level l < L
   // x of level l prolongated to the finest level, through the chain buf
@@ -303,22 +334,22 @@ struct Run {
   rmtr_status ft_grad(int l, const double* x, double* out) {
     Level& v = c->lv[l];
     if (!fine_model) {
-      HIPCHK(c, launch_gradient(eargs(c, l, nullptr), x, v.p, out, st));
+      HIPCHK(c, launch_gradient(eargs(c, l, dir(l)), x, v.p, out, st));
       return RMTR_OK;
     }
     Level& f = c->lv[c->L];
     rmtr_status r;
     if ((r = to_finest(l, x, &Level::ca)) != RMTR_OK) return r;
-    HIPCHK(c, launch_gradient(eargs(c, c->L, fdir), f.ca, f.p, f.cc, st));
+    if ((r = fine_grad(f.ca, f.cc)) != RMTR_OK) return r;
     if ((r = from_finest(l, f.cc, out)) != RMTR_OK) return r;
-    HIPCHK(c, launch_zero_masked(dim(), v.N, out, nullptr, st));
+    HIPCHK(c, launch_zero_masked(dim(), v.N, out, dir(l), st));
     return RMTR_OK;
   }
   // out = grad^2 f~^l(x0^l) w
   rmtr_status ft_hv(int l, const double* w, double* out) {
     Level& v = c->lv[l];
     if (!fine_model) {
-      HIPCHK(c, launch_hessvec(eargs(c, l, nullptr), v.x0, v.p, w, out, 0, st));
+      HIPCHK(c, launch_hessvec(eargs(c, l, dir(l)), v.x0, v.p, w, out, 0, st));
       return RMTR_OK;
     }
     Level& f = c->lv[c->L];
@@ -327,13 +358,14 @@ struct Run {
     if ((r = to_finest(l, w, &Level::cb)) != RMTR_OK) return r;
     HIPCHK(c, launch_hessvec(eargs(c, c->L, fdir), f.ca, f.p, f.cb, f.cc, 0, st));
     if ((r = from_finest(l, f.cc, out)) != RMTR_OK) return r;
-    HIPCHK(c, launch_zero_masked(dim(), v.N, out, nullptr, st));
+    HIPCHK(c, launch_zero_masked(dim(), v.N, out, dir(l), st));
     return RMTR_OK;
   }
   // f~^l(x + s) - f~^l(x) into the device scalar out
   rmtr_status ft_diff(int l, const double* x, const double* s, double* out) {
     Level& v = c->lv[l];
-    if (!fine_model || l == c->L) {
+    if (l == c->L) return fine_diff(x, s, out, c->scal + 63);
+    if (!fine_model) {
       HIPCHK(c, launch_energy(eargs(c, l, dir(l)), x, s, 0, v.p, c->partials, out, st));
       return RMTR_OK;
     }
@@ -341,23 +373,19 @@ struct Run {
     rmtr_status r;
     if ((r = to_finest(l, x, &Level::ca)) != RMTR_OK) return r;
     if ((r = to_finest(l, s, &Level::cb)) != RMTR_OK) return r;
-    HIPCHK(c, launch_energy(eargs(c, c->L, fdir), f.ca, f.cb, 0, f.p, c->partials, out, st));
-    return RMTR_OK;
+    return fine_diff(f.ca, f.cb, out, c->scal + 63);
   }
 
   // out = grad h^l(x)
   rmtr_status h_grad(int l, const double* x, double* out) {
     Level& v = c->lv[l];
-    if (l == c->L) {
-      HIPCHK(c, launch_gradient(eargs(c, l, fdir), x, v.p, out, st));
-      return RMTR_OK;
-    }
+    if (l == c->L) return fine_grad(x, out);
     rmtr_status r;
     if (first_order) {
       // h = f~ + <dg, x - x0>: its Hessian is the lagged grad^2 f~ itself
       if ((r = ft_grad(l, x, v.t3)) != RMTR_OK) return r;
       HIPCHK(c, launch_add_scaled(v.n, v.dg, 1.0, v.t3, 1.0, nullptr, out, st));
-      HIPCHK(c, launch_zero_masked(dim(), v.N, out, nullptr, st));
+      HIPCHK(c, launch_zero_masked(dim(), v.N, out, dir(l), st));
       return RMTR_OK;
     }
     HIPCHK(c, launch_add_scaled(v.n, x, 1.0, v.x0, -1.0, nullptr, v.t1, st));
@@ -368,7 +396,7 @@ struct Run {
       if ((r = ft_hv(l, v.t1, v.t4)) != RMTR_OK) return r;
       HIPCHK(c, launch_add_scaled(v.n, v.t3, 1.0, v.t4, -1.0, out, out, st));
     }
-    HIPCHK(c, launch_zero_masked(dim(), v.N, out, nullptr, st));
+    HIPCHK(c, launch_zero_masked(dim(), v.N, out, dir(l), st));
     return RMTR_OK;
   }
 
@@ -640,20 +668,20 @@ struct Run {
       // the coarse level's own Hessian at x0 (rediscretised, lagged); the
       // finest level's coefficient buffer is free once its stencil is built
       // and holds the coarse level's coefficients
-      HIPCHK(c, launch_st_assemble(eargs(c, l - 1, nullptr), cc.x0, cc.p, c->lv[c->L].coef, cc.S, 0, st));
+      HIPCHK(c, launch_st_assemble(eargs(c, l - 1, dir(l - 1)), cc.x0, cc.p, c->lv[c->L].coef, cc.S, 0, st));
     } else {
       // lagged coarse Hessian R H I (default coarse Dirichlet set) from the
       // level's stencil
       const bool f32 = l == c->L && mixed;
       HIPCHK(c, launch_st_rap(d, f.N, f32 ? static_cast<const void*>(f.Sf) : static_cast<const void*>(f.S),
-                              f32 ? 1 : 0, cc.S, nullptr, c->rap_work, st));
+                              f32 ? 1 : 0, cc.S, dir(l - 1), c->rap_work, st));
     }
     HIPCHK(c, launch_restrict(d, cc.N, RMTR_R_DUAL, f.g, cc.dg, 0, st));
     if (energy_model) {
       if ((r = ft_grad(l - 1, cc.x0, cc.t3)) != RMTR_OK) return r;
       HIPCHK(c, launch_add_scaled(cc.n, cc.t3, -1.0, nullptr, 0.0, cc.dg, cc.dg, st));
     }
-    HIPCHK(c, launch_zero_masked(d, cc.N, cc.dg, nullptr, st));
+    HIPCHK(c, launch_zero_masked(d, cc.N, cc.dg, dir(l - 1), st));
     return RMTR_OK;
   }
 
@@ -1129,8 +1157,8 @@ rmtr_status rmtr_chi(rmtr_ctx* c, int32_t level, const double* x, const double* 
 }
 
 rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lower, const uint8_t* dir,
-                                const rmtr_params* prm, double* x, rmtr_stats* stats, double* chi_history,
-                                void* stream) {
+                                const double* f_ext, const rmtr_params* prm, double* x, rmtr_stats* stats,
+                                double* chi_history, void* stream) {
   if (!c || !p || !c_lower || !prm || !x) return fail(c, RMTR_E_ARG, "rmtr_solve_loadstep: bad arguments");
   if (prm->mu1 < 0 || prm->mu2 < 0 || prm->pgs_sweeps < 0 || prm->max_vcycles < 0 || !(prm->eta1 > 0.0) ||
       prm->eta1 > prm->eta2 || !(prm->gamma1 > 0.0) || prm->gamma1 > 1.0 || prm->gamma2 < 1.0 ||
@@ -1162,7 +1190,7 @@ rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lo
     const size_t cv = coef_values(c->model.dim, c->lv[c->L].N);
     HIPCHK(c, grow(c, &c->lv[c->L].coef, &c->lv[c->L].coef_cap, fine32 ? (cv + 1) / 2 : cv));
   }
-  Run run{c, *prm, st, dir, mixed, prm->coarse_model != 1, prm->coarse_model == 2, prm->first_order != 0};
+  Run run{c, *prm, st, dir, f_ext, mixed, prm->coarse_model != 1, prm->coarse_model == 2, prm->first_order != 0};
   const int L = c->L, d = c->model.dim;
   Level& f = c->lv[L];
   // pressure on every level: fine copy, then injection
@@ -1170,13 +1198,20 @@ rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lo
   for (int l = L - 1; l >= 1; --l) HIPCHK(c, launch_inject_scalar(d, c->lv[l].N, c->lv[l + 1].p, c->lv[l].p, st));
   if (mixed) HIPCHK(c, launch_convert(f.nodes, f.p, 0, f.pf, 1, st));
   HIPCHK(c, launch_fine_bounds(d, f.N, c_lower, f.Lb, f.Ub, st));
+  if (dir)
+    for (int l = L - 1; l >= 1; --l)
+      HIPCHK(c, launch_inject_mask(d, c->lv[l].N, l + 1 == L ? dir : c->lv[l + 1].mask, c->lv[l].mask, st));
   double delta = prm->delta0;
-  HIPCHK(c, launch_gradient(eargs(c, L, dir), x, f.p, f.g, st));
+  if ((r = run.fine_grad(x, f.g)) != RMTR_OK) return r;
   HIPCHK(c, launch_chi(d, f.N, x, f.g, c_lower, dir, c->partials, c->scal, st));
   HIPCHK(c, launch_energy(eargs(c, L, dir), x, nullptr, 0, f.p, c->partials, c->scal + 1, st));
-  if ((r = run.fetch(2, false)) != RMTR_OK) return r;
+  if (f_ext)
+    HIPCHK(c, launch_dot(f.n, f_ext, x, c->partials, c->scal + 2, st));
+  else
+    HIPCHK(c, launch_fill(1, 0.0, c->scal + 2, st));
+  if ((r = run.fetch(3, false)) != RMTR_OK) return r;
   const double chi0 = sqrt(c->hs[0]);
-  run.f_ref = c->hs[1];
+  run.f_ref = c->hs[1] - c->hs[2];
   rmtr_stats out{};
   out.chi0 = out.chi = chi0;
   int vc = 0;
@@ -1197,7 +1232,7 @@ rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lo
       }
       if ((r = run.vcycle(L, x, delta)) != RMTR_OK) return r;
       ++vc;
-      HIPCHK(c, launch_gradient(eargs(c, L, dir), x, f.p, f.g, st));
+      if ((r = run.fine_grad(x, f.g)) != RMTR_OK) return r;
       HIPCHK(c, launch_chi(d, f.N, x, f.g, c_lower, dir, c->partials, c->scal, st));
       if ((r = run.fetch(1, false)) != RMTR_OK) return r;
       out.chi = sqrt(c->hs[0]);
@@ -1212,8 +1247,12 @@ rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lo
     }
   }
   HIPCHK(c, launch_energy(eargs(c, L, dir), x, nullptr, 0, f.p, c->partials, c->scal, st));
-  if ((r = run.fetch(1, false)) != RMTR_OK) return r;
-  out.energy = c->hs[0];
+  if (f_ext)
+    HIPCHK(c, launch_dot(f.n, f_ext, x, c->partials, c->scal + 1, st));
+  else
+    HIPCHK(c, launch_fill(1, 0.0, c->scal + 1, st));
+  if ((r = run.fetch(2, false)) != RMTR_OK) return r;
+  out.energy = c->hs[0] - c->hs[1];
   out.vcycles = vc;
   out.tr_accepted = run.accepted;
   out.tr_rejected = run.rejected;
@@ -1237,6 +1276,19 @@ rmtr_status rmtr_step_box(rmtr_ctx* c, int32_t level, const double* x, const dou
   double* Ub = c->box_tmp + v.n;
   HIPCHK(c, launch_fine_bounds(c->model.dim, v.N, cl, Lb, Ub, S(stream)));
   HIPCHK(c, launch_step_box(c->model.dim, v.N, x, Lb, Ub, delta, dir, lo, hi, S(stream)));
+  return RMTR_OK;
+}
+
+rmtr_status rmtr_neumann_load(rmtr_ctx* c, int32_t level, int32_t face_mask, const double* traction,
+                              const double* p, double* b, void* stream) {
+  if (!valid_level(c, level) || !b || !p || face_mask < 0 || face_mask >= (1 << (2 * c->model.dim)) ||
+      (face_mask && !traction))
+    return fail(c, RMTR_E_ARG, "rmtr_neumann_load: bad arguments");
+  NeumannTraction tr{};
+  const int d = c->model.dim;
+  for (int f = 0; f < 2 * d; ++f)
+    for (int i = 0; i < d; ++i) tr.t[f][i] = traction ? traction[d * f + i] : 0.0;
+  HIPCHK(c, launch_neumann_load(d, c->lv[level].N, face_mask, tr, p, b, S(stream)));
   return RMTR_OK;
 }
 

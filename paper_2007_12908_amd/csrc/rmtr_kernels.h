@@ -65,6 +65,16 @@ hipError_t launch_restrict(int dim, int Nc, int mode, const void* xf, void* xc, 
 hipError_t launch_init_fields(int dim, int N, const double* table, int n_frac, double band, int p_mode,
                               double p_value, double p_band, double* c0, double* p, hipStream_t st);
 
+// ---- Neumann boundary load (boundary_kernels.hip)
+// traction per face (face = 2 axis + side), constant on the face
+struct NeumannTraction {
+  double t[6][3];
+};
+// b = int_{Gamma_N} (tbar + p n) N ds on the u components of the faces in
+// face_mask (bit f = face f), 0 elsewhere (c components included)
+hipError_t launch_neumann_load(int dim, int N, int face_mask, const NeumannTraction& tr, const double* p, double* b,
+                               hipStream_t st);
+
 // ---- vector kernels (linalg_kernels.hip)
 hipError_t launch_dot(int64_t n, const double* a, const double* b, double* partials, double* out,
                       hipStream_t st);
@@ -84,6 +94,9 @@ hipError_t launch_zero_masked(int dim, int N, double* v, const uint8_t* dir, hip
 hipError_t launch_fill(int64_t n, double v, double* out, hipStream_t st);
 hipError_t launch_clamp(int64_t n, const double* lo, const double* hi, double* s, hipStream_t st);
 hipError_t launch_inject_scalar(int dim, int Nc, const double* fine, double* coarse, hipStream_t st);
+// per-node Dirichlet bits of a coarse level: those of the fine node it
+// coincides with (fine node (2i, 2j, 2k) -> coarse node (i, j, k))
+hipError_t launch_inject_mask(int dim, int Nc, const uint8_t* fine, uint8_t* coarse, hipStream_t st);
 hipError_t launch_any_nonzero(int64_t n, const double* v, int* flag, hipStream_t st);
 
 // ---- MPRGP (mprgp.hip)

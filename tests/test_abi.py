@@ -156,6 +156,6 @@ def test_bind_workspace_and_gs_mode_argument_checks_without_gpu():
     assert b"once" in lib.rmtr_last_error(h)
     prm = binding.default_params(gs_mode=1)
     st = binding.Stats()
-    r = lib.rmtr_solve_loadstep(h, fake, fake, None, ctypes.byref(prm), fake, ctypes.byref(st), None, None)
+    r = lib.rmtr_solve_loadstep(h, fake, fake, None, None, ctypes.byref(prm), fake, ctypes.byref(st), None, None)
     assert r == binding.RMTR_E_ARG and b"gs_mode" in lib.rmtr_last_error(h)
     lib.rmtr_destroy(h)

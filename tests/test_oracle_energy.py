@@ -278,3 +278,34 @@ def test_energy_difference_is_a_difference_and_matches_taylor(d, N):
         assert abs(de - (fem.energy(g, x + s, p, mat) - f0)) <= 1e-13 * abs(f0)
         gaps.append(abs(de - (gr @ s + 0.5 * s @ (H @ s))))
     assert gaps[1] > 0 and 7.0 <= gaps[0] / gaps[1] <= 9.0
+
+
+@pytest.mark.parametrize("d,N", [(2, 5), (3, 3)])
+def test_neumann_load_divergence_theorem(d, N):
+    """The pressure work of an intact body (c = 0, so g_p = 1) with no
+    Dirichlet set equals the boundary term b . u of every face (divergence
+    theorem, exact under the Gauss rules for Q1 fields), so f(x) - b . x
+    carries no pressure load where the material is intact; and a uniform
+    traction on one face integrates to traction x face area."""
+    rng = np.random.default_rng(4 + d)
+    g = fem.Grid(d, N)
+    mat = fem.material_from_E_nu(1.0, 0.3, 1e-3, 2.0 / N)
+    x = rng.standard_normal(g.n_dofs) * 1e-2
+    x[d::d + 1] = 0.0
+    p = rng.uniform(0.5, 1.5, g.n_nodes) * 1e-3
+    work = fem.energy(g, x, p, mat) - fem.energy(g, x, np.zeros(g.n_nodes), mat)
+    b = fem.neumann_load(g, range(2 * d), np.zeros((2 * d, d)), p)
+    assert work == pytest.approx(float(b @ x), rel=1e-12)
+    # uniform traction on the face x = 1 (face 1), no pressure
+    tb = np.zeros((2 * d, d))
+    tb[1] = rng.standard_normal(d)
+    b1 = fem.neumann_load(g, [1], tb, np.zeros(g.n_nodes)).reshape(-1, d + 1)
+    assert np.allclose(b1[:, :d].sum(axis=0), tb[1], rtol=1e-13, atol=0)
+    nodes, nrm = fem.face_nodes(g, 1)
+    assert np.all(b1[np.setdiff1d(np.arange(g.n_nodes), nodes)] == 0.0)
+    assert np.all(b1[:, d] == 0.0)
+    # uniform pressure on face y = 0 (face 2): sum = p0 n area
+    b2 = fem.neumann_load(g, [2], np.zeros((2 * d, d)), np.full(g.n_nodes, 2e-3)).reshape(-1, d + 1)
+    want = np.zeros(d)
+    want[1] = -2e-3
+    assert np.allclose(b2[:, :d].sum(axis=0), want, rtol=1e-13, atol=1e-18)
