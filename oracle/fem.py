@@ -12,8 +12,13 @@ the readings listed in the design notes):
   psi+ = K/2 <t>+^2 + mu e:e,  psi- = K/2 <t>-^2,   t = tr eps,  e = eps - t/3 I3,
   K    = lambda + 2 mu / 3   (volumetric-deviatoric split; in 2D plane strain).
 
-With split=False the paper's unsplit density is used: psi+ = psi_e =
-lambda/2 t^2 + mu eps:eps, psi- = 0 (Sec. 2, first paragraph).
+With split=False (0) the paper's unsplit density is used: psi+ = psi_e =
+lambda/2 t^2 + mu eps:eps, psi- = 0 (Sec. 2, first paragraph).  split=2 is
+the spectral split on the principal strains eps_a (the principal strains the
+implementation section names among its precomputed quantities; Miehe, Hofacker
+and Welschinger's form):
+  psi+- = lambda/2 <t>+-^2 + mu sum_a <eps_a>+-^2,
+  sigma+- = lambda <t>+- I + 2 mu eps+-,   eps+- = sum_a <eps_a>+- n_a n_a^T.
 
 z_q collects, at one quadrature point, the values that W depends on:
   z = (u_0..u_{d-1}, G_00, G_01, .., G_{d-1,d-1}, c, dc_0..dc_{d-1}),
@@ -32,6 +37,9 @@ import numpy as np
 import scipy.sparse as sp
 
 
+SPLIT_NONE, SPLIT_VOLDEV, SPLIT_SPECTRAL = 0, 1, 2
+
+
 @dataclass
 class Material:
     lam: float
@@ -39,7 +47,7 @@ class Material:
     Gc: float
     ls: float
     k: float = 1e-6
-    split: bool = True
+    split: int = SPLIT_VOLDEV  # True / False read as 1 / 0
 
     @property
     def K(self):
@@ -188,13 +196,39 @@ def _unpack(z, d):
     return u, G, c, dc
 
 
+def principal_strains(eps):
+    """Eigenvalues (ascending) and unit eigenvectors (columns) of the
+    symmetric strain at every point (LAPACK's symmetric eigensolver)."""
+    return np.linalg.eigh(eps)
+
+
+def spectral_theta(ev):
+    """theta_ab of the derivative of eps+ = sum_a <eps_a>+ n_a n_a^T:
+    dEps+ = sum_ab theta_ab (n_a^T dEps n_b) n_a n_b^T with theta_aa =
+    H(eps_a) and, for eps_a != eps_b, the divided difference
+    (<eps_a>+ - <eps_b>+) / (eps_a - eps_b) (its limit H(eps_a) when equal).
+    H(0) = 0, the compressive side, as for the other splits' indicators."""
+    pos = np.maximum(ev, 0.0)
+    Hs = (ev > 0.0).astype(np.float64)
+    la, lb = ev[..., :, None], ev[..., None, :]
+    diff = la - lb
+    same = diff == 0.0
+    num = pos[..., :, None] - pos[..., None, :]
+    th = np.where(same, np.broadcast_to(Hs[..., :, None], diff.shape), num / np.where(same, 1.0, diff))
+    return th
+
+
 def density(z, pq, dpq, mat, d):
     """W(z) at quadrature points; pq = p, dpq = grad p at the same points."""
     u, G, c, dc = _unpack(z, d)
     eps = 0.5 * (G + np.swapaxes(G, -1, -2))
     t = np.trace(eps, axis1=-2, axis2=-1)
     epsq = np.sum(eps * eps, axis=(-2, -1))
-    if mat.split:
+    if int(mat.split) == SPLIT_SPECTRAL:
+        ev, _ = principal_strains(eps)
+        psip = 0.5 * mat.lam * np.maximum(t, 0.0) ** 2 + mat.mu * np.sum(np.maximum(ev, 0.0) ** 2, axis=-1)
+        psim = 0.5 * mat.lam * np.minimum(t, 0.0) ** 2 + mat.mu * np.sum(np.minimum(ev, 0.0) ** 2, axis=-1)
+    elif mat.split:
         K = mat.K
         psip = 0.5 * K * np.maximum(t, 0.0) ** 2 + mat.mu * (epsq - t * t / 3.0)
         psim = 0.5 * K * np.minimum(t, 0.0) ** 2
@@ -214,7 +248,15 @@ def _stress_parts(G, mat, d):
     t = np.trace(eps, axis1=-2, axis2=-1)
     epsq = np.sum(eps * eps, axis=(-2, -1))
     I = np.eye(d)
-    if mat.split:
+    if int(mat.split) == SPLIT_SPECTRAL:
+        tp, tm = np.maximum(t, 0.0), np.minimum(t, 0.0)
+        ev, Q = principal_strains(eps)
+        evp = np.maximum(ev, 0.0)
+        epsp = np.einsum('...ia,...a,...ja->...ij', Q, evp, Q)
+        psip = 0.5 * mat.lam * tp * tp + mat.mu * np.sum(evp * evp, axis=-1)
+        sigp = (mat.lam * tp)[..., None, None] * I + 2.0 * mat.mu * epsp
+        sigm = (mat.lam * tm)[..., None, None] * I + 2.0 * mat.mu * (eps - epsp)
+    elif mat.split:
         K = mat.K
         tp, tm = np.maximum(t, 0.0), np.minimum(t, 0.0)
         e = eps - (t / 3.0)[..., None, None] * I
@@ -262,7 +304,21 @@ def density_hess(z, pq, dpq, mat, d):
     iG = lambda i, j: d + d * i + j
     ic = d + d * d
     # uu block: only through G.  dW/dG_ij = S_ij(eps); S depends on eps = sym G.
-    if mat.split:
+    Pp = None
+    if int(mat.split) == SPLIT_SPECTRAL:
+        # lambda (g H+ + H-) tr dEps tr DEps + 2 mu (g dEps+ + dEps-) : DEps,
+        # dEps- = dEps - dEps+: the shear part is 2 mu dEps : DEps plus
+        # 2 mu (g - 1) dEps+ : DEps, dEps+ = P+ dEps with
+        # P+_ijkl = sum_ab theta_ab sym(n_a n_b^T)_ij sym(n_a n_b^T)_kl
+        Hp = (t > 0.0).astype(np.float64)
+        vol = mat.lam * (g * Hp + (1.0 - Hp))
+        shear = mat.mu + 0.0 * g
+        ev, Q = principal_strains(0.5 * (G + np.swapaxes(G, -1, -2)))
+        th = spectral_theta(ev)
+        M = 0.5 * (np.einsum('...ia,...jb->...abij', Q, Q) + np.einsum('...ja,...ib->...abij', Q, Q))
+        Pp = np.einsum('...ab,...abij,...abkl->...ijkl', th, M, M)
+        Pp = 2.0 * mat.mu * (g - 1.0)[..., None, None, None, None] * Pp
+    elif mat.split:
         K = mat.K
         Hp = (t > 0.0).astype(np.float64)
         vol = g * K * Hp + K * (1.0 - Hp) - g * 2.0 * mat.mu / 3.0
@@ -281,6 +337,8 @@ def density_hess(z, pq, dpq, mat, d):
                         v = v + shear
                     if i == l and j == kk:
                         v = v + shear
+                    if Pp is not None:
+                        v = v + Pp[..., i, j, kk, l]
                     if not np.isscalar(v) or v != 0.0:
                         Hm[..., iG(i, j), iG(kk, l)] = v
     # uc coupling
