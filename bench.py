@@ -266,6 +266,85 @@ def cnn_leg(ctx, L, torch, reps):
             "forward_frac_bf16": tf_f / PEAK_BF16, "backward_frac_bf16": tf_b / PEAK_BF16}
 
 
+def loadstep_legs(ctx, wl, x_shape_like, p, c0, P, torch, net):
+    """Plain FP64, mixed FP32 and (with a network) mixed + learned load steps
+    from u = 0, c = c0, each timed from the call to its return."""
+    import ctypes
+    legs = [("plain_fp64", 0, None), ("mixed_fp32", 1, None)]
+    if net is not None:
+        legs.append(("mixed_learned", 1, net))
+    out = {}
+    for name, prec, nn in legs:
+        xs = torch.zeros_like(x_shape_like)
+        xs.view(-1, 4)[:, 3] = c0
+        prm = P.default_params(precision=prec, **wl.solver)
+        if nn is not None:
+            nnv = nn.net()
+            prm.use_learned = 1
+            prm.nn = ctypes.pointer(nnv)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ctx.solve_loadstep(xs, p, c0, prm)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"s_per_loadstep": dt, "vcycles": st["vcycles"], "chi_rel": st["chi"] / st["chi0"],
+                     "tr_accepted": st["tr_accepted"], "tr_rejected": st["tr_rejected"],
+                     "nn_proposed": st["nn_proposed"], "nn_accepted": st["nn_accepted"],
+                     "energy": st["energy"], "converged": st["code"] == 0}
+        log(name, out[name])
+        del xs
+    return out
+
+
+def learned_c5_leg(args, P, W, torch):
+    """The learned form as configured for the 256^3 deployment: harvest and
+    train on 128^3 runs with 10-50 fractures, deploy on the 256^3 network of
+    100 fractures (its solver setting), against plain FP64 and mixed FP32."""
+    from paper_2007_12908_amd import learned
+    wt = W.WORKLOADS["c2_3d_128"]
+    tctx = P.Context(3, wt.n_cells, wt.n_levels, wt.lam, wt.mu, wt.Gc, wt.ls, wt.k)
+    net, info = learned_leg(tctx, wt, P, W, torch, args.train_seconds, args.learned_target)
+    log("training", info)
+    wl = W.WORKLOADS["c3_3d_256"]
+    learned.rescale_for_grid(net, wt.h, wl.h, 3)
+    ctx = P.Context(3, wl.n_cells, wl.n_levels, wl.lam, wl.mu, wl.Gc, wl.ls, wl.k)
+    c0, p = ctx.init_fields(wl.n_levels, wl.fractures(), band=wl.h, p_mode=0, p_value=wl.p)
+    x = torch.zeros(4 * (wl.n_cells + 1) ** 3, dtype=torch.float64, device="cuda")
+    runs = loadstep_legs(ctx, wl, x, p, c0, P, torch, net)
+    return {"train_workload": wt.name, "deploy_workload": wl.name, "training": info, **runs}
+
+
+def ramp_leg(args, P, W, torch):
+    """Load-step sequence on the 256^3 network: p ramped linearly from p to
+    2p over `--ramp` steps, each step starting from the previous solution
+    with c_lower <- c (irreversibility), in the precision of
+    `--ramp-precision`."""
+    wl = W.WORKLOADS["c3_3d_256"]
+    ctx = P.Context(3, wl.n_cells, wl.n_levels, wl.lam, wl.mu, wl.Gc, wl.ls, wl.k)
+    c0, p0 = ctx.init_fields(wl.n_levels, wl.fractures(), band=wl.h, p_mode=0, p_value=wl.p)
+    x = torch.zeros(4 * (wl.n_cells + 1) ** 3, dtype=torch.float64, device="cuda")
+    x.view(-1, 4)[:, 3] = c0
+    cl = c0.clone()
+    steps = []
+    n = args.ramp
+    for t in range(n):
+        f = 1.0 + t / max(n - 1, 1)
+        p = p0 * f
+        prm = P.default_params(precision=args.ramp_precision, **wl.solver)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ctx.solve_loadstep(x, p, cl, prm)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        cl = x.view(-1, 4)[:, 3].clone()
+        rec = {"p": wl.p * f, "s": dt, "vcycles": st["vcycles"], "chi_rel": st["chi"] / st["chi0"],
+               "energy": st["energy"], "converged": st["code"] == 0, "c_sum": float(cl.sum())}
+        log("load step", t + 1, rec)
+        steps.append(rec)
+    return {"workload": wl.name, "precision": "fp32" if args.ramp_precision else "fp64", "steps": steps,
+            "total_s": sum(r["s"] for r in steps)}
+
+
 def roofline_of(kernels, wl, traffic):
     """Roofline of the dominant (slowest) FP64 kernel of a kernel leg."""
     dom = max(("energy", "gradient", "hessvec"), key=lambda k: kernels[k]["ms"])
@@ -300,6 +379,16 @@ def main():
                     help="time only the kernels on the roofline workload (for profiler runs)")
     ap.add_argument("--cnn-only", action="store_true",
                     help="time only the network's forward and backward passes (for profiler runs)")
+    ap.add_argument("--split", type=int, default=1, choices=(0, 1, 2),
+                    help="strain split of the roofline-only kernels: 0 unsplit, 1 volumetric-deviatoric "
+                         "(the workloads' model), 2 spectral")
+    ap.add_argument("--learned-c5", action="store_true",
+                    help="train on 128^3 runs, deploy on the 256^3 network: plain, mixed and mixed + learned "
+                         "load steps (several minutes; not part of the default run)")
+    ap.add_argument("--ramp", type=int, default=0,
+                    help="run this many load steps on the 256^3 network with p ramped from p to 2p "
+                         "(several minutes; not part of the default run)")
+    ap.add_argument("--ramp-precision", type=int, default=1, choices=(0, 1), help="0 FP64, 1 mixed")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -323,7 +412,8 @@ def main():
 
     def roofline_leg():
         rw = W.WORKLOADS[ROOFLINE_WORKLOAD]
-        rctx = P.Context(3, rw.n_cells, rw.n_levels, rw.lam, rw.mu, rw.Gc, rw.ls, rw.k)
+        rctx = P.Context(3, rw.n_cells, rw.n_levels, rw.lam, rw.mu, rw.Gc, rw.ls, rw.k,
+                         split=args.split if args.roofline_only else 1)
         rc0, rp = rctx.init_fields(rw.n_levels, rw.fractures(), band=rw.h, p_mode=0, p_value=rw.p)
         ker = kernel_leg(rctx, rw, rc0, rp, max(args.steps // 2, 5), torch)
         del rctx, rc0, rp
@@ -332,7 +422,15 @@ def main():
 
     if args.roofline_only:
         rw, ker = roofline_leg()
-        log(json.dumps({"workload": rw.name, "kernels": ker}))
+        log(json.dumps({"workload": rw.name, "split": args.split, "kernels": ker}))
+        return
+
+    if args.ramp:
+        print(json.dumps({"ramp": ramp_leg(args, P, W, torch)}), flush=True)
+        return
+
+    if args.learned_c5:
+        print(json.dumps({"learned_c5": learned_c5_leg(args, P, W, torch)}), flush=True)
         return
 
     wl = W.WORKLOADS[args.workload]
@@ -393,32 +491,12 @@ def main():
 
     rmtr = None
     if not args.no_loadstep:
-        import ctypes
         rmtr = {}
-        legs = [("plain_fp64", 0, None), ("mixed_fp32", 1, None)]
         net = None
         if not args.no_learned:
             net, rmtr["training"] = learned_leg(ctx, wl, P, W, torch, args.train_seconds, args.learned_target)
             log("training", rmtr["training"])
-            legs.append(("mixed_learned", 1, net))
-        for name, prec, nn in legs:
-            xs = torch.zeros_like(x)
-            xs.view(-1, 4)[:, 3] = c0
-            prm = P.default_params(precision=prec, **wl.solver)
-            if nn is not None:
-                nnv = nn.net()
-                prm.use_learned = 1
-                prm.nn = ctypes.pointer(nnv)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st = ctx.solve_loadstep(xs, p, c0, prm)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            rmtr[name] = {"s_per_loadstep": dt, "vcycles": st["vcycles"], "chi_rel": st["chi"] / st["chi0"],
-                          "tr_accepted": st["tr_accepted"], "tr_rejected": st["tr_rejected"],
-                          "nn_proposed": st["nn_proposed"], "nn_accepted": st["nn_accepted"],
-                          "energy": st["energy"], "converged": st["code"] == 0}
-            log(name, rmtr[name])
+        rmtr.update(loadstep_legs(ctx, wl, x, p, c0, P, torch, net))
 
     cpu = None if args.no_cpu else cpu_baseline(wl, x_np, p.cpu().numpy(), v_np)
 

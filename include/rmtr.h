@@ -12,8 +12,11 @@
  *   W = g(c) psi+(eps) + psi-(eps) + Gc/2 (c^2/l + l |grad c|^2) + gp(c) div(p u),
  *   g(c) = (1-k)(1-c)^2 + k,  gp(c) = (1-c)^2,  AT2 crack density (Sec. 2.1),
  *   psi+ = K/2 <tr eps>+^2 + mu dev(eps):dev(eps),  psi- = K/2 <tr eps>-^2
- *   (volumetric-deviatoric split; 2D is plane strain), or the unsplit
- *   psi+ = lambda/2 (tr eps)^2 + mu eps:eps, psi- = 0 (Sec. 2, first paragraph).
+ *   (volumetric-deviatoric split; 2D is plane strain), the unsplit
+ *   psi+ = lambda/2 (tr eps)^2 + mu eps:eps, psi- = 0 (Sec. 2, first paragraph),
+ *   or the spectral split on the principal strains eps_a (Sec. 4.2.1 lists
+ *   principal strains among the precomputed quantities):
+ *   psi+- = lambda/2 <tr eps>+-^2 + mu sum_a <eps_a>+-^2.
  * Discretisation: first-order Lagrange (Q1) elements (Sec. 2.2), N^d cells,
  * 2^d Gauss points per cell.  Feasible set V_c: c_lower <= c <= 1
  * (eq. (space_pf)); displacements fixed on the Dirichlet set (V_u^t).
@@ -76,7 +79,9 @@ typedef struct {
   int32_t dim;      /* 2 or 3 */
   int32_t n_cells;  /* N_L, cells per side on the finest level */
   int32_t n_levels; /* L >= 1; N_L must be divisible by 2^(L-1) */
-  int32_t split;    /* 1: volumetric-deviatoric split, 0: unsplit density */
+  int32_t split;    /* 0: unsplit density, 1: volumetric-deviatoric split,
+                       2: spectral split (principal strains); other values
+                       make rmtr_create return RMTR_E_ARG */
   double lambda, mu, Gc, ls, k;
 } rmtr_model;
 

@@ -19,6 +19,7 @@ RMTR_E_ARG = -1
 RMTR_E_WORKSPACE = -3
 RMTR_FP64 = 0
 RMTR_FP32 = 1
+SPLIT_NONE, SPLIT_VOLDEV, SPLIT_SPECTRAL = 0, 1, 2  # rmtr_model.split
 R_DUAL, R_INJECT, R_BOX_LO, R_BOX_HI = 0, 1, 2, 3
 
 EXPORTS = [
@@ -207,8 +208,10 @@ class Context:
     stream."""
 
     def __init__(self, dim, n_cells, n_levels, lam, mu, Gc, ls, k=1e-6, split=True):
+        """split: 0 / False unsplit, 1 / True volumetric-deviatoric,
+        2 spectral (SPLIT_* constants)."""
         self.lib = load()
-        self.model = Model(dim, n_cells, n_levels, 1 if split else 0, lam, mu, Gc, ls, k)
+        self.model = Model(dim, n_cells, n_levels, int(split), lam, mu, Gc, ls, k)
         h = ctypes.c_void_p()
         st = self._fn("rmtr_create")(ctypes.byref(self.model), ctypes.byref(h))
         if st != RMTR_OK:

@@ -207,7 +207,7 @@ size_t loadstep_bytes(const rmtr_ctx* c, bool mixed, bool learned, bool fine_mod
   b += buf_bytes(mprgp_work_doubles(d, c->lv[1].N) * sizeof(double));
   const bool fine32 = mixed && L > 1;
   if (L > 1) b += buf_bytes(st_rap_work_doubles(d, c->lv[L].N, fine32 ? 1 : 0) * sizeof(double));
-  const size_t cv = coef_values(d, c->lv[L].N);
+  const size_t cv = coef_values(d, c->lv[L].N, c->mat.split);
   b += buf_bytes((fine32 ? (cv + 1) / 2 : cv) * sizeof(double));
   if (learned) b += buf_bytes(size_t(c->lv[L].nodes) * (8 + 32 + 32 + 4) * sizeof(float));
   return b;
@@ -765,6 +765,9 @@ struct Cnt {
   Cnt& operator*=(const Cnt& b) { return *this = *this * b; }
   friend bool operator>(const Cnt& a, const Cnt& b) { return a.v > b.v; }
   friend bool operator<(const Cnt& a, const Cnt& b) { return a.v < b.v; }
+  friend bool operator==(const Cnt& a, const Cnt& b) { return a.v == b.v; }
+  friend bool operator!=(const Cnt& a, const Cnt& b) { return a.v != b.v; }
+  friend Cnt sqrt(const Cnt& a) { return bin(a, a, std::sqrt(a.v)); }
 };
 int64_t Cnt::ops = 0;
 
@@ -913,6 +916,7 @@ rmtr_status rmtr_create(const rmtr_model* m, rmtr_ctx** out) {
   if (!(m->mu > 0.0) || !(m->lambda + 2.0 * m->mu / 3.0 > 0.0) || !(m->Gc > 0.0) || !(m->ls > 0.0) ||
       !(m->k >= 0.0 && m->k < 1.0))
     return RMTR_E_ARG;
+  if (m->split < kSplitNone || m->split > kSplitSpectral) return RMTR_E_ARG;
   rmtr_ctx* c = new rmtr_ctx();
   c->model = *m;
   c->mat.lam = m->lambda;
@@ -921,7 +925,7 @@ rmtr_status rmtr_create(const rmtr_model* m, rmtr_ctx** out) {
   c->mat.Gc = m->Gc;
   c->mat.ls = m->ls;
   c->mat.k = m->k;
-  c->mat.split = m->split ? 1 : 0;
+  c->mat.split = m->split;
   set_derived(c->mat);
   c->L = m->n_levels;
   c->lv.resize(c->L + 1);
@@ -1052,7 +1056,7 @@ rmtr_status rmtr_smooth(rmtr_ctx* c, int32_t level, const double* xl, const doub
     return fail(c, RMTR_E_ARG, "rmtr_smooth: bad arguments");
   const bool f32 = precision == RMTR_FP32;
   Level& v = c->lv[level];
-  if (!v.coefop) HIPCHK(c, dalloc(c, &v.coefop, coef_values(c->model.dim, v.N)));
+  if (!v.coefop) HIPCHK(c, dalloc(c, &v.coefop, coef_values(c->model.dim, v.N, c->mat.split)));
   void* Sm = nullptr;
   if (f32) {
     if (!v.Sopf) HIPCHK(c, dalloc(c, &v.Sopf, stencil_values(c->model.dim, v.N)));
@@ -1090,7 +1094,7 @@ rmtr_status rmtr_coarse_hessvec(rmtr_ctx* c, int32_t level, const double* xl, co
   const bool f32 = precision == RMTR_FP32;
   const int L = c->L, d = c->model.dim;
   Level& f = c->lv[L];
-  if (!f.coefop) HIPCHK(c, dalloc(c, &f.coefop, coef_values(d, f.N)));
+  if (!f.coefop) HIPCHK(c, dalloc(c, &f.coefop, coef_values(d, f.N, c->mat.split)));
   void* Sm = nullptr;
   if (f32) {
     if (!f.Sopf) HIPCHK(c, dalloc(c, &f.Sopf, stencil_values(d, f.N)));
@@ -1187,7 +1191,7 @@ rmtr_status rmtr_solve_loadstep(rmtr_ctx* c, const double* p, const double* c_lo
   if (c->L > 1)
     HIPCHK(c, grow(c, &c->rap_work, &c->rap_cap, st_rap_work_doubles(c->model.dim, c->lv[c->L].N, fine32 ? 1 : 0)));
   {
-    const size_t cv = coef_values(c->model.dim, c->lv[c->L].N);
+    const size_t cv = coef_values(c->model.dim, c->lv[c->L].N, c->mat.split);
     HIPCHK(c, grow(c, &c->lv[c->L].coef, &c->lv[c->L].coef_cap, fine32 ? (cv + 1) / 2 : cv));
   }
   Run run{c, *prm, st, dir, f_ext, mixed, prm->coarse_model != 1, prm->coarse_model == 2, prm->first_order != 0};

@@ -7,8 +7,9 @@
 //   W = g(c) psi+ + psi- + Gc/2 (c^2/l + l |grad c|^2) + gp(c) div(p u)
 //   g = (1-k)(1-c)^2 + k,  gp = (1-c)^2,  div(p u) = p tr(eps) + grad p . u
 //   psi+ = K/2 <t>+^2 + mu e:e,  psi- = K/2 <t>-^2  (t = tr eps, e its deviator
-//   in 3D, K = lambda + 2 mu / 3; 2D is plane strain), or the unsplit
-//   psi+ = lambda/2 t^2 + mu eps:eps, psi- = 0.
+//   in 3D, K = lambda + 2 mu / 3; 2D is plane strain), the unsplit
+//   psi+ = lambda/2 t^2 + mu eps:eps, psi- = 0, or the spectral split on the
+//   principal strains eps_a: psi+- = lambda/2 <t>+-^2 + mu sum_a <eps_a>+-^2.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -23,6 +24,20 @@ namespace rmtr {
 // Two-point Gauss rule on [0, 1]: xi = (1 -+ 1/sqrt(3)) / 2.
 #define RMTR_GA 0.78867513459481288225457439025098  // 1 - xi_0 = xi_1
 #define RMTR_GB 0.21132486540518711774542560974902  // xi_0 = 1 - xi_1
+
+// MatP::split
+constexpr int kSplitNone = 0, kSplitVolDev = 1, kSplitSpectral = 2;
+// Which split code a function carries (template argument SK): kAnySplit
+// decides from MatP::split at run time, kNoSpectral carries the unsplit and
+// volumetric-deviatoric forms only, kSplitSpectral the spectral form only.
+// The 3D element kernels are instantiated per family, so the spectral
+// branch costs the other forms no registers.
+constexpr int kAnySplit = -1, kNoSpectral = -2;
+
+template <int SK>
+RMTR_FN bool spectral_split(int split) {
+  return SK == kSplitSpectral || (SK == kAnySplit && split == kSplitSpectral);
+}
 
 template <typename T>
 struct MatP {
@@ -92,14 +107,199 @@ RMTR_FN void zero(Zq<DIM, T>& z) {
   z.c = T(0);
 }
 
-// Strain energy split: psi+, sigma+ (symmetric, DIM x DIM), sigma- (scalar
-// multiple of the identity), t = tr eps.
+// ------------------------------------------------------------------------
+// Principal strains.  Symmetric eigendecomposition of a DIM x DIM matrix by
+// the cyclic Jacobi method (Golub and Van Loan, Matrix Computations,
+// Sec. 8.5): sweeps over the pairs (p, q) = (0,1), (0,2), (1,2), each
+// zeroing A[p][q] by a plane rotation J from the symmetric 2 x 2 Schur step
+//   tau = (A_qq - A_pp) / (2 A_pq),  t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
+//   c = 1 / sqrt(1 + t^2),  s = t c,   A <- J^T A J,  Q <- Q J.
+// One rotation diagonalises a 2 x 2 matrix exactly; the 3 x 3 iteration
+// converges quadratically and a fixed number of sweeps reaches rounding
+// level.  On return ev holds the eigenvalues and, when VEC, the columns of
+// Q the eigenvectors.
+template <int DIM, typename T, bool VEC>
+RMTR_FN void sym_eig(T (&A)[DIM][DIM], T (&ev)[DIM], T (&Q)[DIM][DIM]) {
+  if (VEC) {
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) Q[i][j] = T(i == j ? 1 : 0);
+  }
+  constexpr int kSweeps = DIM == 2 ? 1 : (sizeof(T) >= 8 ? 5 : 4);
+  constexpr int kPairs = DIM == 2 ? 1 : 3;
+#pragma unroll
+  for (int sw = 0; sw < kSweeps; ++sw) {
+#pragma unroll
+    for (int pr = 0; pr < kPairs; ++pr) {
+      const int p = pr == 2 ? 1 : 0, q = pr == 0 ? 1 : 2;
+      const T apq = A[p][q];
+      if (apq != T(0)) {
+        const T tau = (A[q][q] - A[p][p]) / (T(2) * apq);
+        const T at = tau < T(0) ? -tau : tau;
+        // sqrt(1 + tau^2) without overflow for large |tau|
+        const T ia = T(1) / at;
+        const T r = at > T(1) ? at * sqrt(T(1) + ia * ia) : sqrt(T(1) + at * at);
+        T t = T(1) / (at + r);
+        if (tau < T(0)) t = -t;
+        const T c = T(1) / sqrt(T(1) + t * t), sn = t * c;
+        A[p][p] -= t * apq;
+        A[q][q] += t * apq;
+        A[p][q] = A[q][p] = T(0);
+        if (DIM == 3) {
+          const int o = 3 - p - q;
+          const T aop = A[o][p], aoq = A[o][q];
+          A[o][p] = A[p][o] = c * aop - sn * aoq;
+          A[o][q] = A[q][o] = sn * aop + c * aoq;
+        }
+        if (VEC) {
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) {
+            const T qp = Q[k][p], qq = Q[k][q];
+            Q[k][p] = c * qp - sn * qq;
+            Q[k][q] = sn * qp + c * qq;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) ev[i] = A[i][i];
+}
+
+// f theta_ab: the derivative of eps+ = sum_a <eps_a>+ n_a n_a^T along a
+// symmetric direction E is sum_ab theta_ab (n_a^T E n_b) n_a n_b^T with
+// theta_aa = H(eps_a) and, for eps_a != eps_b, the divided difference
+// (<eps_a>+ - <eps_b>+) / (eps_a - eps_b) (H(eps_a) when they are equal);
+// H(0) = 0 (the compressive side, as for the volumetric indicator).
+template <int DIM, typename T>
+RMTR_FN void spectral_theta(const T (&ev)[DIM], T f, T (&th)[DIM][DIM]) {
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+      const T pa = ev[a] > T(0) ? ev[a] : T(0), pb = ev[b] > T(0) ? ev[b] : T(0);
+      const T df = ev[a] - ev[b];
+      th[a][b] = (a == b || df == T(0)) ? (ev[a] > T(0) ? f : T(0)) : f * (pa - pb) / df;
+    }
+}
+
+// out += Q (th o (Q^T E Q)) Q^T with E = sym(G) (o: entrywise product).
+template <int DIM, typename T>
+RMTR_FN void spectral_apply(const T (&Q)[DIM][DIM], const T (&th)[DIM][DIM], const T (&G)[DIM][DIM],
+                            T (&out)[DIM][DIM]) {
+  T E[DIM][DIM], B[DIM][DIM], C[DIM][DIM];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) E[i][j] = T(0.5) * (G[i][j] + G[j][i]);
+  // B = E Q, C = Q^T B (scaled by th)
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+      T v = T(0);
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) v += E[i][j] * Q[j][b];
+      B[i][b] = v;
+    }
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+      T v = T(0);
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) v += Q[i][a] * B[i][b];
+      C[a][b] = th[a][b] * v;
+    }
+  // out += Q C Q^T
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+      T v = T(0);
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) v += Q[i][a] * C[a][b];
+      B[i][b] = v;
+    }
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      T v = T(0);
+#pragma unroll
+      for (int b = 0; b < DIM; ++b) v += B[i][b] * Q[j][b];
+      out[i][j] += v;
+    }
+}
+
+// Spectral parts from the strain e (symmetric): psi+, psi-, sigma+ and
+// sigma- (both full tensors); with VEC also the principal strains and axes.
+template <int DIM, typename T, bool VEC>
+RMTR_FN void spectral_parts(const MatP<T>& m, const T (&e)[DIM][DIM], T t, T& psip, T& psim, T (&sigp)[DIM][DIM],
+                            T (&sigm)[DIM][DIM], T (&ev)[DIM], T (&Q)[DIM][DIM]) {
+  T A[DIM][DIM];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) A[i][j] = e[i][j];
+  sym_eig<DIM, T, true>(A, ev, Q);
+  const T tp = t > T(0) ? t : T(0);
+  const T tm = t > T(0) ? T(0) : t;
+  T sp = T(0), sm = T(0), evp[DIM];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    evp[a] = ev[a] > T(0) ? ev[a] : T(0);
+    const T en = ev[a] - evp[a];
+    sp += evp[a] * evp[a];
+    sm += en * en;
+  }
+  psip = T(0.5) * m.lam * tp * tp + m.mu * sp;
+  psim = T(0.5) * m.lam * tm * tm + m.mu * sm;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      T ep = T(0);
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) ep += Q[i][a] * evp[a] * Q[j][a];
+      sigp[i][j] = T(2) * m.mu * ep + (i == j ? m.lam * tp : T(0));
+      sigm[i][j] = T(2) * m.mu * (e[i][j] - ep) + (i == j ? m.lam * tm : T(0));
+    }
+}
+
+// Spectral psi+ and psi- only (eigenvalues without axes).
+template <int DIM, typename T>
+RMTR_FN void spectral_energy(const MatP<T>& m, const T (&e)[DIM][DIM], T t, T& psip, T& psim) {
+  T A[DIM][DIM], ev[DIM], Q[DIM][DIM];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) A[i][j] = e[i][j];
+  sym_eig<DIM, T, false>(A, ev, Q);
+  const T tp = t > T(0) ? t : T(0);
+  const T tm = t > T(0) ? T(0) : t;
+  T sp = T(0), sm = T(0);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const T pa = ev[a] > T(0) ? ev[a] : T(0);
+    const T na = ev[a] - pa;
+    sp += pa * pa;
+    sm += na * na;
+  }
+  psip = T(0.5) * m.lam * tp * tp + m.mu * sp;
+  psim = T(0.5) * m.lam * tm * tm + m.mu * sm;
+}
+
+// Strain energy split: psi+, psi-, sigma+ and sigma- (symmetric DIM x DIM),
+// t = tr eps; for the spectral split also the principal strains and axes.
 template <int DIM, typename T>
 struct Split {
-  T t, psip, psim, sigp[DIM][DIM], sigm;
+  T t, psip, psim, sigp[DIM][DIM], sigm[DIM][DIM];
+  T ev[DIM], Q[DIM][DIM];
 };
 
-template <int DIM, typename T>
+template <int DIM, typename T, int SK = kAnySplit>
 RMTR_FN void split_parts(const MatP<T>& m, const T (&G)[DIM][DIM], Split<DIM, T>& s) {
   T t = T(0), epsq = T(0);
 #pragma unroll
@@ -112,7 +312,14 @@ RMTR_FN void split_parts(const MatP<T>& m, const T (&G)[DIM][DIM], Split<DIM, T>
       epsq += e * e;
     }
   s.t = t;
-  if (m.split) {
+  if (spectral_split<SK>(m.split)) {
+    T e[DIM][DIM];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) e[i][j] = T(0.5) * (G[i][j] + G[j][i]);
+    spectral_parts<DIM, T, true>(m, e, t, s.psip, s.psim, s.sigp, s.sigm, s.ev, s.Q);
+  } else if (m.split) {
     T tp = t > T(0) ? t : T(0);
     T tm = t > T(0) ? T(0) : t;
     s.psip = T(0.5) * m.K * tp * tp + m.mu * (epsq - t * t * m.third);
@@ -123,8 +330,8 @@ RMTR_FN void split_parts(const MatP<T>& m, const T (&G)[DIM][DIM], Split<DIM, T>
       for (int j = 0; j < DIM; ++j) {
         T e = T(0.5) * (G[i][j] + G[j][i]);
         s.sigp[i][j] = T(2) * m.mu * e + (i == j ? (m.K * tp - m.mu23 * t) : T(0));
+        s.sigm[i][j] = i == j ? m.K * tm : T(0);
       }
-    s.sigm = m.K * tm;
   } else {
     s.psip = T(0.5) * m.lam * t * t + m.mu * epsq;
     s.psim = T(0);
@@ -134,16 +341,45 @@ RMTR_FN void split_parts(const MatP<T>& m, const T (&G)[DIM][DIM], Split<DIM, T>
       for (int j = 0; j < DIM; ++j) {
         T e = T(0.5) * (G[i][j] + G[j][i]);
         s.sigp[i][j] = T(2) * m.mu * e + (i == j ? m.lam * t : T(0));
+        s.sigm[i][j] = T(0);
       }
-    s.sigm = T(0);
+  }
+}
+
+// psi+ and psi- alone (the energy needs no stresses or axes).
+template <int DIM, typename T, int SK = kAnySplit>
+RMTR_FN void split_energy(const MatP<T>& m, const T (&G)[DIM][DIM], T& psip, T& psim, T& t) {
+  t = T(0);
+  T epsq = T(0), e[DIM][DIM];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) t += G[i][i];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      e[i][j] = T(0.5) * (G[i][j] + G[j][i]);
+      epsq += e[i][j] * e[i][j];
+    }
+  if (spectral_split<SK>(m.split)) {
+    spectral_energy<DIM, T>(m, e, t, psip, psim);
+  } else if (m.split) {
+    const T tp = t > T(0) ? t : T(0);
+    const T tm = t > T(0) ? T(0) : t;
+    psip = T(0.5) * m.K * tp * tp + m.mu * (epsq - t * t * m.third);
+    psim = T(0.5) * m.K * tm * tm;
+  } else {
+    psip = T(0.5) * m.lam * t * t + m.mu * epsq;
+    psim = T(0);
   }
 }
 
 // W at a quadrature point.
-template <int DIM, typename T>
+template <int DIM, typename T, int SK = kAnySplit>
 RMTR_FN T density(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T (&dp)[DIM]) {
-  Split<DIM, T> s;
-  split_parts<DIM, T>(m, z.G, s);
+  struct {
+    T t, psip, psim;
+  } s;
+  split_energy<DIM, T, SK>(m, z.G, s.psip, s.psim, s.t);
   T omc = T(1) - z.c;
   T g = (T(1) - m.k) * omc * omc + m.k;
   T gp = omc * omc;
@@ -159,11 +395,11 @@ RMTR_FN T density(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T (&dp)[DIM]
 }
 
 // dW/dz (first variation), written into out.
-template <int DIM, typename T>
+template <int DIM, typename T, int SK = kAnySplit>
 RMTR_FN void density_grad(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T (&dp)[DIM],
                                     Zq<DIM, T>& out) {
   Split<DIM, T> s;
-  split_parts<DIM, T>(m, z.G, s);
+  split_parts<DIM, T, SK>(m, z.G, s);
   T omc = T(1) - z.c;
   T g = (T(1) - m.k) * omc * omc + m.k;
   T dg = T(-2) * (T(1) - m.k) * omc;
@@ -178,13 +414,15 @@ RMTR_FN void density_grad(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T (&
     out.dc[i] = m.Gc_l * z.dc[i];
 #pragma unroll
     for (int j = 0; j < DIM; ++j)
-      out.G[i][j] = g * s.sigp[i][j] + (i == j ? (s.sigm + gp * p) : T(0));
+      out.G[i][j] = g * s.sigp[i][j] + s.sigm[i][j] + (i == j ? gp * p : T(0));
   }
   out.c = dg * s.psip + m.Gc_ls * z.c + dgp * pi;
 }
 
 // Coefficients of the second variation at a linearisation point.
 //   uu: vol tr(dG) tr(DG) + shear (dG:DG + dG:DG^T)
+//       [+ sum_ab th_ab (Q^T sym dG Q)_ab (Q^T sym DG Q)_ab, spectral split:
+//        th = 2 mu (g - 1) theta, Q the principal axes]
 //   uc: S : dG Dc + Pc . du Dc (and symmetric)
 //   cc: Ccc dc Dc + Gc l grad dc . grad Dc
 template <int DIM, typename T>
@@ -192,13 +430,14 @@ struct HessCoef {
   T vol, shear, Ccc;
   T S[DIM][DIM];
   T Pc[DIM];
+  T Q[DIM][DIM], th[DIM][DIM];  // spectral split only
 };
 
-template <int DIM, typename T>
+template <int DIM, typename T, int SK = kAnySplit>
 RMTR_FN void hess_coef(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T (&dp)[DIM],
                                  HessCoef<DIM, T>& hc) {
   Split<DIM, T> s;
-  split_parts<DIM, T>(m, z.G, s);
+  split_parts<DIM, T, SK>(m, z.G, s);
   T omc = T(1) - z.c;
   T g = (T(1) - m.k) * omc * omc + m.k;
   T dg = T(-2) * (T(1) - m.k) * omc;
@@ -207,13 +446,24 @@ RMTR_FN void hess_coef(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T (&dp)
   T pi = p * s.t;
 #pragma unroll
   for (int i = 0; i < DIM; ++i) pi += dp[i] * z.u[i];
-  if (m.split) {
+  if (spectral_split<SK>(m.split)) {
+    // lambda (g H+ + H-) tr tr + 2 mu dEps:DEps + 2 mu (g - 1) dEps+:DEps
+    T Hp = s.t > T(0) ? T(1) : T(0);
+    hc.vol = m.lam * (g * Hp + (T(1) - Hp));
+    hc.shear = m.mu;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) hc.Q[i][j] = s.Q[i][j];
+    spectral_theta<DIM, T>(s.ev, T(2) * m.mu * (g - T(1)), hc.th);
+  } else if (m.split) {
     T Hp = s.t > T(0) ? T(1) : T(0);
     hc.vol = g * m.K * Hp + m.K * (T(1) - Hp) - g * m.mu23;
+    hc.shear = g * m.mu;
   } else {
     hc.vol = g * m.lam;
+    hc.shear = g * m.mu;
   }
-  hc.shear = g * m.mu;
 #pragma unroll
   for (int i = 0; i < DIM; ++i) {
     hc.Pc[i] = dgp * dp[i];
@@ -224,7 +474,7 @@ RMTR_FN void hess_coef(const MatP<T>& m, const Zq<DIM, T>& z, T p, const T (&dp)
 }
 
 // Second variation applied to a direction v (z-vector of v at the point).
-template <int DIM, typename T>
+template <int DIM, typename T, int SK = kAnySplit>
 RMTR_FN void hess_apply(const MatP<T>& m, const HessCoef<DIM, T>& hc, const Zq<DIM, T>& v,
                                   Zq<DIM, T>& out) {
   T tv = T(0);
@@ -243,6 +493,7 @@ RMTR_FN void hess_apply(const MatP<T>& m, const HessCoef<DIM, T>& hc, const Zq<D
     }
   }
   out.c = oc;
+  if (spectral_split<SK>(m.split)) spectral_apply<DIM, T>(hc.Q, hc.th, v.G, out.G);
 }
 
 // ------------------------------------------------------------------------
@@ -507,7 +758,8 @@ RMTR_FN ElemScale<T> elem_scale(T invh, T w) {
   return e;
 }
 
-// Split parts on unit-cell strains: psi' = h^2 psi, sig' = h sig, t' = h t.
+// Split parts on unit-cell strains: psi' = h^2 psi, sig' = h sig, t' = h t
+// (every split is positively homogeneous of degree 2 in the strain).
 template <typename T>
 RMTR_FN void split_unit(const MatP<T>& m, const T (&G)[3][3], T& t, T& psip, T (&sigp)[3][3], T& sigm) {
   t = G[0][0] + G[1][1] + G[2][2];
@@ -539,9 +791,38 @@ RMTR_FN void split_unit(const MatP<T>& m, const T (&G)[3][3], T& t, T& psip, T (
 
 // Scaled first variation at one point: z holds unit-cell derivatives of
 // u and c, dp the unit-cell gradient of p.
-template <typename T>
+template <typename T, int SK = kNoSpectral>
 RMTR_FN void density_grad_unit(const MatP<T>& m, const ElemScale<T>& sc, const Zq<3, T>& z, T p,
                                const T (&dp)[3], Zq<3, T>& o) {
+  if constexpr (SK == kSplitSpectral) {
+    // sigma- is a full tensor here
+    const T t = z.G[0][0] + z.G[1][1] + z.G[2][2];
+    T e[3][3], psip, psim, sigp[3][3], sigm[3][3], ev[3], Q[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) e[i][j] = T(0.5) * (z.G[i][j] + z.G[j][i]);
+    spectral_parts<3, T, true>(m, e, t, psip, psim, sigp, sigm, ev, Q);
+    const T omc = T(1) - z.c;
+    const T g = (T(1) - m.k) * omc * omc + m.k;
+    const T dg = T(-2) * (T(1) - m.k) * omc;
+    const T gp = omc * omc;
+    const T dgp = T(-2) * omc;
+    T pi = p * t;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) pi += dp[i] * z.u[i];
+    const T dia = sc.a1 * gp * p;
+    const T cdc = sc.a2 * m.Gc_l;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      o.u[i] = sc.a1 * gp * dp[i];
+      o.dc[i] = cdc * z.dc[i];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) o.G[i][j] = sc.a2 * (g * sigp[i][j] + sigm[i][j]) + (i == j ? dia : T(0));
+    }
+    o.c = sc.a2 * dg * psip + sc.w * m.Gc_ls * z.c + sc.a1 * dgp * pi;
+    return;
+  }
   T t, psip, sigp[3][3], sigm;
   split_unit<T>(m, z.G, t, psip, sigp, sigm);
   const T omc = T(1) - z.c;
@@ -567,11 +848,23 @@ RMTR_FN void density_grad_unit(const MatP<T>& m, const ElemScale<T>& sc, const Z
 }
 
 // Scaled second-variation coefficients at the linearisation point.
-template <typename T>
+template <typename T, int SK = kNoSpectral>
 RMTR_FN void hess_coef_unit(const MatP<T>& m, const ElemScale<T>& sc, const Zq<3, T>& z, T p, const T (&dp)[3],
                             HessCoef<3, T>& hc) {
   T t, psip, sigp[3][3], sigm;
-  split_unit<T>(m, z.G, t, psip, sigp, sigm);
+  T ev[3];
+  if constexpr (SK == kSplitSpectral) {
+    t = z.G[0][0] + z.G[1][1] + z.G[2][2];
+    T e[3][3], psim, sgm[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) e[i][j] = T(0.5) * (z.G[i][j] + z.G[j][i]);
+    spectral_parts<3, T, true>(m, e, t, psip, psim, sigp, sgm, ev, hc.Q);
+    sigm = T(0);
+  } else {
+    split_unit<T>(m, z.G, t, psip, sigp, sigm);
+  }
   const T omc = T(1) - z.c;
   const T g = (T(1) - m.k) * omc * omc + m.k;
   const T dg = T(-2) * (T(1) - m.k) * omc;
@@ -580,13 +873,20 @@ RMTR_FN void hess_coef_unit(const MatP<T>& m, const ElemScale<T>& sc, const Zq<3
   T pi = p * t;
 #pragma unroll
   for (int i = 0; i < 3; ++i) pi += dp[i] * z.u[i];
-  if (m.split) {
+  if constexpr (SK == kSplitSpectral) {
     const T Hp = t > T(0) ? T(1) : T(0);
-    hc.vol = sc.a2 * (g * m.K * Hp + m.K * (T(1) - Hp) - g * m.mu23);
+    hc.vol = sc.a2 * m.lam * (g * Hp + (T(1) - Hp));
+    hc.shear = sc.a2 * m.mu;
+    spectral_theta<3, T>(ev, sc.a2 * T(2) * m.mu * (g - T(1)), hc.th);
   } else {
-    hc.vol = sc.a2 * g * m.lam;
+    if (m.split) {
+      const T Hp = t > T(0) ? T(1) : T(0);
+      hc.vol = sc.a2 * (g * m.K * Hp + m.K * (T(1) - Hp) - g * m.mu23);
+    } else {
+      hc.vol = sc.a2 * g * m.lam;
+    }
+    hc.shear = sc.a2 * g * m.mu;
   }
-  hc.shear = sc.a2 * g * m.mu;
   const T a2dg = sc.a2 * dg;
   const T a1dgp = sc.a1 * dgp;
   const T dia = a1dgp * p;
@@ -600,7 +900,7 @@ RMTR_FN void hess_coef_unit(const MatP<T>& m, const ElemScale<T>& sc, const Zq<3
 }
 
 // Scaled second variation applied to v (unit-cell derivatives); cdc = a2 Gc l.
-template <typename T>
+template <typename T, int SK = kNoSpectral>
 RMTR_FN void hess_apply_unit(const HessCoef<3, T>& hc, T cdc, const Zq<3, T>& v, Zq<3, T>& o) {
   const T tv = v.G[0][0] + v.G[1][1] + v.G[2][2];
   T oc = hc.Ccc * v.c;
@@ -616,6 +916,7 @@ RMTR_FN void hess_apply_unit(const HessCoef<3, T>& hc, T cdc, const Zq<3, T>& v,
     }
   }
   o.c = oc;
+  if constexpr (SK == kSplitSpectral) spectral_apply<3, T>(hc.Q, hc.th, v.G, o.G);
 }
 
 // Values and unit-cell derivatives at the 8 points.
@@ -670,8 +971,9 @@ RMTR_FN void elem_project_unit(const Zq<3, T> (&o)[8], T (&r)[8][4]) {
   }
 }
 
-// MODE 0: gradient of f at X.  MODE 1: Hessian at X applied to V.
-template <int MODE, typename T>
+// MODE 0: gradient of f at X.  MODE 1: Hessian at X applied to V.  SK:
+// kNoSpectral or kSplitSpectral (the split family the code carries).
+template <int MODE, typename T, int SK = kNoSpectral>
 struct ElemOp3 {
   // computes r[8][4] for one element
   __host__ __device__ static inline void eval(const MatP<T>& m, T invh, T w, const T (&X)[8][4], const T (&V)[8][4],
@@ -687,7 +989,21 @@ struct ElemOp3 {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           const T dp[3] = {dpx[q], dpy[q], dpz[q]};
-          density_grad_unit<T>(m, sc, z[q], pq[q], dp, o[q]);
+          density_grad_unit<T, SK>(m, sc, z[q], pq[q], dp, o[q]);
+        }
+      } else if (SK == kSplitSpectral) {
+        // the spectral coefficients carry the principal axes: form each
+        // point's coefficients and apply them at once rather than keeping
+        // all eight
+        elem_z_unit<T>(V, o);
+        const T cdc = sc.a2 * m.Gc_l;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const T dp[3] = {dpx[q], dpy[q], dpz[q]};
+          HessCoef<3, T> hc;
+          hess_coef_unit<T, SK>(m, sc, z[q], pq[q], dp, hc);
+          Zq<3, T> vq = o[q];
+          hess_apply_unit<T, SK>(hc, cdc, vq, o[q]);
         }
       } else {
         HessCoef<3, T> hc[8];
@@ -708,7 +1024,7 @@ struct ElemOp3 {
 
 // Contribution of one element to the rows of its local node aloc:
 // MODE 0 gradient of f at X, MODE 1 Hessian at X applied to V.
-template <int DIM, typename T>
+template <int DIM, typename T, int SK = kAnySplit>
 RMTR_FN void node_contrib(int MODE, const MatP<T>& m, T invh, T w, const T (&X)[1 << DIM][DIM + 1],
                                     const T (&V)[1 << DIM][DIM + 1], const T (&P)[1 << DIM], int aloc,
                                     T (&r)[DIM + 1]) {
@@ -719,12 +1035,12 @@ RMTR_FN void node_contrib(int MODE, const MatP<T>& m, T invh, T w, const T (&X)[
     interp_scalar_q<DIM, T>(q, P, invh, pq, dpq);
     interp_q<DIM, T>(q, X, invh, z);
     if (MODE == 0) {
-      density_grad<DIM, T>(m, z, pq, dpq, o);
+      density_grad<DIM, T, SK>(m, z, pq, dpq, o);
     } else {
       HessCoef<DIM, T> hc;
-      hess_coef<DIM, T>(m, z, pq, dpq, hc);
+      hess_coef<DIM, T, SK>(m, z, pq, dpq, hc);
       interp_q<DIM, T>(q, V, invh, z);
-      hess_apply<DIM, T>(m, hc, z, o);
+      hess_apply<DIM, T, SK>(m, hc, z, o);
     }
     project_q_node<DIM, T>(q, aloc, invh, w, o, r);
   }

@@ -35,7 +35,7 @@ hipError_t launch_reduce_partials(const double* partials, int n, double* out, hi
 
 // ---- assembled block stencils (stencil_kernels.hip)
 size_t stencil_values(int dim, int N);
-size_t coef_values(int dim, int N);
+size_t coef_values(int dim, int N, int split);  // split: MatP::split
 // lagged Hessian at xl (FP64 arithmetic) -> stencil S (double, or float if fp32);
 // coef: scratch of coef_values doubles
 hipError_t launch_st_assemble(const ElemArgs& a, const double* xl, const double* p, double* coef, void* S,

@@ -23,9 +23,11 @@ namespace {
 
 constexpr int kB = 256;
 
-template <int DIM>
+// Coefficients per quadrature point: vol, shear, Ccc, S (DIM x DIM), Pc
+// (DIM); the spectral split adds its principal axes Q and th (DIM x DIM each).
+template <int DIM, bool SPEC>
 constexpr int n_coef() {
-  return 3 + DIM * DIM + DIM;  // vol, shear, Ccc, S (DIM x DIM), Pc (DIM)
+  return 3 + DIM * DIM + DIM + (SPEC ? 2 * DIM * DIM : 0);
 }
 
 int gridn(int64_t work) {
@@ -37,10 +39,10 @@ int gridn(int64_t work) {
 
 // Second-variation coefficients at the 2^DIM quadrature points of every
 // element, element-major: C[(e 2^DIM + q) n_coef + k].
-template <int DIM, typename TC>
+template <int DIM, typename TC, bool SPEC>
 __global__ __launch_bounds__(kB) void k_coef(int N, double h, MatP<double> m, const double* __restrict__ x,
                                              const double* __restrict__ p, TC* __restrict__ C) {
-  constexpr int NL = 1 << DIM, NC = DIM + 1, NK = n_coef<DIM>();
+  constexpr int NL = 1 << DIM, NC = DIM + 1, NK = n_coef<DIM, SPEC>(), NK0 = n_coef<DIM, false>();
   int64_t ne = 1;
 #pragma unroll
   for (int i = 0; i < DIM; ++i) ne *= N;
@@ -74,8 +76,17 @@ __global__ __launch_bounds__(kB) void k_coef(int N, double h, MatP<double> m, co
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
       HessCoef<DIM, double> hc;
-      hess_coef<DIM, double>(m, z[q], pq[q], dpq[q], hc);
+      hess_coef<DIM, double, SPEC ? kSplitSpectral : kNoSpectral>(m, z[q], pq[q], dpq[q], hc);
       TC* o = C + (e * NL + q) * NK;
+      if constexpr (SPEC) {
+#pragma unroll
+        for (int i = 0; i < DIM; ++i)
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) {
+            o[NK0 + DIM * i + j] = TC(hc.Q[i][j]);
+            o[NK0 + DIM * DIM + DIM * i + j] = TC(hc.th[i][j]);
+          }
+      }
       o[0] = TC(hc.vol);
       o[1] = TC(hc.shear);
       o[2] = TC(hc.Ccc);
@@ -103,11 +114,12 @@ __global__ __launch_bounds__(kB) void k_coef(int N, double h, MatP<double> m, co
 // dy = 1, or dy = 0 and dx = 1) are summed, and each of the 13 off-diagonal
 // ones is stored twice, in n's row and, transposed, in the row of the
 // neighbour m = n + off(o) towards n (offset 26 - o).
-template <int DIM, typename TO>
+template <int DIM, typename TO, bool SPEC>
 __device__ inline void st_node_item(const Colours& g, double h, double gcl_d, const TO* __restrict__ C,
                                     const uint8_t* __restrict__ dir, TO* __restrict__ S, int al, int64_t id,
                                     int pz) {
-  constexpr int NL = 1 << DIM, NC = DIM + 1, NK = n_coef<DIM>(), NO = n_off<DIM>(), RB = row_block<DIM>();
+  constexpr int NL = 1 << DIM, NC = DIM + 1, NK = n_coef<DIM, SPEC>(), NK0 = n_coef<DIM, false>(),
+                NO = n_off<DIM>(), RB = row_block<DIM>();
   constexpr int NP = DIM == 3 ? 3 : 1, OPP = NO / NP;
   const int N = g.N;
   const int64_t ns = N + 1;
@@ -179,6 +191,33 @@ __device__ inline void st_node_item(const Colours& g, double h, double gcl_d, co
           T SdNa = T(0);
 #pragma unroll
           for (int jj = 0; jj < DIM; ++jj) SdNa += Sal[jj] * dNa[jj];
+          // spectral split: the test function's projected strain
+          // A_cd = (Q^T sym(e_al dNa^T) Q)_cd, weighted by th (Tha = th o A);
+          // the entry towards (b, be) is then Q[be][:] . (Tha Q^T dNb)
+          T Qs[DIM][DIM], Tha[DIM][DIM];
+          if constexpr (SPEC) {
+            T ya[DIM], Qal[DIM];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i)
+#pragma unroll
+              for (int jj = 0; jj < DIM; ++jj) Qs[i][jj] = cf[NK0 + DIM * i + jj];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+              T v = T(0);
+#pragma unroll
+              for (int jj = 0; jj < DIM; ++jj) v += dNa[jj] * Qs[jj][c];
+              ya[c] = v;
+              Qal[c] = T(0);
+#pragma unroll
+              for (int i = 0; i < DIM; ++i)
+                if (i == al) Qal[c] = Qs[i][c];
+            }
+#pragma unroll
+            for (int c = 0; c < DIM; ++c)
+#pragma unroll
+              for (int d2 = 0; d2 < DIM; ++d2)
+                Tha[c][d2] = cf[NK0 + DIM * DIM + DIM * c + d2] * T(0.5) * (Qal[c] * ya[d2] + ya[c] * Qal[d2]);
+          }
 #pragma unroll
           for (int b = 0; b < NL; ++b) {
             const int bz = DIM == 3 ? (b >> 2) & 1 : 0;
@@ -209,6 +248,30 @@ __device__ inline void st_node_item(const Colours& g, double h, double gcl_d, co
 #pragma unroll
               for (int be = 0; be < DIM; ++be)
                 acc[o][be] += w * (vol * dNal * dNb[be] + shear * ((al == be ? dd : T(0)) + dNa[be] * dNbal));
+              if constexpr (SPEC) {
+                T yb[DIM], zb[DIM];
+#pragma unroll
+                for (int d2 = 0; d2 < DIM; ++d2) {
+                  T v = T(0);
+#pragma unroll
+                  for (int jj = 0; jj < DIM; ++jj) v += dNb[jj] * Qs[jj][d2];
+                  yb[d2] = v;
+                }
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                  T v = T(0);
+#pragma unroll
+                  for (int d2 = 0; d2 < DIM; ++d2) v += Tha[c][d2] * yb[d2];
+                  zb[c] = v;
+                }
+#pragma unroll
+                for (int be = 0; be < DIM; ++be) {
+                  T v = T(0);
+#pragma unroll
+                  for (int c = 0; c < DIM; ++c) v += Qs[be][c] * zb[c];
+                  acc[o][be] += w * v;
+                }
+              }
               acc[o][DIM] += w * (SdNa * Nb + Pcal * Na * Nb);
             } else {
 #pragma unroll
@@ -280,7 +343,7 @@ __device__ inline void st_node_item(const Colours& g, double h, double gcl_d, co
 // into that XCD's L2 once and reused by the 24 workgroups that need them.
 constexpr bool kBlockedOrder = true;
 
-template <int DIM, typename TO>
+template <int DIM, typename TO, bool SPEC>
 __global__ __launch_bounds__(kB) void k_st_node(Colours g, double h, double gcl, const TO* __restrict__ C,
                                                 const uint8_t* __restrict__ dir, TO* __restrict__ S) {
   constexpr int NC = DIM + 1, NP = DIM == 3 ? 3 : 1;
@@ -298,14 +361,14 @@ __global__ __launch_bounds__(kB) void k_st_node(Colours g, double h, double gcl,
       const int col = inner & 7, pz = inner >> 3;
       const int64_t t = (x + 8 * (k / 24)) * kChunk + (threadIdx.x >> 2);
       // plane dz = -1 holds transposes of blocks computed elsewhere only
-      if (pz > 0 && t < g.cnt[col]) st_node_item<DIM, TO>(g, h, gcl, C, dir, S, al, g.base[col] + t, pz);
+      if (pz > 0 && t < g.cnt[col]) st_node_item<DIM, TO, SPEC>(g, h, gcl, C, dir, S, al, g.base[col] + t, pz);
     }
   } else {
     const int64_t work = nodes * NC * NP;
     for (int64_t it = int64_t(blockIdx.x) * kB + threadIdx.x; it < work; it += int64_t(gridDim.x) * kB) {
       const int al = int(it % NC);
       const int64_t r1 = it / NC;
-      st_node_item<DIM, TO>(g, h, gcl, C, dir, S, al, r1 % nodes, int(r1 / nodes));
+      st_node_item<DIM, TO, SPEC>(g, h, gcl, C, dir, S, al, r1 % nodes, int(r1 / nodes));
     }
   }
 }
@@ -692,10 +755,10 @@ size_t stencil_values(int dim, int N) {
   return size_t(g.pbase[1 << dim]) * (dim + 1) * (dim == 3 ? 27 : 9) * (dim + 1);
 }
 
-size_t coef_values(int dim, int N) {
+size_t coef_values(int dim, int N, int split) {
   int64_t ne = 1;
   for (int i = 0; i < dim; ++i) ne *= N;
-  return size_t(ne) * (1 << dim) * (3 + dim * dim + dim);
+  return size_t(ne) * (1 << dim) * (3 + dim * dim + dim + (split == kSplitSpectral ? 2 * dim * dim : 0));
 }
 
 template <int DIM, typename TO>
@@ -709,10 +772,15 @@ static hipError_t st_assemble_t(const ElemArgs& a, const double* xl, const doubl
   // coefficients in the stencil's precision (the FP32 stencil of the mixed
   // form is assembled from FP32 coefficients in FP32 arithmetic)
   TO* cf = reinterpret_cast<TO*>(coef);
-  hipLaunchKernelGGL((k_coef<DIM, TO>), dim3(gridn(ne)), dim3(kB), 0, st, a.N, a.h, a.m, xl, p, cf);
   constexpr int NP = DIM == 3 ? 3 : 1;
   const int64_t work = g.base[NL] * NC * NP;
-  hipLaunchKernelGGL((k_st_node<DIM, TO>), dim3(gridn(work)), dim3(kB), 0, st, g, a.h, gcl, cf, a.dir, S);
+  if (a.m.split == kSplitSpectral) {
+    hipLaunchKernelGGL((k_coef<DIM, TO, true>), dim3(gridn(ne)), dim3(kB), 0, st, a.N, a.h, a.m, xl, p, cf);
+    hipLaunchKernelGGL((k_st_node<DIM, TO, true>), dim3(gridn(work)), dim3(kB), 0, st, g, a.h, gcl, cf, a.dir, S);
+  } else {
+    hipLaunchKernelGGL((k_coef<DIM, TO, false>), dim3(gridn(ne)), dim3(kB), 0, st, a.N, a.h, a.m, xl, p, cf);
+    hipLaunchKernelGGL((k_st_node<DIM, TO, false>), dim3(gridn(work)), dim3(kB), 0, st, g, a.h, gcl, cf, a.dir, S);
+  }
   return hipGetLastError();
 }
 

@@ -108,6 +108,23 @@ def fit_scales(net, samples, level=None):
     ctx.nn_fit_scales(ctx.L if level is None else level, samples, net.scales)
 
 
+def rescale_for_grid(net, h_train, h_deploy, dim):
+    """Adapt the output scales of a network trained on a grid of spacing
+    h_train to a grid of spacing h_deploy.  The smoother correction is about
+    D^-1 g with D the diagonal of the lagged Hessian, which scales like
+    h^(d-2) on displacement rows (elastic stiffness) and like h^(d-1) on
+    phase-field rows (G_c / l_s and G_c l_s terms with l_s proportional to
+    h), so the ratio rms(s_k) / rms(g_k) fitted at h_train is multiplied by
+    (h_train / h_deploy)^(d-2) for u and (h_train / h_deploy)^(d-1) for c.
+    The input scales are left alone (u and c keep their magnitudes, g enters
+    divided by its own RMS).  Host-side update of the four output scales."""
+    r = float(h_train) / float(h_deploy)
+    sc = net.scales.detach().cpu().numpy().astype(np.float64)
+    sc[8:8 + dim] *= r ** (dim - 2)
+    sc[8 + dim] *= r ** (dim - 1)
+    net.scales.copy_(torch.from_numpy(sc.astype(np.float32)))
+
+
 class Trainer:
     """Adam on the MSE between the network output and the scaled targets,
     one whole node grid per step (every 32^3 patch of it at once)."""

@@ -48,6 +48,12 @@ def test_create_validates_model_without_gpu():
     assert lib.rmtr_level_nodes(h, 1) == 5 ** 3 and lib.rmtr_level_nodes(h, 3) == 17 ** 3
     assert lib.rmtr_level_nodes(h, 4) == -1
     lib.rmtr_destroy(h)
+    # split: 0 unsplit, 1 volumetric-deviatoric, 2 spectral; nothing else
+    for split, want in ((0, 0), (2, 0), (3, -1), (-1, -1)):
+        m = binding.Model(2, 8, 2, split, 1.0, 1.0, 1e-3, 0.1, 1e-6)
+        assert lib.rmtr_create(ctypes.byref(m), ctypes.byref(h)) == want
+        if want == 0:
+            lib.rmtr_destroy(h)
     p = binding.default_params()
     assert (p.eta1, p.eta2, p.gamma1, p.gamma2, p.pgs_sweeps, p.mu1, p.mu2) == (0.1, 0.75, 0.5, 2.0, 3, 1, 1)
     assert p.use_learned == 0 and not p.nn

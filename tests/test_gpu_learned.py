@@ -99,10 +99,13 @@ def test_absurd_proposals_are_gated():
 
 def test_trained_network_against_plain_and_untrained():
     """Train on states of three fracture networks, deploy on a held-out one;
-    each variant runs 40 V-cycles (or to 1e-8).  Every result is feasible
-    and its chi, re-evaluated by the FP64 oracle, equals the GPU's; what the
-    trained network gains (accepted proposals, chi reached, time) is
-    recorded."""
+    each variant runs 40 V-cycles (or to 1e-8).  Training must lower the
+    loss; every result is feasible and its chi, re-evaluated by the FP64
+    oracle, equals the GPU's; runs whose proposals are all refused by the
+    gate are the plain run bit for bit.  What the trained network gains
+    (accepted proposals, chi reached, time) is recorded, not asserted: the
+    measured gain on these networks is nil (no proposal passes the gate's
+    comparison with the smoother step)."""
     from paper_2007_12908_amd import learned
     print("case train and deploy", flush=True)
     samples = []
@@ -139,4 +142,7 @@ def test_trained_network_against_plain_and_untrained():
         with open(out, "w") as f:
             json.dump({"training": {"samples": len(samples), "steps": done, "seconds": secs, "loss0": loss0,
                                     "loss1": loss1}, "runs": runs}, f, indent=1)
-    assert runs["trained"]["nn_accepted"] >= runs["untrained"]["nn_accepted"]
+    for name in ("untrained", "trained"):
+        if runs[name]["nn_accepted"] == 0:
+            assert runs[name]["vcycles"] == runs["plain"]["vcycles"]
+            assert runs[name]["energy"] == runs["plain"]["energy"]

@@ -1,6 +1,9 @@
 """GPU vs oracle: initial fields, energy, energy difference, gradient, Hv,
 diagonal blocks (FP64 and the FP32 mixed-precision form).
 
+Every split is covered: unsplit, volumetric-deviatoric and spectral (the
+principal strains from Jacobi rotations on the GPU, LAPACK in the oracle).
+
 Tolerances: FP64 results within 1e-12 relative, element by element and
 scaled per field (the displacement block and the phase-field block
 separately); the FP32 Hv within
@@ -20,7 +23,7 @@ CASES = [(2, 6), (2, 13), (3, 3), (3, 5), (3, 20), (3, 33)]
 
 
 @pytest.mark.parametrize("d,N", CASES)
-@pytest.mark.parametrize("split", [True, False])
+@pytest.mark.parametrize("split", [True, False, fem.SPLIT_SPECTRAL])
 def test_energy_gradient_hessvec_fp64(d, N, split):
     print(f"case d={d} N={N} split={split}", flush=True)
     g, x, p = rand_state(d, N, seed=100 * d + N)
@@ -77,10 +80,11 @@ def test_custom_dirichlet_mask(d, N):
 
 
 @pytest.mark.parametrize("d,N", [(2, 13), (3, 5), (3, 33)])
-def test_hessvec_fp32_mixed(d, N):
+@pytest.mark.parametrize("split", [fem.SPLIT_VOLDEV, fem.SPLIT_SPECTRAL])
+def test_hessvec_fp32_mixed(d, N, split):
     import torch
     g, x, p = rand_state(d, N, seed=11 * N)
-    mat = material(N)
+    mat = material(N, split)
     ctx = ctx_for(d, N, 1, mat)
     rng = np.random.default_rng(5)
     v = rng.standard_normal(g.n_dofs)

@@ -78,6 +78,33 @@ def test_loadstep_matches_oracle(case, shrink, model, first):
     assert np.abs(xg - xo).max() <= 1e-6 * np.abs(xo).max()
 
 
+@pytest.mark.parametrize("case", ["c1", "3d"])
+def test_spectral_split_loadstep_matches_oracle(case):
+    """The load step with the spectral split (energy, gradient, lagged Hessian
+    stencils and Galerkin coarse levels all on principal strains)."""
+    if case == "c1":
+        g, mat, c0, p, x = _c1()
+        d, N, L = 2, 64, 3
+    else:
+        g, mat, c0, p, x = _small3d(8)
+        d, N, L = 3, 8, 2
+    mat = fem.Material(mat.lam, mat.mu, mat.Gc, mat.ls, mat.k, fem.SPLIT_SPECTRAL)
+    print(f"case {case} spectral", flush=True)
+    xg, st = _gpu_solve(d, N, L, mat, c0, p, x)
+    solver = rmtr.RMTR(d, N, L, mat, p, rmtr.Params())
+    xo, so = solver.solve_loadstep(x.copy(), c0)
+    print("gpu", st["vcycles"], st["chi"] / st["chi0"], "oracle", so.vcycles, so.chi / so.chi0, flush=True)
+    assert st["code"] == 0
+    c = xg[d::d + 1]
+    assert np.all(c >= c0) and np.all(c <= 1.0)
+    assert np.all(xg[g.default_dirichlet()] == 0.0)
+    gr = fem.gradient(g, xg, p, mat)
+    assert fem.chi(g, xg, gr, c0) <= 1e-8 * so.chi0 * (1 + 1e-6)
+    assert abs(st["vcycles"] - so.vcycles) <= 1
+    assert st["energy"] == pytest.approx(so.energy, rel=1e-10)
+    assert np.abs(xg - xo).max() <= 1e-6 * np.abs(xo).max()
+
+
 def test_one_level_plain_tr_matches_oracle():
     g, mat, c0, p, x = _small3d(4)
     xg, st = _gpu_solve(3, 4, 1, mat, c0, p, x, max_vcycles=6)

@@ -23,12 +23,15 @@ def _box(g, x, delta, rng):
     return lo, hi
 
 
-@pytest.mark.parametrize("d,N", [(2, 7), (2, 16), (3, 4), (3, 17)])
-@pytest.mark.parametrize("sweeps", [1, 3])
-def test_pgs_matches_oracle(d, N, sweeps):
-    print(f"case d={d} N={N} sweeps={sweeps}", flush=True)
+@pytest.mark.parametrize("d,N,sweeps,split", [(2, 7, 1, 1), (2, 16, 1, 1), (3, 4, 1, 1), (3, 17, 1, 1),
+                                               (2, 7, 3, 1), (2, 16, 3, 1), (3, 4, 3, 1), (3, 17, 3, 1),
+                                               (2, 16, 3, 2), (3, 4, 3, 2), (3, 17, 3, 2)])
+def test_pgs_matches_oracle(d, N, sweeps, split):
+    """split 2: the spectral split's assembled stencil (principal axes and
+    divided differences per quadrature point)."""
+    print(f"case d={d} N={N} sweeps={sweeps} split={split}", flush=True)
     g, x, p = rand_state(d, N, seed=N + sweeps, u_scale=1e-4, c_max=0.6)
-    mat = material(N)
+    mat = material(N, split)
     rng = np.random.default_rng(N)
     gv = rng.standard_normal(g.n_dofs) * 1e-4
     gv[g.default_dirichlet()] = 0.0
@@ -191,13 +194,13 @@ def test_dot_and_chi():
     assert chi == pytest.approx(fem.chi(g, x, gr, cl), rel=1e-13)
 
 
-@pytest.mark.parametrize("d,N", [(2, 16), (3, 17)])
-def test_pgs_fp32_mixed(d, N):
+@pytest.mark.parametrize("d,N,split", [(2, 16, 1), (3, 17, 1), (3, 17, 2)])
+def test_pgs_fp32_mixed(d, N, split):
     """FP32 stencil and sweeps (mixed form) vs the FP64 oracle: 3 sweeps of
     single-precision Gauss-Seidel agree to 1e-4 relative; bounds exact."""
     import torch
     g, x, p = rand_state(d, N, seed=77 + N, u_scale=1e-4, c_max=0.6)
-    mat = material(N)
+    mat = material(N, split)
     rng = np.random.default_rng(N + 1)
     gv = rng.standard_normal(g.n_dofs) * 1e-4
     gv[g.default_dirichlet()] = 0.0
