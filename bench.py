@@ -345,6 +345,32 @@ def ramp_leg(args, P, W, torch):
             "total_s": sum(r["s"] for r in steps)}
 
 
+def loadstep_leg(args, P, W, torch):
+    """One load step of any workload (2D or 3D) from u = 0, c = c0, with the
+    strain split of `--split` (the workloads' model is 1), the precision of
+    `--ramp-precision` and solver settings from `--solver` (JSON; default:
+    the workload's own)."""
+    wl = W.WORKLOADS[args.loadstep]
+    N, L, d = wl.n_cells, wl.n_levels, wl.dim
+    ctx = P.Context(d, N, L, wl.lam, wl.mu, wl.Gc, wl.ls, wl.k, split=args.split)
+    if wl.extra.get("p_lo") is not None:
+        c0, p = ctx.init_fields(L, wl.fractures(), band=wl.h, p_mode=1, p_band=4.0 * wl.ls)
+    else:
+        c0, p = ctx.init_fields(L, wl.fractures(), band=wl.h, p_mode=0, p_value=wl.p)
+    x = torch.zeros((d + 1) * (N + 1) ** d, dtype=torch.float64, device="cuda")
+    x.view(-1, d + 1)[:, d] = c0
+    settings = dict(wl.solver) if args.solver is None else json.loads(args.solver)
+    prm = P.default_params(precision=args.ramp_precision, max_vcycles=args.max_vcycles, **settings)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = ctx.solve_loadstep(x, p, c0, prm)
+    torch.cuda.synchronize()
+    return {"workload": wl.name, "split": args.split, "precision": args.ramp_precision, "settings": settings,
+            "s": time.perf_counter() - t0, "vcycles": st["vcycles"], "chi_rel": st["chi"] / st["chi0"],
+            "tr_accepted": st["tr_accepted"], "tr_rejected": st["tr_rejected"], "delta": st["delta"],
+            "converged": st["code"] == 0}
+
+
 def roofline_of(kernels, wl, traffic):
     """Roofline of the dominant (slowest) FP64 kernel of a kernel leg."""
     dom = max(("energy", "gradient", "hessvec"), key=lambda k: kernels[k]["ms"])
@@ -380,15 +406,19 @@ def main():
     ap.add_argument("--cnn-only", action="store_true",
                     help="time only the network's forward and backward passes (for profiler runs)")
     ap.add_argument("--split", type=int, default=1, choices=(0, 1, 2),
-                    help="strain split of the roofline-only kernels: 0 unsplit, 1 volumetric-deviatoric "
-                         "(the workloads' model), 2 spectral")
+                    help="strain split of --roofline-only and --loadstep: 0 unsplit (the paper's energy), "
+                         "1 volumetric-deviatoric (the workloads' model), 2 spectral")
     ap.add_argument("--learned-c5", action="store_true",
                     help="train on 128^3 runs, deploy on the 256^3 network: plain, mixed and mixed + learned "
                          "load steps (several minutes; not part of the default run)")
     ap.add_argument("--ramp", type=int, default=0,
                     help="run this many load steps on the 256^3 network with p ramped from p to 2p "
                          "(several minutes; not part of the default run)")
-    ap.add_argument("--ramp-precision", type=int, default=1, choices=(0, 1), help="0 FP64, 1 mixed")
+    ap.add_argument("--ramp-precision", type=int, default=1, choices=(0, 1),
+                    help="precision of --ramp and --loadstep: 0 FP64, 1 mixed")
+    ap.add_argument("--loadstep", default=None, help="run one load step of this workload (any split) and exit")
+    ap.add_argument("--max-vcycles", type=int, default=200)
+    ap.add_argument("--solver", default=None, help="solver settings of --loadstep as JSON (default: the workload's)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -427,6 +457,10 @@ def main():
 
     if args.ramp:
         print(json.dumps({"ramp": ramp_leg(args, P, W, torch)}), flush=True)
+        return
+
+    if args.loadstep:
+        print(json.dumps({"loadstep": loadstep_leg(args, P, W, torch)}), flush=True)
         return
 
     if args.learned_c5:
