@@ -411,10 +411,13 @@ def gradient(grid, x, p, mat, dirichlet=None, elems=None):
 
 
 def element_matrices(grid, x, p, mat, elems=None):
-    """K_e = sum_q w B_q^T W_zz B_q for the selected elements."""
+    """K_e = sum_q w B_q^T W_zz B_q for the selected elements, as two matrix
+    products: W_zz B_q per point, then B^T (all points stacked) times it."""
     B, w, dofs, z, pq, dpq = _quad_data(grid, x, p, elems)
     Wzz = density_hess(z, pq, dpq, mat, grid.d)
-    Ke = w * np.einsum("qmk,eqmn,qnl->ekl", B, Wzz, B)
+    WB = np.matmul(Wzz, B[None])                      # (e, q, m, k): W_zz B_q
+    ne, nq, m, nk = WB.shape
+    Ke = w * np.matmul(B.reshape(nq * m, nk).T[None], WB.reshape(ne, nq * m, nk))
     return dofs, Ke
 
 
