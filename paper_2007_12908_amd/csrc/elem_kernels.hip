@@ -193,27 +193,29 @@ constexpr int kTNodes = kTN * kTN;     // nodes per tile layer
 
 #define RMTR_LDS(ptr) ((void __attribute__((address_space(3)))*)(ptr))
 
+// Node layers in LDS component-major (one array of the tile's 17 x 17
+// nodes per component), so that the lanes of a wavefront, which take
+// neighbouring nodes, read neighbouring words.
 template <typename T>
 struct LayerLds {
-  T x[3][kTNodes][4];
-  T v[3][kTNodes][4];
+  T x[3][4][kTNodes];
+  T v[3][4][kTNodes];
   T p[3][kTNodes];
 };
 
-// The pieces one thread copies for every node layer of a tile: 16-byte
-// pieces of x (and v) and 4-byte pieces of p.  Per round r the thread's piece
-// is c = 256 r + tid; its node's in-plane offset (nodes outside the grid are
-// clamped: only inactive elements see them) and the piece's byte offset
-// within the node are the same for every layer, so they are formed once per
-// column segment.
+// The 4-byte pieces one thread copies for every node layer of a tile.  Per
+// round r the thread's piece is c = 256 r + tid of one component array (node
+// c / W, word c % W of the value, W = sizeof(T) / 4); the piece's offset in a
+// node layer of x (and v) and of p is the same for every layer and, up to
+// the component, for every component, so it is formed once per column
+// segment (nodes outside the grid are clamped: only inactive elements see
+// them).
 template <typename T>
 struct DmaPlan {
-  static constexpr int kCpn = 4 * int(sizeof(T)) / 16;  // 16-byte pieces per node (x or v)
-  static constexpr int kPpn = int(sizeof(T)) / 4;       // 4-byte pieces per node (p)
-  static constexpr int kRx = (kTNodes * kCpn + 255) / 256;
-  static constexpr int kRp = (kTNodes * kPpn + 255) / 256;
-  int xoff[kRx];  // byte offset of the piece in x (within a node layer), -1: none
-  int poff[kRp];
+  static constexpr int kW = int(sizeof(T)) / 4;                 // words per value
+  static constexpr int kR = (kTNodes * kW + 255) / 256;         // rounds per component array
+  int xoff[kR];  // byte offset of the piece in x (component 0), -1: none
+  int poff[kR];  // byte offset of the piece in p
 };
 
 template <typename T>
@@ -221,33 +223,30 @@ __device__ inline DmaPlan<T> dma_plan(int N, int bx, int by) {
   DmaPlan<T> d;
   const int tid = threadIdx.x;
   const int ns = N + 1;
-  auto plane = [&](int node) {
-    const int ix = node % kTN, iy = node / kTN;
-    const int gx = min(max(bx * kOwn - 1 + ix, 0), N);
-    const int gy = min(max(by * kOwn - 1 + iy, 0), N);
-    return gx + ns * gy;
-  };
 #pragma unroll
-  for (int r = 0; r < DmaPlan<T>::kRx; ++r) {
+  for (int r = 0; r < DmaPlan<T>::kR; ++r) {
     const int c = r * 256 + tid;
-    d.xoff[r] = c < kTNodes * DmaPlan<T>::kCpn
-                    ? plane(c / DmaPlan<T>::kCpn) * 4 * int(sizeof(T)) + 16 * (c % DmaPlan<T>::kCpn)
-                    : -1;
-  }
-#pragma unroll
-  for (int r = 0; r < DmaPlan<T>::kRp; ++r) {
-    const int c = r * 256 + tid;
-    d.poff[r] = c < kTNodes * DmaPlan<T>::kPpn
-                    ? plane(c / DmaPlan<T>::kPpn) * int(sizeof(T)) + 4 * (c % DmaPlan<T>::kPpn)
-                    : -1;
+    if (c < kTNodes * DmaPlan<T>::kW) {
+      const int node = c / DmaPlan<T>::kW, word = c % DmaPlan<T>::kW;
+      const int ix = node % kTN, iy = node / kTN;
+      const int gx = min(max(bx * kOwn - 1 + ix, 0), N);
+      const int gy = min(max(by * kOwn - 1 + iy, 0), N);
+      const int pl = gx + ns * gy;
+      d.xoff[r] = pl * 4 * int(sizeof(T)) + 4 * word;
+      d.poff[r] = pl * int(sizeof(T)) + 4 * word;
+    } else {
+      d.xoff[r] = -1;
+      d.poff[r] = -1;
+    }
   }
   return d;
 }
 
-// Copy node layer z of the tile into LDS slot `slot`.
-template <int MODE, typename T>
+// Copy node layer z of the tile into LDS slot `slot` (x, v when MODE == 1,
+// and p), transposing the node-major vectors into component arrays.
+template <int MODE, typename T, class LDS>
 __device__ inline void dma_layer(int N, const DmaPlan<T>& d, int z, int slot, const T* __restrict__ x,
-                                 const T* __restrict__ p, const T* __restrict__ v, LayerLds<T>& L) {
+                                 const T* __restrict__ p, const T* __restrict__ v, LDS& L) {
   // the global-to-LDS copy exists in device code only (the host pass of a
   // template instantiated from several kernels would otherwise reject it)
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -258,21 +257,19 @@ __device__ inline void dma_layer(int N, const DmaPlan<T>& d, int z, int slot, co
   const char* vz = reinterpret_cast<const char*>(v + 4 * zl);
   const char* pz = reinterpret_cast<const char*>(p + zl);
 #pragma unroll
-  for (int r = 0; r < DmaPlan<T>::kRx; ++r) {
+  for (int r = 0; r < DmaPlan<T>::kR; ++r) {
     if (d.xoff[r] >= 0) {
-      char* xb = reinterpret_cast<char*>(&L.x[slot][0][0]) + (r * 256 + wave * 64) * 16;
-      __builtin_amdgcn_global_load_lds(xz + d.xoff[r], RMTR_LDS(xb), 16, 0, 0);
-      if (MODE == 1) {
-        char* vb = reinterpret_cast<char*>(&L.v[slot][0][0]) + (r * 256 + wave * 64) * 16;
-        __builtin_amdgcn_global_load_lds(vz + d.xoff[r], RMTR_LDS(vb), 16, 0, 0);
-      }
-    }
-  }
+      const int lb = (r * 256 + wave * 64) * 4;
 #pragma unroll
-  for (int r = 0; r < DmaPlan<T>::kRp; ++r) {
-    if (d.poff[r] >= 0) {
-      char* pb = reinterpret_cast<char*>(&L.p[slot][0]) + (r * 256 + wave * 64) * 4;
-      __builtin_amdgcn_global_load_lds(pz + d.poff[r], RMTR_LDS(pb), 4, 0, 0);
+      for (int k = 0; k < 4; ++k) {
+        __builtin_amdgcn_global_load_lds(xz + d.xoff[r] + k * int(sizeof(T)),
+                                         RMTR_LDS(reinterpret_cast<char*>(&L.x[slot][k][0]) + lb), 4, 0, 0);
+        if constexpr (MODE == 1)
+          __builtin_amdgcn_global_load_lds(vz + d.xoff[r] + k * int(sizeof(T)),
+                                           RMTR_LDS(reinterpret_cast<char*>(&L.v[slot][k][0]) + lb), 4, 0, 0);
+      }
+      __builtin_amdgcn_global_load_lds(pz + d.poff[r], RMTR_LDS(reinterpret_cast<char*>(&L.p[slot][0]) + lb), 4, 0,
+                                       0);
     }
   }
 #endif
@@ -295,8 +292,8 @@ __device__ inline void elem_segment3_lds(int N, const MatP<T>& m, T invh, T w, i
   // node layers sit in a ring of three LDS slots: layer z in slot (z - zs) % 3
   const DmaPlan<T> dp = dma_plan<T>(N, bx, by);
   if (zs <= ze) {
-    dma_layer<MODE, T>(N, dp, zs, 0, x, p, v, L);
-    dma_layer<MODE, T>(N, dp, zs + 1, 1, x, p, v, L);
+    dma_layer<MODE, T, LayerLds<T>>(N, dp, zs, 0, x, p, v, L);
+    dma_layer<MODE, T, LayerLds<T>>(N, dp, zs + 1, 1, x, p, v, L);
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
@@ -311,8 +308,8 @@ __device__ inline void elem_segment3_lds(int N, const MatP<T>& m, T invh, T w, i
       const int sl = (a >> 2) ? st : sb;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        X[a][k] = L.x[sl][node][k];
-        V[a][k] = MODE == 1 ? L.v[sl][node][k] : T(0);
+        X[a][k] = L.x[sl][k][node];
+        V[a][k] = MODE == 1 ? L.v[sl][k][node] : T(0);
       }
       P[a] = L.p[sl][node];
     }
@@ -322,7 +319,7 @@ __device__ inline void elem_segment3_lds(int N, const MatP<T>& m, T invh, T w, i
     // before the previous iteration's closing barrier); it is issued after
     // this element's reads (and its Dirichlet bits), so none of them waits
     // for it
-    if (ez + 2 <= N && ez + 1 <= ze) dma_layer<MODE, T>(N, dp, ez + 2, sn, x, p, v, L);
+    if (ez + 2 <= N && ez + 1 <= ze) dma_layer<MODE, T, LayerLds<T>>(N, dp, ez + 2, sn, x, p, v, L);
     T r[8][4];
     if (ecol) {
       ElemOp3<MODE, T, SK>::eval(m, invh, w, X, V, P, r);
@@ -402,8 +399,8 @@ __device__ inline double energy3_lds(int N, double h, const MatP<double>& m, int
     const int zs = z0, ze = min(z1, N) - 1;
     if (zs <= ze) {
       const DmaPlan<double> dp = dma_plan<double>(N, bx, by);
-      dma_layer<MODE, double>(N, dp, zs, 0, x, p, s, L);
-      dma_layer<MODE, double>(N, dp, zs + 1, 1, x, p, s, L);
+      dma_layer<MODE, double, LayerLds<double>>(N, dp, zs, 0, x, p, s, L);
+      dma_layer<MODE, double, LayerLds<double>>(N, dp, zs + 1, 1, x, p, s, L);
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       int sb = 0;
@@ -416,12 +413,12 @@ __device__ inline double energy3_lds(int N, double h, const MatP<double>& m, int
           const int sl = (a >> 2) ? st : sb;
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
-            X[a][k] = L.x[sl][node][k];
-            S[a][k] = DIFF ? L.v[sl][node][k] : 0.0;
+            X[a][k] = L.x[sl][k][node];
+            S[a][k] = DIFF ? L.v[sl][k][node] : 0.0;
           }
           P[a] = L.p[sl][node];
         }
-        if (ez + 2 <= N && ez + 1 <= ze) dma_layer<MODE, double>(N, dp, ez + 2, sn, x, p, s, L);
+        if (ez + 2 <= N && ez + 1 <= ze) dma_layer<MODE, double, LayerLds<double>>(N, dp, ez + 2, sn, x, p, s, L);
         if (mine) {
           double pq[8], dpq[8][3];
           elem_pq<3, double>(P, invh, pq, dpq);
@@ -451,6 +448,105 @@ __device__ inline double energy3_lds(int N, double h, const MatP<double>& m, int
     u += z1 - z0;
   }
   return acc;
+}
+
+// Node layers of x and p only (the energy's ring).
+template <typename T>
+struct LayerLdsXP {
+  T x[3][4][kTNodes];
+  T p[3][kTNodes];
+};
+
+// Energy, unsplit and volumetric-deviatoric forms: the quarter-wise
+// evaluation of the element kernels (two Gauss points at a time from the
+// nodal values in LDS), which keeps the state small enough for four
+// workgroups per compute unit.  Same tiles, element ownership and fixed
+// summation order as energy3_lds.
+__device__ inline double energy3_q(int N, double h, const MatP<double>& m, int tiles, const double* __restrict__ x,
+                                   const double* __restrict__ p, LayerLdsXP<double>& L) {
+  using T = double;
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const ElemScale<T> sc = elem_scale<T>(T(1) / h, h * h * h / T(8));
+  const int64_t nz = N + 1;
+  const int64_t work = int64_t(tiles) * tiles * nz;
+  const int64_t u1 = work * (blockIdx.x + 1) / gridDim.x;
+  int nd[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) nd[a] = (ty + ((a >> 1) & 1)) * kTN + tx + (a & 1);
+  double acc = 0.0;
+  for (int64_t u = work * blockIdx.x / gridDim.x; u < u1;) {
+    const int64_t col = u / nz;
+    const int z0 = int(u - col * nz);
+    const int z1 = int(min(nz, int64_t(z0) + (u1 - u)));
+    const int bx = int(col % tiles), by = int(col / tiles);
+    const int ex = bx * kOwn - 1 + tx, ey = by * kOwn - 1 + ty;
+    const bool mine = tx >= 1 && ty >= 1 && ex < N && ey < N;
+    const int zs = z0, ze = min(z1, N) - 1;
+    if (zs <= ze) {
+      const DmaPlan<T> dp = dma_plan<T>(N, bx, by);
+      dma_layer<0, T, LayerLdsXP<T>>(N, dp, zs, 0, x, p, x, L);
+      dma_layer<0, T, LayerLdsXP<T>>(N, dp, zs + 1, 1, x, p, x, L);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      int sb = 0;
+      for (int ez = zs; ez <= ze; ++ez) {
+        const int st = sb == 2 ? 0 : sb + 1, sn = st == 2 ? 0 : st + 1;
+        if (ez + 2 <= N && ez + 1 <= ze) dma_layer<0, T, LayerLdsXP<T>>(N, dp, ez + 2, sn, x, p, x, L);
+        if (mine) {
+#pragma nounroll
+          for (int qq = 0; qq < 4; ++qq) {
+            // re-read the nodal values in every quarter (see elem_segment3_q)
+            __asm__ __volatile__("" ::: "memory");
+            const T xy = gauss_xi<T>(qq & 1), xz = gauss_xi<T>(qq >> 1);
+            QPoint<T> zq[2];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+              T f[8];
+#pragma unroll
+              for (int a = 0; a < 8; ++a) f[a] = k < 4 ? L.x[(a >> 2) ? st : sb][k][nd[a]] : L.p[(a >> 2) ? st : sb][nd[a]];
+              T val[2], dx, dy[2], dz[2];
+              qtr_forward<T>(f, xz, xy, val, dx, dy, dz);
+#pragma unroll
+              for (int qx = 0; qx < 2; ++qx) {
+                if (k < 3) {
+                  zq[qx].u[k] = val[qx];
+                  zq[qx].G[k][0] = dx;
+                  zq[qx].G[k][1] = dy[qx];
+                  zq[qx].G[k][2] = dz[qx];
+                } else if (k == 3) {
+                  zq[qx].c = val[qx];
+                  zq[qx].dc[0] = dx;
+                  zq[qx].dc[1] = dy[qx];
+                  zq[qx].dc[2] = dz[qx];
+                } else {
+                  zq[qx].p = val[qx];
+                  zq[qx].dp[0] = dx;
+                  zq[qx].dp[1] = dy[qx];
+                  zq[qx].dp[2] = dz[qx];
+                }
+              }
+            }
+            acc += energy_point_sym<T>(m, sc, zq[0]) + energy_point_sym<T>(m, sc, zq[1]);
+          }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        sb = st;
+      }
+    }
+    u += z1 - z0;
+  }
+  return acc;
+}
+
+__global__ __launch_bounds__(256, 4) void k_energy_q3(int N, double h, MatP<double> m, int tiles,
+                                                      const double* __restrict__ x, const double* __restrict__ p,
+                                                      double* __restrict__ partials) {
+  __shared__ LayerLdsXP<double> L;
+  __shared__ double sh[256];
+  const double tot = block_sum(energy3_q(N, h, m, tiles, x, p, L), sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
 // The energy alone fits two workgroups per compute unit (<= 256 registers,
@@ -503,9 +599,8 @@ __device__ inline void elem_scatter3(int N, T h, const MatP<double>& md, int til
   }
 }
 
-// FP64: one wavefront per SIMD (the element state does not fit in less than
-// the full register file); FP32: two, which the smaller state allows (the
-// spectral split's FP32 variant, with the principal axes, runs one).
+// All eight points of an element at once: the FP32 Hv (two wavefronts per
+// SIMD) and the spectral split (one).
 template <int MODE, typename T, int SK>
 __global__ __launch_bounds__(256) void k_elem_scatter3(int N, T h, MatP<double> md, int tiles,
                                                        const uint8_t* __restrict__ dir,
@@ -521,6 +616,246 @@ __global__ __launch_bounds__(256, 2) void k_elem_scatter3_f32(int N, float h, Ma
                                                               const float* __restrict__ p,
                                                               const float* __restrict__ v, float* __restrict__ out) {
   elem_scatter3<MODE, float, kNoSpectral>(N, h, md, tiles, dir, x, p, v, out);
+}
+
+// ------------------------------------------------- quarter-wise element kernels
+// Gradient and Hessian action (unsplit and volumetric-deviatoric forms) on
+// the same tiles and LDS ring as elem_segment3_lds, with a per-element state
+// small enough for two workgroups per compute unit in FP64 (four in FP32):
+// the element's nodal values are read from the LDS ring once per quarter of
+// its Gauss points (qtr_forward) instead of being held for all eight, and
+// the element's nodal results are combined with the neighbours' in two
+// steps: along x between adjacent lanes of a 16-lane row (DPP row shift),
+// then along y through a small LDS buffer.
+
+// Value of v held by lane + 1 of the same 16-lane row (row_shl:1); the last
+// lane of a row gets 0.
+__device__ inline float row_next(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xF, 0xF, true));
+}
+__device__ inline double row_next(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x101, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x101, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
+template <int MODE, typename T>
+__device__ inline void elem_segment3_q(int N, const MatP<T>& m, const ElemScale<T>& sc, int bx, int by, int z0, int z1,
+                                       const uint8_t* __restrict__ dir, const T* __restrict__ x,
+                                       const T* __restrict__ p, const T* __restrict__ v, T* __restrict__ out,
+                                       T (*ysh)[4][256], LayerLds<T>& L) {
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int ex = bx * kOwn - 1 + tx;
+  const int ey = by * kOwn - 1 + ty;
+  const int ox = ex + 1, oy = ey + 1;
+  const bool ecol = ex >= 0 && ex < N && ey >= 0 && ey < N;
+  const bool owner = tx < kOwn && ty < kOwn && ox <= N && oy <= N;
+  const int64_t nside = N + 1;
+  const T cdc = sc.a2 * m.Gc_l;
+  const int zs = max(z0 - 1, 0), ze = min(z1 - 1, N - 1);
+  const DmaPlan<T> dp = dma_plan<T>(N, bx, by);
+  if (zs <= ze) {
+    dma_layer<MODE, T, LayerLds<T>>(N, dp, zs, 0, x, p, v, L);
+    dma_layer<MODE, T, LayerLds<T>>(N, dp, zs + 1, 1, x, p, v, L);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  T acc[4] = {T(0), T(0), T(0), T(0)};
+  int sb = 0;
+  for (int ez = zs; ez <= ze; ++ez) {
+    const int st = sb == 2 ? 0 : sb + 1, sn = st == 2 ? 0 : st + 1;
+    // node layer ez + 2 goes to the slot that held layer ez - 1, free since
+    // the previous iteration's closing barrier
+    if (ez + 2 <= N && ez + 1 <= ze) dma_layer<MODE, T, LayerLds<T>>(N, dp, ez + 2, sn, x, p, v, L);
+    T r[4][8];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int a = 0; a < 8; ++a) r[k][a] = T(0);
+    if (ecol) {
+      // Dirichlet bits of the direction's 8 nodes (4 per node)
+      uint32_t vm = 0;
+      if (MODE == 1) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          const int c[3] = {ex + (a & 1), ey + ((a >> 1) & 1), ez + (a >> 2)};
+          const int64_t n = int64_t(c[0]) + nside * (int64_t(c[1]) + nside * c[2]);
+          vm |= uint32_t(node_mask<3>(dir, n, c, N)) << (4 * a);
+        }
+      }
+      int nd[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) nd[a] = (ty + ((a >> 1) & 1)) * kTN + tx + (a & 1);
+#pragma nounroll
+      for (int qq = 0; qq < 4; ++qq) {
+        // the nodal values are re-read from LDS in every quarter: keep the
+        // compiler from hoisting the reads out of the loop (which would hold
+        // all of them in registers)
+        __asm__ __volatile__("" ::: "memory");
+        const T xy = gauss_xi<T>(qq & 1), xz = gauss_xi<T>(qq >> 1);
+        QPoint<T> zq[2];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          T f[8];
+#pragma unroll
+          for (int a = 0; a < 8; ++a) f[a] = L.x[(a >> 2) ? st : sb][k][nd[a]];
+          if (k < 3 || MODE == 0) {
+            T val[2], dx, dy[2], dz[2];
+            qtr_forward<T>(f, xz, xy, val, dx, dy, dz);
+#pragma unroll
+            for (int qx = 0; qx < 2; ++qx) {
+              if (k < 3) {
+                zq[qx].u[k] = val[qx];
+                zq[qx].G[k][0] = dx;
+                zq[qx].G[k][1] = dy[qx];
+                zq[qx].G[k][2] = dz[qx];
+              } else {
+                zq[qx].c = val[qx];
+                zq[qx].dc[0] = dx;
+                zq[qx].dc[1] = dy[qx];
+                zq[qx].dc[2] = dz[qx];
+              }
+            }
+          } else {
+            T val[2];
+            qtr_forward_val<T>(f, xz, xy, val);
+            zq[0].c = val[0];
+            zq[1].c = val[1];
+          }
+        }
+        {
+          T f[8];
+#pragma unroll
+          for (int a = 0; a < 8; ++a) f[a] = L.p[(a >> 2) ? st : sb][nd[a]];
+          T val[2], dx, dy[2], dz[2];
+          qtr_forward<T>(f, xz, xy, val, dx, dy, dz);
+#pragma unroll
+          for (int qx = 0; qx < 2; ++qx) {
+            zq[qx].p = val[qx];
+            zq[qx].dp[0] = dx;
+            zq[qx].dp[1] = dy[qx];
+            zq[qx].dp[2] = dz[qx];
+          }
+        }
+        Zq<3, T> o[2];
+        if (MODE == 0) {
+#pragma unroll
+          for (int qx = 0; qx < 2; ++qx) grad_point_sym<T>(m, sc, cdc, zq[qx], o[qx]);
+        } else {
+          HessSym<T> hc[2];
+#pragma unroll
+          for (int qx = 0; qx < 2; ++qx) hess_sym_coef<T>(m, sc, zq[qx], hc[qx]);
+          Zq<3, T> zv[2];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            T f[8];
+#pragma unroll
+            for (int a = 0; a < 8; ++a) f[a] = L.v[(a >> 2) ? st : sb][k][nd[a]];
+            if (vm) {
+#pragma unroll
+              for (int a = 0; a < 8; ++a)
+                if ((vm >> (4 * a + k)) & 1u) f[a] = T(0);
+            }
+            T val[2], dx, dy[2], dz[2];
+            qtr_forward<T>(f, xz, xy, val, dx, dy, dz);
+#pragma unroll
+            for (int qx = 0; qx < 2; ++qx) {
+              if (k < 3) {
+                zv[qx].u[k] = val[qx];
+                zv[qx].G[k][0] = dx;
+                zv[qx].G[k][1] = dy[qx];
+                zv[qx].G[k][2] = dz[qx];
+              } else {
+                zv[qx].c = val[qx];
+                zv[qx].dc[0] = dx;
+                zv[qx].dc[1] = dy[qx];
+                zv[qx].dc[2] = dz[qx];
+              }
+            }
+          }
+#pragma unroll
+          for (int qx = 0; qx < 2; ++qx) hess_sym_apply<T>(hc[qx], cdc, zv[qx], o[qx]);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          T cv[2], cx[2], cy[2], cz[2];
+#pragma unroll
+          for (int qx = 0; qx < 2; ++qx) {
+            cv[qx] = k < 3 ? o[qx].u[k] : o[qx].c;
+            cx[qx] = k < 3 ? o[qx].G[k][0] : o[qx].dc[0];
+            cy[qx] = k < 3 ? o[qx].G[k][1] : o[qx].dc[1];
+            cz[qx] = k < 3 ? o[qx].G[k][2] : o[qx].dc[2];
+          }
+          qtr_backward<T>(cv, cx, cy, cz, xz, xy, r[k]);
+        }
+      }
+    }
+    // combine: along x from the next lane of the row (every lane takes part)
+    T cs[2][2][4];  // [ay][az][k]: this and the next element's share of node (tx + 1, ty + ay, ez + az)
+#pragma unroll
+    for (int ay = 0; ay < 2; ++ay)
+#pragma unroll
+      for (int az = 0; az < 2; ++az)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cs[ay][az][k] = r[k][1 + 2 * ay + 4 * az] + row_next(r[k][2 * ay + 4 * az]);
+    // along y through LDS
+#pragma unroll
+    for (int az = 0; az < 2; ++az)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) ysh[az][k][tid] = cs[0][az][k];
+    __syncthreads();
+    if (owner) {
+      if (ez >= z0) {
+        const int c[3] = {ox, oy, ez};
+        const int64_t n = int64_t(ox) + nside * (int64_t(oy) + nside * ez);
+        const uint8_t mk = node_mask<3>(dir, n, c, N);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const T s = acc[k] + cs[1][0][k] + ysh[0][k][tid + 16];
+          out[4 * n + k] = (mk & (1u << k)) ? T(0) : s;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[k] = cs[1][1][k] + ysh[1][k][tid + 16];
+    }
+    // layer ez + 2 is in LDS, slot sb and the y buffer are free again
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    sb = st;
+  }
+  if (owner && ze + 1 < z1) {
+    const int nz = ze + 1;
+    const int64_t n = int64_t(ox) + nside * (int64_t(oy) + nside * nz);
+    const int c[3] = {ox, oy, nz};
+    const uint8_t mk = node_mask<3>(dir, n, c, N);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[4 * n + k] = (mk & (1u << k)) ? T(0) : acc[k];
+  }
+}
+
+// FP64, two workgroups per compute unit (at most 256 registers, 77 KB of
+// LDS each).
+template <int MODE>
+__global__ __launch_bounds__(256, 2) void k_elem_q3(int N, double h, MatP<double> md, int tiles,
+                                                    const uint8_t* __restrict__ dir, const double* __restrict__ x,
+                                                    const double* __restrict__ p, const double* __restrict__ v,
+                                                    double* __restrict__ out) {
+  using T = double;
+  __shared__ T ysh[2][4][256];
+  __shared__ LayerLds<T> lds;
+  const MatP<T> m = md;
+  const ElemScale<T> sc = elem_scale<T>(T(1) / h, h * h * h / T(8));
+  const int64_t nz = N + 1;
+  const int64_t work = int64_t(tiles) * tiles * nz;
+  const int64_t u1 = work * (blockIdx.x + 1) / gridDim.x;
+  for (int64_t u = work * blockIdx.x / gridDim.x; u < u1;) {
+    const int64_t col = u / nz;
+    const int z0 = int(u - col * nz);
+    const int z1 = int(min(nz, int64_t(z0) + (u1 - u)));
+    elem_segment3_q<MODE, T>(N, m, sc, int(col % tiles), int(col / tiles), z0, z1, dir, x, p, v, out, ysh, lds);
+    u += z1 - z0;
+  }
 }
 
 // Node-centric kernels (any DIM): a thread per node sums the contributions
@@ -690,16 +1025,18 @@ hipError_t launch_reduce_partials(const double* partials, int n, double* out, hi
 }
 
 // Workgroups of the tiled 3D energy: as many as fit on the chip at once
-// (two per compute unit for the energy, one for the difference), fewer on
-// coarse levels with fewer tile layers.
-int64_t energy3_groups(int N, bool diff) {
+// (four per compute unit for the quarter-wise energy, two for the spectral
+// split's, one for the difference), fewer on coarse levels with fewer tile
+// layers.
+int64_t energy3_groups(int N, bool diff, bool spec) {
   const int tiles = (N + 1 + kOwn - 1) / kOwn;
   const int64_t work = int64_t(tiles) * tiles * (N + 1);
-  return std::max<int64_t>(1, std::min<int64_t>(int64_t(compute_units()) * (diff ? 1 : 2), work));
+  return std::max<int64_t>(1, std::min<int64_t>(int64_t(compute_units()) * (diff ? 1 : spec ? 2 : 4), work));
 }
 
 int energy_partials(const ElemArgs& a) {
-  if (a.dim == 3) return int(std::min<int64_t>(energy3_groups(a.N, false), kMaxPartials));
+  if (a.dim == 3)
+    return int(std::min<int64_t>(energy3_groups(a.N, false, a.m.split == kSplitSpectral), kMaxPartials));
   const int64_t ne = int64_t(a.N) * a.N;
   int64_t nb = (ne + kBlock - 1) / kBlock;
   if (nb > kMaxPartials) nb = kMaxPartials;
@@ -714,7 +1051,7 @@ hipError_t launch_energy(const ElemArgs& a, const double* x, const void* s, int 
     const int tiles = (a.N + 1 + kOwn - 1) / kOwn;
     const bool spec = a.m.split == kSplitSpectral;
     if (s) {
-      nb = int(std::min<int64_t>(energy3_groups(a.N, true), kMaxPartials));
+      nb = int(std::min<int64_t>(energy3_groups(a.N, true, spec), kMaxPartials));
       if (spec)
         hipLaunchKernelGGL(k_energy_diff3_lds<kSplitSpectral>, dim3(nb), dim3(256), 0, st, a.N, a.h, a.m, tiles, x,
                            (const double*)s, p, partials);
@@ -725,7 +1062,7 @@ hipError_t launch_energy(const ElemArgs& a, const double* x, const void* s, int 
       hipLaunchKernelGGL(k_energy3_lds<kSplitSpectral>, dim3(nb), dim3(256), 0, st, a.N, a.h, a.m, tiles, x, p,
                          partials);
     } else {
-      hipLaunchKernelGGL(k_energy3_lds<kNoSpectral>, dim3(nb), dim3(256), 0, st, a.N, a.h, a.m, tiles, x, p, partials);
+      hipLaunchKernelGGL(k_energy_q3, dim3(nb), dim3(256), 0, st, a.N, a.h, a.m, tiles, x, p, partials);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -768,7 +1105,11 @@ static hipError_t launch_scatter(const ElemArgs& a, const T* x, const T* p, cons
     // the recomputed element layer, bounds it there)
     const int64_t work = int64_t(tiles) * tiles * (a.N + 1);
     const bool spec = a.m.split == kSplitSpectral;
-    int64_t nb = int64_t(compute_units()) * (sizeof(T) == 4 && !spec ? 2 : 1);
+    // FP64 (unsplit, volumetric-deviatoric): the quarter-wise kernel, two
+    // workgroups per compute unit; FP32: all eight points per element, two
+    // workgroups (fewer instructions, and FP32 state fits); spectral split:
+    // one workgroup
+    int64_t nb = int64_t(compute_units()) * (spec ? 1 : 2);
     nb = std::max<int64_t>(1, std::min(nb, work));
     if (spec)
       hipLaunchKernelGGL((k_elem_scatter3<MODE, T, kSplitSpectral>), dim3(unsigned(nb)), dim3(256), 0, st, a.N,
@@ -777,8 +1118,8 @@ static hipError_t launch_scatter(const ElemArgs& a, const T* x, const T* p, cons
       hipLaunchKernelGGL((k_elem_scatter3_f32<MODE>), dim3(unsigned(nb)), dim3(256), 0, st, a.N, T(a.h), a.m, tiles,
                          a.dir, x, p, v, out);
     else
-      hipLaunchKernelGGL((k_elem_scatter3<MODE, T, kNoSpectral>), dim3(unsigned(nb)), dim3(256), 0, st, a.N, T(a.h),
-                         a.m, tiles, a.dir, x, p, v, out);
+      hipLaunchKernelGGL((k_elem_q3<MODE>), dim3(unsigned(nb)), dim3(256), 0, st, a.N, T(a.h), a.m, tiles, a.dir, x,
+                         p, v, out);
   } else {
     int64_t nn = int64_t(a.N + 1) * (a.N + 1);
     with_split(a.m, [&](auto sk) {

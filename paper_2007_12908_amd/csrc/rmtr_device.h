@@ -1022,6 +1022,256 @@ struct ElemOp3 {
   }
 };
 
+// ------------------------------------------------------------------------
+// Quarter-wise 3D element operators.  The 8 Gauss points of an element are
+// taken two at a time: a quarter fixes the point's y and z coordinates
+// (qy, qz) and holds the two points qx = 0, 1.  A quarter's values and
+// unit-cell derivatives come from the element's 8 nodal values by one
+// interpolation stage per direction (z, then y, then x), each written as
+// f0 + xi (f1 - f0) so that the difference f1 - f0 is also the derivative
+// along that direction; the adjoint runs the stages backwards.  Working on
+// two points at a time keeps the per-element state small (the operator
+// coefficients of two points, not eight), at the price of repeating the
+// first two stages once per quarter.
+
+// Gauss coordinate of point index q in one direction: xi_0 = 1 - xi_1.
+template <typename T>
+RMTR_FN T gauss_xi(int q) {
+  return q ? T(RMTR_GA) : T(RMTR_GB);
+}
+
+// Values and unit-cell derivatives of one nodal field at the quarter's two
+// points.  f[a], a = ax + 2 ay + 4 az; xz, xy the quarter's z and y Gauss
+// coordinates.  dx is the same at both points.
+template <typename T>
+RMTR_FN void qtr_forward(const T (&f)[8], T xz, T xy, T (&val)[2], T& dx, T (&dy)[2], T (&dz)[2]) {
+  T vz[2][2], gz[2][2];
+#pragma unroll
+  for (int ay = 0; ay < 2; ++ay)
+#pragma unroll
+    for (int ax = 0; ax < 2; ++ax) {
+      const T f0 = f[ax + 2 * ay], f1 = f[ax + 2 * ay + 4];
+      gz[ax][ay] = f1 - f0;
+      vz[ax][ay] = f0 + xz * gz[ax][ay];
+    }
+  T vy[2], gy[2], gzy[2];
+#pragma unroll
+  for (int ax = 0; ax < 2; ++ax) {
+    gy[ax] = vz[ax][1] - vz[ax][0];
+    vy[ax] = vz[ax][0] + xy * gy[ax];
+    gzy[ax] = gz[ax][0] + xy * (gz[ax][1] - gz[ax][0]);
+  }
+  dx = vy[1] - vy[0];
+  const T ddy = gy[1] - gy[0], ddz = gzy[1] - gzy[0];
+#pragma unroll
+  for (int qx = 0; qx < 2; ++qx) {
+    const T xx = gauss_xi<T>(qx);
+    val[qx] = vy[0] + xx * dx;
+    dy[qx] = gy[0] + xx * ddy;
+    dz[qx] = gzy[0] + xx * ddz;
+  }
+}
+
+// Values only (a field whose gradient the operator does not need).
+template <typename T>
+RMTR_FN void qtr_forward_val(const T (&f)[8], T xz, T xy, T (&val)[2]) {
+  T vy[2];
+#pragma unroll
+  for (int ax = 0; ax < 2; ++ax) {
+    const T v0 = f[ax] + xz * (f[ax + 4] - f[ax]);
+    const T v1 = f[ax + 2] + xz * (f[ax + 6] - f[ax + 2]);
+    vy[ax] = v0 + xy * (v1 - v0);
+  }
+  const T dx = vy[1] - vy[0];
+#pragma unroll
+  for (int qx = 0; qx < 2; ++qx) val[qx] = vy[0] + gauss_xi<T>(qx) * dx;
+}
+
+// Transpose of qtr_forward: r[a] += sum over the two points of
+// N_a cv + dN_a/dx cx + dN_a/dy cy + dN_a/dz cz (unit-cell derivatives).
+template <typename T>
+RMTR_FN void qtr_backward(const T (&cv)[2], const T (&cx)[2], const T (&cy)[2], const T (&cz)[2], T xz, T xy,
+                          T (&r)[8]) {
+  const T A = T(RMTR_GA), B = T(RMTR_GB);
+  // x stage: the two points' weights back onto the x-nodes of the quarter
+  const T sx = cx[0] + cx[1];
+  T avy[2], agy[2], agz[2];
+  avy[0] = A * cv[0] + B * cv[1] - sx;
+  avy[1] = B * cv[0] + A * cv[1] + sx;
+  agy[0] = A * cy[0] + B * cy[1];
+  agy[1] = B * cy[0] + A * cy[1];
+  agz[0] = A * cz[0] + B * cz[1];
+  agz[1] = B * cz[0] + A * cz[1];
+  // y stage, then z stage into the nodes
+  const T wy0 = T(1) - xy, wz0 = T(1) - xz;
+#pragma unroll
+  for (int ax = 0; ax < 2; ++ax) {
+    const T av0 = wy0 * avy[ax] - agy[ax], av1 = xy * avy[ax] + agy[ax];
+    const T ag0 = wy0 * agz[ax], ag1 = xy * agz[ax];
+    r[ax] += wz0 * av0 - ag0;
+    r[ax + 4] += xz * av0 + ag0;
+    r[ax + 2] += wz0 * av1 - ag1;
+    r[ax + 6] += xz * av1 + ag1;
+  }
+}
+
+// X-side quantities of one point that the operators need (unit cell):
+// u, the symmetric strain parts, c, dc (gradient only), p, grad p.
+template <typename T>
+struct QPoint {
+  T u[3];
+  T G[3][3];
+  T c;
+  T dc[3];
+  T p;
+  T dp[3];
+};
+
+// Unit-cell split parts at one point, symmetric form: t = tr G', psip = h^2
+// psi+, the diagonal and off-diagonal of sigma+' = h sigma+ (sig_ij for
+// i < j in the order xy, xz, yz), sigm' the diagonal of sigma-' (h sigma-).
+template <typename T>
+RMTR_FN void split_sym_unit(const MatP<T>& m, const T (&G)[3][3], T& t, T& psip, T (&sd)[3], T (&so)[3], T& sigm) {
+  t = G[0][0] + G[1][1] + G[2][2];
+  const T e01 = T(0.5) * (G[0][1] + G[1][0]);
+  const T e02 = T(0.5) * (G[0][2] + G[2][0]);
+  const T e12 = T(0.5) * (G[1][2] + G[2][1]);
+  const T epsq = G[0][0] * G[0][0] + G[1][1] * G[1][1] + G[2][2] * G[2][2] +
+                 T(2) * (e01 * e01 + e02 * e02 + e12 * e12);
+  T diag;
+  if (m.split) {
+    const T tp = t > T(0) ? t : T(0);
+    const T tm = t > T(0) ? T(0) : t;
+    psip = T(0.5) * m.K * tp * tp + m.mu * (epsq - t * t * m.third);
+    diag = m.K * tp - m.mu23 * t;
+    sigm = m.K * tm;
+  } else {
+    psip = T(0.5) * m.lam * t * t + m.mu * epsq;
+    diag = m.lam * t;
+    sigm = T(0);
+  }
+  const T mu2 = T(2) * m.mu;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) sd[i] = mu2 * G[i][i] + diag;
+  so[0] = mu2 * e01;
+  so[1] = mu2 * e02;
+  so[2] = mu2 * e12;
+}
+
+// Scaled second-variation coefficients at a point (unsplit or
+// volumetric-deviatoric split) in symmetric form: S = Sd on the diagonal and
+// So off it (xy, xz, yz).
+template <typename T>
+struct HessSym {
+  T vol, shear, Ccc;
+  T Sd[3], So[3], Pc[3];
+};
+
+template <typename T>
+RMTR_FN void hess_sym_coef(const MatP<T>& m, const ElemScale<T>& sc, const QPoint<T>& z, HessSym<T>& hc) {
+  T t, psip, sd[3], so[3], sigm;
+  split_sym_unit<T>(m, z.G, t, psip, sd, so, sigm);
+  const T omc = T(1) - z.c;
+  const T g = (T(1) - m.k) * omc * omc + m.k;
+  const T dg = T(-2) * (T(1) - m.k) * omc;
+  const T d2g = T(2) * (T(1) - m.k);
+  const T dgp = T(-2) * omc;
+  const T pi = z.p * t + z.dp[0] * z.u[0] + z.dp[1] * z.u[1] + z.dp[2] * z.u[2];
+  if (m.split) {
+    hc.vol = sc.a2 * ((t > T(0) ? g * m.K : m.K) - g * m.mu23);
+  } else {
+    hc.vol = sc.a2 * g * m.lam;
+  }
+  hc.shear = sc.a2 * g * m.mu;
+  const T a2dg = sc.a2 * dg;
+  const T a1dgp = sc.a1 * dgp;
+  const T dia = a1dgp * z.p;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    hc.Sd[i] = a2dg * sd[i] + dia;
+    hc.So[i] = a2dg * so[i];
+    hc.Pc[i] = a1dgp * z.dp[i];
+  }
+  hc.Ccc = sc.a2 * d2g * psip + sc.w * m.Gc_ls + T(2) * sc.a1 * pi;
+}
+
+// The coefficients applied to the direction v (unit-cell quantities); o is
+// symmetric in G, so o.G[i][j] and o.G[j][i] are written from one value.
+template <typename T>
+RMTR_FN void hess_sym_apply(const HessSym<T>& hc, T cdc, const Zq<3, T>& v, Zq<3, T>& o) {
+  const T tv = v.G[0][0] + v.G[1][1] + v.G[2][2];
+  const T s01 = v.G[0][1] + v.G[1][0], s02 = v.G[0][2] + v.G[2][0], s12 = v.G[1][2] + v.G[2][1];
+  const T vt = hc.vol * tv, sh2 = T(2) * hc.shear;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    o.u[i] = hc.Pc[i] * v.c;
+    o.dc[i] = cdc * v.dc[i];
+    o.G[i][i] = sh2 * v.G[i][i] + hc.Sd[i] * v.c + vt;
+  }
+  o.G[0][1] = o.G[1][0] = hc.shear * s01 + hc.So[0] * v.c;
+  o.G[0][2] = o.G[2][0] = hc.shear * s02 + hc.So[1] * v.c;
+  o.G[1][2] = o.G[2][1] = hc.shear * s12 + hc.So[2] * v.c;
+  o.c = hc.Ccc * v.c + hc.Pc[0] * v.u[0] + hc.Pc[1] * v.u[1] + hc.Pc[2] * v.u[2] + hc.Sd[0] * v.G[0][0] +
+        hc.Sd[1] * v.G[1][1] + hc.Sd[2] * v.G[2][2] + hc.So[0] * s01 + hc.So[1] * s02 + hc.So[2] * s12;
+}
+
+// Scaled energy density at a point (unsplit or volumetric-deviatoric),
+// w W from the unit-cell quantities: the strain energies are h^2 times the
+// true ones and the pressure work h times, so
+//   w W = a2 (g psi+' + psi-' + Gc l/2 |dc'|^2) + w Gc/(2 l) c^2 + a1 gp pi'.
+template <typename T>
+RMTR_FN T energy_point_sym(const MatP<T>& m, const ElemScale<T>& sc, const QPoint<T>& z) {
+  const T t = z.G[0][0] + z.G[1][1] + z.G[2][2];
+  const T e01 = T(0.5) * (z.G[0][1] + z.G[1][0]);
+  const T e02 = T(0.5) * (z.G[0][2] + z.G[2][0]);
+  const T e12 = T(0.5) * (z.G[1][2] + z.G[2][1]);
+  const T epsq = z.G[0][0] * z.G[0][0] + z.G[1][1] * z.G[1][1] + z.G[2][2] * z.G[2][2] +
+                 T(2) * (e01 * e01 + e02 * e02 + e12 * e12);
+  T psip, psim;
+  if (m.split) {
+    const T tp = t > T(0) ? t : T(0);
+    const T tm = t > T(0) ? T(0) : t;
+    psip = T(0.5) * m.K * tp * tp + m.mu * (epsq - t * t * m.third);
+    psim = T(0.5) * m.K * tm * tm;
+  } else {
+    psip = T(0.5) * m.lam * t * t + m.mu * epsq;
+    psim = T(0);
+  }
+  const T omc = T(1) - z.c;
+  const T g = (T(1) - m.k) * omc * omc + m.k;
+  const T gp = omc * omc;
+  const T pi = z.p * t + z.dp[0] * z.u[0] + z.dp[1] * z.u[1] + z.dp[2] * z.u[2];
+  const T dcq = z.dc[0] * z.dc[0] + z.dc[1] * z.dc[1] + z.dc[2] * z.dc[2];
+  return sc.a2 * (g * psip + psim + T(0.5) * m.Gc_l * dcq) + sc.w * T(0.5) * m.Gc_ls * z.c * z.c +
+         sc.a1 * gp * pi;
+}
+
+// Scaled first variation at a point (unsplit or volumetric-deviatoric).
+template <typename T>
+RMTR_FN void grad_point_sym(const MatP<T>& m, const ElemScale<T>& sc, T cdc, const QPoint<T>& z, Zq<3, T>& o) {
+  T t, psip, sd[3], so[3], sigm;
+  split_sym_unit<T>(m, z.G, t, psip, sd, so, sigm);
+  const T omc = T(1) - z.c;
+  const T g = (T(1) - m.k) * omc * omc + m.k;
+  const T dg = T(-2) * (T(1) - m.k) * omc;
+  const T gp = omc * omc;
+  const T dgp = T(-2) * omc;
+  const T pi = z.p * t + z.dp[0] * z.u[0] + z.dp[1] * z.u[1] + z.dp[2] * z.u[2];
+  const T a2g = sc.a2 * g;
+  const T dia = sc.a2 * sigm + sc.a1 * gp * z.p;
+  const T a1gp = sc.a1 * gp;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    o.u[i] = a1gp * z.dp[i];
+    o.dc[i] = cdc * z.dc[i];
+    o.G[i][i] = a2g * sd[i] + dia;
+  }
+  o.G[0][1] = o.G[1][0] = a2g * so[0];
+  o.G[0][2] = o.G[2][0] = a2g * so[1];
+  o.G[1][2] = o.G[2][1] = a2g * so[2];
+  o.c = sc.a2 * dg * psip + sc.w * m.Gc_ls * z.c + sc.a1 * dgp * pi;
+}
+
 // Contribution of one element to the rows of its local node aloc:
 // MODE 0 gradient of f at X, MODE 1 Hessian at X applied to V.
 template <int DIM, typename T, int SK = kAnySplit>
