@@ -192,7 +192,8 @@ def kernel_leg(ctx, wl, c0, p, reps, torch):
     }
     out = {}
     for name, fn in calls.items():
-        fn()
+        for _ in range(5):     # warm-up: clocks and caches settle
+            fn()
         ms = time_calls(fn, reps, torch)
         a = ALGO[name]
         gbs = a["bytes_per_node"] * n_nodes / ms / 1e6
