@@ -154,6 +154,133 @@ __global__ __launch_bounds__(256) void k_conv_tile(Box b, const float* __restric
   }
 }
 
+// Register-blocked variant of the same convolution, used for the forward
+// pass (2.28 ms against 2.47 ms for k_conv_tile at 129^3; the data
+// gradient keeps k_conv_tile, 6.36 ms against 6.69 ms for the backward pass
+// with this kernel): a workgroup computes
+// 32 x 4 x 4 output voxels, wavefront w the four x-rows (y0 .. y0 + 3,
+// z0 + w).  For one input shift (dx, dz) and one 16-channel chunk the
+// wavefront reads the six input rows y0 - 1 .. y0 + 4 once and the three
+// weight blocks of dy = -1, 0, 1, and issues the twelve products row r x
+// offset dy (input row r + 1 + dy): 0.75 operand reads per matrix-core
+// product instead of 1.5.  The tile's input with its halo (34 x 6 x 6
+// voxels) is converted to BF16 into LDS once per tile (loaded into registers
+// one tile ahead); the weights stay in LDS.  Rows are padded by four BF16
+// values (72 bytes between voxels) so that input and weights fit the
+// compute unit's LDS together.  Operand and accumulator layouts as in
+// k_conv_tile.
+template <int NI, int NO, int SIGN, int TRANS, int BIAS, int RELU_OUT, int MASK_OUT>
+__global__ __launch_bounds__(256) void k_conv_blk(Box b, const float* __restrict__ in,
+                                                  const float* __restrict__ mask, const uint16_t* __restrict__ W,
+                                                  const float* __restrict__ bias, float* __restrict__ out) {
+  constexpr int NIP = NI < 16 ? 16 : NI;
+  static_assert(NI % 4 == 0 && NIP % 16 == 0 && NO <= 32, "channel counts");
+  constexpr int SP = NIP + 4, WP = NIP + 4;
+  constexpr int SX = 34, SY = 6, SZ = 6, NG = NIP / 4;
+  __shared__ __align__(16) uint16_t sW[27 * 32 * WP];
+  __shared__ __align__(16) uint16_t sIn[SZ * SY * SX * SP];
+  for (int e = threadIdx.x; e < 27 * 32 * NIP; e += 256) {
+    const int k = e / (32 * NIP), o = (e / NIP) % 32, i = e % NIP;
+    uint16_t wv = 0;
+    if (o < NO && i < NI) wv = TRANS ? W[(k * NO + o) * NI + i] : W[(k * NI + i) * NO + o];
+    sW[(k * 32 + o) * WP + i] = wv;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 31, lk = lane >> 5;
+  const int xt = (b.nx + 31) / 32, yt = (b.ny + 3) / 4, zt = (b.nz + 3) / 4;
+  const int64_t ntiles = int64_t(xt) * yt * zt;
+  constexpr int NST = SZ * SY * SX * NG, NIT = (NST + 255) / 256;
+  float4 buf[NIT];
+  auto load_tile = [&](int64_t T) {
+    const int x0 = 32 * int(T % xt);
+    const int y0 = 4 * int((T / xt) % yt);
+    const int z0 = 4 * int(T / (int64_t(xt) * yt));
+#pragma unroll
+    for (int j = 0; j < NIT; ++j) {
+      const int e = int(threadIdx.x) + 256 * j;
+      const int g = e % NG, vs = e / NG;
+      const int sx = vs % SX, sy = (vs / SX) % SY, sz = vs / (SX * SY);
+      const int X = x0 - 1 + sx, Y = y0 - 1 + sy, Z = z0 - 1 + sz;
+      float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e < NST && 4 * g < NI && X >= 0 && X < b.nx && Y >= 0 && Y < b.ny && Z >= 0 && Z < b.nz) {
+        const int64_t off = ((int64_t(Z) * b.ny + Y) * b.nx + X) * NI + 4 * g;
+        a = *reinterpret_cast<const float4*>(in + off);
+      }
+      buf[j] = a;
+    }
+  };
+  if (int64_t(blockIdx.x) < ntiles) load_tile(blockIdx.x);
+  for (int64_t T = blockIdx.x; T < ntiles; T += gridDim.x) {
+    const int x0 = 32 * int(T % xt);
+    const int y0 = 4 * int((T / xt) % yt);
+    const int z0 = 4 * int(T / (int64_t(xt) * yt));
+    __syncthreads();  // the previous tile's reads of sIn are done (and sW is staged)
+#pragma unroll
+    for (int j = 0; j < NIT; ++j) {
+      const int e = int(threadIdx.x) + 256 * j;
+      if (e < NST) {
+        const int g = e % NG, vs = e / NG;
+        bf16x4 q;
+        q[0] = short(f2bf(buf[j].x));
+        q[1] = short(f2bf(buf[j].y));
+        q[2] = short(f2bf(buf[j].z));
+        q[3] = short(f2bf(buf[j].w));
+        *reinterpret_cast<bf16x4*>(sIn + vs * SP + 4 * g) = q;
+      }
+    }
+    __syncthreads();
+    if (T + gridDim.x < ntiles) load_tile(T + gridDim.x);
+    f32x16 acc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[r][i] = 0.0f;
+    for (int dzi = 0; dzi < 3; ++dzi) {
+      const int zs = wave + dzi;  // LDS z of the input rows: output z + (dzi - 1)
+#pragma unroll
+      for (int dxi = 0; dxi < 3; ++dxi) {
+#pragma unroll
+        for (int ic = 0; ic < NIP / 16; ++ic) {
+          bf16x8 a[6];
+#pragma unroll
+          for (int j = 0; j < 6; ++j)
+            a[j] = *reinterpret_cast<const bf16x8*>(sIn + ((zs * SY + j) * SX + li + dxi) * SP + 16 * ic + 8 * lk);
+#pragma unroll
+          for (int dyi = 0; dyi < 3; ++dyi) {
+            // the input shift (dxi - 1, dyi - 1, dzi - 1) is offset k of
+            // the forward weights, or the mirrored offset for the data
+            // gradient
+            const int k = SIGN > 0 ? dxi + 3 * dyi + 9 * dzi : (2 - dxi) + 3 * (2 - dyi) + 9 * (2 - dzi);
+            const bf16x8 bw = *reinterpret_cast<const bf16x8*>(sW + (k * 32 + li) * WP + 16 * ic + 8 * lk);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[r + dyi], bw, acc[r], 0, 0, 0);
+          }
+        }
+      }
+    }
+    const int o = li, z = z0 + wave;
+    if (o < NO && z < b.nz) {
+      const float bo = BIAS ? bias[o] : 0.0f;
+#pragma unroll
+      for (int yr = 0; yr < 4; ++yr) {
+        const int y = y0 + yr;
+        if (y >= b.ny) continue;
+        const int64_t base = ((int64_t(z) * b.ny + y) * b.nx + x0) * NO + o;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int i = 8 * (r / 4) + 4 * lk + (r % 4);
+          if (x0 + i < b.nx) {
+            float val = acc[yr][r] + bo;
+            if (RELU_OUT) val = fmaxf(val, 0.0f);
+            if (MASK_OUT && !(mask[base + int64_t(i) * NO] > 0.0f)) val = 0.0f;
+            out[base + int64_t(i) * NO] = val;
+          }
+        }
+      }
+    }
+  }
+}
+
 // Weight and bias gradient on the matrix cores with LDS tiles: for each
 // offset k,
 //   dW[k][ci][co] = sum_v X[v + off(k)][ci] dYm[v][co],   db[co] = sum_v dYm[v][co]
@@ -455,6 +582,12 @@ int conv_tile_grid(const Box& b, int cap = 512) {
   return int(std::max<int64_t>(1, std::min<int64_t>(tiles, cap)));
 }
 
+// k_conv_blk: one workgroup per compute unit (150 KB of LDS)
+int conv_blk_grid(const Box& b) {
+  const int64_t tiles = int64_t((b.nx + 31) / 32) * ((b.ny + 3) / 4) * ((b.nz + 3) / 4);
+  return int(std::max<int64_t>(1, std::min<int64_t>(tiles, 256)));
+}
+
 }  // namespace
 
 // ------------------------------------------------------------- launchers
@@ -504,13 +637,13 @@ hipError_t nn_forward(const uint16_t* w, const float* bias, float* const layer[7
     float* Y = layer[l + 1];
     const uint16_t* W = w + w_off(l);
     const float* bb = bias + b_off(l);
-    const dim3 grid(conv_tile_grid(b));
+    const dim3 grid(conv_blk_grid(b));
     if (l == 0)
-      hipLaunchKernelGGL((k_conv_tile<8, 32, 1, 0, 1, 1, 0>), grid, dim3(256), 0, st, b, X, nullptr, W, bb, Y);
+      hipLaunchKernelGGL((k_conv_blk<8, 32, 1, 0, 1, 1, 0>), grid, dim3(256), 0, st, b, X, nullptr, W, bb, Y);
     else if (l < 5)
-      hipLaunchKernelGGL((k_conv_tile<32, 32, 1, 0, 1, 1, 0>), grid, dim3(256), 0, st, b, X, nullptr, W, bb, Y);
+      hipLaunchKernelGGL((k_conv_blk<32, 32, 1, 0, 1, 1, 0>), grid, dim3(256), 0, st, b, X, nullptr, W, bb, Y);
     else
-      hipLaunchKernelGGL((k_conv_tile<32, 4, 1, 0, 1, 0, 0>), grid, dim3(256), 0, st, b, X, nullptr, W, bb, Y);
+      hipLaunchKernelGGL((k_conv_blk<32, 4, 1, 0, 1, 0, 0>), grid, dim3(256), 0, st, b, X, nullptr, W, bb, Y);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
