@@ -191,6 +191,9 @@ constexpr int kOwn = kTile - 1;
 constexpr int kTN = kTile + 1;         // nodes per tile side
 constexpr int kTNodes = kTN * kTN;     // nodes per tile layer
 
+// Last word of a raw buffer resource (32-bit data, no swizzle) on gfx950.
+constexpr int kRsrcWord3 = 0x00020000;
+
 #define RMTR_LDS(ptr) ((void __attribute__((address_space(3)))*)(ptr))
 
 // Node layers in LDS component-major (one array of the tile's 17 x 17
@@ -253,23 +256,27 @@ __device__ inline void dma_layer(int N, const DmaPlan<T>& d, int z, int slot, co
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
   const int64_t ns = N + 1;
   const int64_t zl = ns * ns * int64_t(z);
-  const char* xz = reinterpret_cast<const char*>(x + 4 * zl);
-  const char* vz = reinterpret_cast<const char*>(v + 4 * zl);
-  const char* pz = reinterpret_cast<const char*>(p + zl);
+  // buffer resources over node layer z of x, v and p (uniform base, byte
+  // size of the layer): the copies then need one unsigned 32-bit offset per
+  // lane and no 64-bit address
+  const int xbytes = int(4 * ns * ns * int64_t(sizeof(T))), pbytes = int(ns * ns * int64_t(sizeof(T)));
+  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc((void*)(x + 4 * zl), (short)0, xbytes, kRsrcWord3);
+  const __amdgpu_buffer_rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc((void*)(v + 4 * zl), (short)0, xbytes, kRsrcWord3);
+  const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc((void*)(p + zl), (short)0, pbytes, kRsrcWord3);
 #pragma unroll
   for (int r = 0; r < DmaPlan<T>::kR; ++r) {
     if (d.xoff[r] >= 0) {
       const int lb = (r * 256 + wave * 64) * 4;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        __builtin_amdgcn_global_load_lds(xz + d.xoff[r] + k * int(sizeof(T)),
-                                         RMTR_LDS(reinterpret_cast<char*>(&L.x[slot][k][0]) + lb), 4, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, RMTR_LDS(reinterpret_cast<char*>(&L.x[slot][k][0]) + lb), 4,
+                                                 d.xoff[r], k * int(sizeof(T)), 0, 0);
         if constexpr (MODE == 1)
-          __builtin_amdgcn_global_load_lds(vz + d.xoff[r] + k * int(sizeof(T)),
-                                           RMTR_LDS(reinterpret_cast<char*>(&L.v[slot][k][0]) + lb), 4, 0, 0);
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rv, RMTR_LDS(reinterpret_cast<char*>(&L.v[slot][k][0]) + lb), 4,
+                                                   d.xoff[r], k * int(sizeof(T)), 0, 0);
       }
-      __builtin_amdgcn_global_load_lds(pz + d.poff[r], RMTR_LDS(reinterpret_cast<char*>(&L.p[slot][0]) + lb), 4, 0,
-                                       0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rp, RMTR_LDS(reinterpret_cast<char*>(&L.p[slot][0]) + lb), 4,
+                                               d.poff[r], 0, 0, 0);
     }
   }
 #endif
