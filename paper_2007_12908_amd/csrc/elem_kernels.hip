@@ -469,12 +469,12 @@ struct LayerLdsXP {
 // nodal values in LDS), which keeps the state small enough for four
 // workgroups per compute unit.  Same tiles, element ownership and fixed
 // summation order as energy3_lds.
-__device__ inline double energy3_q(int N, double h, const MatP<double>& m, int tiles, const double* __restrict__ x,
-                                   const double* __restrict__ p, LayerLdsXP<double>& L) {
+template <bool VD>
+__device__ inline double energy3_q(int N, const SymConst<double>& kc, double a2Gcl2, int tiles,
+                                   const double* __restrict__ x, const double* __restrict__ p, LayerLdsXP<double>& L) {
   using T = double;
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
-  const ElemScale<T> sc = elem_scale<T>(T(1) / h, h * h * h / T(8));
   const int64_t nz = N + 1;
   const int64_t work = int64_t(tiles) * tiles * nz;
   const int64_t u1 = work * (blockIdx.x + 1) / gridDim.x;
@@ -534,7 +534,7 @@ __device__ inline double energy3_q(int N, double h, const MatP<double>& m, int t
                 }
               }
             }
-            acc += energy_point_sym<T>(m, sc, zq[0]) + energy_point_sym<T>(m, sc, zq[1]);
+            acc += energy_point_sym<T, VD>(kc, a2Gcl2, zq[0]) + energy_point_sym<T, VD>(kc, a2Gcl2, zq[1]);
           }
         }
         __builtin_amdgcn_s_waitcnt(0);
@@ -547,12 +547,14 @@ __device__ inline double energy3_q(int N, double h, const MatP<double>& m, int t
   return acc;
 }
 
-__global__ __launch_bounds__(256, 4) void k_energy_q3(int N, double h, MatP<double> m, int tiles,
+// kc from sym_const on the host; a2Gcl2 = a2 Gc l / 2
+template <bool VD>
+__global__ __launch_bounds__(256, 4) void k_energy_q3(int N, SymConst<double> kc, double a2Gcl2, int tiles,
                                                       const double* __restrict__ x, const double* __restrict__ p,
                                                       double* __restrict__ partials) {
   __shared__ LayerLdsXP<double> L;
   __shared__ double sh[256];
-  const double tot = block_sum(energy3_q(N, h, m, tiles, x, p, L), sh);
+  const double tot = block_sum(energy3_q<VD>(N, kc, a2Gcl2, tiles, x, p, L), sh);
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
@@ -646,8 +648,9 @@ __device__ inline double row_next(double v) {
   return __hiloint2double(hi, lo);
 }
 
-template <int MODE, typename T>
-__device__ inline void elem_segment3_q(int N, const MatP<T>& m, const ElemScale<T>& sc, int bx, int by, int z0, int z1,
+template <int MODE, typename T, bool VD>
+__device__ inline void elem_segment3_q(int N, const MatP<T>& m, const ElemScale<T>& sc, const SymConst<T>& kc, int bx,
+                                       int by, int z0, int z1,
                                        const uint8_t* __restrict__ dir, const T* __restrict__ x,
                                        const T* __restrict__ p, const T* __restrict__ v, T* __restrict__ out,
                                        T (*ysh)[4][256], LayerLds<T>& L) {
@@ -748,11 +751,11 @@ __device__ inline void elem_segment3_q(int N, const MatP<T>& m, const ElemScale<
         Zq<3, T> o[2];
         if (MODE == 0) {
 #pragma unroll
-          for (int qx = 0; qx < 2; ++qx) grad_point_sym<T>(m, sc, cdc, zq[qx], o[qx]);
+          for (int qx = 0; qx < 2; ++qx) grad_point_sym<T, VD>(kc, cdc, zq[qx], o[qx]);
         } else {
           HessSym<T> hc[2];
 #pragma unroll
-          for (int qx = 0; qx < 2; ++qx) hess_sym_coef<T>(m, sc, zq[qx], hc[qx]);
+          for (int qx = 0; qx < 2; ++qx) hess_sym_coef<T, VD>(kc, zq[qx], hc[qx]);
           Zq<3, T> zv[2];
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
@@ -843,8 +846,10 @@ __device__ inline void elem_segment3_q(int N, const MatP<T>& m, const ElemScale<
 
 // FP64, two workgroups per compute unit (at most 256 registers, 77 KB of
 // LDS each).
-template <int MODE>
-__global__ __launch_bounds__(256, 2) void k_elem_q3(int N, double h, MatP<double> md, int tiles,
+// The pointwise constants kc are formed on the host (sym_const), so they
+// reach the kernel as scalar arguments and take no vector registers.
+template <int MODE, bool VD>
+__global__ __launch_bounds__(256, 2) void k_elem_q3(int N, double h, MatP<double> md, SymConst<double> kc, int tiles,
                                                     const uint8_t* __restrict__ dir, const double* __restrict__ x,
                                                     const double* __restrict__ p, const double* __restrict__ v,
                                                     double* __restrict__ out) {
@@ -860,7 +865,7 @@ __global__ __launch_bounds__(256, 2) void k_elem_q3(int N, double h, MatP<double
     const int64_t col = u / nz;
     const int z0 = int(u - col * nz);
     const int z1 = int(min(nz, int64_t(z0) + (u1 - u)));
-    elem_segment3_q<MODE, T>(N, m, sc, int(col % tiles), int(col / tiles), z0, z1, dir, x, p, v, out, ysh, lds);
+    elem_segment3_q<MODE, T, VD>(N, m, sc, kc, int(col % tiles), int(col / tiles), z0, z1, dir, x, p, v, out, ysh, lds);
     u += z1 - z0;
   }
 }
@@ -1069,7 +1074,10 @@ hipError_t launch_energy(const ElemArgs& a, const double* x, const void* s, int 
       hipLaunchKernelGGL(k_energy3_lds<kSplitSpectral>, dim3(nb), dim3(256), 0, st, a.N, a.h, a.m, tiles, x, p,
                          partials);
     } else {
-      hipLaunchKernelGGL(k_energy_q3, dim3(nb), dim3(256), 0, st, a.N, a.h, a.m, tiles, x, p, partials);
+      const ElemScale<double> sc = elem_scale<double>(1.0 / a.h, a.h * a.h * a.h / 8.0);
+      hipLaunchKernelGGL((a.m.split ? k_energy_q3<true> : k_energy_q3<false>), dim3(nb), dim3(256), 0, st, a.N,
+                         sym_const<double>(a.m, sc),
+                         0.5 * sc.a2 * a.m.Gc_l, tiles, x, p, partials);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1125,8 +1133,10 @@ static hipError_t launch_scatter(const ElemArgs& a, const T* x, const T* p, cons
       hipLaunchKernelGGL((k_elem_scatter3_f32<MODE>), dim3(unsigned(nb)), dim3(256), 0, st, a.N, T(a.h), a.m, tiles,
                          a.dir, x, p, v, out);
     else
-      hipLaunchKernelGGL((k_elem_q3<MODE>), dim3(unsigned(nb)), dim3(256), 0, st, a.N, T(a.h), a.m, tiles, a.dir, x,
-                         p, v, out);
+      hipLaunchKernelGGL((a.m.split ? k_elem_q3<MODE, true> : k_elem_q3<MODE, false>), dim3(unsigned(nb)), dim3(256),
+                         0, st, a.N, T(a.h), a.m,
+                         sym_const<double>(a.m, elem_scale<double>(1.0 / a.h, a.h * a.h * a.h / 8.0)), tiles, a.dir,
+                         x, p, v, out);
   } else {
     int64_t nn = int64_t(a.N + 1) * (a.N + 1);
     with_split(a.m, [&](auto sk) {

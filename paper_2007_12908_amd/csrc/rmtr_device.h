@@ -1167,32 +1167,86 @@ struct HessSym {
   T Sd[3], So[3], Pc[3];
 };
 
+// Products of the material constants and the element scale factors that
+// the pointwise coefficients use, formed once per kernel (uniform).
 template <typename T>
-RMTR_FN void hess_sym_coef(const MatP<T>& m, const ElemScale<T>& sc, const QPoint<T>& z, HessSym<T>& hc) {
-  T t, psip, sd[3], so[3], sigm;
-  split_sym_unit<T>(m, z.G, t, psip, sd, so, sigm);
-  const T omc = T(1) - z.c;
-  const T g = (T(1) - m.k) * omc * omc + m.k;
-  const T dg = T(-2) * (T(1) - m.k) * omc;
-  const T d2g = T(2) * (T(1) - m.k);
-  const T dgp = T(-2) * omc;
-  const T pi = z.p * t + z.dp[0] * z.u[0] + z.dp[1] * z.u[1] + z.dp[2] * z.u[2];
+struct SymConst {
+  int split;
+  T k, omk;           // k, 1 - k
+  T hK, mu3, K, mu23;  // K / 2, mu / 3, K, 2 mu / 3 (split); lambda / 2, 0, lambda, 0 (unsplit)
+  T mu, mu2;          // mu, 2 mu
+  T a2K, a2Kmu, a2mu23, a2mu;   // a2 K, a2 (K - 2 mu / 3), a2 2 mu / 3, a2 mu (unsplit: a2 lambda for K)
+  T m2a2omk, m2a1;    // -2 a2 (1 - k), -2 a1: a2 g' / (1 - c), a1 gp' / (1 - c)
+  T a2d2g, a1x2, wGcl;  // a2 g'', 2 a1, w Gc / l
+  T a1, a2;
+};
+
+template <typename T>
+RMTR_FN SymConst<T> sym_const(const MatP<T>& m, const ElemScale<T>& sc) {
+  SymConst<T> c;
+  c.split = m.split;
+  c.k = m.k;
+  c.omk = T(1) - m.k;
+  c.mu = m.mu;
+  c.mu2 = T(2) * m.mu;
   if (m.split) {
-    hc.vol = sc.a2 * ((t > T(0) ? g * m.K : m.K) - g * m.mu23);
+    c.hK = T(0.5) * m.K;
+    c.mu3 = m.mu * m.third;
+    c.K = m.K;
+    c.mu23 = m.mu23;
   } else {
-    hc.vol = sc.a2 * g * m.lam;
+    c.hK = T(0.5) * m.lam;
+    c.mu3 = T(0);
+    c.K = m.lam;
+    c.mu23 = T(0);
   }
-  hc.shear = sc.a2 * g * m.mu;
-  const T a2dg = sc.a2 * dg;
-  const T a1dgp = sc.a1 * dgp;
-  const T dia = a1dgp * z.p;
+  c.a2K = sc.a2 * c.K;
+  c.a2mu23 = sc.a2 * c.mu23;
+  c.a2Kmu = c.a2K - c.a2mu23;
+  c.a2mu = sc.a2 * m.mu;
+  c.m2a2omk = T(-2) * sc.a2 * c.omk;
+  c.m2a1 = T(-2) * sc.a1;
+  c.a2d2g = T(2) * sc.a2 * c.omk;
+  c.a1x2 = T(2) * sc.a1;
+  c.wGcl = sc.w * m.Gc_ls;
+  c.a1 = sc.a1;
+  c.a2 = sc.a2;
+  return c;
+}
+
+// VD: the volumetric-deviatoric split (else the unsplit form), fixed at
+// compile time so the kernels carry one form's arithmetic only.
+template <typename T, bool VD>
+RMTR_FN void hess_sym_coef(const SymConst<T>& k, const QPoint<T>& z, HessSym<T>& hc) {
+  const T t = z.G[0][0] + z.G[1][1] + z.G[2][2];
+  const T s01 = z.G[0][1] + z.G[1][0], s02 = z.G[0][2] + z.G[2][0], s12 = z.G[1][2] + z.G[2][1];
+  // |eps|^2 = sum G_ii^2 + (s01^2 + s02^2 + s12^2) / 2
+  const T epsq = z.G[0][0] * z.G[0][0] + z.G[1][1] * z.G[1][1] + z.G[2][2] * z.G[2][2] +
+                 T(0.5) * (s01 * s01 + s02 * s02 + s12 * s12);
+  // split: psi+ = K/2 <t>+^2 + mu (|eps|^2 - t^2 / 3), diag(sigma+) - 2 mu eps = K <t>+ - 2 mu t / 3;
+  // unsplit: lambda/2 t^2 + mu |eps|^2 and lambda t (tp = t, mu3 = mu23 = 0)
+  const T tp = VD ? (t > T(0) ? t : T(0)) : t;
+  const T psip = VD ? k.hK * tp * tp + k.mu * epsq - k.mu3 * t * t : k.hK * t * t + k.mu * epsq;
+  const T diag = VD ? k.K * tp - k.mu23 * t : k.K * t;
+  const T omc = T(1) - z.c;
+  const T g = k.omk * (omc * omc) + k.k;
+  const T pi = z.p * t + z.dp[0] * z.u[0] + z.dp[1] * z.u[1] + z.dp[2] * z.u[2];
+  // vol = a2 (g K H+ + K H- - g 2 mu / 3) (split), a2 g lambda (unsplit)
+  hc.vol = VD ? (t > T(0) ? g * k.a2Kmu : k.a2K - g * k.a2mu23) : g * k.a2K;
+  hc.shear = k.a2mu * g;
+  const T a2dg = k.m2a2omk * omc;
+  const T a1dgp = k.m2a1 * omc;
+  const T dd = a2dg * diag + a1dgp * z.p;
+  const T a2dg2mu = a2dg * k.mu2, a2dgmu = a2dg * k.mu;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    hc.Sd[i] = a2dg * sd[i] + dia;
-    hc.So[i] = a2dg * so[i];
+    hc.Sd[i] = a2dg2mu * z.G[i][i] + dd;
     hc.Pc[i] = a1dgp * z.dp[i];
   }
-  hc.Ccc = sc.a2 * d2g * psip + sc.w * m.Gc_ls + T(2) * sc.a1 * pi;
+  hc.So[0] = a2dgmu * s01;
+  hc.So[1] = a2dgmu * s02;
+  hc.So[2] = a2dgmu * s12;
+  hc.Ccc = k.a2d2g * psip + (k.a1x2 * pi + k.wGcl);
 }
 
 // The coefficients applied to the direction v (unit-cell quantities); o is
@@ -1219,57 +1273,55 @@ RMTR_FN void hess_sym_apply(const HessSym<T>& hc, T cdc, const Zq<3, T>& v, Zq<3
 // w W from the unit-cell quantities: the strain energies are h^2 times the
 // true ones and the pressure work h times, so
 //   w W = a2 (g psi+' + psi-' + Gc l/2 |dc'|^2) + w Gc/(2 l) c^2 + a1 gp pi'.
-template <typename T>
-RMTR_FN T energy_point_sym(const MatP<T>& m, const ElemScale<T>& sc, const QPoint<T>& z) {
+template <typename T, bool VD>
+RMTR_FN T energy_point_sym(const SymConst<T>& k, T a2Gcl2, const QPoint<T>& z) {
   const T t = z.G[0][0] + z.G[1][1] + z.G[2][2];
-  const T e01 = T(0.5) * (z.G[0][1] + z.G[1][0]);
-  const T e02 = T(0.5) * (z.G[0][2] + z.G[2][0]);
-  const T e12 = T(0.5) * (z.G[1][2] + z.G[2][1]);
+  const T s01 = z.G[0][1] + z.G[1][0], s02 = z.G[0][2] + z.G[2][0], s12 = z.G[1][2] + z.G[2][1];
   const T epsq = z.G[0][0] * z.G[0][0] + z.G[1][1] * z.G[1][1] + z.G[2][2] * z.G[2][2] +
-                 T(2) * (e01 * e01 + e02 * e02 + e12 * e12);
-  T psip, psim;
-  if (m.split) {
-    const T tp = t > T(0) ? t : T(0);
-    const T tm = t > T(0) ? T(0) : t;
-    psip = T(0.5) * m.K * tp * tp + m.mu * (epsq - t * t * m.third);
-    psim = T(0.5) * m.K * tm * tm;
-  } else {
-    psip = T(0.5) * m.lam * t * t + m.mu * epsq;
-    psim = T(0);
-  }
+                 T(0.5) * (s01 * s01 + s02 * s02 + s12 * s12);
+  const T tp = VD ? (t > T(0) ? t : T(0)) : t;
+  const T tm = VD ? (t > T(0) ? T(0) : t) : T(0);
+  const T psip = VD ? k.hK * tp * tp + k.mu * epsq - k.mu3 * t * t : k.hK * t * t + k.mu * epsq;
+  const T psim = VD ? k.hK * tm * tm : T(0);
   const T omc = T(1) - z.c;
-  const T g = (T(1) - m.k) * omc * omc + m.k;
   const T gp = omc * omc;
+  const T g = k.omk * gp + k.k;
   const T pi = z.p * t + z.dp[0] * z.u[0] + z.dp[1] * z.u[1] + z.dp[2] * z.u[2];
   const T dcq = z.dc[0] * z.dc[0] + z.dc[1] * z.dc[1] + z.dc[2] * z.dc[2];
-  return sc.a2 * (g * psip + psim + T(0.5) * m.Gc_l * dcq) + sc.w * T(0.5) * m.Gc_ls * z.c * z.c +
-         sc.a1 * gp * pi;
+  return k.a2 * (g * psip + psim) + a2Gcl2 * dcq + T(0.5) * k.wGcl * z.c * z.c + k.a1 * gp * pi;
 }
 
-// Scaled first variation at a point (unsplit or volumetric-deviatoric).
-template <typename T>
-RMTR_FN void grad_point_sym(const MatP<T>& m, const ElemScale<T>& sc, T cdc, const QPoint<T>& z, Zq<3, T>& o) {
-  T t, psip, sd[3], so[3], sigm;
-  split_sym_unit<T>(m, z.G, t, psip, sd, so, sigm);
+// Scaled first variation at a point (unsplit or volumetric-deviatoric),
+// symmetric in G.
+template <typename T, bool VD>
+RMTR_FN void grad_point_sym(const SymConst<T>& k, T cdc, const QPoint<T>& z, Zq<3, T>& o) {
+  const T t = z.G[0][0] + z.G[1][1] + z.G[2][2];
+  const T s01 = z.G[0][1] + z.G[1][0], s02 = z.G[0][2] + z.G[2][0], s12 = z.G[1][2] + z.G[2][1];
+  const T epsq = z.G[0][0] * z.G[0][0] + z.G[1][1] * z.G[1][1] + z.G[2][2] * z.G[2][2] +
+                 T(0.5) * (s01 * s01 + s02 * s02 + s12 * s12);
+  const T tp = VD ? (t > T(0) ? t : T(0)) : t;
+  const T tm = VD ? (t > T(0) ? T(0) : t) : T(0);
+  const T psip = VD ? k.hK * tp * tp + k.mu * epsq - k.mu3 * t * t : k.hK * t * t + k.mu * epsq;
+  const T diag = VD ? k.K * tp - k.mu23 * t : k.K * t;
+  const T sigm = VD ? k.K * tm : T(0);
   const T omc = T(1) - z.c;
-  const T g = (T(1) - m.k) * omc * omc + m.k;
-  const T dg = T(-2) * (T(1) - m.k) * omc;
   const T gp = omc * omc;
-  const T dgp = T(-2) * omc;
+  const T g = k.omk * gp + k.k;
   const T pi = z.p * t + z.dp[0] * z.u[0] + z.dp[1] * z.u[1] + z.dp[2] * z.u[2];
-  const T a2g = sc.a2 * g;
-  const T dia = sc.a2 * sigm + sc.a1 * gp * z.p;
-  const T a1gp = sc.a1 * gp;
+  const T a2g = k.a2 * g;
+  const T a1gp = k.a1 * gp;
+  const T dia = a2g * diag + (k.a2 * sigm + a1gp * z.p);
+  const T a2g2mu = a2g * k.mu2, a2gmu = a2g * k.mu;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     o.u[i] = a1gp * z.dp[i];
     o.dc[i] = cdc * z.dc[i];
-    o.G[i][i] = a2g * sd[i] + dia;
+    o.G[i][i] = a2g2mu * z.G[i][i] + dia;
   }
-  o.G[0][1] = o.G[1][0] = a2g * so[0];
-  o.G[0][2] = o.G[2][0] = a2g * so[1];
-  o.G[1][2] = o.G[2][1] = a2g * so[2];
-  o.c = sc.a2 * dg * psip + sc.w * m.Gc_ls * z.c + sc.a1 * dgp * pi;
+  o.G[0][1] = o.G[1][0] = a2gmu * s01;
+  o.G[0][2] = o.G[2][0] = a2gmu * s02;
+  o.G[1][2] = o.G[2][1] = a2gmu * s12;
+  o.c = (k.m2a2omk * omc) * psip + k.wGcl * z.c + (k.m2a1 * omc) * pi;
 }
 
 // Contribution of one element to the rows of its local node aloc:
