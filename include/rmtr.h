@@ -402,12 +402,13 @@ rmtr_status rmtr_nn_propose(rmtr_ctx* ctx, int32_t level, const rmtr_nn* net, co
 
 /* Floating-point additions, subtractions, multiplications and divisions that
    the library's element operators perform on data for ONE element (the
-   figure used for arithmetic rooflines; host-only, no GPU call).  kind:
-   0 energy, 1 energy difference, 2 gradient, 3 Hessian-vector product (3D:
-   sum-factorised element-centric kernels), 4 one element's contribution to
-   one node's rows in a Gauss-Seidel colour pass.  In 2D, kinds 2 and 3 are
-   per element and node (node-centric kernels).  Returns -1 for a bad
-   argument. */
+   executed arithmetic, a multiply-add counting two; host-only, no GPU call).
+   kind: 0 energy, 1 energy difference, 2 gradient, 3 Hessian-vector product
+   (3D: kinds 0, 2 and 3 as the quarter-wise FP64 kernels evaluate them, the
+   volumetric-deviatoric form; kind 1 all eight Gauss points at once), 4 one
+   element's contribution to one node's rows in a Gauss-Seidel colour pass.
+   In 2D, kinds 2 and 3 are per element and node (node-centric kernels).
+   Returns -1 for a bad argument. */
 int64_t rmtr_element_flops(int32_t dim, int32_t kind);
 
 #ifdef __cplusplus

@@ -834,6 +834,92 @@ int64_t count_kind(int kind) {
   return -1;
 }
 
+// The quarter-wise evaluation of the 3D FP64 kernels (energy, gradient, Hv;
+// volumetric-deviatoric form), as k_energy_q3 / k_elem_q3 run it.
+int64_t count_quarter(int kind) {
+  const MatP<Cnt> m = cnt_mat<3>();
+  const ElemScale<Cnt> sc = elem_scale<Cnt>(Cnt(20.0), Cnt(1e-4));
+  const SymConst<Cnt> kc = sym_const<Cnt>(m, sc);
+  const Cnt cdc = sc.a2 * m.Gc_l, a2Gcl2 = Cnt(0.5) * sc.a2 * m.Gc_l;
+  Cnt X[8][4], V[8][4], P[8];
+  for (int a = 0; a < 8; ++a) {
+    P[a] = Cnt::var(1e-3 * (1 + a));
+    for (int k = 0; k < 4; ++k) {
+      X[a][k] = Cnt::var(k == 3 ? 0.1 * a : 1e-3 * (a + k));
+      V[a][k] = Cnt::var(0.3 * (a - k));
+    }
+  }
+  Cnt::ops = 0;
+  Cnt e = 0.0;
+  e.k = false;
+  Cnt r[4][8];
+  for (int qq = 0; qq < 4; ++qq) {
+    const Cnt xy = gauss_xi<Cnt>(qq & 1), xz = gauss_xi<Cnt>(qq >> 1);
+    QPoint<Cnt> zq[2];
+    for (int k = 0; k < 5; ++k) {
+      Cnt f[8];
+      for (int a = 0; a < 8; ++a) f[a] = k < 4 ? X[a][k] : P[a];
+      if (k == 3 && kind == 3) {
+        Cnt val[2];
+        qtr_forward_val<Cnt>(f, xz, xy, val);
+        zq[0].c = val[0];
+        zq[1].c = val[1];
+        continue;
+      }
+      Cnt val[2], dx, dy[2], dz[2];
+      qtr_forward<Cnt>(f, xz, xy, val, dx, dy, dz);
+      for (int qx = 0; qx < 2; ++qx) {
+        Cnt* d = k < 3 ? zq[qx].G[k] : k == 3 ? zq[qx].dc : zq[qx].dp;
+        if (k < 3) zq[qx].u[k] = val[qx];
+        if (k == 3) zq[qx].c = val[qx];
+        if (k == 4) zq[qx].p = val[qx];
+        d[0] = dx;
+        d[1] = dy[qx];
+        d[2] = dz[qx];
+      }
+    }
+    if (kind == 0) {
+      for (int qx = 0; qx < 2; ++qx) e += energy_point_sym<Cnt, true>(kc, a2Gcl2, zq[qx]);
+      continue;
+    }
+    Zq<3, Cnt> o[2];
+    if (kind == 2) {
+      for (int qx = 0; qx < 2; ++qx) grad_point_sym<Cnt, true>(kc, cdc, zq[qx], o[qx]);
+    } else {
+      HessSym<Cnt> hc[2];
+      for (int qx = 0; qx < 2; ++qx) hess_sym_coef<Cnt, true>(kc, zq[qx], hc[qx]);
+      Zq<3, Cnt> zv[2];
+      for (int k = 0; k < 4; ++k) {
+        Cnt f[8];
+        for (int a = 0; a < 8; ++a) f[a] = V[a][k];
+        Cnt val[2], dx, dy[2], dz[2];
+        qtr_forward<Cnt>(f, xz, xy, val, dx, dy, dz);
+        for (int qx = 0; qx < 2; ++qx) {
+          Cnt* d = k < 3 ? zv[qx].G[k] : zv[qx].dc;
+          if (k < 3) zv[qx].u[k] = val[qx]; else zv[qx].c = val[qx];
+          d[0] = dx;
+          d[1] = dy[qx];
+          d[2] = dz[qx];
+        }
+      }
+      for (int qx = 0; qx < 2; ++qx) hess_sym_apply<Cnt>(hc[qx], cdc, zv[qx], o[qx]);
+    }
+    for (int k = 0; k < 4; ++k) {
+      Cnt cv[2], cx[2], cy[2], cz[2];
+      for (int qx = 0; qx < 2; ++qx) {
+        cv[qx] = k < 3 ? o[qx].u[k] : o[qx].c;
+        cx[qx] = k < 3 ? o[qx].G[k][0] : o[qx].dc[0];
+        cy[qx] = k < 3 ? o[qx].G[k][1] : o[qx].dc[1];
+        cz[qx] = k < 3 ? o[qx].G[k][2] : o[qx].dc[2];
+      }
+      if (qq == 0)
+        for (int a = 0; a < 8; ++a) r[k][a] = Cnt(0.0);
+      qtr_backward<Cnt>(cv, cx, cy, cz, xz, xy, r[k]);
+    }
+  }
+  return Cnt::ops;
+}
+
 }  // namespace
 
 // ----------------------------------------- fixed scratch of the no-alloc call
@@ -875,6 +961,7 @@ extern "C" {
 
 int64_t rmtr_element_flops(int32_t dim, int32_t kind) {
   if (kind < 0 || kind > 4) return -1;
+  if (dim == 3 && (kind == 0 || kind == 2 || kind == 3)) return count_quarter(kind);
   if (dim == 3) return count_kind<3>(kind);
   if (dim == 2) return count_kind<2>(kind);
   return -1;
