@@ -221,8 +221,9 @@ struct DmaPlan {
   int poff[kR];  // byte offset of the piece in p
 };
 
+// (gx0, gy0): the grid node of the tile's first LDS node
 template <typename T>
-__device__ inline DmaPlan<T> dma_plan(int N, int bx, int by) {
+__device__ inline DmaPlan<T> dma_plan(int N, int gx0, int gy0) {
   DmaPlan<T> d;
   const int tid = threadIdx.x;
   const int ns = N + 1;
@@ -232,8 +233,8 @@ __device__ inline DmaPlan<T> dma_plan(int N, int bx, int by) {
     if (c < kTNodes * DmaPlan<T>::kW) {
       const int node = c / DmaPlan<T>::kW, word = c % DmaPlan<T>::kW;
       const int ix = node % kTN, iy = node / kTN;
-      const int gx = min(max(bx * kOwn - 1 + ix, 0), N);
-      const int gy = min(max(by * kOwn - 1 + iy, 0), N);
+      const int gx = min(max(gx0 + ix, 0), N);
+      const int gy = min(max(gy0 + iy, 0), N);
       const int pl = gx + ns * gy;
       d.xoff[r] = pl * 4 * int(sizeof(T)) + 4 * word;
       d.poff[r] = pl * int(sizeof(T)) + 4 * word;
@@ -297,7 +298,7 @@ __device__ inline void elem_segment3_lds(int N, const MatP<T>& m, T invh, T w, i
   const int64_t nside = N + 1;
   const int zs = max(z0 - 1, 0), ze = min(z1 - 1, N - 1);
   // node layers sit in a ring of three LDS slots: layer z in slot (z - zs) % 3
-  const DmaPlan<T> dp = dma_plan<T>(N, bx, by);
+  const DmaPlan<T> dp = dma_plan<T>(N, bx * kOwn - 1, by * kOwn - 1);
   if (zs <= ze) {
     dma_layer<MODE, T, LayerLds<T>>(N, dp, zs, 0, x, p, v, L);
     dma_layer<MODE, T, LayerLds<T>>(N, dp, zs + 1, 1, x, p, v, L);
@@ -405,7 +406,7 @@ __device__ inline double energy3_lds(int N, double h, const MatP<double>& m, int
     const bool mine = tx >= 1 && ty >= 1 && ex < N && ey < N;
     const int zs = z0, ze = min(z1, N) - 1;
     if (zs <= ze) {
-      const DmaPlan<double> dp = dma_plan<double>(N, bx, by);
+      const DmaPlan<double> dp = dma_plan<double>(N, bx * kOwn - 1, by * kOwn - 1);
       dma_layer<MODE, double, LayerLds<double>>(N, dp, zs, 0, x, p, s, L);
       dma_layer<MODE, double, LayerLds<double>>(N, dp, zs + 1, 1, x, p, s, L);
       __builtin_amdgcn_s_waitcnt(0);
@@ -467,8 +468,12 @@ struct LayerLdsXP {
 // Energy, unsplit and volumetric-deviatoric forms: the quarter-wise
 // evaluation of the element kernels (two Gauss points at a time from the
 // nodal values in LDS), which keeps the state small enough for four
-// workgroups per compute unit.  Same tiles, element ownership and fixed
-// summation order as energy3_lds.
+// workgroups per compute unit.  The tiles do not overlap here: tile
+// (bx, by) holds the 16 x 16 element columns from (16 bx, 16 by) (its LDS
+// nodes from the same corner), and every element of the grid belongs to
+// exactly one tile column and, through the node-layer ranges, one element
+// layer; partial sums per workgroup in a fixed order, as energy3_lds.
+// `tiles`: element tiles per side, ceil(N / 16).
 template <bool VD>
 __device__ inline double energy3_q(int N, const SymConst<double>& kc, double a2Gcl2, int tiles,
                                    const double* __restrict__ x, const double* __restrict__ p, LayerLdsXP<double>& L) {
@@ -487,11 +492,11 @@ __device__ inline double energy3_q(int N, const SymConst<double>& kc, double a2G
     const int z0 = int(u - col * nz);
     const int z1 = int(min(nz, int64_t(z0) + (u1 - u)));
     const int bx = int(col % tiles), by = int(col / tiles);
-    const int ex = bx * kOwn - 1 + tx, ey = by * kOwn - 1 + ty;
-    const bool mine = tx >= 1 && ty >= 1 && ex < N && ey < N;
+    const int ex = bx * kTile + tx, ey = by * kTile + ty;
+    const bool mine = ex < N && ey < N;
     const int zs = z0, ze = min(z1, N) - 1;
     if (zs <= ze) {
-      const DmaPlan<T> dp = dma_plan<T>(N, bx, by);
+      const DmaPlan<T> dp = dma_plan<T>(N, bx * kTile, by * kTile);
       dma_layer<0, T, LayerLdsXP<T>>(N, dp, zs, 0, x, p, x, L);
       dma_layer<0, T, LayerLdsXP<T>>(N, dp, zs + 1, 1, x, p, x, L);
       __builtin_amdgcn_s_waitcnt(0);
@@ -664,7 +669,7 @@ __device__ inline void elem_segment3_q(int N, const MatP<T>& m, const ElemScale<
   const int64_t nside = N + 1;
   const T cdc = sc.a2 * m.Gc_l;
   const int zs = max(z0 - 1, 0), ze = min(z1 - 1, N - 1);
-  const DmaPlan<T> dp = dma_plan<T>(N, bx, by);
+  const DmaPlan<T> dp = dma_plan<T>(N, bx * kOwn - 1, by * kOwn - 1);
   if (zs <= ze) {
     dma_layer<MODE, T, LayerLds<T>>(N, dp, zs, 0, x, p, v, L);
     dma_layer<MODE, T, LayerLds<T>>(N, dp, zs + 1, 1, x, p, v, L);
@@ -1041,7 +1046,9 @@ hipError_t launch_reduce_partials(const double* partials, int n, double* out, hi
 // split's, one for the difference), fewer on coarse levels with fewer tile
 // layers.
 int64_t energy3_groups(int N, bool diff, bool spec) {
-  const int tiles = (N + 1 + kOwn - 1) / kOwn;
+  // the quarter-wise energy tiles the elements without overlap (16 x 16
+  // element columns), the others the nodes with one element of overlap
+  const int tiles = diff || spec ? (N + 1 + kOwn - 1) / kOwn : (N + kTile - 1) / kTile;
   const int64_t work = int64_t(tiles) * tiles * (N + 1);
   return std::max<int64_t>(1, std::min<int64_t>(int64_t(compute_units()) * (diff ? 1 : spec ? 2 : 4), work));
 }
@@ -1075,9 +1082,9 @@ hipError_t launch_energy(const ElemArgs& a, const double* x, const void* s, int 
                          partials);
     } else {
       const ElemScale<double> sc = elem_scale<double>(1.0 / a.h, a.h * a.h * a.h / 8.0);
+      const int etiles = (a.N + kTile - 1) / kTile;
       hipLaunchKernelGGL((a.m.split ? k_energy_q3<true> : k_energy_q3<false>), dim3(nb), dim3(256), 0, st, a.N,
-                         sym_const<double>(a.m, sc),
-                         0.5 * sc.a2 * a.m.Gc_l, tiles, x, p, partials);
+                         sym_const<double>(a.m, sc), 0.5 * sc.a2 * a.m.Gc_l, etiles, x, p, partials);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

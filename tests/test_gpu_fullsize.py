@@ -41,8 +41,10 @@ def _state(c0):
 
 
 def _sample_nodes(g, rng, n_random=1500):
-    s = [0, 1, 14, 15, 16, 29, 30, 31, 63, 64, 65, N - 1, N]
-    ijk = np.array([(i, j, k) for i in s for j in s[::3] for k in s[::2]])
+    # tile edges of both tilings (15-node overlapping tiles and 16-element
+    # tiles), chunk edges, the boundary
+    s = [0, 1, 14, 15, 16, 17, 29, 30, 31, 32, 33, 47, 48, 63, 64, 65, 96, 112, N - 1, N]
+    ijk = np.array([(i, j, k) for i in s for j in s[::2] for k in s[::3]])
     nodes = ijk[:, 0] + (N + 1) * (ijk[:, 1] + (N + 1) * ijk[:, 2])
     return np.unique(np.concatenate([nodes, rng.choice(g.n_nodes, n_random, replace=False)]))
 

@@ -57,6 +57,40 @@ def test_energy_gradient_hessvec_fp64(d, N, split):
     assert np.abs(D - Do).max() <= 1e-12 * np.abs(Do).max()
 
 
+@pytest.mark.parametrize("N,split,masked", [(48, True, False), (52, False, True)])
+def test_large_level_tiles(N, split, masked):
+    """Levels of several tiles per side: the energy tiles the elements in
+    16 x 16 columns (48 is three whole tiles per side, 52 leaves a ragged
+    last one), the gradient and Hv the nodes in overlapping 17 x 17 node
+    tiles (neither divides evenly).  Element-by-element parity over the
+    whole grid, with the default and a random Dirichlet mask."""
+    print(f"case N={N} split={split} masked={masked}", flush=True)
+    import torch
+    d = 3
+    g, x, p = rand_state(d, N, seed=900 + N)
+    mat = material(N, split)
+    ctx = ctx_for(d, N, 1, mat)
+    rng = np.random.default_rng(N)
+    dirm, md = None, None
+    if masked:
+        mask_nodes = rng.integers(0, 1 << (d + 1), g.n_nodes).astype(np.uint8)
+        dirm = np.zeros((g.n_nodes, d + 1), bool)
+        for k in range(d + 1):
+            dirm[:, k] = (mask_nodes >> k) & 1
+        dirm = dirm.reshape(-1)
+        md = torch.from_numpy(mask_nodes).cuda()
+    xd, pd = dev(x), dev(p)
+    E = float(host(ctx.energy(1, xd, pd))[0])
+    assert E == pytest.approx(fem.energy(g, x, p, mat), rel=1e-12)
+    G = host(ctx.gradient(1, xd, pd, md))
+    assert field_rel_err(G, fem.gradient(g, x, p, mat, dirm), d) <= 1e-12
+    v = rng.standard_normal(g.n_dofs)
+    HV = host(ctx.hessvec(1, xd, pd, dev(v), md))
+    dmask = g.default_dirichlet() if dirm is None else dirm
+    HVo = fem.hessian(g, x, p, mat, dirm) @ np.where(dmask, 0.0, v)
+    assert field_rel_err(HV, HVo, d) <= 1e-12
+
+
 @pytest.mark.parametrize("d,N", [(2, 13), (3, 5), (3, 33)])
 def test_custom_dirichlet_mask(d, N):
     g, x, p = rand_state(d, N, seed=7 + N)
