@@ -43,7 +43,11 @@
  *     first use of an operation on a level and frees them in rmtr_destroy().
  *     A caller that owns the memory binds one buffer instead
  *     (rmtr_workspace_bytes, rmtr_bind_workspace) and the library then makes
- *     no device allocation.  A context is not thread safe.
+ *     no device allocation.  A context is not thread safe, and its calls must
+ *     not overlap in time on different streams: they share its scratch
+ *     buffers (reduction partials; in 3D the ring partials that carry the
+ *     FP64 gradient's and Hv's tile-border sums from the element kernel to
+ *     the kernel that adds them).
  */
 #ifndef RMTR_H
 #define RMTR_H

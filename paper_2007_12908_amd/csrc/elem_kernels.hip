@@ -191,6 +191,32 @@ constexpr int kOwn = kTile - 1;
 constexpr int kTN = kTile + 1;         // nodes per tile side
 constexpr int kTNodes = kTN * kTN;     // nodes per tile layer
 
+// The FP64 gradient and Hv tile the elements without overlap instead
+// (16 x 16 element columns from (16 bx, 16 by)): the nodes on a tile's border
+// (local x or y index 0 or 16) are touched by the elements of the tiles next
+// to it too.  A tile writes its partial sums of those 64 nodes per node
+// layer to a ring buffer, ring[(tile column, z)][slot][component], and a
+// second kernel adds the partials of the one to four tiles around each
+// border node in a fixed order (no atomics).
+constexpr int kRing = 4 * kTile;
+
+// slot of border node (ix, iy): bottom row 0..16, top row 17..33, left
+// column (iy = 1..15) 34..48, right column 49..63
+__host__ __device__ constexpr int ring_slot(int ix, int iy) {
+  return iy == 0 ? ix : iy == kTile ? kTN + ix : ix == 0 ? 2 * kTN + iy - 1 : 2 * kTN + kOwn + iy - 1;
+}
+
+// LDS of the border nodes outside the lanes' own (tx + 1, ty + 1): element
+// column 0's shares of the left column (its y-combine), and the z carries
+// of the bottom row, the left column and the corner
+template <typename T>
+struct EdgeLds {
+  T col[2][4][kTN];
+  T cr[4][kTile];
+  T cc[4][kTile];
+  T c0[4];
+};
+
 // Last word of a raw buffer resource (32-bit data, no swizzle) on gfx950.
 constexpr int kRsrcWord3 = 0x00020000;
 
@@ -653,23 +679,53 @@ __device__ inline double row_next(double v) {
   return __hiloint2double(hi, lo);
 }
 
-template <int MODE, typename T, bool VD>
+template <int MODE, typename T, bool VD, bool EDGE>
 __device__ inline void elem_segment3_q(int N, const MatP<T>& m, const ElemScale<T>& sc, const SymConst<T>& kc, int bx,
-                                       int by, int z0, int z1,
+                                       int by, int tiles, int z0, int z1,
                                        const uint8_t* __restrict__ dir, const T* __restrict__ x,
                                        const T* __restrict__ p, const T* __restrict__ v, T* __restrict__ out,
-                                       T (*ysh)[4][256], LayerLds<T>& L) {
+                                       T* __restrict__ edge, T (*ysh)[4][256], EdgeLds<T>& R, LayerLds<T>& L) {
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
-  const int ex = bx * kOwn - 1 + tx;
-  const int ey = by * kOwn - 1 + ty;
+  // EDGE: the tile's elements start at (16 bx, 16 by); otherwise one column
+  // and row earlier (overlapping tiles)
+  const int gx0 = EDGE ? bx * kTile : bx * kOwn - 1, gy0 = EDGE ? by * kTile : by * kOwn - 1;
+  const int ex = gx0 + tx;
+  const int ey = gy0 + ty;
   const int ox = ex + 1, oy = ey + 1;
   const bool ecol = ex >= 0 && ex < N && ey >= 0 && ey < N;
-  const bool owner = tx < kOwn && ty < kOwn && ox <= N && oy <= N;
+  const bool owner = (EDGE || (tx < kOwn && ty < kOwn)) && ox <= N && oy <= N;
   const int64_t nside = N + 1;
   const T cdc = sc.a2 * m.Gc_l;
   const int zs = max(z0 - 1, 0), ze = min(z1 - 1, N - 1);
-  const DmaPlan<T> dp = dma_plan<T>(N, bx * kOwn - 1, by * kOwn - 1);
+  const DmaPlan<T> dp = dma_plan<T>(N, gx0, gy0);
+  // tile-local node (ix, iy) of node layer z: a border node's sum goes to
+  // the ring partials, any other node's (every element around it is in the
+  // tile) to the output, Dirichlet components zero
+  const int64_t ring0 = (int64_t(by) * tiles + bx) * nside;
+  auto emit = [&](int ix, int iy, int z, const T (&s)[4]) {
+    if (EDGE && (ix == 0 || iy == 0 || ix == kTile || iy == kTile)) {
+      T* e = edge + ((ring0 + z) * kRing + ring_slot(ix, iy)) * 4;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) e[k] = s[k];
+    } else {
+      const int c[3] = {gx0 + ix, gy0 + iy, z};
+      const int64_t n = int64_t(c[0]) + nside * (int64_t(c[1]) + nside * z);
+      const uint8_t mk = node_mask<3>(dir, n, c, N);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) out[4 * n + k] = (mk & (1u << k)) ? T(0) : s[k];
+    }
+  };
+  if (EDGE) {
+    // z carries of the border nodes this lane holds besides its own node
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (ty == 0) R.cr[k][tx] = T(0);
+      if (tx == 0) R.cc[k][ty] = T(0);
+      if (tid == 0) R.c0[k] = T(0);
+      if (tid < 2) R.col[tid][k][kTile] = T(0);
+    }
+  }
   if (zs <= ze) {
     dma_layer<MODE, T, LayerLds<T>>(N, dp, zs, 0, x, p, v, L);
     dma_layer<MODE, T, LayerLds<T>>(N, dp, zs + 1, 1, x, p, v, L);
@@ -807,6 +863,12 @@ __device__ inline void elem_segment3_q(int N, const MatP<T>& m, const ElemScale<
       }
     }
     // combine: along x from the next lane of the row (every lane takes part)
+    // (the lane's indices are formed again here, opaque to the compiler, so
+    // that the addresses below are not held in registers through the
+    // quarter loop)
+    int tidr = tid;
+    __asm__ __volatile__("" : "+v"(tidr));
+    const int txr = tidr & 15, tyr = tidr >> 4;
     T cs[2][2][4];  // [ay][az][k]: this and the next element's share of node (tx + 1, ty + ay, ez + az)
 #pragma unroll
     for (int ay = 0; ay < 2; ++ay)
@@ -818,34 +880,88 @@ __device__ inline void elem_segment3_q(int N, const MatP<T>& m, const ElemScale<
 #pragma unroll
     for (int az = 0; az < 2; ++az)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) ysh[az][k][tid] = cs[0][az][k];
+      for (int k = 0; k < 4; ++k) {
+        ysh[az][k][tidr] = cs[0][az][k];
+        // EDGE: column 0's shares of the left border nodes (0, ty)
+        if (EDGE && txr == 0) R.col[az][k][tyr] = r[k][4 * az];
+      }
     __syncthreads();
     if (owner) {
-      if (ez >= z0) {
-        const int c[3] = {ox, oy, ez};
-        const int64_t n = int64_t(ox) + nside * (int64_t(oy) + nside * ez);
-        const uint8_t mk = node_mask<3>(dir, n, c, N);
+      // the last element row's nodes (EDGE) have no row above in the tile
+      T up[2][4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const T s = acc[k] + cs[1][0][k] + ysh[0][k][tid + 16];
-          out[4 * n + k] = (mk & (1u << k)) ? T(0) : s;
-        }
+      for (int az = 0; az < 2; ++az)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) up[az][k] = (!EDGE || tyr < kOwn) ? ysh[az][k][(tidr + 16) & 255] : T(0);
+      if (ez >= z0) {
+        T s[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[k] = acc[k] + cs[1][0][k] + up[0][k];
+        emit(txr + 1, tyr + 1, ez, s);
       }
 #pragma unroll
-      for (int k = 0; k < 4; ++k) acc[k] = cs[1][1][k] + ysh[1][k][tid + 16];
+      for (int k = 0; k < 4; ++k) acc[k] = cs[1][1][k] + up[1][k];
+    }
+    if (EDGE) {
+      // border nodes outside the lanes' own: the bottom row (tx + 1, 0), the
+      // left column (0, ty + 1) and the corner (0, 0)
+      if (tyr == 0 && ox <= N) {
+        if (ez >= z0) {
+          T s[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) s[k] = R.cr[k][txr] + cs[0][0][k];
+          emit(txr + 1, 0, ez, s);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) R.cr[k][txr] = cs[0][1][k];
+      }
+      if (txr == 0 && oy <= N) {
+        if (ez >= z0) {
+          T s[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) s[k] = R.cc[k][tyr] + r[k][2] + R.col[0][k][tyr + 1];
+          emit(0, tyr + 1, ez, s);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) R.cc[k][tyr] = r[k][6] + R.col[1][k][tyr + 1];
+      }
+      if (tidr == 0) {
+        if (ez >= z0) {
+          T s[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) s[k] = R.c0[k] + r[k][0];
+          emit(0, 0, ez, s);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) R.c0[k] = r[k][4];
+      }
     }
     // layer ez + 2 is in LDS, slot sb and the y buffer are free again
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     sb = st;
   }
-  if (owner && ze + 1 < z1) {
+  if (ze + 1 < z1) {
     const int nz = ze + 1;
-    const int64_t n = int64_t(ox) + nside * (int64_t(oy) + nside * nz);
-    const int c[3] = {ox, oy, nz};
-    const uint8_t mk = node_mask<3>(dir, n, c, N);
+    if (owner) emit(tx + 1, ty + 1, nz, acc);
+    if (EDGE) {
+      T s[4];
+      if (ty == 0 && ox <= N) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) out[4 * n + k] = (mk & (1u << k)) ? T(0) : acc[k];
+        for (int k = 0; k < 4; ++k) s[k] = R.cr[k][tx];
+        emit(tx + 1, 0, nz, s);
+      }
+      if (tx == 0 && oy <= N) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[k] = R.cc[k][ty];
+        emit(0, ty + 1, nz, s);
+      }
+      if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[k] = R.c0[k];
+        emit(0, 0, nz, s);
+      }
+    }
   }
 }
 
@@ -853,13 +969,14 @@ __device__ inline void elem_segment3_q(int N, const MatP<T>& m, const ElemScale<
 // LDS each).
 // The pointwise constants kc are formed on the host (sym_const), so they
 // reach the kernel as scalar arguments and take no vector registers.
-template <int MODE, bool VD>
+template <int MODE, bool VD, bool EDGE>
 __global__ __launch_bounds__(256, 2) void k_elem_q3(int N, double h, MatP<double> md, SymConst<double> kc, int tiles,
                                                     const uint8_t* __restrict__ dir, const double* __restrict__ x,
                                                     const double* __restrict__ p, const double* __restrict__ v,
-                                                    double* __restrict__ out) {
+                                                    double* __restrict__ out, double* __restrict__ edge) {
   using T = double;
   __shared__ T ysh[2][4][256];
+  __shared__ EdgeLds<T> rl;
   __shared__ LayerLds<T> lds;
   const MatP<T> m = md;
   const ElemScale<T> sc = elem_scale<T>(T(1) / h, h * h * h / T(8));
@@ -870,8 +987,54 @@ __global__ __launch_bounds__(256, 2) void k_elem_q3(int N, double h, MatP<double
     const int64_t col = u / nz;
     const int z0 = int(u - col * nz);
     const int z1 = int(min(nz, int64_t(z0) + (u1 - u)));
-    elem_segment3_q<MODE, T, VD>(N, m, sc, kc, int(col % tiles), int(col / tiles), z0, z1, dir, x, p, v, out, ysh, lds);
+    elem_segment3_q<MODE, T, VD, EDGE>(N, m, sc, kc, int(col % tiles), int(col / tiles), tiles, z0, z1, dir, x, p, v,
+                                       out, edge, ysh, rl, lds);
     u += z1 - z0;
+  }
+}
+
+// Border nodes of the non-overlapping tiles: a thread per node and layer
+// adds the ring partials of the tiles that hold the node (tile rows, then
+// columns, ascending) and writes the sum, Dirichlet components zero.  The
+// border nodes of a layer are those on the lines x = 16 i (every y), then
+// those on the lines y = 16 j off them.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ring_sum(int N, int tiles, const uint8_t* __restrict__ dir,
+                                                     const T* __restrict__ ring, T* __restrict__ out) {
+  const int nside = N + 1;
+  const int nvl = N / kTile + 1;
+  const int per_v = nvl * nside;
+  const int nh = nside - nvl;
+  const int per_layer = per_v + nvl * nh;
+  const int64_t total = int64_t(per_layer) * nside;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
+    const int z = int(t / per_layer);
+    int r = int(t - int64_t(z) * per_layer);
+    int gx, gy;
+    if (r < per_v) {
+      gx = kTile * (r / nside);
+      gy = r % nside;
+    } else {
+      r -= per_v;
+      gy = kTile * (r / nh);
+      const int q = r % nh;
+      gx = kTile * (q / kOwn) + q % kOwn + 1;
+    }
+    const int bx0 = (gx % kTile == 0 && gx > 0) ? gx / kTile - 1 : gx / kTile, bx1 = min(gx / kTile, tiles - 1);
+    const int by0 = (gy % kTile == 0 && gy > 0) ? gy / kTile - 1 : gy / kTile, by1 = min(gy / kTile, tiles - 1);
+    T s[4] = {T(0), T(0), T(0), T(0)};
+    for (int by = by0; by <= by1; ++by)
+      for (int bx = bx0; bx <= bx1; ++bx) {
+        const T* e = ring + ((int64_t(by) * tiles + bx) * nside + z) * (4 * kRing) +
+                     4 * ring_slot(gx - kTile * bx, gy - kTile * by);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[k] += e[k];
+      }
+    const int c[3] = {gx, gy, z};
+    const int64_t n = int64_t(gx) + int64_t(nside) * (int64_t(gy) + int64_t(nside) * z);
+    const uint8_t mk = node_mask<3>(dir, n, c, N);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[4 * n + k] = (mk & (1u << k)) ? T(0) : s[k];
   }
 }
 
@@ -1035,6 +1198,11 @@ int grid_for(int64_t work) {
 
 }  // namespace
 
+size_t ring_values(int N) {
+  const size_t et = size_t((N + kTile - 1) / kTile);
+  return et * et * size_t(N + 1) * 4 * kRing;
+}
+
 // ----------------------------------------------------------------- launch
 hipError_t launch_reduce_partials(const double* partials, int n, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, partials, n, out);
@@ -1139,11 +1307,28 @@ static hipError_t launch_scatter(const ElemArgs& a, const T* x, const T* p, cons
     else if constexpr (sizeof(T) == 4)
       hipLaunchKernelGGL((k_elem_scatter3_f32<MODE>), dim3(unsigned(nb)), dim3(256), 0, st, a.N, T(a.h), a.m, tiles,
                          a.dir, x, p, v, out);
-    else
-      hipLaunchKernelGGL((a.m.split ? k_elem_q3<MODE, true> : k_elem_q3<MODE, false>), dim3(unsigned(nb)), dim3(256),
-                         0, st, a.N, T(a.h), a.m,
-                         sym_const<double>(a.m, elem_scale<double>(1.0 / a.h, a.h * a.h * a.h / 8.0)), tiles, a.dir,
-                         x, p, v, out);
+    else {
+      const SymConst<double> kc = sym_const<double>(a.m, elem_scale<double>(1.0 / a.h, a.h * a.h * a.h / 8.0));
+      if (a.ring) {
+        // non-overlapping tiles, then the border nodes' sums
+        const int et = (a.N + kTile - 1) / kTile;
+        const int64_t ework = int64_t(et) * et * (a.N + 1);
+        const int64_t enb = std::max<int64_t>(1, std::min<int64_t>(int64_t(compute_units()) * 2, ework));
+        hipLaunchKernelGGL((a.m.split ? k_elem_q3<MODE, true, true> : k_elem_q3<MODE, false, true>),
+                           dim3(unsigned(enb)), dim3(256), 0, st, a.N, T(a.h), a.m, kc, et, a.dir, x, p, v, out,
+                           a.ring);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int nvl = a.N / kTile + 1;
+        const int64_t border = (int64_t(nvl) * (a.N + 1) + int64_t(nvl) * (a.N + 1 - nvl)) * (a.N + 1);
+        hipLaunchKernelGGL(k_ring_sum<double>, dim3(grid_for(border)), dim3(kBlock), 0, st, a.N, et, a.dir,
+                           (const double*)a.ring, out);
+      } else {
+        hipLaunchKernelGGL((a.m.split ? k_elem_q3<MODE, true, false> : k_elem_q3<MODE, false, false>),
+                           dim3(unsigned(nb)), dim3(256), 0, st, a.N, T(a.h), a.m, kc, tiles, a.dir, x, p, v, out,
+                           (double*)nullptr);
+      }
+    }
   } else {
     int64_t nn = int64_t(a.N + 1) * (a.N + 1);
     with_split(a.m, [&](auto sk) {

@@ -57,6 +57,7 @@ struct rmtr_ctx {
   int L = 0;
   std::vector<Level> lv;  // index 1..L
   double* partials = nullptr;
+  double* ring = nullptr;  // ring partials of the 3D element kernels (finest level's size)
   double* scal = nullptr;  // device scalars
   int* flag = nullptr;     // device int flag
   double* hs = nullptr;    // pinned host scalars
@@ -136,14 +137,20 @@ ElemArgs eargs(const rmtr_ctx* c, int l, const uint8_t* dir) {
   a.h = c->lv[l].h;
   a.m = c->mat;
   a.dir = dir;
+  a.ring = c->ring;
   return a;
 }
 
 hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
 
+// 3D levels run the FP64 gradient and Hv on non-overlapping tiles, except
+// with the spectral split
+bool uses_ring(const rmtr_ctx* c) { return c->model.dim == 3 && c->mat.split != kSplitSpectral; }
+
 rmtr_status ensure_common(rmtr_ctx* c) {
   if (c->partials) return RMTR_OK;
   HIPCHK(c, dalloc(c, &c->partials, kMaxPartials));
+  if (uses_ring(c)) HIPCHK(c, dalloc(c, &c->ring, ring_values(c->lv[c->L].N)));
   HIPCHK(c, dalloc(c, &c->scal, kScal));
   HIPCHK(c, dalloc(c, &c->flag, 4));
   void* h = nullptr;
@@ -188,13 +195,15 @@ rmtr_status ensure_solver_level(rmtr_ctx* c, int l, bool mixed, bool fine_model)
 // Device bytes of the buffers above: the common scalars and reduction
 // partials, and (with a load step) everything rmtr_solve_loadstep allocates
 // for its hierarchy, in the same sizes and rounding as dalloc.
-size_t common_bytes() {
-  return buf_bytes(kMaxPartials * sizeof(double)) + buf_bytes(kScal * sizeof(double)) + buf_bytes(4 * sizeof(int));
+size_t common_bytes(const rmtr_ctx* c) {
+  return buf_bytes(kMaxPartials * sizeof(double)) +
+         (uses_ring(c) ? buf_bytes(ring_values(c->lv[c->L].N) * sizeof(double)) : 0) +
+         buf_bytes(kScal * sizeof(double)) + buf_bytes(4 * sizeof(int));
 }
 
 size_t loadstep_bytes(const rmtr_ctx* c, bool mixed, bool learned, bool fine_model) {
   const int d = c->model.dim, L = c->L;
-  size_t b = common_bytes();
+  size_t b = common_bytes(c);
   for (int l = 1; l <= L; ++l) {
     const Level& v = c->lv[l];
     if (fine_model && l >= 2) b += (l == L ? 3 : 2) * buf_bytes(size_t(v.n) * sizeof(double));
@@ -1087,7 +1096,7 @@ rmtr_status rmtr_energy_noalloc(rmtr_ctx* c, int32_t level, const double* x, con
 
 size_t rmtr_workspace_bytes(const rmtr_ctx* c, const rmtr_params* prm) {
   if (!c) return 0;
-  if (!prm) return common_bytes();
+  if (!prm) return common_bytes(c);
   return loadstep_bytes(c, prm->precision == RMTR_FP32, prm->use_learned != 0, prm->coarse_model == 2);
 }
 
@@ -1117,6 +1126,8 @@ rmtr_status rmtr_energy_diff(rmtr_ctx* c, int32_t level, const double* x, const 
 rmtr_status rmtr_gradient(rmtr_ctx* c, int32_t level, const double* x, const double* p, const uint8_t* dir,
                           double* g, void* stream) {
   if (!valid_level(c, level) || !x || !p || !g) return fail(c, RMTR_E_ARG, "rmtr_gradient: bad arguments");
+  rmtr_status r = ensure_common(c);
+  if (r != RMTR_OK) return r;
   HIPCHK(c, launch_gradient(eargs(c, level, dir), x, p, g, S(stream)));
   return RMTR_OK;
 }
@@ -1125,6 +1136,8 @@ rmtr_status rmtr_hessvec(rmtr_ctx* c, int32_t level, const void* xl, const void*
                          const void* v, void* hv, int32_t precision, void* stream) {
   if (!valid_level(c, level) || !xl || !p || !v || !hv) return fail(c, RMTR_E_ARG, "rmtr_hessvec: bad arguments");
   if (v == hv) return fail(c, RMTR_E_ARG, "rmtr_hessvec: v and Hv must not alias");
+  rmtr_status r = ensure_common(c);
+  if (r != RMTR_OK) return r;
   HIPCHK(c, launch_hessvec(eargs(c, level, dir), xl, p, v, hv, precision == RMTR_FP32, S(stream)));
   return RMTR_OK;
 }

@@ -19,7 +19,13 @@ struct ElemArgs {
   double h;
   MatP<double> m;
   const uint8_t* dir;  // per-node Dirichlet bits, or null (default set)
+  // ring partials of the FP64 3D gradient and Hv on non-overlapping tiles
+  // (ring_values(N) doubles at least), or null: overlapping tiles
+  double* ring = nullptr;
 };
+
+// doubles of the ring partials a 3D level of N cells per side needs
+size_t ring_values(int N);
 
 // ---- element kernels (elem_kernels.hip)
 // workgroups of the energy kernel = partial sums it writes (<= kMaxPartials)
