@@ -200,6 +200,14 @@ constexpr int kTNodes = kTN * kTN;     // nodes per tile layer
 // border node in a fixed order (no atomics).
 constexpr int kRing = 4 * kTile;
 
+// A workgroup's column segment [z0, z1) evaluates only its own element
+// layers, so its first node layer misses the share of the element layer
+// below; the segment under it, which ends there, writes that share (all
+// 17 x 17 tile nodes) to the workgroup's seam slot, and the border kernel
+// adds it.  Doubles per slot, and the most slots (workgroups) a launch uses.
+constexpr int kSeam = kTNodes * 4;
+constexpr int kMaxSeams = 2048;
+
 // slot of border node (ix, iy): bottom row 0..16, top row 17..33, left
 // column (iy = 1..15) 34..48, right column 49..63
 __host__ __device__ constexpr int ring_slot(int ix, int iy) {
@@ -684,7 +692,8 @@ __device__ inline void elem_segment3_q(int N, const MatP<T>& m, const ElemScale<
                                        int by, int tiles, int z0, int z1,
                                        const uint8_t* __restrict__ dir, const T* __restrict__ x,
                                        const T* __restrict__ p, const T* __restrict__ v, T* __restrict__ out,
-                                       T* __restrict__ edge, T (*ysh)[4][256], EdgeLds<T>& R, LayerLds<T>& L) {
+                                       T* __restrict__ edge, T* __restrict__ seam, T (*ysh)[4][256], EdgeLds<T>& R,
+                                       LayerLds<T>& L) {
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
   // EDGE: the tile's elements start at (16 bx, 16 by); otherwise one column
@@ -697,7 +706,11 @@ __device__ inline void elem_segment3_q(int N, const MatP<T>& m, const ElemScale<
   const bool owner = (EDGE || (tx < kOwn && ty < kOwn)) && ox <= N && oy <= N;
   const int64_t nside = N + 1;
   const T cdc = sc.a2 * m.Gc_l;
-  const int zs = max(z0 - 1, 0), ze = min(z1 - 1, N - 1);
+  // EDGE: only the segment's own element layers; its first node layer is
+  // left without the share of the element layer below, which the segment
+  // under it leaves in its seam slot.  Otherwise that element layer is
+  // recomputed here.
+  const int zs = EDGE ? z0 : max(z0 - 1, 0), ze = min(z1 - 1, N - 1);
   const DmaPlan<T> dp = dma_plan<T>(N, gx0, gy0);
   // tile-local node (ix, iy) of node layer z: a border node's sum goes to
   // the ring partials, any other node's (every element around it is in the
@@ -941,25 +954,39 @@ __device__ inline void elem_segment3_q(int N, const MatP<T>& m, const ElemScale<
     __syncthreads();
     sb = st;
   }
-  if (ze + 1 < z1) {
+  // node layer ze + 1 from the carries: the top layer N, or (EDGE, a
+  // segment that ends below the top) the next segment's first layer, whose
+  // share from this segment goes to the seam slot (tile-local node-major,
+  // four components)
+  const bool top = ze + 1 < z1;
+  if (top || (EDGE && z1 <= N)) {
     const int nz = ze + 1;
-    if (owner) emit(tx + 1, ty + 1, nz, acc);
+    auto put = [&](int ix, int iy, const T (&s)[4]) {
+      if (top) {
+        emit(ix, iy, nz, s);
+      } else {
+        T* q = seam + (iy * kTN + ix) * 4;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q[k] = s[k];
+      }
+    };
+    if (owner) put(tx + 1, ty + 1, acc);
     if (EDGE) {
       T s[4];
       if (ty == 0 && ox <= N) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) s[k] = R.cr[k][tx];
-        emit(tx + 1, 0, nz, s);
+        put(tx + 1, 0, s);
       }
       if (tx == 0 && oy <= N) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) s[k] = R.cc[k][ty];
-        emit(0, ty + 1, nz, s);
+        put(0, ty + 1, s);
       }
       if (tid == 0) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) s[k] = R.c0[k];
-        emit(0, 0, nz, s);
+        put(0, 0, s);
       }
     }
   }
@@ -973,7 +1000,8 @@ template <int MODE, bool VD, bool EDGE>
 __global__ __launch_bounds__(256, 2) void k_elem_q3(int N, double h, MatP<double> md, SymConst<double> kc, int tiles,
                                                     const uint8_t* __restrict__ dir, const double* __restrict__ x,
                                                     const double* __restrict__ p, const double* __restrict__ v,
-                                                    double* __restrict__ out, double* __restrict__ edge) {
+                                                    double* __restrict__ out, double* __restrict__ edge,
+                                                    double* __restrict__ seam) {
   using T = double;
   __shared__ T ysh[2][4][256];
   __shared__ EdgeLds<T> rl;
@@ -988,51 +1016,89 @@ __global__ __launch_bounds__(256, 2) void k_elem_q3(int N, double h, MatP<double
     const int z0 = int(u - col * nz);
     const int z1 = int(min(nz, int64_t(z0) + (u1 - u)));
     elem_segment3_q<MODE, T, VD, EDGE>(N, m, sc, kc, int(col % tiles), int(col / tiles), tiles, z0, z1, dir, x, p, v,
-                                       out, edge, ysh, rl, lds);
+                                       out, edge, EDGE ? seam + int64_t(blockIdx.x) * kSeam : nullptr, ysh, rl,
+                                       lds);
     u += z1 - z0;
   }
 }
 
-// Border nodes of the non-overlapping tiles: a thread per node and layer
-// adds the ring partials of the tiles that hold the node (tile rows, then
-// columns, ascending) and writes the sum, Dirichlet components zero.  The
-// border nodes of a layer are those on the lines x = 16 i (every y), then
-// those on the lines y = 16 j off them.
+// Border nodes and seams of the non-overlapping tiles.  Threads
+// [0, border): a thread per border node and layer adds the ring partials of
+// the tiles that hold the node (tile rows, then columns, ascending), each
+// with the seam share below it when the node layer starts a segment, and
+// writes the sum, Dirichlet components zero.  The border nodes of a layer
+// are those on the lines x = 16 i (every y), then those on the lines
+// y = 16 j off them.  Threads [border, border + (g - 1) 225): the interior
+// nodes of the first node layer of each segment that starts above the
+// bottom (workgroup b >= 1 of the g the element kernel ran), which get the
+// seam share of workgroup b - 1 added.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_ring_sum(int N, int tiles, const uint8_t* __restrict__ dir,
-                                                     const T* __restrict__ ring, T* __restrict__ out) {
+__global__ __launch_bounds__(kBlock) void k_ring_sum(int N, int tiles, int g, const uint8_t* __restrict__ dir,
+                                                     const T* __restrict__ ring, const T* __restrict__ seam,
+                                                     T* __restrict__ out) {
   const int nside = N + 1;
   const int nvl = N / kTile + 1;
   const int per_v = nvl * nside;
   const int nh = nside - nvl;
   const int per_layer = per_v + nvl * nh;
-  const int64_t total = int64_t(per_layer) * nside;
+  const int64_t border = int64_t(per_layer) * nside;
+  const int64_t total = border + int64_t(g - 1) * kOwn * kOwn;
+  const int64_t work = int64_t(tiles) * tiles * nside;
   for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
-    const int z = int(t / per_layer);
-    int r = int(t - int64_t(z) * per_layer);
-    int gx, gy;
-    if (r < per_v) {
-      gx = kTile * (r / nside);
-      gy = r % nside;
-    } else {
-      r -= per_v;
-      gy = kTile * (r / nh);
-      const int q = r % nh;
-      gx = kTile * (q / kOwn) + q % kOwn + 1;
-    }
-    const int bx0 = (gx % kTile == 0 && gx > 0) ? gx / kTile - 1 : gx / kTile, bx1 = min(gx / kTile, tiles - 1);
-    const int by0 = (gy % kTile == 0 && gy > 0) ? gy / kTile - 1 : gy / kTile, by1 = min(gy / kTile, tiles - 1);
-    T s[4] = {T(0), T(0), T(0), T(0)};
-    for (int by = by0; by <= by1; ++by)
-      for (int bx = bx0; bx <= bx1; ++bx) {
-        const T* e = ring + ((int64_t(by) * tiles + bx) * nside + z) * (4 * kRing) +
-                     4 * ring_slot(gx - kTile * bx, gy - kTile * by);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) s[k] += e[k];
+    int gx, gy, z;
+    const T* sl0 = nullptr;  // seam slot of an interior node
+    if (t < border) {
+      z = int(t / per_layer);
+      int r = int(t - int64_t(z) * per_layer);
+      if (r < per_v) {
+        gx = kTile * (r / nside);
+        gy = r % nside;
+      } else {
+        r -= per_v;
+        gy = kTile * (r / nh);
+        const int q = r % nh;
+        gx = kTile * (q / kOwn) + q % kOwn + 1;
       }
+    } else {
+      const int64_t t2 = t - border;
+      const int64_t b = 1 + t2 / (kOwn * kOwn);
+      const int j = int(t2 % (kOwn * kOwn));
+      const int64_t u0 = work * b / g;
+      const int64_t col = u0 / nside;
+      z = int(u0 - col * nside);
+      gx = kTile * int(col % tiles) + 1 + j % kOwn;
+      gy = kTile * int(col / tiles) + 1 + j / kOwn;
+      if (z == 0 || gx > N || gy > N) continue;
+      sl0 = seam + (b - 1) * kSeam + ((gy % kTile) * kTN + gx % kTile) * 4;
+    }
     const int c[3] = {gx, gy, z};
     const int64_t n = int64_t(gx) + int64_t(nside) * (int64_t(gy) + int64_t(nside) * z);
     const uint8_t mk = node_mask<3>(dir, n, c, N);
+    T s[4];
+    if (sl0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s[k] = out[4 * n + k] + sl0[k];
+    } else {
+      const int bx0 = (gx % kTile == 0 && gx > 0) ? gx / kTile - 1 : gx / kTile, bx1 = min(gx / kTile, tiles - 1);
+      const int by0 = (gy % kTile == 0 && gy > 0) ? gy / kTile - 1 : gy / kTile, by1 = min(gy / kTile, tiles - 1);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s[k] = T(0);
+      for (int by = by0; by <= by1; ++by)
+        for (int bx = bx0; bx <= bx1; ++bx) {
+          const int ix = gx - kTile * bx, iy = gy - kTile * by;
+          const int64_t u = (int64_t(by) * tiles + bx) * nside + z;
+          const T* e = ring + u * (4 * kRing) + 4 * ring_slot(ix, iy);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) s[k] += e[k];
+          // the workgroup whose range starts at this node layer, if any
+          const int64_t b = (u * g + work - 1) / work;
+          if (z > 0 && b >= 1 && b < g && work * b / g == u) {
+            const T* q = seam + (b - 1) * kSeam + (iy * kTN + ix) * 4;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s[k] += q[k];
+          }
+        }
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) out[4 * n + k] = (mk & (1u << k)) ? T(0) : s[k];
   }
@@ -1196,11 +1262,18 @@ int grid_for(int64_t work) {
   return int(b);
 }
 
+// doubles of the ring partials proper (the seam slots follow them)
+size_t ring_part(int N) {
+  const size_t et = size_t((N + kTile - 1) / kTile);
+  return et * et * size_t(N + 1) * 4 * kRing;
+}
+
 }  // namespace
 
 size_t ring_values(int N) {
   const size_t et = size_t((N + kTile - 1) / kTile);
-  return et * et * size_t(N + 1) * 4 * kRing;
+  const size_t slots = std::min(et * et * size_t(N + 1), size_t(kMaxSeams));
+  return ring_part(N) + slots * kSeam;
 }
 
 // ----------------------------------------------------------------- launch
@@ -1313,20 +1386,23 @@ static hipError_t launch_scatter(const ElemArgs& a, const T* x, const T* p, cons
         // non-overlapping tiles, then the border nodes' sums
         const int et = (a.N + kTile - 1) / kTile;
         const int64_t ework = int64_t(et) * et * (a.N + 1);
-        const int64_t enb = std::max<int64_t>(1, std::min<int64_t>(int64_t(compute_units()) * 2, ework));
+        const int enb = int(std::max<int64_t>(
+            1, std::min<int64_t>({int64_t(compute_units()) * 2, ework, int64_t(kMaxSeams)})));
+        double* seam = a.ring + ring_part(a.N);
         hipLaunchKernelGGL((a.m.split ? k_elem_q3<MODE, true, true> : k_elem_q3<MODE, false, true>),
                            dim3(unsigned(enb)), dim3(256), 0, st, a.N, T(a.h), a.m, kc, et, a.dir, x, p, v, out,
-                           a.ring);
+                           a.ring, seam);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         const int nvl = a.N / kTile + 1;
         const int64_t border = (int64_t(nvl) * (a.N + 1) + int64_t(nvl) * (a.N + 1 - nvl)) * (a.N + 1);
-        hipLaunchKernelGGL(k_ring_sum<double>, dim3(grid_for(border)), dim3(kBlock), 0, st, a.N, et, a.dir,
-                           (const double*)a.ring, out);
+        hipLaunchKernelGGL(k_ring_sum<double>, dim3(grid_for(border + int64_t(enb - 1) * kOwn * kOwn)),
+                           dim3(kBlock), 0, st, a.N, et, enb, a.dir, (const double*)a.ring, (const double*)seam,
+                           out);
       } else {
         hipLaunchKernelGGL((a.m.split ? k_elem_q3<MODE, true, false> : k_elem_q3<MODE, false, false>),
                            dim3(unsigned(nb)), dim3(256), 0, st, a.N, T(a.h), a.m, kc, tiles, a.dir, x, p, v, out,
-                           (double*)nullptr);
+                           (double*)nullptr, (double*)nullptr);
       }
     }
   } else {

@@ -19,8 +19,9 @@ struct ElemArgs {
   double h;
   MatP<double> m;
   const uint8_t* dir;  // per-node Dirichlet bits, or null (default set)
-  // ring partials of the FP64 3D gradient and Hv on non-overlapping tiles
-  // (ring_values(N) doubles at least), or null: overlapping tiles
+  // ring partials and seam slots of the FP64 3D gradient and Hv on
+  // non-overlapping tiles (ring_values(N) doubles at least), or null:
+  // overlapping tiles
   double* ring = nullptr;
 };
 
