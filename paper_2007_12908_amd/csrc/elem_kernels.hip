@@ -225,6 +225,18 @@ struct EdgeLds {
   T c0[4];
 };
 
+// Workgroups are dispatched to the eight XCDs in turn (workgroup b to XCD
+// b mod 8).  Numbering them XCD by XCD instead (a bijection of [0, g)) gives
+// each XCD a contiguous range of the column-major (tile column, layer) work:
+// tiles next to each other in x then run on one XCD, at the same layers at
+// about the same time, and the node lines their halos share are read into
+// that XCD's L2 once.
+constexpr int kXcds = 8;
+__device__ inline int64_t xcd_block() {
+  const int64_t b = blockIdx.x, g = gridDim.x, x = b % kXcds;
+  return x * (g / kXcds) + min(x, g % kXcds) + b / kXcds;
+}
+
 // Last word of a raw buffer resource (32-bit data, no swizzle) on gfx950.
 constexpr int kRsrcWord3 = 0x00020000;
 
@@ -429,9 +441,10 @@ __device__ inline double energy3_lds(int N, double h, const MatP<double>& m, int
   const double w = h * h * h / 8.0;
   const int64_t nz = N + 1;
   const int64_t work = int64_t(tiles) * tiles * nz;
-  const int64_t u1 = work * (blockIdx.x + 1) / gridDim.x;
+  const int64_t lb = xcd_block();
+  const int64_t u1 = work * (lb + 1) / gridDim.x;
   double acc = 0.0;
-  for (int64_t u = work * blockIdx.x / gridDim.x; u < u1;) {
+  for (int64_t u = work * lb / gridDim.x; u < u1;) {
     const int64_t col = u / nz;
     const int z0 = int(u - col * nz);
     const int z1 = int(min(nz, int64_t(z0) + (u1 - u)));
@@ -516,12 +529,13 @@ __device__ inline double energy3_q(int N, const SymConst<double>& kc, double a2G
   const int tx = tid & 15, ty = tid >> 4;
   const int64_t nz = N + 1;
   const int64_t work = int64_t(tiles) * tiles * nz;
-  const int64_t u1 = work * (blockIdx.x + 1) / gridDim.x;
+  const int64_t lb = xcd_block();
+  const int64_t u1 = work * (lb + 1) / gridDim.x;
   int nd[8];
 #pragma unroll
   for (int a = 0; a < 8; ++a) nd[a] = (ty + ((a >> 1) & 1)) * kTN + tx + (a & 1);
   double acc = 0.0;
-  for (int64_t u = work * blockIdx.x / gridDim.x; u < u1;) {
+  for (int64_t u = work * lb / gridDim.x; u < u1;) {
     const int64_t col = u / nz;
     const int z0 = int(u - col * nz);
     const int z1 = int(min(nz, int64_t(z0) + (u1 - u)));
@@ -636,8 +650,9 @@ __device__ inline void elem_scatter3(int N, T h, const MatP<double>& md, int til
   const T w = h * h * h / T(8);
   const int64_t nz = N + 1;
   const int64_t work = int64_t(tiles) * tiles * nz;
-  const int64_t u1 = work * (blockIdx.x + 1) / gridDim.x;
-  for (int64_t u = work * blockIdx.x / gridDim.x; u < u1;) {
+  const int64_t lb = xcd_block();
+  const int64_t u1 = work * (lb + 1) / gridDim.x;
+  for (int64_t u = work * lb / gridDim.x; u < u1;) {
     const int64_t col = u / nz;
     const int z0 = int(u - col * nz);
     const int z1 = int(min(nz, int64_t(z0) + (u1 - u)));
@@ -1010,14 +1025,15 @@ __global__ __launch_bounds__(256, 2) void k_elem_q3(int N, double h, MatP<double
   const ElemScale<T> sc = elem_scale<T>(T(1) / h, h * h * h / T(8));
   const int64_t nz = N + 1;
   const int64_t work = int64_t(tiles) * tiles * nz;
-  const int64_t u1 = work * (blockIdx.x + 1) / gridDim.x;
-  for (int64_t u = work * blockIdx.x / gridDim.x; u < u1;) {
+  // the seam slot and the work range belong to the logical index
+  const int64_t lb = xcd_block();
+  const int64_t u1 = work * (lb + 1) / gridDim.x;
+  for (int64_t u = work * lb / gridDim.x; u < u1;) {
     const int64_t col = u / nz;
     const int z0 = int(u - col * nz);
     const int z1 = int(min(nz, int64_t(z0) + (u1 - u)));
     elem_segment3_q<MODE, T, VD, EDGE>(N, m, sc, kc, int(col % tiles), int(col / tiles), tiles, z0, z1, dir, x, p, v,
-                                       out, edge, EDGE ? seam + int64_t(blockIdx.x) * kSeam : nullptr, ysh, rl,
-                                       lds);
+                                       out, edge, EDGE ? seam + lb * kSeam : nullptr, ysh, rl, lds);
     u += z1 - z0;
   }
 }
@@ -1030,8 +1046,8 @@ __global__ __launch_bounds__(256, 2) void k_elem_q3(int N, double h, MatP<double
 // are those on the lines x = 16 i (every y), then those on the lines
 // y = 16 j off them.  Threads [border, border + (g - 1) 225): the interior
 // nodes of the first node layer of each segment that starts above the
-// bottom (workgroup b >= 1 of the g the element kernel ran), which get the
-// seam share of workgroup b - 1 added.
+// bottom (workgroup b >= 1 of the g the element kernel ran, in its logical
+// numbering, xcd_block), which get the seam share of workgroup b - 1 added.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_ring_sum(int N, int tiles, int g, const uint8_t* __restrict__ dir,
                                                      const T* __restrict__ ring, const T* __restrict__ seam,
