@@ -678,8 +678,14 @@ __device__ inline T pgs_update_st(T s, T r, T d, T lo, T hi) {
 
 // One colour pass of projected Gauss-Seidel: a thread per node of colour
 // `col`; the components are updated in order (backward: reverse) with the
-// node's diagonal block (offset (3^d - 1) / 2).
-template <int DIM, typename T, int BACKWARD>
+// node's diagonal block (offset (3^d - 1) / 2).  MODE 0: forward, 1:
+// backward, 2: forward then backward, 3: backward then forward.  The last
+// two are two passes over the same colour in a row, where a symmetric sweep
+// turns (the forward half ends on the colour the backward half starts
+// with, and a backward half ends on the colour the next sweep starts
+// with): the neighbours do not change in between, so the second component
+// sweep continues from the same neighbour sum and the row is read once.
+template <int DIM, typename T, int MODE>
 __global__ __launch_bounds__(kB) void k_st_pgs(Colours g, int col, const T* __restrict__ S,
                                                const uint8_t* __restrict__ dir, const T* __restrict__ gv,
                                                const T* __restrict__ lo, const T* __restrict__ hi,
@@ -735,13 +741,17 @@ __global__ __launch_bounds__(kB) void k_st_pgs(Colours g, int col, const T* __re
       for (int l = 0; l < NC; ++l) D[k][l] = Sn[((k * NO + CEN) * NC + l) * kChunk];
     }
 #pragma unroll
-    for (int kk = 0; kk < NC; ++kk) {
-      const int k = BACKWARD ? NC - 1 - kk : kk;
-      if (mk & (1u << k)) continue;
-      T rk = r[k];
+    for (int pass = 0; pass < (MODE >= 2 ? 2 : 1); ++pass) {
+      const bool backward = (MODE == 1 || MODE == 3) != (pass == 1);
 #pragma unroll
-      for (int l = 0; l < NC; ++l) rk += D[k][l] * (sn[l] - s0[l]);
-      sn[k] = pgs_update_st<T>(sn[k], rk, D[k][k], lo[NC * n + k], hi[NC * n + k]);
+      for (int kk = 0; kk < NC; ++kk) {
+        const int k = backward ? NC - 1 - kk : kk;
+        if (mk & (1u << k)) continue;
+        T rk = r[k];
+#pragma unroll
+        for (int l = 0; l < NC; ++l) rk += D[k][l] * (sn[l] - s0[l]);
+        sn[k] = pgs_update_st<T>(sn[k], rk, D[k][k], lo[NC * n + k], hi[NC * n + k]);
+      }
     }
 #pragma unroll
     for (int k = 0; k < NC; ++k) s[NC * n + k] = sn[k];
@@ -849,19 +859,26 @@ static hipError_t st_sweeps(int N, const T* S, const uint8_t* dir, const T* gv, 
                             int n_sweeps, hipStream_t st) {
   constexpr int NCOL = 1 << DIM;
   const Colours g = colours(DIM, N);
-  for (int it = 0; it < n_sweeps; ++it)
-    for (int bw = 0; bw < 2; ++bw)
-      for (int cc = 0; cc < NCOL; ++cc) {
-        const int col = bw ? NCOL - 1 - cc : cc;
-        if (bw)
-          hipLaunchKernelGGL((k_st_pgs<DIM, T, 1>), dim3(gridn(g.cnt[col])), dim3(kB), 0, st, g, col, S, dir, gv, lo,
-                             hi, s);
-        else
-          hipLaunchKernelGGL((k_st_pgs<DIM, T, 0>), dim3(gridn(g.cnt[col])), dim3(kB), 0, st, g, col, S, dir, gv, lo,
-                             hi, s);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-      }
+  // the colour passes of the sweeps in order: colours 0 .. NCOL-1 forward,
+  // then NCOL-1 .. 0 backward, per sweep; two passes in a row over the same
+  // colour run as one launch (MODE 2 or 3)
+  const int np = 2 * NCOL * n_sweeps;
+  for (int i = 0; i < np;) {
+    const int half = (i / NCOL) & 1, cc = i % NCOL;
+    const int col = half ? NCOL - 1 - cc : cc;
+    const bool twice = i + 1 < np && cc == NCOL - 1;  // the next pass is over the same colour
+    const int mode = twice ? 2 + half : half;
+    const dim3 gd(gridn(g.cnt[col])), tb(kB);
+    switch (mode) {
+      case 0: hipLaunchKernelGGL((k_st_pgs<DIM, T, 0>), gd, tb, 0, st, g, col, S, dir, gv, lo, hi, s); break;
+      case 1: hipLaunchKernelGGL((k_st_pgs<DIM, T, 1>), gd, tb, 0, st, g, col, S, dir, gv, lo, hi, s); break;
+      case 2: hipLaunchKernelGGL((k_st_pgs<DIM, T, 2>), gd, tb, 0, st, g, col, S, dir, gv, lo, hi, s); break;
+      default: hipLaunchKernelGGL((k_st_pgs<DIM, T, 3>), gd, tb, 0, st, g, col, S, dir, gv, lo, hi, s); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    i += twice ? 2 : 1;
+  }
   return hipSuccess;
 }
 
