@@ -116,8 +116,10 @@ RMTR_FN void zero(Zq<DIM, T>& z) {
 //   c = 1 / sqrt(1 + t^2),  s = t c,   A <- J^T A J,  Q <- Q J.
 // One rotation diagonalises a 2 x 2 matrix exactly; the 3 x 3 iteration
 // converges quadratically and a fixed number of sweeps reaches rounding
-// level.  On return ev holds the eigenvalues and, when VEC, the columns of
-// Q the eigenvectors.
+// level.  With eigenvectors (VEC) it stops earlier once the off-diagonal
+// part is below rounding against the diagonal (usually after two or three
+// sweeps): there each rotation also turns Q.  On return ev holds the
+// eigenvalues and, when VEC, the columns of Q the eigenvectors.
 template <int DIM, typename T, bool VEC>
 RMTR_FN void sym_eig(T (&A)[DIM][DIM], T (&ev)[DIM], T (&Q)[DIM][DIM]) {
   if (VEC) {
@@ -128,8 +130,16 @@ RMTR_FN void sym_eig(T (&A)[DIM][DIM], T (&ev)[DIM], T (&Q)[DIM][DIM]) {
   }
   constexpr int kSweeps = DIM == 2 ? 1 : (sizeof(T) >= 8 ? 5 : 4);
   constexpr int kPairs = DIM == 2 ? 1 : 3;
+  const T eps = sizeof(T) >= 8 ? T(1.1102230246251565e-16) : T(5.9604645e-8);  // unit roundoff
 #pragma unroll
   for (int sw = 0; sw < kSweeps; ++sw) {
+    if (DIM == 3 && VEC && sw > 0) {
+      const T off = (A[0][1] < T(0) ? -A[0][1] : A[0][1]) + (A[0][2] < T(0) ? -A[0][2] : A[0][2]) +
+                    (A[1][2] < T(0) ? -A[1][2] : A[1][2]);
+      const T dg = (A[0][0] < T(0) ? -A[0][0] : A[0][0]) + (A[1][1] < T(0) ? -A[1][1] : A[1][1]) +
+                   (A[2][2] < T(0) ? -A[2][2] : A[2][2]);
+      if (!(off > eps * dg)) break;
+    }
 #pragma unroll
     for (int pr = 0; pr < kPairs; ++pr) {
       const int p = pr == 2 ? 1 : 0, q = pr == 0 ? 1 : 2;
