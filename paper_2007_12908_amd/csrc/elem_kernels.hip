@@ -423,12 +423,12 @@ __device__ inline void elem_segment3_lds(int N, const MatP<T>& m, T invh, T w, i
   }
 }
 
-// 3D energy (and FP64 energy difference) on the same tiles: each tile
-// column counts the elements it owns (tile-local column tx >= 1, the column
-// tx = 0 belonging to the tile before it) and the element layers of its
-// segment of node layers, so every element is counted exactly once; node
-// layers are staged in LDS as for the scatter kernels (x in the x slots, the
-// step s in the v slots).  Each workgroup writes one partial sum (threads in
+// 3D energy (and FP64 energy difference) on non-overlapping tiles: tile
+// (bx, by) holds the 16 x 16 element columns from (16 bx, 16 by) (its LDS
+// nodes from the same corner) and counts the element layers of its segment
+// of node layers, so every element is counted exactly once; node layers are
+// staged in LDS as for the scatter kernels (x in the x slots, the step s in
+// the v slots).  Each workgroup writes one partial sum (threads in
 // element order, then a fixed tree), so the result is deterministic.
 template <bool DIFF, int SK>
 __device__ inline double energy3_lds(int N, double h, const MatP<double>& m, int tiles, const double* __restrict__ x,
@@ -449,11 +449,11 @@ __device__ inline double energy3_lds(int N, double h, const MatP<double>& m, int
     const int z0 = int(u - col * nz);
     const int z1 = int(min(nz, int64_t(z0) + (u1 - u)));
     const int bx = int(col % tiles), by = int(col / tiles);
-    const int ex = bx * kOwn - 1 + tx, ey = by * kOwn - 1 + ty;
-    const bool mine = tx >= 1 && ty >= 1 && ex < N && ey < N;
+    const int ex = bx * kTile + tx, ey = by * kTile + ty;
+    const bool mine = ex < N && ey < N;
     const int zs = z0, ze = min(z1, N) - 1;
     if (zs <= ze) {
-      const DmaPlan<double> dp = dma_plan<double>(N, bx * kOwn - 1, by * kOwn - 1);
+      const DmaPlan<double> dp = dma_plan<double>(N, bx * kTile, by * kTile);
       dma_layer<MODE, double, LayerLds<double>>(N, dp, zs, 0, x, p, s, L);
       dma_layer<MODE, double, LayerLds<double>>(N, dp, zs + 1, 1, x, p, s, L);
       __builtin_amdgcn_s_waitcnt(0);
@@ -1303,9 +1303,9 @@ hipError_t launch_reduce_partials(const double* partials, int n, double* out, hi
 // split's, one for the difference), fewer on coarse levels with fewer tile
 // layers.
 int64_t energy3_groups(int N, bool diff, bool spec) {
-  // the quarter-wise energy tiles the elements without overlap (16 x 16
-  // element columns), the others the nodes with one element of overlap
-  const int tiles = diff || spec ? (N + 1 + kOwn - 1) / kOwn : (N + kTile - 1) / kTile;
+  // the energy kernels tile the elements without overlap (16 x 16 element
+  // columns)
+  const int tiles = (N + kTile - 1) / kTile;
   const int64_t work = int64_t(tiles) * tiles * (N + 1);
   return std::max<int64_t>(1, std::min<int64_t>(int64_t(compute_units()) * (diff ? 1 : spec ? 2 : 4), work));
 }
@@ -1324,7 +1324,7 @@ hipError_t launch_energy(const ElemArgs& a, const double* x, const void* s, int 
                          double* partials, double* out, hipStream_t st) {
   int nb = energy_partials(a);
   if (a.dim == 3 && !s_fp32) {
-    const int tiles = (a.N + 1 + kOwn - 1) / kOwn;
+    const int tiles = (a.N + kTile - 1) / kTile;
     const bool spec = a.m.split == kSplitSpectral;
     if (s) {
       nb = int(std::min<int64_t>(energy3_groups(a.N, true, spec), kMaxPartials));
@@ -1339,9 +1339,8 @@ hipError_t launch_energy(const ElemArgs& a, const double* x, const void* s, int 
                          partials);
     } else {
       const ElemScale<double> sc = elem_scale<double>(1.0 / a.h, a.h * a.h * a.h / 8.0);
-      const int etiles = (a.N + kTile - 1) / kTile;
       hipLaunchKernelGGL((a.m.split ? k_energy_q3<true> : k_energy_q3<false>), dim3(nb), dim3(256), 0, st, a.N,
-                         sym_const<double>(a.m, sc), 0.5 * sc.a2 * a.m.Gc_l, etiles, x, p, partials);
+                         sym_const<double>(a.m, sc), 0.5 * sc.a2 * a.m.Gc_l, tiles, x, p, partials);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
