@@ -171,17 +171,22 @@ __global__ __launch_bounds__(kBlock) void k_reduce_partials(const double* __rest
   if (threadIdx.x == 0) *out = tot;
 }
 
-// 3D element-centric kernel: a 16 x 16 tile of element columns marches up
-// in z; each element's 8 nodal contributions are exchanged through LDS and
-// summed by the thread that owns the node, so no atomics are needed and the
-// sum order is fixed.  Tiles overlap by one element column so that each
-// tile owns the 15 x 15 nodes whose four in-plane elements it computes.
+// 3D element-centric kernels: a 16 x 16 tile of element columns marches up
+// in z; each element's 8 nodal contributions are exchanged through LDS (or
+// registers) and summed by the thread that owns the node, so no atomics
+// are needed and the sum order is fixed.  Two tilings: tiles that overlap
+// by one element column and row, so that each tile owns the 15 x 15 nodes
+// whose four in-plane elements it computes (the all-points kernels of the
+// FP32 Hv and the spectral split), and non-overlapping tiles whose border
+// nodes are summed by a second kernel (the FP64 gradient and Hv, below);
+// the energy kernels count each element once on non-overlapping tiles.
 constexpr int kTile = 16;
 constexpr int kOwn = kTile - 1;
 
 // One column segment: the tile (bx, by) writes its owned nodes of node
-// layers [z0, z1); it computes element layers z0 - 1 .. z1 - 1 (those that
-// touch them).  The tile's node layers are staged in LDS: each
+// layers [z0, z1); on overlapping tiles it computes element layers
+// z0 - 1 .. z1 - 1 (those that touch them).  The tile's node layers are
+// staged in LDS: each
 // node layer of the tile (17 x 17 nodes: x, v and p) is copied from memory
 // into LDS by the asynchronous global-to-LDS loads, one layer ahead of the
 // element layer that needs it, so the loads of the next layer overlap the
@@ -634,10 +639,10 @@ __global__ __launch_bounds__(256) void k_energy_diff3_lds(int N, double h, MatP<
 }
 
 // The work is the tiles x (N + 1) node layers, ordered column by column,
-// and split into gridDim.x equal contiguous ranges, one per workgroup: the
-// grid is sized to the workgroups the chip holds at once, so every compute
-// unit gets the same number of layers (a range that starts inside a column
-// recomputes one element layer).
+// and split into gridDim.x equal contiguous ranges, one per workgroup in its
+// XCD-major numbering (xcd_block): the grid is sized to the workgroups the
+// chip holds at once, so every compute unit gets the same number of layers
+// (a range that starts inside a column recomputes one element layer).
 template <int MODE, typename T, int SK>
 __device__ inline void elem_scatter3(int N, T h, const MatP<double>& md, int tiles,
                                      const uint8_t* __restrict__ dir, const T* __restrict__ x,
@@ -1377,10 +1382,10 @@ hipError_t launch_energy(const ElemArgs& a, const double* x, const void* s, int 
 template <int MODE, typename T>
 static hipError_t launch_scatter(const ElemArgs& a, const T* x, const T* p, const T* v, T* out, hipStream_t st) {
   if (a.dim == 3) {
+    // overlapping tiles (the all-points kernels, and the quarter-wise one
+    // without a ring buffer); a coarse level with fewer tile layers than the
+    // grid gets one layer per workgroup (latency bounds it there)
     const int tiles = (a.N + 1 + kOwn - 1) / kOwn;
-    // one workgroup per compute unit (FP64), two (FP32); a coarse level with
-    // fewer node layers than that gets one layer per workgroup (latency, not
-    // the recomputed element layer, bounds it there)
     const int64_t work = int64_t(tiles) * tiles * (a.N + 1);
     const bool spec = a.m.split == kSplitSpectral;
     // FP64 (unsplit, volumetric-deviatoric): the quarter-wise kernel, two
