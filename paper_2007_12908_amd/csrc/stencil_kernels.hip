@@ -114,6 +114,27 @@ __global__ __launch_bounds__(kB) void k_coef(int N, double h, MatP<double> m, co
 // dy = 1, or dy = 0 and dx = 1) are summed, and each of the 13 off-diagonal
 // ones is stored twice, in n's row and, transposed, in the row of the
 // neighbour m = n + off(o) towards n (offset 26 - o).
+// Basis values and unit-cell gradients of the Q1 element at its Gauss
+// points, [q][a][0] = N_a(q), [q][a][1 + j] = dN_a/dxi_j(q), as a constant
+// table: the point index of the assembly's loop is uniform, so its entries
+// come in through scalar loads instead of vector arithmetic.
+template <int DIM, typename T>
+struct RefTab {
+  T v[1 << DIM][1 << DIM][DIM + 1];
+};
+template <int DIM, typename T>
+constexpr RefTab<DIM, T> make_ref_tab() {
+  RefTab<DIM, T> t{};
+  for (int q = 0; q < (1 << DIM); ++q)
+    for (int a = 0; a < (1 << DIM); ++a) {
+      t.v[q][a][0] = T(refN<DIM>(q, a));
+      for (int j = 0; j < DIM; ++j) t.v[q][a][1 + j] = T(refdN<DIM>(q, a, j));
+    }
+  return t;
+}
+template <int DIM, typename T>
+__constant__ RefTab<DIM, T> kRefTab = make_ref_tab<DIM, T>();
+
 template <int DIM, typename TO, bool SPEC>
 __device__ inline void st_node_item(const Colours& g, double h, double gcl_d, const TO* __restrict__ C,
                                     const uint8_t* __restrict__ dir, TO* __restrict__ S, int al, int64_t id,
@@ -173,10 +194,10 @@ __device__ inline void st_node_item(const Colours& g, double h, double gcl_d, co
 #pragma unroll
             for (int jj = 0; jj < DIM; ++jj) Sr[i][jj] = cf[3 + DIM * i + jj];
           }
-          const T Na = T(refN<DIM>(q, a));
+          const T Na = kRefTab<DIM, T>.v[q][a][0];
           T dNa[DIM];
 #pragma unroll
-          for (int jj = 0; jj < DIM; ++jj) dNa[jj] = T(refdN<DIM>(q, a, jj)) * invh;
+          for (int jj = 0; jj < DIM; ++jj) dNa[jj] = kRefTab<DIM, T>.v[q][a][1 + jj] * invh;
           T dNal = T(0), Sal[DIM], Pcal = T(0);
 #pragma unroll
           for (int jj = 0; jj < DIM; ++jj) Sal[jj] = T(0);
@@ -232,12 +253,12 @@ __device__ inline void st_node_item(const Colours& g, double h, double gcl_d, co
             // 3D: blocks towards lower neighbours are the transposes of
             // blocks the neighbour computes and stores for this node too
             if (DIM == 3 && pz == 1 && o < 4) continue;
-            const T Nb = T(refN<DIM>(q, b));
+            const T Nb = kRefTab<DIM, T>.v[q][b][0];
             T dNb[DIM];
             T dd = T(0);
 #pragma unroll
             for (int jj = 0; jj < DIM; ++jj) {
-              dNb[jj] = T(refdN<DIM>(q, b, jj)) * invh;
+              dNb[jj] = kRefTab<DIM, T>.v[q][b][1 + jj] * invh;
               dd += dNa[jj] * dNb[jj];
             }
             if (al < DIM) {
