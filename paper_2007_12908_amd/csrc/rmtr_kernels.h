@@ -25,7 +25,8 @@ struct ElemArgs {
   double* ring = nullptr;
 };
 
-// doubles of the ring partials a 3D level of N cells per side needs
+// doubles of the ring partials and seam slots that the gradient and Hv of
+// a 3D level of N cells per side (or of any coarser level) need
 size_t ring_values(int N);
 
 // ---- element kernels (elem_kernels.hip)
