@@ -59,11 +59,14 @@ def test_energy_gradient_hessvec_fp64(d, N, split):
 
 @pytest.mark.parametrize("N,split,masked", [(48, True, False), (52, False, True)])
 def test_large_level_tiles(N, split, masked):
-    """Levels of several tiles per side: the energy tiles the elements in
-    16 x 16 columns (48 is three whole tiles per side, 52 leaves a ragged
-    last one), the gradient and Hv the nodes in overlapping 17 x 17 node
-    tiles (neither divides evenly).  Element-by-element parity over the
-    whole grid, with the default and a random Dirichlet mask."""
+    """Levels of several tiles per side: the energy, gradient and Hv tile
+    the elements in 16 x 16 columns (48 is three whole tiles per side, so
+    the last border line is the domain's face; 52 leaves a ragged last
+    tile), and the gradient and Hv add the tile-border nodes and segment
+    seams in their second kernel (at 48, 441 workgroups take one node layer
+    each, so every layer above the first is a seam; at 52 some ranges
+    cross a column).  Element-by-element parity over the whole grid, with
+    the default and a random Dirichlet mask."""
     print(f"case N={N} split={split} masked={masked}", flush=True)
     import torch
     d = 3
