@@ -418,16 +418,33 @@ __global__ __launch_bounds__(576) void k_conv_bwd_w_tile(Box b, const float* __r
   }
 }
 
-// second stage: fixed-order sum of the partial rows
+// second stage: fixed-order sum of the partial rows.  A workgroup takes
+// kSumCols consecutive entries; its kSumGroups thread groups sum the rows
+// i = g, g + kSumGroups, ... (in increasing order) of each entry, and the
+// group sums are added in group order.
+constexpr int kSumCols = 32, kSumGroups = kB / kSumCols;
+
 __global__ __launch_bounds__(kB) void k_sum_partials(const float* __restrict__ partial, int nblk, int64_t len,
                                                      float* __restrict__ dw, float* __restrict__ db, int64_t nw) {
-  for (int64_t e = int64_t(blockIdx.x) * kB + threadIdx.x; e < len; e += int64_t(gridDim.x) * kB) {
+  __shared__ float sh[kSumGroups][kSumCols];
+  const int c = int(threadIdx.x) % kSumCols, grp = int(threadIdx.x) / kSumCols;
+  for (int64_t e0 = int64_t(blockIdx.x) * kSumCols; e0 < len; e0 += int64_t(gridDim.x) * kSumCols) {
+    const int64_t e = e0 + c;
     float s = 0.0f;
-    for (int i = 0; i < nblk; ++i) s += partial[int64_t(i) * len + e];
-    if (e < nw)
-      dw[e] = s;
-    else
-      db[e - nw] = s;
+    if (e < len)
+      for (int i = grp; i < nblk; i += kSumGroups) s += partial[int64_t(i) * len + e];
+    sh[grp][c] = s;
+    __syncthreads();
+    if (grp == 0 && e < len) {
+      float t = sh[0][c];
+#pragma unroll
+      for (int k = 1; k < kSumGroups; ++k) t += sh[k][c];
+      if (e < nw)
+        dw[e] = t;
+      else
+        db[e - nw] = t;
+    }
+    __syncthreads();
   }
 }
 
@@ -685,8 +702,8 @@ hipError_t nn_backward(const uint16_t* w, const float* act, const float* dout, f
       hipLaunchKernelGGL((k_conv_bwd_w_tile<32, 32>), dim3(nblk), dim3(576), 0, st, b, X, dY, part);
     else
       hipLaunchKernelGGL((k_conv_bwd_w_tile<8, 32>), dim3(nblk), dim3(576), 0, st, b, X, dY, part);
-    hipLaunchKernelGGL(k_sum_partials, dim3(gridn(len)), dim3(kB), 0, st, part, nblk, len, dw + w_off(l),
-                       db + b_off(l), int64_t(27) * cin * cout);
+    hipLaunchKernelGGL(k_sum_partials, dim3(unsigned((len + kSumCols - 1) / kSumCols)), dim3(kB), 0, st, part, nblk,
+                       len, dw + w_off(l), db + b_off(l), int64_t(27) * cin * cout);
     if (l == 0) break;
     float* dX = (l % 2) ? gA : gB;
     // data gradient: input dY (cout channels), output cin channels,
