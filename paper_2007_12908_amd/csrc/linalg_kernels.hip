@@ -147,16 +147,24 @@ __global__ __launch_bounds__(kB) void k_step_box(int N, const double* __restrict
       r /= ns;
     }
     const uint8_t mk = dir ? dir[n] : default_mask<DIM>(c, N);
+    // a node's components are read and written together (3D: 32 bytes)
+    double xv[NC], lv[NC], uv[NC], lo_v[NC], hi_v[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      const int64_t j = NC * n + k;
-      if (mk & (1u << k)) {
-        lo[j] = 0.0;
-        hi[j] = 0.0;
-      } else {
-        lo[j] = fmax(Lb[j] - x[j], -delta);
-        hi[j] = fmin(Ub[j] - x[j], delta);
-      }
+      xv[k] = x[NC * n + k];
+      lv[k] = Lb[NC * n + k];
+      uv[k] = Ub[NC * n + k];
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const bool fixed = mk & (1u << k);
+      lo_v[k] = fixed ? 0.0 : fmax(lv[k] - xv[k], -delta);
+      hi_v[k] = fixed ? 0.0 : fmin(uv[k] - xv[k], delta);
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      lo[NC * n + k] = lo_v[k];
+      hi[NC * n + k] = hi_v[k];
     }
   }
 }
